@@ -1,0 +1,145 @@
+/*
+ * leg2cheb.h -- C ABI of the MI355X (gfx950) Legendre <-> Chebyshev transform.
+ *
+ * The operation (Mortensen, arXiv 2411.00033, Sec. 1, Eqs. (AfCf), (directmv)):
+ *
+ *   leg2cheb:  out = C^{-1} A in        (Legendre coefficients -> Chebyshev coefficients)
+ *   cheb2leg:  out = A^{-1} C in        (Chebyshev coefficients -> Legendre coefficients)
+ *
+ * with a_ij = Lambda((j-i)/2) Lambda((j+i)/2) for j >= i, j - i even, zero otherwise
+ * (Eqs. (aij), (Lambda)), Lambda(x) = Gamma(x+1/2)/Gamma(x+1), and C = diag(c_i pi/2),
+ * c_0 = 2, c_i = 1 otherwise.  Both are applied in O(n) work by the modal fast
+ * multipole method of Alg. 4: near-diagonal leaf blocks done directly, an upward
+ * pass (Eq. (wtk), App. A2), low-rank far-field products with Chebyshev
+ * coefficient matrices Ahat (Eq. (aklmore)), and the downward spreading of
+ * step (4).  cheb2leg uses the reverse kernel of Eq. (Lxymod) with c applied to
+ * the input first (Sec. 4.1).
+ *
+ * Conventions
+ *   - All data pointers passed to leg2cheb_execute are DEVICE pointers on the
+ *     device that was current when the plan was made.  Layout: contiguous FP64
+ *     [batch][n], row-major (item b starts at ptr + b*n).  in and out must not
+ *     overlap.
+ *   - stream is a hipStream_t (NULL = the null stream).  Execution is
+ *     asynchronous with respect to the host; errors in arguments are reported
+ *     synchronously before anything is enqueued.
+ *   - Every call returns an l2c_status code; no exception crosses the ABI.
+ *   - Plans own their device tables; they are freed by leg2cheb_destroy.  A plan
+ *     may be used from one host thread at a time.
+ */
+#ifndef LEG2CHEB_H
+#define LEG2CHEB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct l2c_plan_s *l2c_plan_t;
+
+enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
+
+/* Arithmetic of the far-field and leaf products (the plan tables and the
+ * final accumulation stay FP64).  Only L2C_FP64 is available in this build. */
+enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
+
+enum l2c_status {
+    L2C_OK = 0,
+    L2C_EINVAL = -1,      /* invalid argument (null pointer, bad size, overlap, ...) */
+    L2C_ENOMEM = -2,      /* device or host allocation failed */
+    L2C_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+    L2C_EUNSUPPORTED = -4 /* valid request that this build does not implement */
+};
+
+struct l2c_plan_info {
+    int64_t n;             /* input length */
+    int64_t n_pad;         /* N = s 2^(L+2) >= n, Eq. (numlevels); n_pad = n when direct-only */
+    int32_t levels;        /* L; 0 means the plan applies the whole product directly (Alg. 1) */
+    int32_t s;             /* half the side of the smallest submatrices, Sec. 3.1 */
+    int32_t rank;          /* M, Chebyshev expansion rank, Eq. (Aij) */
+    int32_t direction;     /* l2c_direction */
+    int32_t precision;     /* l2c_precision */
+    int32_t reserved;
+    int64_t n_blocks;      /* N_b, Eq. (total_blocks_and_mats) */
+    int64_t n_submatrices; /* N_c = 3 N_b */
+    int64_t table_bytes;   /* device bytes of the plan tables (Ahat, T, B, ...) */
+    int64_t workspace_bytes; /* device bytes of the execution workspace for the current batch capacity */
+    int64_t ahat_bytes;    /* bytes of the Ahat table alone (read once per execute) */
+};
+
+/*
+ * Build a plan for transforms of length n (Sec. 3.1 sizes; Secs. 3.2, 4.3 tables).
+ *   plan       [out] receives the new plan handle (set to NULL on error).
+ *   n          input length, n >= 1.
+ *   direction  L2C_LEG2CHEB or L2C_CHEB2LEG.
+ *   leaf_size  side 2*s_hat of the smallest far-field submatrices (Eq. (numlevels)
+ *              uses s_hat); even, 4 <= leaf_size <= 256.  The paper uses s = 32,
+ *              i.e. leaf_size 64 (Sec. 5).  The effective s lies in [s_hat/2, s_hat].
+ *   rank       M, number of Chebyshev modes per axis; one of the ranks this build
+ *              instantiates (leg2cheb_rank_supported).  The paper uses 18.
+ * The device tables are built with kernels on the current device and stream 0;
+ * the call returns after they are complete.
+ * Errors: L2C_EINVAL, L2C_EUNSUPPORTED (rank), L2C_ENOMEM, L2C_EHIP.
+ */
+int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank);
+
+/*
+ * As leg2cheb_plan, plus:
+ *   precision  l2c_precision (only L2C_FP64 in this build, else L2C_EUNSUPPORTED);
+ *   max_batch  workspace is sized for this many items (>= 1); execute grows it on
+ *              demand (a synchronizing allocation) when a larger batch arrives;
+ *   stream     hipStream_t on which the table-building kernels run (NULL = null stream).
+ */
+int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank,
+                     int precision, int64_t max_batch, void *stream);
+
+/*
+ * out[b, 0:n] = T(in[b, 0:n]) for b < batch, T = C^{-1}A (leg2cheb) or A^{-1}C
+ * (cheb2leg) as fixed at plan time (Alg. 4, steps (1)-(7)).
+ *   in, out  device pointers, FP64 [batch][n], non-overlapping.
+ *   batch    >= 0; 0 is a no-op.
+ *   stream   hipStream_t.
+ * Enqueues the kernels and returns.  Allocates only when batch exceeds the
+ * workspace capacity.  On L2C_EHIP, out is undefined.
+ */
+int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
+
+/* Release the plan and its device memory (synchronizes the device first). NULL is a no-op. */
+int leg2cheb_destroy(l2c_plan_t plan);
+
+/* Sizes and memory of a plan. */
+int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info);
+
+/*
+ * Copy one plan table to host memory, in the paper's canonical layout
+ * (used by tests to check the plan stage).
+ *   table 0 = Ahat: [level][block][r][k][l], levels 0..L-1, b_gamma = 2^(gamma+1)-1
+ *                   blocks each, r = p + q(q+1)/2 (Eq. (cfrompq)), M x M row-major;
+ *         1 = T:    [sigma][m][k] = T_k(-1 + (2m+sigma)/s), 2 x s x M (Eq. (Xs));
+ *         2 = B:    B(0) then B(1), 2 x M x M row-major (Eq. (Tky)).
+ *   dst   host buffer of at least `bytes` bytes; bytes must equal the table size
+ *         (query with dst = NULL: *needed receives the size and nothing is copied).
+ * Errors: L2C_EINVAL (bad table id, size mismatch, direct-only plan), L2C_EHIP.
+ */
+int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed);
+
+/*
+ * Optional timing hook for benchmarks: when both events (hipEvent_t) are
+ * non-NULL, execute records `before` immediately before and `after`
+ * immediately after the far-field kernel (the one that streams Ahat), on the
+ * execute stream.  Pass NULLs to turn it off.
+ */
+int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after);
+
+/* Non-zero if this build instantiates kernels for rank M. */
+int leg2cheb_rank_supported(int rank);
+
+/* Static description of a status code. */
+const char *leg2cheb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEG2CHEB_H */

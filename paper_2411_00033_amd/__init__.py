@@ -1,0 +1,103 @@
+"""MI355X (gfx950) Legendre <-> Chebyshev coefficient transforms.
+
+The modal fast multipole method of Mortensen (arXiv 2411.00033, Alg. 4) behind the
+C ABI of ``include/leg2cheb.h``; this package is the thin Python side of it.
+PyTorch supplies device memory and streams; all arithmetic runs in the HIP
+library ``libleg2cheb.so``.
+
+    import torch, paper_2411_00033_amd as l2c
+    plan = l2c.Plan(1_000_000, l2c.LEG2CHEB, leaf_size=64, rank=18)
+    z = plan.execute(x)            # x: float64 CUDA tensor, shape (n,) or (batch, n)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import (  # noqa: F401  (re-exported ABI names)
+    L2C_BF16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
+    L2C_LEG2CHEB, L2C_OK, L2CError, TABLE_AHAT, TABLE_B, TABLE_T, leg2cheb_destroy, leg2cheb_execute,
+    leg2cheb_plan, leg2cheb_plan_ex, leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_rank_supported,
+    leg2cheb_set_timing_events,
+)
+
+LEG2CHEB, CHEB2LEG = L2C_LEG2CHEB, L2C_CHEB2LEG
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """Owns one library plan (device tables + workspace) for transforms of length n."""
+
+    def __init__(self, n: int, direction: int = LEG2CHEB, leaf_size: int = 64, rank: int = 18,
+                 precision: int = L2C_FP64, max_batch: int = 1, stream=None):
+        torch = _torch()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.cuda.current_device()
+        self.handle = leg2cheb_plan_ex(n, direction, leaf_size, rank, precision, max_batch, st.cuda_stream)
+        self.n, self.direction, self.leaf_size, self.rank = int(n), int(direction), int(leaf_size), int(rank)
+
+    @property
+    def info(self) -> dict:
+        return leg2cheb_plan_info(self.handle)
+
+    def execute(self, x, out=None, stream=None):
+        """Transform x (float64 CUDA tensor, (n,) or (batch, n), contiguous) into out."""
+        torch = _torch()
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float64 CUDA tensor")
+        if x.shape[-1] != self.n or x.dim() not in (1, 2):
+            raise ValueError("x must have shape (n,) or (batch, n) with n = %d" % self.n)
+        if x.device.index != self.device:
+            raise ValueError("x is on cuda:%d but the plan was made on cuda:%d" % (x.device.index, self.device))
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.shape != x.shape or out.dtype != torch.float64 or not out.is_contiguous() or out.device != x.device:
+            raise ValueError("out must match x in shape, dtype, device and be contiguous")
+        batch = 1 if x.dim() == 1 else x.shape[0]
+        st = stream if stream is not None else torch.cuda.current_stream()
+        leg2cheb_execute(self.handle, x.data_ptr(), out.data_ptr(), batch, st.cuda_stream)
+        return out
+
+    __call__ = execute
+
+    def export(self, table: int) -> np.ndarray:
+        """A plan table in the canonical layout documented in include/leg2cheb.h (host copy)."""
+        need = leg2cheb_plan_export(self.handle, table)
+        buf = np.empty(need // 8, dtype=np.float64)
+        leg2cheb_plan_export(self.handle, table, buf.ctypes.data, need)
+        return buf
+
+    def set_timing_events(self, before, after) -> None:
+        """Record torch.cuda.Event pair around the far-field kernel of each execute (None: off)."""
+        leg2cheb_set_timing_events(self.handle, before.cuda_event if before is not None else 0,
+                                   after.cuda_event if after is not None else 0)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            leg2cheb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def transform(x, direction: int = LEG2CHEB, leaf_size: int = 64, rank: int = 18):
+    """One-shot transform (builds and frees a plan)."""
+    batch = 1 if x.dim() == 1 else x.shape[0]
+    with Plan(x.shape[-1], direction, leaf_size, rank, max_batch=batch) as p:
+        out = p.execute(x)
+        _torch().cuda.current_stream().synchronize()
+        return out

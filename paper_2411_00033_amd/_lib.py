@@ -1,0 +1,130 @@
+"""ctypes binding of libleg2cheb.so (include/leg2cheb.h).
+
+Argument marshalling only: every step of the transform runs in the HIP library.
+If the library is missing or cannot be loaded, every call raises; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libleg2cheb.so")
+
+L2C_LEG2CHEB, L2C_CHEB2LEG = 0, 1
+L2C_FP64, L2C_FP32, L2C_BF16X2 = 0, 1, 2
+L2C_OK, L2C_EINVAL, L2C_ENOMEM, L2C_EHIP, L2C_EUNSUPPORTED = 0, -1, -2, -3, -4
+TABLE_AHAT, TABLE_T, TABLE_B = 0, 1, 2
+
+EXPORTED = (
+    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_destroy", "leg2cheb_plan_info",
+    "leg2cheb_plan_export", "leg2cheb_set_timing_events", "leg2cheb_rank_supported", "leg2cheb_strerror",
+)
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_pad", ctypes.c_int64),
+        ("levels", ctypes.c_int32), ("s", ctypes.c_int32), ("rank", ctypes.c_int32),
+        ("direction", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int64), ("n_submatrices", ctypes.c_int64),
+        ("table_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("ahat_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class L2CError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libleg2cheb.so not found at %s; build it with "
+                          "`python -m paper_2411_00033_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.leg2cheb_plan.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci]
+    lib.leg2cheb_plan_ex.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, vp]
+    lib.leg2cheb_execute.argtypes = [vp, vp, vp, i64, vp]
+    lib.leg2cheb_destroy.argtypes = [vp]
+    lib.leg2cheb_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.leg2cheb_plan_export.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
+    lib.leg2cheb_set_timing_events.argtypes = [vp, vp, vp]
+    lib.leg2cheb_rank_supported.argtypes = [ci]
+    lib.leg2cheb_strerror.argtypes = [ci]
+    lib.leg2cheb_strerror.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "leg2cheb_strerror":
+            getattr(lib, name).restype = ci
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().leg2cheb_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != L2C_OK:
+        raise L2CError(rc, what)
+
+
+# ----------------------------------------------------------------- ABI-named wrappers
+def leg2cheb_plan(n: int, direction: int, leaf_size: int, rank: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_plan(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank)), "leg2cheb_plan")
+    return h.value
+
+
+def leg2cheb_plan_ex(n: int, direction: int, leaf_size: int, rank: int, precision: int = L2C_FP64,
+                     max_batch: int = 1, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_plan_ex(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
+                                   int(precision), int(max_batch), ctypes.c_void_p(stream or None)),
+           "leg2cheb_plan_ex")
+    return h.value
+
+
+def leg2cheb_execute(plan: int, in_ptr: int, out_ptr: int, batch: int, stream: int = 0) -> None:
+    _check(load().leg2cheb_execute(ctypes.c_void_p(plan), ctypes.c_void_p(in_ptr or None),
+                                   ctypes.c_void_p(out_ptr or None), int(batch), ctypes.c_void_p(stream or None)),
+           "leg2cheb_execute")
+
+
+def leg2cheb_destroy(plan: int) -> None:
+    _check(load().leg2cheb_destroy(ctypes.c_void_p(plan)), "leg2cheb_destroy")
+
+
+def leg2cheb_plan_info(plan: int) -> dict:
+    info = PlanInfo()
+    _check(load().leg2cheb_plan_info(ctypes.c_void_p(plan), ctypes.byref(info)), "leg2cheb_plan_info")
+    return info.as_dict()
+
+
+def leg2cheb_plan_export(plan: int, table: int, dst_ptr: int = 0, nbytes: int = 0) -> int:
+    """Copy a plan table to host memory at dst_ptr; with dst_ptr = 0 return its size."""
+    need = ctypes.c_int64(0)
+    _check(load().leg2cheb_plan_export(ctypes.c_void_p(plan), int(table), ctypes.c_void_p(dst_ptr or None),
+                                       int(nbytes), ctypes.byref(need)), "leg2cheb_plan_export")
+    return need.value
+
+
+def leg2cheb_set_timing_events(plan: int, before: int, after: int) -> None:
+    _check(load().leg2cheb_set_timing_events(ctypes.c_void_p(plan), ctypes.c_void_p(before or None),
+                                             ctypes.c_void_p(after or None)), "leg2cheb_set_timing_events")
+
+
+def leg2cheb_rank_supported(rank: int) -> bool:
+    return bool(load().leg2cheb_rank_supported(int(rank)))

@@ -1,0 +1,324 @@
+// l2c_api.hip -- C ABI (include/leg2cheb.h): argument checking, plan sizes and host-side
+// constant tables, device memory ownership, and dispatch to the kernels.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/leg2cheb.h"
+#include "l2c_internal.h"
+
+namespace {
+
+using l2c::FarLayout;
+
+// Sizes of Eq. (numlevels): s_hat = leaf/2, L = ceil(log2(n/s_hat)) - 2,
+// s = ceil(n / 2^(L+2)), N = s 2^(L+2).  L <= 0: the plan applies Alg. 1 directly.
+void plan_sizes(int64_t n, int leaf, int *L, int *s, int64_t *n_pad)
+{
+    const int64_t shat = leaf / 2;
+    int p = 0;
+    while ((shat << p) < n) ++p;
+    *L = p - 2;
+    if (*L <= 0) {
+        *L = 0;
+        *s = 0;
+        *n_pad = n;
+        return;
+    }
+    const int64_t span = int64_t(1) << (*L + 2);
+    *s = (int)((n + span - 1) / span);
+    *n_pad = (int64_t)(*s) * span;
+}
+
+// B(0) and B(1) of Eq. (Tky): row n holds the coefficients of T_n((Y + 2l - 1)/2) in
+// T_k(Y).  Built by the three-term recurrence T_{n+1}(u) = 2u T_n(u) - T_{n-1}(u)
+// with u = (Y + a)/2, a = 2l - 1, and Y T_j = (T_{j+1} + T_{|j-1|})/2.  Every
+// coefficient is a dyadic rational with a small denominator (App. A3), so the FP64
+// arithmetic here is exact.
+void b_matrices(int M, std::vector<double> &B)
+{
+    B.assign(2 * M * M, 0.0);
+    for (int l = 0; l < 2; ++l) {
+        const double a = 2.0 * l - 1.0;
+        std::vector<std::vector<double>> c(M, std::vector<double>(M + 1, 0.0));
+        c[0][0] = 1.0;
+        if (M > 1) {
+            c[1][0] = 0.5 * a;
+            c[1][1] = 0.5;
+        }
+        for (int n = 1; n + 1 < M; ++n) {
+            std::vector<double> nxt(M + 1, 0.0);
+            for (int j = 0; j <= n; ++j) {
+                const double v = c[n][j];
+                if (v == 0.0) continue;
+                // 2u T_n = (Y + a) T_n
+                nxt[j + 1] += 0.5 * v;
+                nxt[j == 0 ? 1 : j - 1] += 0.5 * v;
+                nxt[j] += a * v;
+            }
+            for (int j = 0; j <= n + 1; ++j) nxt[j] -= c[n - 1][j];
+            c[n + 1] = nxt;
+        }
+        for (int n = 0; n < M; ++n)
+            for (int k = 0; k < M; ++k) B[(size_t)l * M * M + n * M + k] = c[n][k];
+    }
+}
+
+// T(sigma)_{mk} = T_k(-1 + (2m + sigma)/s), Eq. (Xs); three-term recurrence.
+void vandermonde(int s, int M, std::vector<double> &T)
+{
+    T.assign((size_t)2 * s * M, 0.0);
+    for (int sig = 0; sig < 2; ++sig)
+        for (int m = 0; m < s; ++m) {
+            const double X = -1.0 + (double)(2 * m + sig) / (double)s;
+            double t0 = 1.0, t1 = X;
+            for (int k = 0; k < M; ++k) {
+                T[((size_t)sig * s + m) * M + k] = t0;
+                const double t2 = 2.0 * X * t1 - t0;
+                t0 = t1;
+                t1 = t2;
+            }
+        }
+}
+
+bool rank_supported(int M)
+{
+    switch (M) {
+#define L2C_CASE(MM) \
+    case MM: return true;
+        L2C_FOR_EACH_RANK(L2C_CASE)
+#undef L2C_CASE
+    default: return false;
+    }
+}
+
+void free_plan(l2c_plan_s *p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_ahat);
+    (void)hipFree(p->d_T);
+    (void)hipFree(p->d_B);
+    (void)hipFree(p->d_XG);
+    (void)hipFree(p->d_D);
+    (void)hipFree(p->d_w);
+    (void)hipFree(p->d_c);
+    delete p;
+}
+
+int ensure_workspace(l2c_plan_s *p, int64_t batch)
+{
+    if (p->L == 0 || batch <= p->ws_batch) return L2C_OK;
+    if (p->ws_batch > 0) {
+        if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
+    }
+    (void)hipFree(p->d_w);
+    (void)hipFree(p->d_c);
+    p->d_w = p->d_c = nullptr;
+    p->ws_batch = 0;
+    const size_t bytes = (size_t)batch * p->NT * 2 * p->M * sizeof(double);
+    if (hipMalloc(&p->d_w, bytes) != hipSuccess || hipMalloc(&p->d_c, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_w);
+        (void)hipFree(p->d_c);
+        p->d_w = p->d_c = nullptr;
+        return L2C_ENOMEM;
+    }
+    p->ws_batch = batch;
+    return L2C_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *leg2cheb_strerror(int code)
+{
+    switch (code) {
+    case L2C_OK: return "success";
+    case L2C_EINVAL: return "invalid argument";
+    case L2C_ENOMEM: return "out of memory";
+    case L2C_EHIP: return "HIP runtime error";
+    case L2C_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+int leg2cheb_rank_supported(int rank) { return rank_supported(rank) ? 1 : 0; }
+
+int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
+                     int64_t max_batch, void *stream)
+{
+    if (!plan) return L2C_EINVAL;
+    *plan = nullptr;
+    if (n < 1 || n > (int64_t(1) << 31)) return L2C_EINVAL;
+    if (direction != L2C_LEG2CHEB && direction != L2C_CHEB2LEG) return L2C_EINVAL;
+    if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
+    if (rank < 1 || rank > 32) return L2C_EINVAL;
+    if (max_batch < 1) return L2C_EINVAL;
+    if (precision != L2C_FP64) {
+        if (precision == L2C_FP32 || precision == L2C_BF16X2) return L2C_EUNSUPPORTED;
+        return L2C_EINVAL;
+    }
+    if (!rank_supported(rank)) return L2C_EUNSUPPORTED;
+
+    l2c_plan_s *p = new (std::nothrow) l2c_plan_s();
+    if (!p) return L2C_ENOMEM;
+    p->n = n;
+    p->direction = direction;
+    p->precision = precision;
+    p->leaf = leaf_size;
+    p->M = rank;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return L2C_EHIP;
+    }
+    plan_sizes(n, leaf_size, &p->L, &p->s, &p->n_pad);
+    if (p->L >= L2C_MAX_LEVELS - 1) {
+        delete p;
+        return L2C_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (p->L > 0) {
+        const int L = p->L, M = p->M, s = p->s;
+        p->nb = (p->n_pad / (2 * s)) - L - 2;   // Eq. (total_blocks_and_mats)
+        p->nc = 3 * p->nb;
+        p->NT = (int64_t(1) << (L + 2)) - 4;
+        p->far.L = L;
+        p->far.M = M;
+        int64_t goff = 0;
+        for (int g = 0; g < L; ++g) {
+            p->far.group_off[g] = goff;
+            const int64_t blocks = (int64_t(1) << (g + 1)) - 1;
+            goff += (blocks * M + 63) / 64;
+        }
+        p->far.group_off[L] = goff;
+        p->ahat_bytes = goff * 64 * 3 * M * (int64_t)sizeof(double);
+
+        std::vector<double> T, B, XG(M), Dm((size_t)M * M);
+        vandermonde(s, M, T);
+        b_matrices(M, B);
+        for (int m = 0; m < M; ++m) XG[m] = std::cos((m + 0.5) * M_PI / M);
+        for (int k = 0; k < M; ++k)
+            for (int m = 0; m < M; ++m) Dm[(size_t)k * M + m] = std::cos(k * (m + 0.5) * M_PI / M);
+
+        bool ok = hipMalloc(&p->d_ahat, p->ahat_bytes) == hipSuccess &&
+                  hipMalloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&p->d_D, Dm.size() * sizeof(double)) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            free_plan(p);
+            return L2C_ENOMEM;
+        }
+        p->table_bytes = p->ahat_bytes + (int64_t)(T.size() + B.size() + XG.size() + Dm.size()) * 8;
+        ok = hipMemcpyAsync(p->d_T, T.data(), T.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_XG, XG.data(), XG.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_D, Dm.data(), Dm.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemsetAsync(p->d_ahat, 0, p->ahat_bytes, st) == hipSuccess &&
+             l2c::launch_build_ahat(*p, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            free_plan(p);
+            return L2C_EHIP;
+        }
+        const int rc = ensure_workspace(p, max_batch);
+        if (rc != L2C_OK) {
+            free_plan(p);
+            return rc;
+        }
+    }
+    *plan = p;
+    return L2C_OK;
+}
+
+int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank)
+{
+    return leg2cheb_plan_ex(plan, n, direction, leaf_size, rank, L2C_FP64, 1, nullptr);
+}
+
+int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream)
+{
+    if (!plan || batch < 0) return L2C_EINVAL;
+    if (batch == 0) return L2C_OK;
+    if (!in || !out) return L2C_EINVAL;
+    const int64_t len = batch * plan->n;
+    if (batch > (int64_t(1) << 40) / plan->n) return L2C_EINVAL;
+    const char *ib = (const char *)in, *ie = (const char *)(in + len);
+    const char *ob = (const char *)out, *oe = (const char *)(out + len);
+    if (ib < oe && ob < ie) return L2C_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
+    if (dev != plan->device) return L2C_EINVAL;
+    const int rc = ensure_workspace(plan, batch);
+    if (rc != L2C_OK) return rc;
+    if (l2c::launch_execute(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
+    return L2C_OK;
+}
+
+int leg2cheb_destroy(l2c_plan_t plan)
+{
+    if (!plan) return L2C_OK;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    free_plan(plan);
+    return ok ? L2C_OK : L2C_EHIP;
+}
+
+int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
+{
+    if (!plan || !info) return L2C_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = plan->n;
+    info->n_pad = plan->n_pad;
+    info->levels = plan->L;
+    info->s = plan->s;
+    info->rank = plan->M;
+    info->direction = plan->direction;
+    info->precision = plan->precision;
+    info->n_blocks = plan->nb;
+    info->n_submatrices = plan->nc;
+    info->table_bytes = plan->table_bytes;
+    info->workspace_bytes = 2 * plan->ws_batch * plan->NT * 2 * plan->M * (int64_t)sizeof(double);
+    info->ahat_bytes = plan->ahat_bytes;
+    return L2C_OK;
+}
+
+int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed)
+{
+    if (!plan || plan->L == 0) return L2C_EINVAL;
+    const int M = plan->M;
+    int64_t need;
+    switch (table) {
+    case 0: need = plan->nc * M * M * 8; break;
+    case 1: need = (int64_t)2 * plan->s * M * 8; break;
+    case 2: need = (int64_t)2 * M * M * 8; break;
+    default: return L2C_EINVAL;
+    }
+    if (needed) *needed = need;
+    if (!dst) return L2C_OK;
+    if (bytes != need) return L2C_EINVAL;
+    if (table == 1) return hipMemcpy(dst, plan->d_T, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
+    if (table == 2) return hipMemcpy(dst, plan->d_B, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
+    double *tmp = nullptr;
+    if (hipMalloc(&tmp, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return L2C_ENOMEM;
+    }
+    bool ok = l2c::launch_export_ahat(*plan, tmp, nullptr) == hipSuccess &&
+              hipMemcpy(dst, tmp, need, hipMemcpyDeviceToHost) == hipSuccess;
+    (void)hipFree(tmp);
+    return ok ? L2C_OK : L2C_EHIP;
+}
+
+int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after)
+{
+    if (!plan) return L2C_EINVAL;
+    plan->ev_before = (hipEvent_t)before;
+    plan->ev_after = (hipEvent_t)after;
+    return L2C_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// l2c_plan.hip -- device part of the plan stage (arXiv 2411.00033, Secs. 3.2 and 4.3).
+//
+// k_build_ahat: one workgroup per block (g, b) of the decomposition; for each of its
+// three submatrices r = (p,q) it samples the kernel at the M x M Chebyshev-Gauss
+// points of its domain [i, i+2h] x [j, j+2h] (Eq. (aklmore)),
+//     x_m = i + h (X_m + 1),  y_n = j + h (X_n + 1),  X_m = cos((m+1/2) pi / M),
+// with the leg2cheb kernel A(x,y) = Lambda((y-x)/2) Lambda((y+x)/2) (Sec. 3.2) or the
+// cheb2leg kernel of Eq. (Lxymod), and applies the 2-D DCT-II
+//     ahat_kl = 4/(c_k c_l M^2) sum_m sum_n K(x_m, y_n) D_km D_ln,  D_km = cos(k (m+1/2) pi / M),
+// as two M x M x M products in LDS.  All in FP64.  Results go straight into the
+// slot-interleaved far-field layout that k_far streams (see l2c_internal.h).
+//
+// The paper's planning shortcuts (persymmetry of Lambda^-, reuse across a level,
+// term dropping in Eq. (tau), the radix-2/3 DCT of size 18) reduce CPU flops; here
+// every sample is evaluated directly, which keeps one independent thread per sample.
+#include "l2c_internal.h"
+#include "l2c_math.h"
+
+namespace l2c {
+
+__device__ inline double kernel_value(int dir, double x, double y)
+{
+    if (dir == 0) return lambda_real(0.5 * (y - x)) * lambda_real(0.5 * (y + x));
+    const double g = 2.0 * (x + 0.5) * y / ((x + y) * (x + y + 1.0) * (x - y + 1.0));
+    return g * lambda_real(0.5 * (y - x)) / lambda_real(0.5 * (x + y));
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_build_ahat(double *ahat, FarLayout lay, int s, int dir,
+                                                          const double *XG, const double *Dm)
+{
+    constexpr int MM = M * M;
+    constexpr int NCH = 3 * M / 2;
+    __shared__ double S[3 * MM];
+    __shared__ double U[3 * MM];
+    __shared__ double Dl[MM];
+    __shared__ double Xl[M];
+    const int L = lay.L;
+    // block index -> (level g, block b): level g holds 2^(g+1) - 1 blocks
+    int64_t gb = blockIdx.x;
+    int g = 0;
+    while (gb >= (int64_t(1) << (g + 1)) - 1) {
+        gb -= (int64_t(1) << (g + 1)) - 1;
+        ++g;
+    }
+    const int64_t b = gb;
+    const double h = (double)((int64_t)s << (L - g - 1));
+    const int tid = threadIdx.x;
+    for (int e = tid; e < MM; e += kThreads) Dl[e] = Dm[e];
+    for (int e = tid; e < M; e += kThreads) Xl[e] = XG[e];
+    __syncthreads();
+
+    for (int e = tid; e < 3 * MM; e += kThreads) {
+        const int r = e / MM, mn = e - r * MM;
+        const int m = mn / M, n = mn - m * M;
+        const int p = (r == 2) ? 1 : 0, q = (r == 0) ? 0 : 1;   // r = p + q(q+1)/2
+        const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
+        const double j0 = 2.0 * h * (double)(2 * b + q + 2);
+        S[e] = kernel_value(dir, i0 + h * (Xl[m] + 1.0), j0 + h * (Xl[n] + 1.0));
+    }
+    __syncthreads();
+    // U[r][m][l] = sum_n S[r][m][n] D[l][n]
+    for (int e = tid; e < 3 * MM; e += kThreads) {
+        const int r = e / MM, ml = e - r * MM;
+        const int m = ml / M, l = ml - m * M;
+        double acc = 0.0;
+        for (int n = 0; n < M; ++n) acc = fma(S[r * MM + m * M + n], Dl[l * M + n], acc);
+        U[e] = acc;
+    }
+    __syncthreads();
+    // ahat[r][k][l] = 4/(c_k c_l M^2) sum_m D[k][m] U[r][m][l]
+    for (int e = tid; e < 3 * MM; e += kThreads) {
+        const int r = e / MM, kl = e - r * MM;
+        const int k = kl / M, l = kl - k * M;
+        double acc = 0.0;
+        for (int m = 0; m < M; ++m) acc = fma(Dl[k * M + m], U[r * MM + m * M + l], acc);
+        const double sc = 4.0 / ((k == 0 ? 2.0 : 1.0) * (l == 0 ? 2.0 : 1.0) * M * M);
+        const int64_t slot = b * M + k;
+        const int64_t grp = lay.group_off[g] + slot / 64;
+        const int lane = (int)(slot % 64);
+        const int el = r * M + l;
+        ahat[((grp * NCH + el / 2) * 64 + lane) * 2 + (el & 1)] = acc * sc;
+    }
+}
+
+// Interleaved far-field layout -> canonical [level][block][r][k][l].
+template <int M>
+__global__ void k_export_ahat(const double *ahat, FarLayout lay, double *dst, int64_t total)
+{
+    constexpr int NCH = 3 * M / 2;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int64_t blk = e / (3 * M * M);
+    const int rem = (int)(e - blk * 3 * M * M);
+    const int r = rem / (M * M), k = (rem / M) % M, l = rem % M;
+    int g = 0;
+    while (blk >= (int64_t(1) << (g + 1)) - 1) {
+        blk -= (int64_t(1) << (g + 1)) - 1;
+        ++g;
+    }
+    const int64_t slot = blk * M + k;
+    const int64_t grp = lay.group_off[g] + slot / 64;
+    const int lane = (int)(slot % 64);
+    const int el = r * M + l;
+    dst[e] = ahat[((grp * NCH + el / 2) * 64 + lane) * 2 + (el & 1)];
+}
+
+template <int M>
+static hipError_t build(const l2c_plan_s &p, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)p.nb), dim3(kThreads), 0, st, p.d_ahat, p.far, p.s,
+                       p.direction, p.d_XG, p.d_D);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t xport(const l2c_plan_s &p, double *dst, hipStream_t st)
+{
+    const int64_t total = p.nc * M * M;
+    hipLaunchKernelGGL(k_export_ahat<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, p.d_ahat,
+                       p.far, dst, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t st)
+{
+    switch (p.M) {
+#define L2C_CASE(MM) \
+    case MM: return build<MM>(p, st);
+        L2C_FOR_EACH_RANK(L2C_CASE)
+#undef L2C_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst, hipStream_t st)
+{
+    switch (p.M) {
+#define L2C_CASE(MM) \
+    case MM: return xport<MM>(p, dst, st);
+        L2C_FOR_EACH_RANK(L2C_CASE)
+#undef L2C_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace l2c

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry
+point, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "leg2cheb.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2411_00033_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2411_00033_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(leg2cheb_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    assert "leg2cheb_plan" in names and "leg2cheb_execute" in names and "leg2cheb_destroy" in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], stdout=subprocess.PIPE, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (leg2cheb_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(lib.EXPORTED) == set(declared_functions())
+    cdll = lib.load()
+    for name in declared_functions():
+        assert getattr(cdll, name) is not None
+
+
+def test_strerror_and_rank_query(lib):
+    assert lib.strerror(0) == "success"
+    assert lib.strerror(-1) == "invalid argument"
+    assert lib.strerror(-4) == "unsupported configuration"
+    assert lib.strerror(12345) == "unknown status"
+    assert lib.leg2cheb_rank_supported(18)
+    assert not lib.leg2cheb_rank_supported(7)
+    assert not lib.leg2cheb_rank_supported(0)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 0, 64, 18), -1),        # n < 1
+    ((100, 2, 64, 18), -1),      # bad direction
+    ((100, 0, 63, 18), -1),      # odd leaf
+    ((100, 0, 2, 18), -1),       # leaf too small
+    ((100, 0, 512, 18), -1),     # leaf too large
+    ((100, 0, 64, 0), -1),       # rank < 1
+    ((100, 0, 64, 33), -1),      # rank > 32
+    ((100, 0, 64, 7), -4),       # rank not instantiated
+])
+def test_plan_argument_errors(lib, args, code):
+    h = ctypes.c_void_p(1)
+    rc = lib.load().leg2cheb_plan(ctypes.byref(h), *args)
+    assert rc == code and h.value is None
+
+
+def test_plan_ex_precision_and_batch_errors(lib):
+    h = ctypes.c_void_p()
+    L = lib.load()
+    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 1, 1, None) == -4   # FP32 not in this build
+    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 9, 1, None) == -1
+    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 0, 0, None) == -1   # max_batch < 1
+    assert L.leg2cheb_plan(None, 100, 0, 64, 18) == -1
+
+
+def test_null_plan_calls(lib):
+    L = lib.load()
+    assert L.leg2cheb_execute(None, None, None, 1, None) == -1
+    assert L.leg2cheb_destroy(None) == 0
+    assert L.leg2cheb_plan_info(None, None) == -1
+    assert L.leg2cheb_plan_export(None, 0, None, 0, None) == -1
+    assert L.leg2cheb_set_timing_events(None, None, None) == -1
