@@ -1,0 +1,236 @@
+"""Throughput benchmark of the MI355X Legendre <-> Chebyshev transform.
+
+Workload: one leg2cheb transform of N = 10^6 FP64 coefficients (leaf 64, rank 18),
+inputs f_j = z_j / sqrt(j+1), z_j iid N(0,1) from a fixed seed, resident in HBM.
+A step is one execute of the whole path (all kernels of Alg. 4) over that vector.
+
+Timing protocol
+  * W warm-up steps, then exactly K timed steps between device synchronizations.
+  * Cold: before every timed step a 1 GiB read evicts the 256 MiB Infinity Cache,
+    so the plan tables and the vectors come from HBM; the step itself is timed with
+    HIP events on the execute stream (ms_per_step).  The wall time of the K cold steps
+    (flushes included) is reported too.
+  * Warm: K further steps back to back, no flush (warm_ms_per_step).
+  * The far-field kernel (the one that streams Ahat, the dominant HBM traffic) is
+    bracketed by HIP events recorded by the library on the same stream; its mean
+    duration gives roofline.achieved.
+The CPU baseline times the direct oracle on a bounded sample of rows of the same
+transform and extrapolates by term count to the full transform.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcoeff/s for leg→cheb N=10^6 (FP64 vs batched mixed-prec) at stated rel. error"
+HBM_PEAK_GBS = 8000.0
+N = 10 ** 6
+LEAF, RANK = 64, 18
+PMC_FILE = os.path.join(ROOT, "profiles", "k_far_pmc_leg2cheb_n1e6.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_00033_amd", "csrc", "l2c_exec.hip")
+
+
+class HipEvents:
+    """Raw hipEvent_t handles (the library records them on the execute stream)."""
+
+    def __init__(self, count):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = []
+        for _ in range(count):
+            h = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(h.value)
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.ev[a]), ctypes.c_void_p(self.ev[b])) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for h in self.ev:
+            self.hip.hipEventDestroy(ctypes.c_void_p(h))
+
+
+def pmc_traffic(kernel_bytes_alg):
+    """HBM traffic of k_far from the committed rocprofv3 PMC summary, if it still describes this source."""
+    try:
+        with open(PMC_FILE) as fh:
+            rec = json.load(fh)
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != sha:
+            return None
+        return float(rec["k_far_hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(f, z_gpu, direction):
+    """Direct oracle on every 10th row of the transform; throughput scaled to the full transform."""
+    import oracle
+    n = f.size
+    rows = np.arange(0, n, 10, dtype=np.int64)
+    t0 = time.perf_counter()
+    ref = oracle.transform(f, direction, rows)
+    dt = time.perf_counter() - t0
+    terms_sample = float(np.sum((n - rows + 1) // 2))
+    terms_full = float(np.sum((n - np.arange(n) + 1) // 2))
+    est_full = dt * terms_full / terms_sample
+    err = float(np.max(np.abs(z_gpu[rows] - ref)) / np.max(np.abs(ref)))
+    base = {"value": n / est_full / 1e9, "unit": "Gcoeff/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "rows i = 0 mod 10 of the N=10^6 %s (%d rows, %.3g of %.3g terms, %.1f s), "
+                      "extrapolated by term count" % (("leg2cheb", "cheb2leg")[direction], rows.size, terms_sample,
+                                                      terms_full, dt)}
+    return base, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the transform is a single-GPU kernel path "
+              "(multi-GPU sharding is described in DESIGN.md but not built); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_00033_amd as l2c
+    from paper_2411_00033_amd import inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    f = inputs.decaying(N, 0.5, inputs.SEED_BASE + 2)
+    x = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(x)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+    flush_sink = torch.empty((), dtype=torch.float64, device=dev)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.sum(flush, dim=0, out=flush_sink)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    plan = l2c.Plan(N, l2c.LEG2CHEB, LEAF, RANK)
+    info = plan.info
+    K, W = args.steps, args.warmup
+    ev = HipEvents(2 * K)
+    start = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    end = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+
+    for _ in range(W):
+        plan.execute(x, out)
+    torch.cuda.synchronize()
+
+    # cold timed region
+    t0 = time.perf_counter()
+    for i in range(K):
+        torch.sum(flush, dim=0, out=flush_sink)
+        l2c.leg2cheb_set_timing_events(plan.handle, ev.ev[2 * i], ev.ev[2 * i + 1])
+        start[i].record(stream)
+        plan.execute(x, out)
+        end[i].record(stream)
+    torch.cuda.synchronize()
+    wall_cold = (time.perf_counter() - t0) * 1e3 / K
+    l2c.leg2cheb_set_timing_events(plan.handle, 0, 0)
+    step_ms = [start[i].elapsed_time(end[i]) for i in range(K)]
+    far_ms = [ev.elapsed_ms(2 * i, 2 * i + 1) for i in range(K)]
+    ms = float(np.mean(step_ms))
+    far = float(np.mean(far_ms))
+
+    # warm timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        plan.execute(x, out)
+    torch.cuda.synchronize()
+    warm_ms = (time.perf_counter() - t0) * 1e3 / K
+
+    # the other direction at the same size (cold, same protocol)
+    plan_c = l2c.Plan(N, l2c.CHEB2LEG, LEAF, RANK)
+    out_c = torch.empty_like(x)
+    for _ in range(W):
+        plan_c.execute(x, out_c)
+    cs = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ce = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    torch.cuda.synchronize()
+    for i in range(K):
+        torch.sum(flush, dim=0, out=flush_sink)
+        cs[i].record(stream)
+        plan_c.execute(x, out_c)
+        ce[i].record(stream)
+    torch.cuda.synchronize()
+    c2l_ms = float(np.mean([cs[i].elapsed_time(ce[i]) for i in range(K)]))
+
+    z = out.cpu().numpy()
+    ahat_alg = 8.0 * RANK * RANK * info["n_submatrices"]          # bytes of Ahat, Eq. (aklmore) tables
+    path_alg = 16.0 * N + ahat_alg                                 # + FP64 input and output
+    achieved = ahat_alg / (far * 1e-3) / 1e9
+    traffic = pmc_traffic(ahat_alg)
+    rec = {
+        "metric": METRIC,
+        "value": N / (ms * 1e-3) / 1e9,
+        "unit": "Gcoeff/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "leg2cheb, one transform of N=1000000 FP64 coefficients, f_j = z_j/sqrt(j+1), "
+                               "z_j ~ N(0,1) seeded; leaf 64 (s=31, L=13), rank 18; cold HBM",
+                   "n": N, "direction": "leg2cheb", "leaf_size": LEAF, "rank": RANK, "batch": 1,
+                   "levels": info["levels"], "s": info["s"], "n_pad": info["n_pad"], "precision": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_far<18> (far-field products, streams Ahat)",
+                     "kernel_ms": far, "alg_bytes_per_launch": ahat_alg},
+        "path_roofline": {"alg_bytes_per_step": path_alg, "achieved_GBs": path_alg / (ms * 1e-3) / 1e9,
+                          "frac": path_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "warm_ms_per_step": warm_ms,
+        "cold_wall_ms_per_step_incl_flush": wall_cold,
+        "cheb2leg_ms_per_step": c2l_ms,
+        "plan": {"table_bytes": info["table_bytes"], "ahat_bytes_padded": info["ahat_bytes"]},
+    }
+    if not args.no_cpu_baseline:
+        base, err = cpu_baseline(f, z, 0)
+        rec["cpu_baseline"] = base
+        rec["einf_vs_oracle_sampled"] = err
+    else:
+        rec["cpu_baseline"] = None
+    ev.close()
+    plan.close()
+    plan_c.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

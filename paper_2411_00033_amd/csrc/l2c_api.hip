@@ -11,7 +11,6 @@
 
 namespace {
 
-using l2c::FarLayout;
 
 // Sizes of Eq. (numlevels): s_hat = leaf/2, L = ceil(log2(n/s_hat)) - 2,
 // s = ceil(n / 2^(L+2)), N = s 2^(L+2).  L <= 0: the plan applies Alg. 1 directly.
@@ -97,13 +96,13 @@ bool rank_supported(int M)
 void free_plan(l2c_plan_s *p)
 {
     if (!p) return;
-    (void)hipFree(p->d_ahat);
+    (void)hipFree(p->d_top);
+    (void)hipFree(p->d_bot);
     (void)hipFree(p->d_T);
     (void)hipFree(p->d_B);
     (void)hipFree(p->d_XG);
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_w);
-    (void)hipFree(p->d_c);
     delete p;
 }
 
@@ -114,15 +113,12 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
         if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
     }
     (void)hipFree(p->d_w);
-    (void)hipFree(p->d_c);
-    p->d_w = p->d_c = nullptr;
+    p->d_w = nullptr;
     p->ws_batch = 0;
-    const size_t bytes = (size_t)batch * p->NT * 2 * p->M * sizeof(double);
-    if (hipMalloc(&p->d_w, bytes) != hipSuccess || hipMalloc(&p->d_c, bytes) != hipSuccess) {
+    const size_t bytes = (size_t)batch * p->geo.NT * 2 * p->M * sizeof(double);
+    if (hipMalloc(&p->d_w, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipFree(p->d_w);
-        (void)hipFree(p->d_c);
-        p->d_w = p->d_c = nullptr;
+        p->d_w = nullptr;
         return L2C_ENOMEM;
     }
     p->ws_batch = batch;
@@ -184,17 +180,10 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
         const int L = p->L, M = p->M, s = p->s;
         p->nb = (p->n_pad / (2 * s)) - L - 2;   // Eq. (total_blocks_and_mats)
         p->nc = 3 * p->nb;
-        p->NT = (int64_t(1) << (L + 2)) - 4;
-        p->far.L = L;
-        p->far.M = M;
-        int64_t goff = 0;
-        for (int g = 0; g < L; ++g) {
-            p->far.group_off[g] = goff;
-            const int64_t blocks = (int64_t(1) << (g + 1)) - 1;
-            goff += (blocks * M + 63) / 64;
-        }
-        p->far.group_off[L] = goff;
-        p->ahat_bytes = goff * 64 * 3 * M * (int64_t)sizeof(double);
+        p->geo = l2c::make_geometry(L, M, s);
+        const int64_t top_blocks = l2c::level_block_offset(p->geo.groot + 1);
+        p->top_bytes = top_blocks * 3 * M * M * (int64_t)sizeof(double);
+        p->bot_bytes = (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
 
         std::vector<double> T, B, XG(M), Dm((size_t)M * M);
         vandermonde(s, M, T);
@@ -203,7 +192,8 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
         for (int k = 0; k < M; ++k)
             for (int m = 0; m < M; ++m) Dm[(size_t)k * M + m] = std::cos(k * (m + 0.5) * M_PI / M);
 
-        bool ok = hipMalloc(&p->d_ahat, p->ahat_bytes) == hipSuccess &&
+        bool ok = hipMalloc(&p->d_top, p->top_bytes) == hipSuccess &&
+                  (p->bot_bytes == 0 || hipMalloc(&p->d_bot, p->bot_bytes) == hipSuccess) &&
                   hipMalloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
                   hipMalloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
                   hipMalloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
@@ -213,12 +203,12 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             free_plan(p);
             return L2C_ENOMEM;
         }
-        p->table_bytes = p->ahat_bytes + (int64_t)(T.size() + B.size() + XG.size() + Dm.size()) * 8;
+        p->table_bytes = p->top_bytes + p->bot_bytes + (int64_t)(T.size() + B.size() + XG.size() + Dm.size()) * 8;
         ok = hipMemcpyAsync(p->d_T, T.data(), T.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_XG, XG.data(), XG.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_D, Dm.data(), Dm.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-             hipMemsetAsync(p->d_ahat, 0, p->ahat_bytes, st) == hipSuccess &&
+             (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
              l2c::launch_build_ahat(*p, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
@@ -281,8 +271,8 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
     info->n_blocks = plan->nb;
     info->n_submatrices = plan->nc;
     info->table_bytes = plan->table_bytes;
-    info->workspace_bytes = 2 * plan->ws_batch * plan->NT * 2 * plan->M * (int64_t)sizeof(double);
-    info->ahat_bytes = plan->ahat_bytes;
+    info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double);
+    info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
     return L2C_OK;
 }
 

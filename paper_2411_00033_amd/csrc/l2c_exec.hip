@@ -1,27 +1,62 @@
 // l2c_exec.hip -- execution kernels of the modal multipole Legendre <-> Chebyshev
 // transform (arXiv 2411.00033, Alg. 4) for gfx950, FP64.
 //
-// One execute is four launches on the caller's stream:
-//   k_up    steps (0)+(1)+(2): stage the input (zero padding, c .* f for cheb2leg),
-//           contract each finest node with T(sigma) (Eq. (wMM)) and run the upward
-//           pass (Eq. (wtk), with the even/odd-diagonal split of App. A2) inside a
-//           subtree of 2^ku finest nodes; writes w for every level of the subtree.
-//   k_top   step (2) for the levels above the subtree roots (one workgroup per item).
-//   k_far   step (3): every far-field product c(g,b,p) = sum_q Ahat(g,b,r) w(g,b,q)
-//           of every level, streaming the Ahat table once per launch (the dominant
-//           HBM traffic); Ahat rows stay in registers and are applied to up to
-//           kFarItems batch items.
-//   k_down  steps (4)-(7): per subtree of 2^kd finest nodes, spread c down from level
-//           0 (each workgroup walks its own chain of ancestors), evaluate
-//           z = T(sigma) c at the finest level (Eq. (step5)), add the near-diagonal
-//           direct part (step (6)), scale (step (7)) and write the output.
+// One execute is three launches (plus one more k_top pass per 6 extra levels) on the
+// caller's stream:
+//   k_up    steps (0)-(2): stage the input (zero padding, c .* f for cheb2leg), contract
+//           every finest node with T(sigma) (Eq. (wMM)) and run the upward pass
+//           (Eq. (wtk), with the even/odd-diagonal split of App. A2) inside a subtree
+//           of 2^ku finest nodes; writes w for every level of the subtree.
+//   k_top   step (2) above the k_up subtree roots, 6 levels per pass, in LDS.
+//   k_main  steps (3)-(7) for a subtree of 2^kd finest nodes: the far-field products
+//           of its own blocks (streamed once from the subtree-major table: the
+//           dominant HBM traffic) and of its ancestors (top table, shared in L2), the
+//           downward spreading of step (4) from level 0, the leaf evaluation of
+//           Eq. (step5), the near-diagonal direct part of step (6), the scaling of
+//           step (7), and the output.  Nothing but w crosses kernel boundaries.
 // Plans with L = 0 use k_direct (Alg. 1 for every row).
 #include "l2c_internal.h"
 #include "l2c_math.h"
 
+// Phase timestamps for performance analysis: compiled in only with L2C_PHASE_TIMING
+// (the product build defines nothing and the macro expands to nothing).
+#ifdef L2C_PHASE_TIMING
+extern __device__ unsigned long long l2c_phase_ts[];
+#define L2C_TS(kern, ph)                                                                          \
+    do {                                                                                          \
+        if (threadIdx.x == 0 && blockIdx.y == 0 && blockIdx.x < 4096)                             \
+            l2c_phase_ts[((kern) * 4096 + blockIdx.x) * 16 + (ph)] = wall_clock64();              \
+    } while (0)
+#else
+#define L2C_TS(kern, ph) \
+    do {                 \
+    } while (0)
+#endif
+
 namespace l2c {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Copy count doubles from global memory to LDS.  The loads of each round are issued
+// together (U per thread) before any is waited for, so a round costs one memory
+// latency instead of U.
+template <int U, int NT = kThreads>
+__device__ __forceinline__ void stage_lds(double *dst, const double *src, int count)
+{
+    for (int base = 0; base < count; base += U * NT) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            v[u] = e < count ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            if (e < count) dst[e] = v[u];
+        }
+    }
+}
 
 // ------------------------------------------------------------------------------------
 // Near-field tables.  Both directions are written as
@@ -47,45 +82,273 @@ __device__ __forceinline__ double near_Q(int dir, int64_t S)
     return inv_lambda_int(S) / (S2 * (S2 + 1.0));
 }
 
+// Node arrays in LDS keep a node's [sigma][k] = 2M doubles followed by one pad double:
+// the odd node stride 2M + 1 puts lanes that read consecutive nodes on distinct banks
+// (the workspace in global memory keeps the dense stride 2M).
+template <int M>
+__host__ __device__ constexpr int lds_ns() { return 2 * M + 1; }
+
+// Upward transfer of one level (Eq. (wtk) with App. A2): for every parent node and
+// parity, out_n = sum_{k<=n} b_nk z_{(n-k) mod 2, k} with z0 = w(2T) + w(2T+1) and
+// z1 = w(2T) - w(2T+1) (B(1) is B(0) with its odd diagonals negated).
+// Lane <-> (parent, parity); wave residue H = wave mod 4 takes the outputs n = H mod 4,
+// so its rows of B(0) are the same for every lane: they are read from LDS into
+// registers once per level (one wait), then every product uses registers only.
+template <int M, int H>
+__device__ __forceinline__ void up_level_h(const double *child, double *par, int pn, const double *Bl, int q0,
+                                           int qstep)
+{
+    constexpr int NJ = (M - H + 3) / 4;               // outputs n = H + 4j < M
+    double bv[NJ][M];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int k = 0; k <= H + 4 * j; ++k) bv[j][k] = Bl[(H + 4 * j) * M + k];
+    }
+    for (int q = q0; q < 2 * pn; q += qstep) {
+        const int pnode = q >> 1, sig = q & 1;
+        const double *wa = child + (2 * pnode) * lds_ns<M>() + sig * M;
+        const double *wb = wa + lds_ns<M>();
+        double z0[M], z1[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double x = wa[k], y = wb[k];
+            z0[k] = x + y;
+            z1[k] = x - y;
+        }
+        double *po = par + pnode * lds_ns<M>() + sig * M;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int n = H + 4 * j;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k <= n; ++k) acc = fma(bv[j][k], ((n - k) & 1) ? z1[k] : z0[k], acc);
+            po[n] = acc;
+        }
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void up_level(const double *child, double *par, int pn, const double *Bl)
+{
+    const int wv = wave_id(), nw = blockDim.x >> 6;
+    const int q0 = (threadIdx.x & 63) + 64 * (wv >> 2), qstep = 64 * (nw >> 2);
+    switch (wv & 3) {
+    case 0: up_level_h<M, 0>(child, par, pn, Bl, q0, qstep); break;
+    case 1: up_level_h<M, 1>(child, par, pn, Bl, q0, qstep); break;
+    case 2: up_level_h<M, 2>(child, par, pn, Bl, q0, qstep); break;
+    default: up_level_h<M, 3>(child, par, pn, Bl, q0, qstep); break;
+    }
+}
+
+// Downward transfer of one level (step (4)): c(child) += B(p)^T c(parent), p = child's
+// position in its parent.  With B(1) = B(0) with odd diagonals negated,
+// (B(p)^T c)_n = s_p(n) sum_{k>=n} b_kn s_p(k) c_k, s_p(k) = (-1)^k if p = 1, else 1.
+// cn children; parent of child v is v >> 1; p = v & 1 unless pfix >= 0 (then p = pfix).
+template <int M, int H>
+__device__ __forceinline__ void down_level_h(const double *par, double *cur, int cn, int pfix, const double *Bl,
+                                             int q0, int qstep)
+{
+    constexpr int NJ = (M - H + 3) / 4;
+    double bv[NJ][M];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int k = H + 4 * j; k < M; ++k) bv[j][k] = Bl[k * M + H + 4 * j];
+    }
+    for (int q = q0; q < 2 * cn; q += qstep) {
+        const int v = q >> 1, sig = q & 1;
+        const int p = pfix >= 0 ? pfix : (v & 1);
+        const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
+        double cs[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cs[k] = (p && (k & 1)) ? -cp[k] : cp[k];
+        double *co = cur + v * lds_ns<M>() + sig * M;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int n = H + 4 * j;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = n; k < M; ++k) acc = fma(bv[j][k], cs[k], acc);
+            co[n] += (p && (n & 1)) ? -acc : acc;
+        }
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void down_level(const double *par, double *cur, int cn, int pfix, const double *Bl)
+{
+    const int wv = wave_id(), nw = blockDim.x >> 6;
+    const int q0 = (threadIdx.x & 63) + 64 * (wv >> 2), qstep = 64 * (nw >> 2);
+    switch (wv & 3) {
+    case 0: down_level_h<M, 0>(par, cur, cn, pfix, Bl, q0, qstep); break;
+    case 1: down_level_h<M, 1>(par, cur, cn, pfix, Bl, q0, qstep); break;
+    case 2: down_level_h<M, 2>(par, cur, cn, pfix, Bl, q0, qstep); break;
+    default: down_level_h<M, 3>(par, cur, cn, pfix, Bl, q0, qstep); break;
+    }
+}
+
+// The same two transfers for levels with few nodes: thread <-> (node pair q, output n)
+// with n fixed per thread, so the thread's row (up) or column (down) of B(0) sits in
+// registers for the whole kernel.  Only threads t < M * (blockDim / M) take part:
+// n = t mod M, first pair q0 = t / M, step qstep = blockDim / M.
+template <int M>
+__device__ __forceinline__ void up_level_qn(const double *child, double *par, int pn, const double (&brow)[M],
+                                            int n, int q0, int qstep)
+{
+    for (int q = q0; q < 2 * pn; q += qstep) {
+        const int pnode = q >> 1, sig = q & 1;
+        const double *wa = child + (2 * pnode) * lds_ns<M>() + sig * M;
+        const double *wb = wa + lds_ns<M>();
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double x = wa[k], y = wb[k];
+            acc = fma(brow[k], ((n - k) & 1) ? x - y : x + y, acc);   // brow[k] = b_nk, 0 for k > n
+        }
+        par[pnode * lds_ns<M>() + sig * M + n] = acc;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void down_level_qn(const double *par, double *cur, int cn, int pfix,
+                                              const double (&bcol)[M], int n, int q0, int qstep)
+{
+    for (int q = q0; q < 2 * cn; q += qstep) {
+        const int v = q >> 1, sig = q & 1;
+        const int p = pfix >= 0 ? pfix : (v & 1);
+        const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) acc = fma(bcol[k], (p && (k & 1)) ? -cp[k] : cp[k], acc);   // b_kn, 0 for k < n
+        cur[v * lds_ns<M>() + sig * M + n] += (p && (n & 1)) ? -acc : acc;
+    }
+}
+
+// Copy nodes between the dense workspace layout (stride 2M) and the padded LDS layout
+// (stride 2M + 1), U elements per thread per round (one wait per round).
+template <int M, int U, int NT>
+__device__ __forceinline__ void nodes_lds_to_global(double *dst, const double *src, int nodes)
+{
+    const int count = nodes * 2 * M;
+    for (int base = 0; base < count; base += U * NT) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            const int q = e / (2 * M);
+            v[u] = e < count ? src[q * lds_ns<M>() + (e - q * 2 * M)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            if (e < count) dst[e] = v[u];
+        }
+    }
+}
+
+template <int M, int U, int NT>
+__device__ __forceinline__ void nodes_global_to_lds(double *dst, const double *src, int nodes)
+{
+    const int count = nodes * 2 * M;
+    for (int base = 0; base < count; base += U * NT) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            v[u] = e < count ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT + (int)threadIdx.x;
+            const int q = e / (2 * M);
+            if (e < count) dst[q * lds_ns<M>() + (e - q * 2 * M)] = v[u];
+        }
+    }
+}
+
+// Upward step over a whole subtree held in LDS: level buffer d (0 = the 2^kt input nodes)
+// starts at node 2 nodes - 2 (nodes >> d); every level goes to the workspace at the end.
+template <int M>
+__device__ __forceinline__ void subtree_up(double *lv, int nodes, int kt, const double *Bl)
+{
+    const int qstep = kThreads / M, n = (int)threadIdx.x % M, q0 = (int)threadIdx.x / M;
+    const bool qn_ok = (int)threadIdx.x < M * qstep;
+    double brow[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) brow[k] = Bl[(qn_ok ? n : 0) * M + k];
+    for (int d = 1; d <= kt; ++d) {
+        const int pn = nodes >> d;
+        const double *child = lv + (2 * nodes - 2 * (nodes >> (d - 1))) * lds_ns<M>();
+        double *par = lv + (2 * nodes - 2 * pn) * lds_ns<M>();
+        if (2 * pn <= qstep) {
+            if (qn_ok) up_level_qn<M>(child, par, pn, brow, n, q0, qstep);
+        } else {
+            up_level<M>(child, par, pn, Bl);
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // k_up: one workgroup per (subtree of 2^ku finest nodes, item).
-// LDS: f chunk [nodes][D] (D >= 2s, row stride padded against bank conflicts),
-//      w for every subtree level, B(0).
+// LDS: f chunk [nodes][D] (odd D = 2s + 1: lanes reading consecutive nodes hit distinct
+//      banks), T, B(0), every w level of the subtree.
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_up(ExecArgs a)
 {
     extern __shared__ double lds[];
-    const int s = a.s, L = a.L, ku = a.ku;
+    L2C_TS(0, 0);
+    const Geometry &G = a.geo;
+    const int s = G.s, L = G.L, ku = G.ku;
     const int nodes = 1 << ku;
     const int64_t item = blockIdx.y;
     const int64_t t0 = (int64_t)blockIdx.x << ku;    // first finest node of the subtree
-    const int D = (s & 1) ? 2 * s : 2 * s + 2;        // D = 2 (mod 4) doubles
+    const int D = 2 * s + 1;                          // odd row stride: distinct banks
     double *fl = lds;                                 // nodes * D
-    double *wl = fl + nodes * D;                      // sum_d 2^(ku-d) nodes * 2M
-    double *Bl = wl + (2 * nodes - 1) * 2 * M;        // M * M
+    double *Tl = fl + nodes * D;                      // 2 * s * M
+    double *Bl = Tl + 2 * s * M;                      // M * M
+    double *lv = Bl + M * M;                          // (2 nodes - 1) nodes: every subtree level
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = wave_id();
 
-    for (int e = tid; e < M * M; e += kThreads) Bl[e] = a.B0[e];
     // stage the input: zero past n; cheb2leg uses u = c .* f (u_0 = 2 f_0), Sec. 4.1
     const double *in = a.in + item * a.n;
     const int64_t base = t0 * 2 * s;
-    for (int e = tid; e < nodes * 2 * s; e += kThreads) {
-        const int nd = e / (2 * s), m = e - nd * 2 * s;
-        const int64_t gi = base + e;
-        double v = gi < a.n ? in[gi] : 0.0;
-        if (a.dir == 1 && gi == 0) v *= 2.0;
-        fl[nd * D + m] = v;
+    {
+        constexpr int U = 8;
+        const int cnt = nodes * 2 * s;
+        for (int b0 = 0; b0 < cnt; b0 += U * kThreads) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = b0 + u * kThreads + tid;
+                const int64_t gi = base + e;
+                v[u] = (e < cnt && gi < a.n) ? in[gi] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = b0 + u * kThreads + tid;
+                if (e < cnt) {
+                    const int nd = e / (2 * s);
+                    fl[nd * D + (e - nd * 2 * s)] = (a.dir == 1 && base + e == 0) ? 2.0 * v[u] : v[u];
+                }
+            }
+        }
     }
+    stage_lds<5>(Tl, a.T, 2 * s * M);
+    stage_lds<2>(Bl, a.B0, M * M);
     __syncthreads();
+    L2C_TS(0, 1);
 
     // step (1): w_k(t, sigma) = sum_m T_k(X_m^sigma) f[2s t + 2m + sigma]  (Eq. (wMM)).
-    // Wave -> (sigma, half of k); lane -> node; T is wave-uniform (scalar loads).
+    // Wave -> (sigma, half of k); lane -> node; the T values of a step are the same for
+    // every lane of the wave (LDS broadcast).
     {
         constexpr int KH = M / 2;
-        const int wv = wave_id();
         const int sig = wv & 1, kb = (wv >> 1) * KH;
-        const double *Ts = a.T + (size_t)sig * s * M + kb;
-        for (int nd = tid & 63; nd < nodes; nd += 64) {
+        const double *Ts = Tl + (size_t)sig * s * M + kb;
+        for (int nd = lane; nd < nodes; nd += 64) {
             double acc[KH];
 #pragma unroll
             for (int k = 0; k < KH; ++k) acc[k] = 0.0;
@@ -95,324 +358,375 @@ __global__ __launch_bounds__(kThreads) void k_up(ExecArgs a)
 #pragma unroll
                 for (int k = 0; k < KH; ++k) acc[k] = fma(Ts[m * M + k], fv, acc[k]);
             }
-            double *wo = wl + nd * 2 * M + sig * M + kb;
+            double *wo = lv + nd * lds_ns<M>() + sig * M + kb;
 #pragma unroll
             for (int k = 0; k < KH; ++k) wo[k] = acc[k];
         }
     }
     __syncthreads();
+    L2C_TS(0, 2);
 
-    // step (2) inside the subtree: w(parent) = B(0) w(2T) + B(1) w(2T+1) (Eq. (wtk)).
-    // B(1) = B(0) with odd diagonals negated (App. A2): with z0 = w(2T)+w(2T+1),
-    // z1 = w(2T)-w(2T+1), out_n = sum_{k<=n} b_nk z_{(n-k) mod 2, k}.
-    {
-        double *child = wl;
-        int cn = nodes;
-        for (int d = 1; d <= ku; ++d) {
-            double *par = child + cn * 2 * M;
-            const int pn = cn >> 1;
-            for (int e = tid; e < pn * 2 * M; e += kThreads) {
-                const int pnode = e / (2 * M), r = e - pnode * 2 * M;
-                const int sig = r / M, nn = r - sig * M;
-                const double *wa = child + (2 * pnode) * 2 * M + sig * M;
-                const double *wb = wa + 2 * M;
-                double acc = 0.0;
-                for (int k = 0; k <= nn; ++k) {
-                    const double zk = ((nn - k) & 1) ? wa[k] - wb[k] : wa[k] + wb[k];
-                    acc = fma(Bl[nn * M + k], zk, acc);
-                }
-                par[e] = acc;
-            }
-            __syncthreads();
-            child = par;
-            cn = pn;
-        }
-    }
-
-    // write w of every subtree level to the workspace
-    {
-        double *wg = a.w + item * a.NT * 2 * M;
-        const double *src = wl;
-        int cn = nodes;
-        for (int d = 0; d <= ku; ++d) {
-            const int g = L - 1 - d;
-            double *dst = wg + (node_offset(g) + (t0 >> d)) * 2 * M;
-            for (int e = tid; e < cn * 2 * M; e += kThreads) dst[e] = src[e];
-            src += cn * 2 * M;
-            cn >>= 1;
-        }
-    }
+    // step (2) inside the subtree, then every level to the workspace
+    subtree_up<M>(lv, nodes, ku, Bl);
+    double *wg = a.w + item * G.NT * 2 * M;
+    for (int d = 0; d <= ku; ++d)
+        nodes_lds_to_global<M, 4, kThreads>(wg + (node_offset(L - 1 - d) + (t0 >> d)) * 2 * M,
+                                            lv + (2 * nodes - 2 * (nodes >> d)) * lds_ns<M>(), nodes >> d);
+    L2C_TS(0, 3);
 }
 
 // ------------------------------------------------------------------------------------
-// k_top: step (2) for levels g0-1 .. 0 (g0 = level of the k_up subtree roots).
+// k_top: step (2) for kt levels above level gin; one workgroup per 2^kt nodes of gin.
 template <int M>
-__global__ __launch_bounds__(1024) void k_top(ExecArgs a, int g0)
+__global__ __launch_bounds__(kThreads) void k_top(ExecArgs a, int gin, int kt)
 {
-    __shared__ double Bl[M * M];
-    const int64_t item = blockIdx.x;
-    for (int e = threadIdx.x; e < M * M; e += blockDim.x) Bl[e] = a.B0[e];
+    extern __shared__ double lds[];
+    L2C_TS(1, 0);
+    const int nodes = 1 << kt;
+    const int64_t item = blockIdx.y;
+    const int64_t t0 = (int64_t)blockIdx.x << kt;
+    double *Bl = lds;                          // M * M
+    double *lv = Bl + M * M;                   // (2 nodes - 1) nodes
+    double *wg = a.w + item * a.geo.NT * 2 * M;
+    nodes_global_to_lds<M, 10, kThreads>(lv, wg + (node_offset(gin) + t0) * 2 * M, nodes);
+    stage_lds<2>(Bl, a.B0, M * M);
     __syncthreads();
-    double *wg = a.w + item * a.NT * 2 * M;
-    for (int g = g0 - 1; g >= 0; --g) {
-        const int pn = 1 << (g + 2);
-        const double *child = wg + node_offset(g + 1) * 2 * M;
-        double *par = wg + node_offset(g) * 2 * M;
-        for (int e = threadIdx.x; e < pn * 2 * M; e += blockDim.x) {
-            const int pnode = e / (2 * M), r = e - pnode * 2 * M;
-            const int sig = r / M, nn = r - sig * M;
-            const double *wa = child + (2 * pnode) * 2 * M + sig * M;
-            const double *wb = wa + 2 * M;
-            double acc = 0.0;
-            for (int k = 0; k <= nn; ++k) {
-                const double zk = ((nn - k) & 1) ? wa[k] - wb[k] : wa[k] + wb[k];
-                acc = fma(Bl[nn * M + k], zk, acc);
-            }
-            par[e] = acc;
-        }
-        __syncthreads();
-    }
+    L2C_TS(1, 1);
+    subtree_up<M>(lv, nodes, kt, Bl);
+    for (int d = 1; d <= kt; ++d)
+        nodes_lds_to_global<M, 4, kThreads>(wg + (node_offset(gin - d) + (t0 >> d)) * 2 * M,
+                                            lv + (2 * nodes - 2 * (nodes >> d)) * lds_ns<M>(), nodes >> d);
+    L2C_TS(1, 2);
 }
 
 // ------------------------------------------------------------------------------------
-// k_far: step (3) for all levels.  Wave <-> 64 slots of the far-field table; lane
-// (b, k) computes, for both parities,
-//     c(2b)[k]   = Ahat(b,0)[k,:] w(2b+2) + Ahat(b,1)[k,:] w(2b+3)
-//     c(2b+1)[k] = Ahat(b,2)[k,:] w(2b+3)
-// (row node 2b+p, column node 2b+q+2, r = p + q(q+1)/2).  The 3M doubles of a slot are
-// loaded once (coalesced 16-byte chunks) and applied to kFarItems items.
+// k_main: one workgroup per (subtree root R at level groot, item); one workgroup per CU.
+// Order of work: the staging loads (own column-node w, input) are issued, then the
+// wave's first Ahat group; the near-field tables are computed while both arrive.  The
+// near field (input only) runs while the Ahat stream arrives; then the ancestors' far
+// field (top table in L2), the own far field (Ahat stream, next group refilled while the
+// current one is used), the downward pass, and the leaf evaluation, which writes the
+// output rows directly.
+//
+// Near-field work item = (node nd, parity sig, R rows starting at m0); item wi maps to
+// nd = wi mod nodes, so with 64 nodes a wave holds one (sig, m0) and 64 nodes.  To keep
+// these 64 lanes on distinct LDS banks the per-parity input and the Q table are stored
+// with one pad double after every s (g, when s is even) or 2s (Q) entries.
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_far(ExecArgs a, FarLayout lay)
-{
-    constexpr int NCH = 3 * M / 2;
-    const int64_t grp = (int64_t)blockIdx.x * (kThreads / 64) + wave_id();
-    if (grp >= lay.group_off[lay.L]) return;
-    int g = 0;
-    while (grp >= lay.group_off[g + 1]) ++g;
-    const int lane = threadIdx.x & 63;
-    const int64_t slot = (grp - lay.group_off[g]) * 64 + lane;
-    const int64_t b = slot / M;
-    const int k = (int)(slot - b * M);
-    const int64_t nblk = (int64_t(1) << (g + 1)) - 1;
-
-    double2 ar[NCH];
-    const double2 *src = reinterpret_cast<const double2 *>(a.ahat) + grp * NCH * 64 + lane;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) ar[ch] = src[ch * 64];
-    if (b >= nblk) return;
-
-    const double *A0 = reinterpret_cast<const double *>(ar);
-    const int64_t rown = node_offset(g) + 2 * b;   // row node 2b; column nodes 2b+2, 2b+3
-    const int64_t it0 = (int64_t)blockIdx.y * kFarItems;
-    const int64_t it1 = min(it0 + (int64_t)kFarItems, a.batch);
-    for (int64_t it = it0; it < it1; ++it) {
-        const double *wt = a.w + (it * a.NT + rown + 2) * 2 * M;   // w(2b+2), then w(2b+3)
-        double c00 = 0, c01 = 0, c10 = 0, c11 = 0;                 // c(row p)[sigma]
-#pragma unroll
-        for (int l = 0; l < M; ++l) {
-            const double w20 = wt[l], w21 = wt[M + l];
-            const double w30 = wt[2 * M + l], w31 = wt[3 * M + l];
-            c00 = fma(A0[l], w20, c00);
-            c01 = fma(A0[l], w21, c01);
-            c00 = fma(A0[M + l], w30, c00);
-            c01 = fma(A0[M + l], w31, c01);
-            c10 = fma(A0[2 * M + l], w30, c10);
-            c11 = fma(A0[2 * M + l], w31, c11);
-        }
-        double *co = a.c + (it * a.NT + rown) * 2 * M + k;
-        co[0] = c00;
-        co[M] = c01;
-        co[2 * M] = c10;
-        co[3 * M] = c11;
-    }
-}
-
-// ------------------------------------------------------------------------------------
-// k_down: one workgroup per (subtree of 2^kd finest nodes, item).
-template <int M>
-__global__ __launch_bounds__(kThreads) void k_down(ExecArgs a)
+__global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
 {
     constexpr int R = kNearRows;
+    constexpr int NCH = 3 * M / 2;
+    constexpr int M2 = 2 * M;                          // node stride in the workspace
+    constexpr int NS = lds_ns<M>();                    // node stride in LDS
     extern __shared__ double lds[];
-    const int s = a.s, L = a.L, kd = a.kd, dir = a.dir;
-    const int nodes = 1 << kd;
+    L2C_TS(2, 0);
+    const Geometry &G = a.geo;
+    const int s = G.s, L = G.L, kd = G.kd, groot = G.groot, dir = a.dir;
+    const int nodes = 1 << kd;                        // finest nodes of the subtree
+    const int own = 2 * nodes - 2;                    // own row / column nodes, depths 1..kd
     const int64_t item = blockIdx.y;
-    const int64_t u0 = (int64_t)blockIdx.x << kd;    // first finest row node
-    const int64_t P = int64_t(1) << (L + 1);          // finest nodes
-    const int groot = L - 1 - kd;                     // level of the subtree root
-    const int GS = 2 * s + R;                         // per (node, parity) g segment
-    const int nQ = 2 * s * nodes + s + 2 * R;         // Q_S for S = 2s u0 + [0, nQ)
+    const int64_t Rn = blockIdx.x;                    // subtree root, level groot
+    const int64_t u0 = Rn << kd;                      // first finest row node
+    const int64_t P = int64_t(1) << (L + 1);
+    const int gpad = near_gpad(s);                    // g: node stride s + gpad
+    const int GS = s + gpad;
+    const int GXL = s * (nodes + 1) + R;              // logical per-parity g length
+    const int GX = (int)near_gx(s, kd);               // padded per-parity g length
+    const int qpad = near_qpad(s);                    // Q: node stride 2s + qpad
+    const int QS = 2 * s + qpad;
+    const int nQ = (int)near_nq(s, kd);
     const int nP = 2 * s + 2 * R;                     // P_d for d = [-(R-1), nP - R + 1)
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = wave_id();
 
     double *Bl = lds;                                 // M*M
-    double *Tl = Bl + M * M;                          // 2*s*M
-    double *cl = Tl + 2 * s * M;                      // (2*nodes) * 2M: chain + subtree levels
-    double *gl = cl + 2 * nodes * 2 * M;              // nodes * 2 * GS
-    double *Ql = gl + nodes * 2 * GS;                 // nQ
+    double *canc = Bl + M * M;                        // (groot+1) nodes: ancestors, level 0..groot
+    double *cown = canc + (groot + 1) * NS;           // own nodes: depth d at node offset 2^d - 2
+    double *wl = cown + own * NS;                     // own column nodes
+    double *gp = wl + own * NS;                       // 2 * GX, later T (2 s M)
+    double *Tl = gp;
+    double *Ql = gp + 2 * GX;                         // nQ
     double *Pl = Ql + nQ;                             // nP
-    double *zl = Pl + nP;                             // nodes * 2s
 
-    for (int e = tid; e < M * M; e += kThreads) Bl[e] = a.B0[e];
-    for (int e = tid; e < 2 * s * M; e += kThreads) Tl[e] = a.T[e];
-    // g_j for j in node u and u+1, split by parity: gl[(u*2+sig)*GS + m'] = g[2s u + 2m' + sig]
     const double *in = a.in + item * a.n;
-    const int64_t jb = u0 * 2 * s;
-    for (int e = tid; e < nodes * 2 * GS; e += kThreads) {
-        const int seg = e / GS, mp = e - seg * GS;
-        const int nd = seg >> 1, sig = seg & 1;
-        double v = 0.0;
-        if (mp < 2 * s) {
-            const int64_t j = jb + (int64_t)nd * 2 * s + 2 * mp + sig;
-            if (j < a.n) {
-                v = in[j];
-                if (dir == 1) v *= (double)j;  // g_j = j u_j (u_j = f_j for j >= 1; g_0 = 0)
+    const double *wgl = a.w + item * G.NT * M2;
+    const int64_t jb = u0 * 2 * s;                    // first row of the subtree
+
+    // ---- staging loads: own column-node w and the near-field input (registers)
+    constexpr int UW = kMainStageW, UG = kMainStageG;
+    double vw[UW], vg[UG];
+    const int cntw = own * M2, cntg = 2 * GXL;
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+        // own column-node w: depth d holds column nodes (R << d) + 2 + [0, 2^d) of level
+        // groot + d; flat node q = (2^d - 2) + t.  Nodes past the end of a level are zero.
+        const int e = u * kMainThreads + tid;
+        vw[u] = 0.0;
+        if (e < cntw) {
+            const int q = e / M2, r = e - q * M2;
+            const int d = 31 - __clz(q + 2);
+            const int64_t t = (Rn << d) + 2 + (q - ((1 << d) - 2));
+            const int g = groot + d;
+            if (t < (int64_t(1) << (g + 2))) vw[u] = wgl[(node_offset(g) + t) * M2 + r];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+        const int e = u * kMainThreads + tid;              // e = sig * GXL + x
+        const int sig = e >= GXL, x = e - sig * GXL;
+        const int64_t j = jb + 2 * (int64_t)x + sig;
+        vg[u] = (e < cntg && x < s * (nodes + 1) && j < a.n) ? in[j] : 0.0;
+    }
+    // ---- the wave's first far-field group goes in flight behind them
+    const int nslots = (nodes - 1) * M;
+    const double2 *sub = reinterpret_cast<const double2 *>(a.ahat_bot) + Rn * G.sub_groups * NCH * 64 + lane;
+    double2 ar[NCH];
+    if (wv < G.sub_groups) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) ar[ch] = sub[(wv * NCH + ch) * 64];
+    }
+    // ---- near-field tables (arithmetic only) while the loads are in flight
+    // Q in runs of 8 consecutive S: the first value from Eq. (tau), then the exact ratio
+    // Q_{S+1}/Q_S, (2S+1)/(2S+2) for leg2cheb (Eq. (Lambdaint)) and 2S/(2S+3) for cheb2leg.
+    {
+        const int QL = 2 * s * nodes + 3 * s + 2 * R;   // logical entries read
+        for (int run = tid; run * 8 < QL; run += kMainThreads) {
+            const int x0 = run * 8;
+            int node = x0 / (2 * s), c = x0 - node * 2 * s;
+            int64_t S = jb + x0;
+            double q = near_Q(dir, S);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (x0 + i < QL) Ql[node * QS + c] = q;
+                const double Sd = (double)S;
+                q = dir == 0 ? q * ((2.0 * Sd + 1.0) / (2.0 * Sd + 2.0))
+                             : (S == 0 ? near_Q(dir, 1) : q * ((2.0 * Sd) / (2.0 * Sd + 3.0)));
+                ++S;
+                if (++c == 2 * s) {
+                    c = 0;
+                    ++node;
+                }
             }
         }
-        gl[e] = v;
     }
-    for (int e = tid; e < nQ; e += kThreads) Ql[e] = near_Q(dir, jb + e);
-    for (int e = tid; e < nP; e += kThreads) {
+    for (int e = tid; e < nP; e += kMainThreads) {
         const int d = e - (R - 1);
         Pl[e] = d < 0 ? 0.0 : near_P(dir, d);
     }
-
-    // steps (4): chain of ancestors, level 0 .. groot, then the subtree levels.
-    // c_acc(child) = c_far(child) + B(p)^T c_acc(parent), p = child & 1; with
-    // B(1) = B(0) with odd diagonals negated: (B(p)^T c)_n = sum_{k>=n} b_kn (+-1)^(k-n) c_k.
-    const double *cfar = a.c + item * a.NT * 2 * M;
-    double *chain = cl;                               // 2M, the running ancestor
-    double *sub = cl + 2 * M;                         // subtree levels 1..kd (2^d nodes each)
-    for (int g = 0; g <= groot; ++g) {
-        const int64_t node = u0 >> (kd + groot - g);
-        const bool has = node < (int64_t(1) << (g + 2)) - 2;
-        double v = 0.0;
-        if (tid < 2 * M) {
-            const int sig = tid / M, nn = tid - sig * M;
-            if (has) v = cfar[(node_offset(g) + node) * 2 * M + tid];
-            if (g > 0) {
-                const int p = (int)(node & 1);
-                const double *cp = chain + sig * M;
-                double acc = 0.0;
-                for (int k = nn; k < M; ++k) {
-                    const double bv = Bl[k * M + nn];
-                    acc = fma((p && ((k - nn) & 1)) ? -bv : bv, cp[k], acc);
-                }
-                v += acc;
-            }
-        }
-        __syncthreads();
-        if (tid < 2 * M) chain[tid] = v;
-        __syncthreads();
-    }
-    {
-        const double *par = chain;
-        double *cur = sub;
-        for (int d = 1; d <= kd; ++d) {
-            const int g = groot + d;
-            const int cn = 1 << d;
-            const int64_t first = u0 >> (kd - d);
-            for (int e = tid; e < cn * 2 * M; e += kThreads) {
-                const int v = e / (2 * M), r = e - v * 2 * M;
-                const int sig = r / M, nn = r - sig * M;
-                const int64_t node = first + v;
-                double acc = 0.0;
-                if (node < (int64_t(1) << (g + 2)) - 2) acc = cfar[(node_offset(g) + node) * 2 * M + r];
-                const int p = v & 1;
-                const double *cp = par + (v >> 1) * 2 * M + sig * M;
-                for (int k = nn; k < M; ++k) {
-                    const double bv = Bl[k * M + nn];
-                    acc = fma((p && ((k - nn) & 1)) ? -bv : bv, cp[k], acc);
-                }
-                cur[e] = acc;
-            }
-            __syncthreads();
-            par = cur;
-            cur += cn * 2 * M;
-        }
-    }
-    // the finest-level c of the subtree: level kd of `sub`, i.e. after 2 + 4 + ... + 2^(kd-1) nodes
-    const double *cfine = kd > 0 ? sub + ((1 << kd) - 2) * 2 * M : chain;
-
-    // step (5): z(u)[2m + sig] = sum_k T_k(X_m^sig) c(u)[sig][k] for row nodes u < P - 2
-    for (int e = tid; e < nodes * 2 * s; e += kThreads) {
-        const int nd = e / (2 * s), rr = e - nd * 2 * s;
-        const int m = rr >> 1, sig = rr & 1;
-        double acc = 0.0;
-        if (u0 + nd < P - 2) {
-            const double *cc = cfine + nd * 2 * M + sig * M;
-            const double *tt = Tl + (sig * s + m) * M;
+    stage_lds<1, kMainThreads>(Bl, a.B0, M * M);
+    for (int e = tid; e < 2 * GX; e += kMainThreads) gp[e] = 0.0;
+    __syncthreads();
 #pragma unroll
-            for (int k = 0; k < M; ++k) acc = fma(tt[k], cc[k], acc);
+    for (int u = 0; u < UW; ++u) {
+        const int e = u * kMainThreads + tid;
+        if (e < cntw) wl[(e / M2) * NS + e % M2] = vw[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+        const int e = u * kMainThreads + tid;
+        if (e < cntg) {
+            const int sig = e >= GXL, x = e - sig * GXL;
+            const int64_t j = jb + 2 * (int64_t)x + sig;
+            gp[sig * GX + x + (x / s) * gpad] = dir == 1 ? vg[u] * (double)j : vg[u];   // g_j = j u_j
         }
-        zl[e] = acc;
     }
     __syncthreads();
+    L2C_TS(2, 1);
 
-    // step (6): near field.  Thread <-> (node, parity, R consecutive same-parity rows);
-    // row m (of the node's s rows of this parity) sums over m' in [m, 2s):
-    //   P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig].
-    // P, Q and g enter through small circular windows so each step costs 3 LDS reads
-    // for R rows.
+    // ---- step (6): near field.  Row m of the node's s rows of one parity sums over
+    //      m' in [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig].  P, Q and g
+    //      enter through circular register windows (3 LDS reads per step for R rows);
+    //      the sums stay in registers until the leaf evaluation.
     const int nch = (s + R - 1) / R;
-    for (int wi = tid; wi < nodes * 2 * nch; wi += kThreads) {
-        const int ch = wi % nch;
-        const int seg = wi / nch;
-        const int nd = seg >> 1, sig = seg & 1;
-        const int m0 = ch * R;
-        const double *gs = gl + seg * GS;
-        const double *qs = Ql + nd * 2 * s + sig + m0;   // Q index for row m0 + r at m': qs[r + m']
-        const double *ps = Pl + (R - 1) - m0;            // P index for row m0 + r at m': ps[m' - r]
-        double acc[R], pb[R], qb[R];
+    const int nwork = nodes * 2 * nch;               // <= kNearItems * kMainThreads (geometry)
+    double acc[kNearItems][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            acc[r] = 0.0;
-            pb[r] = 0.0;  // P at negative offsets
+    for (int it = 0; it < kNearItems; ++it) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[it][r] = 0.0;
+        const int wi = lane + 64 * (wv + (kMainThreads / 64) * it);
+        if (wi >= nwork) continue;
+        const int nd = wi % nodes, x = wi / nodes;
+        const int sig = x & 1, m0 = (x >> 1) * R;
+        const double *gs = gp + sig * GX + nd * GS;      // g at m': gs[m' + (m' / s) gpad]
+        const double *qs = Ql + nd * QS;                 // Q at c = sig + m0 + r + m': qs[c + (c >= 2s) qpad]
+        const double *ps = Pl + (R - 1) - m0;            // P for row m0 + r at m': ps[m' - r]
+        double pb[R], qb[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) pb[r] = 0.0;         // P at negative offsets
+#pragma unroll
+        for (int r = 0; r < R - 1; ++r) {
+            const int c = sig + 2 * m0 + r;              // m' = m0
+            qb[(m0 + r) % R] = qs[c + (c >= 2 * s ? qpad : 0)];
         }
-#pragma unroll
-        for (int r = 0; r < R - 1; ++r) qb[(m0 + r) % R] = qs[m0 + r];
         const int steps = ((2 * s - m0) + R - 1) / R;
         for (int st = 0; st < steps; ++st) {
             const int mb = m0 + st * R;
+            const bool tail = mb + R > 2 * s;
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 const int mp = mb + t;                    // m' ; mp % R == t
-                pb[t] = ps[mp];                           // P[m' - m0]
-                qb[(t + R - 1) % R] = qs[mp + R - 1];     // Q for row R-1
-                const double gv = gs[mp];
+                pb[t] = ps[mp];
+                const int c = sig + m0 + mp + R - 1;
+                qb[(t + R - 1) % R] = qs[c + (c >= 2 * s ? qpad : 0)];
+                double gv = gs[mp + (mp >= s ? gpad : 0) + (mp >= 2 * s ? gpad : 0)];
+                if (tail && mp >= 2 * s) gv = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    acc[r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[r]);
+                    acc[it][r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[it][r]);
             }
         }
-        // step (7) pieces: row scales, diagonal special case; accumulate into z
+    }
+    L2C_TS(2, 2);
+
+    // ---- step (3), ancestors a_g = R >> (groot - g), g = 0..groot, from the top table
+    for (int e = tid; e < (groot + 1) * M; e += kMainThreads) {
+        const int g = e / M, k = e - g * M;
+        const int64_t an = Rn >> (groot - g);
+        double c0 = 0.0, c1 = 0.0;
+        if (an < (int64_t(1) << (g + 2)) - 2) {
+            const int64_t b = an >> 1;
+            const double *Ab = a.ahat_top + (level_block_offset(g) + b) * 3 * M * M;
+            const double *wc = wgl + (node_offset(g) + an + 2) * M2;   // w(a+2), w(a+3)
+            if ((an & 1) == 0) {
+                const double *A0r = Ab + k * M, *A1r = Ab + M * M + k * M;
+#pragma unroll 3
+                for (int l = 0; l < M; ++l) {
+                    c0 = fma(A0r[l], wc[l], c0);
+                    c1 = fma(A0r[l], wc[M + l], c1);
+                    c0 = fma(A1r[l], wc[M2 + l], c0);
+                    c1 = fma(A1r[l], wc[M2 + M + l], c1);
+                }
+            } else {
+                const double *A2r = Ab + 2 * M * M + k * M;
+#pragma unroll 3
+                for (int l = 0; l < M; ++l) {
+                    c0 = fma(A2r[l], wc[l], c0);
+                    c1 = fma(A2r[l], wc[M + l], c1);
+                }
+            }
+        }
+        canc[g * NS + k] = c0;
+        canc[g * NS + M + k] = c1;
+    }
+    L2C_TS(2, 3);
+
+    // ---- step (3), own blocks: wave <-> groups of 64 slots; lane (j, k) produces
+    //      c(2i)[k] = Ahat(.,0)[k,:] w(2i+2) + Ahat(.,1)[k,:] w(2i+3),  c(2i+1)[k] = Ahat(.,2)[k,:] w(2i+3)
+    //      for both parities (i = block index within its depth).  The wave's first group
+    //      was put in flight at the start; later groups are loaded when reached.
+    for (int grp = wv; grp < G.sub_groups; grp += kMainThreads / 64) {
+        if (grp != wv) {
+#pragma unroll
+            for (int c2 = 0; c2 < NCH; ++c2) ar[c2] = sub[(grp * NCH + c2) * 64];
+        }
+        const int slot = grp * 64 + lane;
+        const bool valid = slot < nslots;
+        const int j = valid ? slot / M : 0, k = valid ? slot - j * M : 0;
+        const int d = 32 - __clz(j + 1);                // depth: j in [2^(d-1) - 1, 2^d - 1)
+        const int i = j - ((1 << (d - 1)) - 1);          // block index within the depth
+        const double *wt = wl + ((1 << d) - 2 + 2 * i) * NS;   // w(2i+2), then w(2i+3)
+        double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll
+        for (int c2 = 0; c2 < NCH; ++c2) {
+            const double a0 = ar[c2].x, a1 = ar[c2].y;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int el = 2 * c2 + h, r = el / M, l = el - r * M;
+                const double av = h ? a1 : a0;
+                if (r == 0) {
+                    c00 = fma(av, wt[l], c00);
+                    c01 = fma(av, wt[M + l], c01);
+                } else if (r == 1) {
+                    c00 = fma(av, wt[NS + l], c00);
+                    c01 = fma(av, wt[NS + M + l], c01);
+                } else {
+                    c10 = fma(av, wt[NS + l], c10);
+                    c11 = fma(av, wt[NS + M + l], c11);
+                }
+            }
+        }
+        if (valid) {
+            double *co = cown + ((1 << d) - 2 + 2 * i) * NS + k;
+            co[0] = c00;
+            co[M] = c01;
+            co[NS] = c10;
+            co[NS + M] = c11;
+        }
+    }
+    __syncthreads();
+    L2C_TS(2, 4);
+
+    // ---- step (4): the chain of ancestors, c(a_g) += B(p)^T c(a_{g-1}), p = a_g & 1,
+    //      then the subtree depths d = 1..kd from depth d-1 (depth 0 = R); T moves into
+    //      the (now dead) near-field input area meanwhile
+    stage_lds<3, kMainThreads>(Tl, a.T, 2 * s * M);
+    {
+        constexpr int QSTEP = kMainThreads / M;
+        const int n = tid % M, q0 = tid / M;
+        const bool qn_ok = tid < M * QSTEP;
+        double bcol[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) bcol[k] = Bl[k * M + (qn_ok ? n : 0)];
+        for (int g = 1; g <= groot; ++g) {
+            if (qn_ok)
+                down_level_qn<M>(canc + (g - 1) * NS, canc + g * NS, 1, (int)((Rn >> (groot - g)) & 1), bcol, n, q0,
+                                 QSTEP);
+            __syncthreads();
+        }
+        for (int d = 1; d <= kd; ++d) {
+            const int cn = 1 << d;
+            const double *parb = d == 1 ? canc + groot * NS : cown + ((cn >> 1) - 2) * NS;
+            if (2 * cn <= QSTEP) {
+                if (qn_ok) down_level_qn<M>(parb, cown + (cn - 2) * NS, cn, -1, bcol, n, q0, QSTEP);
+            } else {
+                down_level<M>(parb, cown + (cn - 2) * NS, cn, -1, Bl);
+            }
+            __syncthreads();
+        }
+    }
+    if (groot == 0 && kd == 0) __syncthreads();
+    const double *cfine = kd > 0 ? cown + (nodes - 2) * NS : canc + groot * NS;
+    L2C_TS(2, 5);
+
+    // ---- steps (5) and (7) for the thread's rows: z = sum_k T_k(X_m^sig) c(u)[sig][k]
+    //      (row nodes u < P - 2) + rs * near; leg2cheb divides by c_i pi/2
+    double *out = a.out + item * a.n;
+#pragma unroll
+    for (int it = 0; it < kNearItems; ++it) {
+        const int wi = lane + 64 * (wv + (kMainThreads / 64) * it);
+        if (wi >= nwork) continue;
+        const int nd = wi % nodes, x = wi / nodes;
+        const int sig = x & 1, m0 = (x >> 1) * R;
+        const bool far = u0 + nd < P - 2;
+        double cc[M];
+        const double *cs = cfine + nd * NS + sig * M;
+#pragma unroll
+        for (int k = 0; k < M; ++k) cc[k] = cs[k];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int m = m0 + r;
             if (m < s) {
-                const int zi = nd * 2 * s + 2 * m + sig;
-                const int64_t i = jb + zi;
-                double v = acc[r];
+                double z = 0.0;
+                if (far) {
+                    const double *tt = Tl + (sig * s + m) * M;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) z = fma(tt[k], cc[k], z);
+                }
+                const int64_t i = jb + nd * 2 * s + 2 * m + sig;
+                double v = acc[it][r];
                 if (dir == 1) {
                     v *= 2.0 * (double)i + 1.0;
                     if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
                 }
-                zl[zi] += v;
+                v += z;
+                if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
+                if (i < a.n) out[i] = v;
             }
         }
     }
-    __syncthreads();
-
-    // step (7): leg2cheb divides by c_i pi/2; write out the valid part
-    double *out = a.out + item * a.n;
-    for (int e = tid; e < nodes * 2 * s; e += kThreads) {
-        const int64_t i = jb + e;
-        if (i < a.n) {
-            double v = zl[e];
-            if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
-            out[i] = v;
-        }
-    }
+    L2C_TS(2, 6);
 }
 
 // ------------------------------------------------------------------------------------
@@ -447,73 +761,63 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *o
 }
 
 // ------------------------------------------------------------------------------------
-static size_t up_lds_bytes(int s, int M, int ku)
+static size_t up_lds_bytes(const Geometry &G)
 {
-    const int nodes = 1 << ku;
-    const int D = (s & 1) ? 2 * s : 2 * s + 2;
-    return sizeof(double) * ((size_t)nodes * D + (size_t)(2 * nodes - 1) * 2 * M + (size_t)M * M);
+    const int nodes = 1 << G.ku;
+    const int D = 2 * G.s + 1;
+    return sizeof(double) * ((size_t)nodes * D + 2 * (size_t)G.s * G.M + (size_t)G.M * G.M +
+                             (size_t)(2 * nodes - 1) * (2 * G.M + 1));
 }
 
-static size_t down_lds_bytes(int s, int M, int kd)
+static size_t top_lds_bytes(const Geometry &G, int kt)
 {
-    const int R = kNearRows, nodes = 1 << kd;
-    const size_t GS = 2 * s + R;
-    const size_t nQ = 2 * (size_t)s * nodes + s + 2 * R;
-    const size_t nP = 2 * s + 2 * R;
-    return sizeof(double) * ((size_t)M * M + 2 * (size_t)s * M + (size_t)2 * nodes * 2 * M +
-                             (size_t)nodes * 2 * GS + nQ + nP + (size_t)nodes * 2 * s);
+    const int nodes = 1 << kt;
+    return sizeof(double) * ((size_t)G.M * G.M + (size_t)(2 * nodes - 1) * (2 * G.M + 1));
+}
+
+static size_t main_lds_bytes(const Geometry &G)
+{
+    return sizeof(double) * (size_t)main_lds_doubles(G.L, G.M, G.s, G.kd);
 }
 
 template <int M>
 static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st)
 {
+    const Geometry &G = p.geo;
     ExecArgs a;
-    a.in = in;
-    a.out = out;
     a.n = p.n;
-    a.n_pad = p.n_pad;
-    a.batch = batch;
-    a.L = p.L;
-    a.s = p.s;
-    a.M = M;
     a.dir = p.direction;
-    a.ku = p.L - 1 < kUpDepth ? p.L - 1 : kUpDepth;
-    a.kd = p.L - 1 < kDownDepth ? p.L - 1 : kDownDepth;
+    a.geo = G;
     a.T = p.d_T;
     a.B0 = p.d_B;
-    a.ahat = p.d_ahat;
-    a.w = p.d_w;
-    a.c = p.d_c;
-    a.NT = p.NT;
-    const int64_t P = int64_t(1) << (p.L + 1);
-    const size_t up_lds = up_lds_bytes(p.s, M, a.ku), down_lds = down_lds_bytes(p.s, M, a.kd);
+    a.ahat_top = p.d_top;
+    a.ahat_bot = p.d_bot;
+    const int64_t P = int64_t(1) << (G.L + 1);
+    const size_t up_lds = up_lds_bytes(G), main_lds = main_lds_bytes(G);
     static bool attr_set = false;   // allow the full 160 KiB LDS of a gfx950 CU
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_up<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute((const void *)k_down<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute((const void *)k_main<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-
-    // grid.y carries the item index; at most kMaxItemsPerLaunch items per launch
-    const int g0 = p.L - 1 - a.ku;
-    const int64_t groups = p.far.group_off[p.L];
     for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
         ExecArgs c = a;
         c.batch = batch - b0 < kMaxItemsPerLaunch ? batch - b0 : kMaxItemsPerLaunch;
         c.in = in + b0 * p.n;
         c.out = out + b0 * p.n;
-        c.w = p.d_w + b0 * p.NT * 2 * M;
-        c.c = p.d_c + b0 * p.NT * 2 * M;
+        c.w = p.d_w + b0 * G.NT * 2 * M;
         const unsigned items = (unsigned)c.batch;
-        hipLaunchKernelGGL(k_up<M>, dim3((unsigned)(P >> a.ku), items), dim3(kThreads), up_lds, st, c);
-        if (g0 > 0) hipLaunchKernelGGL(k_top<M>, dim3(items), dim3(1024), 0, st, c, g0);
-        const unsigned fx = (unsigned)((groups + 3) / 4);
-        const unsigned fy = (unsigned)((c.batch + kFarItems - 1) / kFarItems);
+        hipLaunchKernelGGL(k_up<M>, dim3((unsigned)(P >> G.ku), items), dim3(kThreads), up_lds, st, c);
+        for (int gin = G.L - 1 - G.ku; gin > 0;) {
+            const int kt = gin < G.kt ? gin : G.kt;
+            const unsigned wgs = (unsigned)((int64_t(1) << (gin + 2)) >> kt);
+            hipLaunchKernelGGL(k_top<M>, dim3(wgs, items), dim3(kThreads), top_lds_bytes(G, kt), st, c, gin, kt);
+            gin -= kt;
+        }
         const bool timed = p.ev_before && p.ev_after && b0 == 0;
         if (timed) (void)hipEventRecord(p.ev_before, st);
-        hipLaunchKernelGGL(k_far<M>, dim3(fx, fy), dim3(kThreads), 0, st, c, p.far);
+        hipLaunchKernelGGL(k_main<M>, dim3((unsigned)(P >> G.kd), items), dim3(kMainThreads), main_lds, st, c);
         if (timed) (void)hipEventRecord(p.ev_after, st);
-        hipLaunchKernelGGL(k_down<M>, dim3((unsigned)(P >> a.kd), items), dim3(kThreads), down_lds, st, c);
     }
     return hipGetLastError();
 }

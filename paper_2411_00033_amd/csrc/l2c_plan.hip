@@ -8,7 +8,7 @@
 // cheb2leg kernel of Eq. (Lxymod), and applies the 2-D DCT-II
 //     ahat_kl = 4/(c_k c_l M^2) sum_m sum_n K(x_m, y_n) D_km D_ln,  D_km = cos(k (m+1/2) pi / M),
 // as two M x M x M products in LDS.  All in FP64.  Results go straight into the
-// slot-interleaved far-field layout that k_far streams (see l2c_internal.h).
+// far-field tables that k_main reads (layouts in l2c_internal.h).
 //
 // The paper's planning shortcuts (persymmetry of Lambda^-, reuse across a level,
 // term dropping in Eq. (tau), the radix-2/3 DCT of size 18) reduce CPU flops; here
@@ -25,17 +25,33 @@ __device__ inline double kernel_value(int dir, double x, double y)
     return g * lambda_real(0.5 * (y - x)) / lambda_real(0.5 * (x + y));
 }
 
+// Address (in doubles) of element (r, k, l) of block b of level g in the plan tables.
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_build_ahat(double *ahat, FarLayout lay, int s, int dir,
+__device__ __forceinline__ double *ahat_addr(double *top, double *bot, const Geometry &G, int g, int64_t b,
+                                             int r, int k, int l)
+{
+    constexpr int NCH = 3 * M / 2;
+    if (g <= G.groot) return top + ((level_block_offset(g) + b) * 3 + r) * M * M + k * M + l;
+    const int d = g - G.groot;                      // depth below the subtree root
+    const int64_t Rn = b >> (d - 1);                // subtree of the block
+    const int64_t j = ((int64_t(1) << (d - 1)) - 1) + (b - (Rn << (d - 1)));
+    const int64_t slot = j * M + k;
+    const int64_t grp = Rn * G.sub_groups + slot / 64;
+    const int lane = (int)(slot % 64);
+    const int el = r * M + l;
+    return bot + ((grp * NCH + el / 2) * 64 + lane) * 2 + (el & 1);
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bot, Geometry G, int dir,
                                                           const double *XG, const double *Dm)
 {
     constexpr int MM = M * M;
-    constexpr int NCH = 3 * M / 2;
     __shared__ double S[3 * MM];
     __shared__ double U[3 * MM];
     __shared__ double Dl[MM];
     __shared__ double Xl[M];
-    const int L = lay.L;
+    const int L = G.L, s = G.s;
     // block index -> (level g, block b): level g holds 2^(g+1) - 1 blocks
     int64_t gb = blockIdx.x;
     int g = 0;
@@ -75,19 +91,14 @@ __global__ __launch_bounds__(kThreads) void k_build_ahat(double *ahat, FarLayout
         double acc = 0.0;
         for (int m = 0; m < M; ++m) acc = fma(Dl[k * M + m], U[r * MM + m * M + l], acc);
         const double sc = 4.0 / ((k == 0 ? 2.0 : 1.0) * (l == 0 ? 2.0 : 1.0) * M * M);
-        const int64_t slot = b * M + k;
-        const int64_t grp = lay.group_off[g] + slot / 64;
-        const int lane = (int)(slot % 64);
-        const int el = r * M + l;
-        ahat[((grp * NCH + el / 2) * 64 + lane) * 2 + (el & 1)] = acc * sc;
+        *ahat_addr<M>(top, bot, G, g, b, r, k, l) = acc * sc;
     }
 }
 
-// Interleaved far-field layout -> canonical [level][block][r][k][l].
+// Plan tables -> canonical [level][block][r][k][l].
 template <int M>
-__global__ void k_export_ahat(const double *ahat, FarLayout lay, double *dst, int64_t total)
+__global__ void k_export_ahat(double *top, double *bot, Geometry G, double *dst, int64_t total)
 {
-    constexpr int NCH = 3 * M / 2;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     int64_t blk = e / (3 * M * M);
@@ -98,17 +109,13 @@ __global__ void k_export_ahat(const double *ahat, FarLayout lay, double *dst, in
         blk -= (int64_t(1) << (g + 1)) - 1;
         ++g;
     }
-    const int64_t slot = blk * M + k;
-    const int64_t grp = lay.group_off[g] + slot / 64;
-    const int lane = (int)(slot % 64);
-    const int el = r * M + l;
-    dst[e] = ahat[((grp * NCH + el / 2) * 64 + lane) * 2 + (el & 1)];
+    dst[e] = *ahat_addr<M>(top, bot, G, g, blk, r, k, l);
 }
 
 template <int M>
 static hipError_t build(const l2c_plan_s &p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)p.nb), dim3(kThreads), 0, st, p.d_ahat, p.far, p.s,
+    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)p.nb), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
                        p.direction, p.d_XG, p.d_D);
     return hipGetLastError();
 }
@@ -117,8 +124,8 @@ template <int M>
 static hipError_t xport(const l2c_plan_s &p, double *dst, hipStream_t st)
 {
     const int64_t total = p.nc * M * M;
-    hipLaunchKernelGGL(k_export_ahat<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, p.d_ahat,
-                       p.far, dst, total);
+    hipLaunchKernelGGL(k_export_ahat<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, p.d_top,
+                       p.d_bot, p.geo, dst, total);
     return hipGetLastError();
 }
 
