@@ -74,7 +74,7 @@ struct l2c_plan_info {
  *   n          input length, n >= 1.
  *   direction  L2C_LEG2CHEB or L2C_CHEB2LEG.
  *   leaf_size  side 2*s_hat of the smallest far-field submatrices (Eq. (numlevels)
- *              uses s_hat); even, 4 <= leaf_size <= 256.  The paper uses s = 32,
+ *              uses s_hat); even, 4 <= leaf_size <= 128.  The paper uses s = 32,
  *              i.e. leaf_size 64 (Sec. 5).  The effective s lies in [s_hat/2, s_hat].
  *   rank       M, number of Chebyshev modes per axis; one of the ranks this build
  *              instantiates (leg2cheb_rank_supported).  The paper uses 18.
