@@ -44,6 +44,18 @@ enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
  * final accumulation stay FP64).  Only L2C_FP64 is available in this build. */
 enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
 
+/* Execution path of a plan (l2c_plan_info.path). */
+enum l2c_path {
+    L2C_PATH_DIRECT = 0, /* L = 0: the whole product directly (Alg. 1) */
+    L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
+    L2C_PATH_SINGLE = 2  /* one launch, workgroups exchange tree nodes through ready flags */
+};
+
+/* Plan options (leg2cheb_plan_set_option). */
+enum l2c_option {
+    L2C_OPT_SINGLE_LAUNCH = 1 /* 1: single-launch path when the plan allows it (default); 0: three launches */
+};
+
 enum l2c_status {
     L2C_OK = 0,
     L2C_EINVAL = -1,      /* invalid argument (null pointer, bad size, overlap, ...) */
@@ -60,7 +72,7 @@ struct l2c_plan_info {
     int32_t rank;          /* M, Chebyshev expansion rank, Eq. (Aij) */
     int32_t direction;     /* l2c_direction */
     int32_t precision;     /* l2c_precision */
-    int32_t reserved;
+    int32_t path;          /* l2c_path used by leg2cheb_execute */
     int64_t n_blocks;      /* N_b, Eq. (total_blocks_and_mats) */
     int64_t n_submatrices; /* N_c = 3 N_b */
     int64_t table_bytes;   /* device bytes of the plan tables (Ahat, T, B, ...) */
@@ -125,10 +137,36 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info);
 int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed);
 
 /*
+ * Set a plan option (enum l2c_option).
+ *   L2C_OPT_SINGLE_LAUNCH  value 1 (default) runs Alg. 4 as one kernel launch when the
+ *       geometry allows it: every subtree of 2^kd finest nodes gets one workgroup, and
+ *       all workgroups of an item must be resident at once (at most one per compute
+ *       unit).  The workgroups exchange only subtree roots, the two boundary nodes of
+ *       each depth, and the upward vectors above the subtrees.  Value 0 selects the
+ *       three-launch path.  Both paths use the same plan tables and agree to rounding.
+ * Single-launch kernels of one device are ordered by the library (a launch on another
+ * stream waits for the previous one), so they never compete for compute units; other
+ * work may delay but not block them.  A plan must not be executed on two streams at
+ * the same time.
+ * Errors: L2C_EINVAL (plan, option or value), L2C_EUNSUPPORTED (value 1 on a plan whose
+ * geometry has no single-launch form).
+ */
+int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value);
+
+/*
+ * Diagnostic status of the plan's single-launch executions since it was made:
+ * bit 0 = a workgroup stopped waiting for another after about a second (the
+ * output of that execute is wrong).  Synchronizes the device.  *status = 0 for
+ * plans without a single-launch path.
+ */
+int leg2cheb_plan_status(l2c_plan_t plan, int *status);
+
+/*
  * Optional timing hook for benchmarks: when both events (hipEvent_t) are
  * non-NULL, execute records `before` immediately before and `after`
- * immediately after the far-field kernel (the one that streams Ahat), on the
- * execute stream.  Pass NULLs to turn it off.
+ * immediately after the kernel that streams Ahat (the single-launch kernel, or
+ * the far-field kernel of the three-launch path), on the execute stream, for the
+ * first launch of the call.  Pass NULLs to turn it off.
  */
 int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after);
 

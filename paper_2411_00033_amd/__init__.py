@@ -16,9 +16,10 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401  (re-exported ABI names)
     L2C_BF16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
-    L2C_LEG2CHEB, L2C_OK, L2CError, TABLE_AHAT, TABLE_B, TABLE_T, leg2cheb_destroy, leg2cheb_execute,
-    leg2cheb_plan, leg2cheb_plan_ex, leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_rank_supported,
-    leg2cheb_set_timing_events,
+    L2C_LEG2CHEB, L2C_OK, L2C_OPT_SINGLE_LAUNCH, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_THREE, L2CError,
+    TABLE_AHAT, TABLE_B, TABLE_T, leg2cheb_destroy, leg2cheb_execute, leg2cheb_plan, leg2cheb_plan_ex,
+    leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
+    leg2cheb_rank_supported, leg2cheb_set_timing_events,
 )
 
 LEG2CHEB, CHEB2LEG = L2C_LEG2CHEB, L2C_CHEB2LEG
@@ -70,6 +71,15 @@ class Plan:
         buf = np.empty(need // 8, dtype=np.float64)
         leg2cheb_plan_export(self.handle, table, buf.ctypes.data, need)
         return buf
+
+    def set_single_launch(self, on: bool) -> None:
+        """Choose the single-launch path (default when the plan allows it) or three launches."""
+        leg2cheb_plan_set_option(self.handle, L2C_OPT_SINGLE_LAUNCH, 1 if on else 0)
+
+    @property
+    def status(self) -> int:
+        """Diagnostic bits of the single-launch path (0 = every wait completed); synchronizes."""
+        return leg2cheb_plan_status(self.handle)
 
     def set_timing_events(self, before, after) -> None:
         """Record torch.cuda.Event pair around the far-field kernel of each execute (None: off)."""

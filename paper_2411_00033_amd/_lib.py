@@ -16,10 +16,13 @@ L2C_LEG2CHEB, L2C_CHEB2LEG = 0, 1
 L2C_FP64, L2C_FP32, L2C_BF16X2 = 0, 1, 2
 L2C_OK, L2C_EINVAL, L2C_ENOMEM, L2C_EHIP, L2C_EUNSUPPORTED = 0, -1, -2, -3, -4
 TABLE_AHAT, TABLE_T, TABLE_B = 0, 1, 2
+L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE = 0, 1, 2
+L2C_OPT_SINGLE_LAUNCH = 1
 
 EXPORTED = (
     "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_destroy", "leg2cheb_plan_info",
-    "leg2cheb_plan_export", "leg2cheb_set_timing_events", "leg2cheb_rank_supported", "leg2cheb_strerror",
+    "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
+    "leg2cheb_rank_supported", "leg2cheb_strerror",
 )
 
 
@@ -27,13 +30,13 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("n_pad", ctypes.c_int64),
         ("levels", ctypes.c_int32), ("s", ctypes.c_int32), ("rank", ctypes.c_int32),
-        ("direction", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("direction", ctypes.c_int32), ("precision", ctypes.c_int32), ("path", ctypes.c_int32),
         ("n_blocks", ctypes.c_int64), ("n_submatrices", ctypes.c_int64),
         ("table_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("ahat_bytes", ctypes.c_int64),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class L2CError(RuntimeError):
@@ -61,6 +64,8 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_destroy.argtypes = [vp]
     lib.leg2cheb_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.leg2cheb_plan_export.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
+    lib.leg2cheb_plan_set_option.argtypes = [vp, ci, i64]
+    lib.leg2cheb_plan_status.argtypes = [vp, ctypes.POINTER(ci)]
     lib.leg2cheb_set_timing_events.argtypes = [vp, vp, vp]
     lib.leg2cheb_rank_supported.argtypes = [ci]
     lib.leg2cheb_strerror.argtypes = [ci]
@@ -119,6 +124,17 @@ def leg2cheb_plan_export(plan: int, table: int, dst_ptr: int = 0, nbytes: int = 
     _check(load().leg2cheb_plan_export(ctypes.c_void_p(plan), int(table), ctypes.c_void_p(dst_ptr or None),
                                        int(nbytes), ctypes.byref(need)), "leg2cheb_plan_export")
     return need.value
+
+
+def leg2cheb_plan_set_option(plan: int, option: int, value: int) -> None:
+    _check(load().leg2cheb_plan_set_option(ctypes.c_void_p(plan), int(option), int(value)),
+           "leg2cheb_plan_set_option")
+
+
+def leg2cheb_plan_status(plan: int) -> int:
+    st = ctypes.c_int(0)
+    _check(load().leg2cheb_plan_status(ctypes.c_void_p(plan), ctypes.byref(st)), "leg2cheb_plan_status")
+    return st.value
 
 
 def leg2cheb_set_timing_events(plan: int, before: int, after: int) -> None:

@@ -4,10 +4,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/leg2cheb.h"
 #include "l2c_internal.h"
+#include "l2c_math.h"
 
 namespace {
 
@@ -82,6 +84,18 @@ void vandermonde(int s, int M, std::vector<double> &T)
         }
 }
 
+// Near-field factor table (the same P_d as the near-field kernels use, Eq. (Lxymod) for
+// cheb2leg): l2c::kPLead leading zeros, then P_d for d = 0, 1, ...
+void near_p_table(int s, int dir, std::vector<double> &P)
+{
+    P.assign((size_t)l2c::p_table_len(s), 0.0);
+    for (int e = l2c::kPLead; e < (int)P.size(); ++e) {
+        const int d = e - l2c::kPLead;
+        const double lam = l2c::lambda_int(d);
+        P[e] = dir == 0 ? lam : lam / (1.0 - 2.0 * (double)d);
+    }
+}
+
 bool rank_supported(int M)
 {
     switch (M) {
@@ -100,11 +114,16 @@ void free_plan(l2c_plan_s *p)
     (void)hipFree(p->d_bot);
     (void)hipFree(p->d_T);
     (void)hipFree(p->d_B);
+    (void)hipFree(p->d_P);
     (void)hipFree(p->d_XG);
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_w);
+    (void)hipFree(p->d_flags);
+    (void)hipFree(p->d_status);
     delete p;
 }
+
+bool use_fused(const l2c_plan_s *p) { return p->fused_ok && p->fused_on; }
 
 int ensure_workspace(l2c_plan_s *p, int64_t batch)
 {
@@ -185,9 +204,10 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
         p->top_bytes = top_blocks * 3 * M * M * (int64_t)sizeof(double);
         p->bot_bytes = (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
 
-        std::vector<double> T, B, XG(M), Dm((size_t)M * M);
+        std::vector<double> T, B, Ptab, XG(M), Dm((size_t)M * M);
         vandermonde(s, M, T);
         b_matrices(M, B);
+        near_p_table(s, direction, Ptab);
         for (int m = 0; m < M; ++m) XG[m] = std::cos((m + 0.5) * M_PI / M);
         for (int k = 0; k < M; ++k)
             for (int m = 0; m < M; ++m) Dm[(size_t)k * M + m] = std::cos(k * (m + 0.5) * M_PI / M);
@@ -196,6 +216,7 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
                   (p->bot_bytes == 0 || hipMalloc(&p->d_bot, p->bot_bytes) == hipSuccess) &&
                   hipMalloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
                   hipMalloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&p->d_P, Ptab.size() * sizeof(double)) == hipSuccess &&
                   hipMalloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
                   hipMalloc(&p->d_D, Dm.size() * sizeof(double)) == hipSuccess;
         if (!ok) {
@@ -203,9 +224,11 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             free_plan(p);
             return L2C_ENOMEM;
         }
-        p->table_bytes = p->top_bytes + p->bot_bytes + (int64_t)(T.size() + B.size() + XG.size() + Dm.size()) * 8;
+        p->table_bytes =
+            p->top_bytes + p->bot_bytes + (int64_t)(T.size() + B.size() + Ptab.size() + XG.size() + Dm.size()) * 8;
         ok = hipMemcpyAsync(p->d_T, T.data(), T.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_P, Ptab.data(), Ptab.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_XG, XG.data(), XG.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              hipMemcpyAsync(p->d_D, Dm.data(), Dm.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
@@ -215,7 +238,26 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             free_plan(p);
             return L2C_EHIP;
         }
-        const int rc = ensure_workspace(p, max_batch);
+        // single-launch path: items per launch with every workgroup resident
+        int64_t items = 0;
+        if (l2c::fused_max_items(*p, &items) != hipSuccess) {
+            (void)hipGetLastError();
+            items = 0;
+        }
+        if (items > 0) {
+            const size_t fbytes = (size_t)items * p->geo.NF * sizeof(unsigned);
+            ok = hipMalloc(&p->d_flags, fbytes) == hipSuccess && hipMalloc(&p->d_status, sizeof(int)) == hipSuccess &&
+                 hipMemsetAsync(p->d_flags, 0, fbytes, st) == hipSuccess &&
+                 hipMemsetAsync(p->d_status, 0, sizeof(int), st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+            if (!ok) {
+                (void)hipGetLastError();
+                free_plan(p);
+                return L2C_ENOMEM;
+            }
+            p->fused_ok = true;
+            p->fused_items = items;
+        }
+        const int rc = ensure_workspace(p, use_fused(p) ? std::min(max_batch, p->fused_items) : max_batch);
         if (rc != L2C_OK) {
             free_plan(p);
             return rc;
@@ -243,6 +285,12 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
     if (dev != plan->device) return L2C_EINVAL;
+    if (plan->L > 0 && use_fused(plan)) {
+        const int rc = ensure_workspace(plan, std::min(batch, plan->fused_items));
+        if (rc != L2C_OK) return rc;
+        if (l2c::launch_fused(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
+        return L2C_OK;
+    }
     const int rc = ensure_workspace(plan, batch);
     if (rc != L2C_OK) return rc;
     if (l2c::launch_execute(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
@@ -273,6 +321,7 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
     info->table_bytes = plan->table_bytes;
     info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double);
     info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
+    info->path = plan->L == 0 ? L2C_PATH_DIRECT : use_fused(plan) ? L2C_PATH_SINGLE : L2C_PATH_THREE;
     return L2C_OK;
 }
 
@@ -301,6 +350,29 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
               hipMemcpy(dst, tmp, need, hipMemcpyDeviceToHost) == hipSuccess;
     (void)hipFree(tmp);
     return ok ? L2C_OK : L2C_EHIP;
+}
+
+int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value)
+{
+    if (!plan) return L2C_EINVAL;
+    switch (option) {
+    case L2C_OPT_SINGLE_LAUNCH:
+        if (value != 0 && value != 1) return L2C_EINVAL;
+        if (value == 1 && !plan->fused_ok) return L2C_EUNSUPPORTED;
+        plan->fused_on = value == 1;
+        return L2C_OK;
+    default: return L2C_EINVAL;
+    }
+}
+
+int leg2cheb_plan_status(l2c_plan_t plan, int *status)
+{
+    if (!plan || !status) return L2C_EINVAL;
+    *status = 0;
+    if (!plan->d_status) return L2C_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
+    if (hipMemcpy(status, plan->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return L2C_EHIP;
+    return L2C_OK;
 }
 
 int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after)

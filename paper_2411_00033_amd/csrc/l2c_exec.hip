@@ -15,280 +15,9 @@
 //           Eq. (step5), the near-diagonal direct part of step (6), the scaling of
 //           step (7), and the output.  Nothing but w crosses kernel boundaries.
 // Plans with L = 0 use k_direct (Alg. 1 for every row).
-#include "l2c_internal.h"
-#include "l2c_math.h"
-
-// Phase timestamps for performance analysis: compiled in only with L2C_PHASE_TIMING
-// (the product build defines nothing and the macro expands to nothing).
-#ifdef L2C_PHASE_TIMING
-extern __device__ unsigned long long l2c_phase_ts[];
-#define L2C_TS(kern, ph)                                                                          \
-    do {                                                                                          \
-        if (threadIdx.x == 0 && blockIdx.y == 0 && blockIdx.x < 4096)                             \
-            l2c_phase_ts[((kern) * 4096 + blockIdx.x) * 16 + (ph)] = wall_clock64();              \
-    } while (0)
-#else
-#define L2C_TS(kern, ph) \
-    do {                 \
-    } while (0)
-#endif
+#include "l2c_device.h"
 
 namespace l2c {
-
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// Copy count doubles from global memory to LDS.  The loads of each round are issued
-// together (U per thread) before any is waited for, so a round costs one memory
-// latency instead of U.
-template <int U, int NT = kThreads>
-__device__ __forceinline__ void stage_lds(double *dst, const double *src, int count)
-{
-    for (int base = 0; base < count; base += U * NT) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            v[u] = e < count ? src[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            if (e < count) dst[e] = v[u];
-        }
-    }
-}
-
-// ------------------------------------------------------------------------------------
-// Near-field tables.  Both directions are written as
-//     z_i = rs_i * sum_{j >= i, j - i even} P[(j-i)/2] * Q[(i+j)/2] * g_j
-// leg2cheb (Eq. (hik)):  P = Q = lambda, g = f, rs = 1.
-// cheb2leg: the reverse kernel of Eq. (Lxymod) with d = (j-i)/2, S = (i+j)/2 factors
-// as L(i,j) = (2i+1) j * [lambda_d / (1-2d)] * [1 / (2S (2S+1) lambda_S)], so
-// P_d = lambda_d/(1-2d), Q_S = 1/(2S(2S+1) lambda_S), g_j = j u_j, rs_i = 2i+1, u = c .* f.
-// At d = 0 this product is sqrt(pi)/(2 lambda_i) = (pi/2)/a_ii, the diagonal of A^{-1}C
-// for i >= 1; the (0,0) entry (where g_0 = 0 and Q_0 := 0) contributes u_0/2 = f_0,
-// added separately.
-__device__ __forceinline__ double near_P(int dir, int64_t d)
-{
-    const double lam = lambda_int(d);
-    return dir == 0 ? lam : lam / (1.0 - 2.0 * (double)d);
-}
-
-__device__ __forceinline__ double near_Q(int dir, int64_t S)
-{
-    if (dir == 0) return lambda_int(S);
-    if (S == 0) return 0.0;
-    const double S2 = 2.0 * (double)S;
-    return inv_lambda_int(S) / (S2 * (S2 + 1.0));
-}
-
-// Node arrays in LDS keep a node's [sigma][k] = 2M doubles followed by one pad double:
-// the odd node stride 2M + 1 puts lanes that read consecutive nodes on distinct banks
-// (the workspace in global memory keeps the dense stride 2M).
-template <int M>
-__host__ __device__ constexpr int lds_ns() { return 2 * M + 1; }
-
-// Upward transfer of one level (Eq. (wtk) with App. A2): for every parent node and
-// parity, out_n = sum_{k<=n} b_nk z_{(n-k) mod 2, k} with z0 = w(2T) + w(2T+1) and
-// z1 = w(2T) - w(2T+1) (B(1) is B(0) with its odd diagonals negated).
-// Lane <-> (parent, parity); wave residue H = wave mod 4 takes the outputs n = H mod 4,
-// so its rows of B(0) are the same for every lane: they are read from LDS into
-// registers once per level (one wait), then every product uses registers only.
-template <int M, int H>
-__device__ __forceinline__ void up_level_h(const double *child, double *par, int pn, const double *Bl, int q0,
-                                           int qstep)
-{
-    constexpr int NJ = (M - H + 3) / 4;               // outputs n = H + 4j < M
-    double bv[NJ][M];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-        for (int k = 0; k <= H + 4 * j; ++k) bv[j][k] = Bl[(H + 4 * j) * M + k];
-    }
-    for (int q = q0; q < 2 * pn; q += qstep) {
-        const int pnode = q >> 1, sig = q & 1;
-        const double *wa = child + (2 * pnode) * lds_ns<M>() + sig * M;
-        const double *wb = wa + lds_ns<M>();
-        double z0[M], z1[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double x = wa[k], y = wb[k];
-            z0[k] = x + y;
-            z1[k] = x - y;
-        }
-        double *po = par + pnode * lds_ns<M>() + sig * M;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int n = H + 4 * j;
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 0; k <= n; ++k) acc = fma(bv[j][k], ((n - k) & 1) ? z1[k] : z0[k], acc);
-            po[n] = acc;
-        }
-    }
-}
-
-template <int M>
-__device__ __forceinline__ void up_level(const double *child, double *par, int pn, const double *Bl)
-{
-    const int wv = wave_id(), nw = blockDim.x >> 6;
-    const int q0 = (threadIdx.x & 63) + 64 * (wv >> 2), qstep = 64 * (nw >> 2);
-    switch (wv & 3) {
-    case 0: up_level_h<M, 0>(child, par, pn, Bl, q0, qstep); break;
-    case 1: up_level_h<M, 1>(child, par, pn, Bl, q0, qstep); break;
-    case 2: up_level_h<M, 2>(child, par, pn, Bl, q0, qstep); break;
-    default: up_level_h<M, 3>(child, par, pn, Bl, q0, qstep); break;
-    }
-}
-
-// Downward transfer of one level (step (4)): c(child) += B(p)^T c(parent), p = child's
-// position in its parent.  With B(1) = B(0) with odd diagonals negated,
-// (B(p)^T c)_n = s_p(n) sum_{k>=n} b_kn s_p(k) c_k, s_p(k) = (-1)^k if p = 1, else 1.
-// cn children; parent of child v is v >> 1; p = v & 1 unless pfix >= 0 (then p = pfix).
-template <int M, int H>
-__device__ __forceinline__ void down_level_h(const double *par, double *cur, int cn, int pfix, const double *Bl,
-                                             int q0, int qstep)
-{
-    constexpr int NJ = (M - H + 3) / 4;
-    double bv[NJ][M];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-        for (int k = H + 4 * j; k < M; ++k) bv[j][k] = Bl[k * M + H + 4 * j];
-    }
-    for (int q = q0; q < 2 * cn; q += qstep) {
-        const int v = q >> 1, sig = q & 1;
-        const int p = pfix >= 0 ? pfix : (v & 1);
-        const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
-        double cs[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) cs[k] = (p && (k & 1)) ? -cp[k] : cp[k];
-        double *co = cur + v * lds_ns<M>() + sig * M;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int n = H + 4 * j;
-            double acc = 0.0;
-#pragma unroll
-            for (int k = n; k < M; ++k) acc = fma(bv[j][k], cs[k], acc);
-            co[n] += (p && (n & 1)) ? -acc : acc;
-        }
-    }
-}
-
-template <int M>
-__device__ __forceinline__ void down_level(const double *par, double *cur, int cn, int pfix, const double *Bl)
-{
-    const int wv = wave_id(), nw = blockDim.x >> 6;
-    const int q0 = (threadIdx.x & 63) + 64 * (wv >> 2), qstep = 64 * (nw >> 2);
-    switch (wv & 3) {
-    case 0: down_level_h<M, 0>(par, cur, cn, pfix, Bl, q0, qstep); break;
-    case 1: down_level_h<M, 1>(par, cur, cn, pfix, Bl, q0, qstep); break;
-    case 2: down_level_h<M, 2>(par, cur, cn, pfix, Bl, q0, qstep); break;
-    default: down_level_h<M, 3>(par, cur, cn, pfix, Bl, q0, qstep); break;
-    }
-}
-
-// The same two transfers for levels with few nodes: thread <-> (node pair q, output n)
-// with n fixed per thread, so the thread's row (up) or column (down) of B(0) sits in
-// registers for the whole kernel.  Only threads t < M * (blockDim / M) take part:
-// n = t mod M, first pair q0 = t / M, step qstep = blockDim / M.
-template <int M>
-__device__ __forceinline__ void up_level_qn(const double *child, double *par, int pn, const double (&brow)[M],
-                                            int n, int q0, int qstep)
-{
-    for (int q = q0; q < 2 * pn; q += qstep) {
-        const int pnode = q >> 1, sig = q & 1;
-        const double *wa = child + (2 * pnode) * lds_ns<M>() + sig * M;
-        const double *wb = wa + lds_ns<M>();
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double x = wa[k], y = wb[k];
-            acc = fma(brow[k], ((n - k) & 1) ? x - y : x + y, acc);   // brow[k] = b_nk, 0 for k > n
-        }
-        par[pnode * lds_ns<M>() + sig * M + n] = acc;
-    }
-}
-
-template <int M>
-__device__ __forceinline__ void down_level_qn(const double *par, double *cur, int cn, int pfix,
-                                              const double (&bcol)[M], int n, int q0, int qstep)
-{
-    for (int q = q0; q < 2 * cn; q += qstep) {
-        const int v = q >> 1, sig = q & 1;
-        const int p = pfix >= 0 ? pfix : (v & 1);
-        const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) acc = fma(bcol[k], (p && (k & 1)) ? -cp[k] : cp[k], acc);   // b_kn, 0 for k < n
-        cur[v * lds_ns<M>() + sig * M + n] += (p && (n & 1)) ? -acc : acc;
-    }
-}
-
-// Copy nodes between the dense workspace layout (stride 2M) and the padded LDS layout
-// (stride 2M + 1), U elements per thread per round (one wait per round).
-template <int M, int U, int NT>
-__device__ __forceinline__ void nodes_lds_to_global(double *dst, const double *src, int nodes)
-{
-    const int count = nodes * 2 * M;
-    for (int base = 0; base < count; base += U * NT) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            const int q = e / (2 * M);
-            v[u] = e < count ? src[q * lds_ns<M>() + (e - q * 2 * M)] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            if (e < count) dst[e] = v[u];
-        }
-    }
-}
-
-template <int M, int U, int NT>
-__device__ __forceinline__ void nodes_global_to_lds(double *dst, const double *src, int nodes)
-{
-    const int count = nodes * 2 * M;
-    for (int base = 0; base < count; base += U * NT) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            v[u] = e < count ? src[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * NT + (int)threadIdx.x;
-            const int q = e / (2 * M);
-            if (e < count) dst[q * lds_ns<M>() + (e - q * 2 * M)] = v[u];
-        }
-    }
-}
-
-// Upward step over a whole subtree held in LDS: level buffer d (0 = the 2^kt input nodes)
-// starts at node 2 nodes - 2 (nodes >> d); every level goes to the workspace at the end.
-template <int M>
-__device__ __forceinline__ void subtree_up(double *lv, int nodes, int kt, const double *Bl)
-{
-    const int qstep = kThreads / M, n = (int)threadIdx.x % M, q0 = (int)threadIdx.x / M;
-    const bool qn_ok = (int)threadIdx.x < M * qstep;
-    double brow[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) brow[k] = Bl[(qn_ok ? n : 0) * M + k];
-    for (int d = 1; d <= kt; ++d) {
-        const int pn = nodes >> d;
-        const double *child = lv + (2 * nodes - 2 * (nodes >> (d - 1))) * lds_ns<M>();
-        double *par = lv + (2 * nodes - 2 * pn) * lds_ns<M>();
-        if (2 * pn <= qstep) {
-            if (qn_ok) up_level_qn<M>(child, par, pn, brow, n, q0, qstep);
-        } else {
-            up_level<M>(child, par, pn, Bl);
-        }
-        __syncthreads();
-    }
-}
 
 // ------------------------------------------------------------------------------------
 // k_up: one workgroup per (subtree of 2^ku finest nodes, item).
@@ -510,10 +239,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
             }
         }
     }
-    for (int e = tid; e < nP; e += kMainThreads) {
-        const int d = e - (R - 1);
-        Pl[e] = d < 0 ? 0.0 : near_P(dir, d);
-    }
+    for (int e = tid; e < nP; e += kMainThreads) Pl[e] = a.Ptab[e + kPLead - (R - 1)];
     stage_lds<1, kMainThreads>(Bl, a.B0, M * M);
     for (int e = tid; e < 2 * GX; e += kMainThreads) gp[e] = 0.0;
     __syncthreads();
@@ -624,8 +350,8 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
         const int slot = grp * 64 + lane;
         const bool valid = slot < nslots;
         const int j = valid ? slot / M : 0, k = valid ? slot - j * M : 0;
-        const int d = 32 - __clz(j + 1);                // depth: j in [2^(d-1) - 1, 2^d - 1)
-        const int i = j - ((1 << (d - 1)) - 1);          // block index within the depth
+        int d, i;                                        // depth and block index within it
+        slot_depth(j, kd, d, i);
         const double *wt = wl + ((1 << d) - 2 + 2 * i) * NS;   // w(2i+2), then w(2i+3)
         double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
 #pragma unroll
@@ -790,6 +516,7 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
     a.geo = G;
     a.T = p.d_T;
     a.B0 = p.d_B;
+    a.Ptab = p.d_P;
     a.ahat_top = p.d_top;
     a.ahat_bot = p.d_bot;
     const int64_t P = int64_t(1) << (G.L + 1);

@@ -44,8 +44,9 @@ __host__ __device__ inline int64_t node_offset(int g) { return (int64_t(1) << (g
 // Far-field tables.
 //   top:    levels 0..groot, level-major, block-major, [r][k][l] row-major (M x M each);
 //           level g starts at block (2^(g+1) - 2 - g).
-//   bottom: per subtree R (R < 2^(groot+2)), its 2^kd - 1 own blocks in level order
-//           (depth d = 1..kd below R, 2^(d-1) blocks each, left to right).  "Slot"
+//   bottom: per subtree R (R < 2^(groot+2)), its 2^kd - 1 own blocks, finest depth
+//           first (depth d = kd, kd-1, ..., 1 below R, 2^(d-1) blocks each, left to
+//           right; depth d starts at block 2^kd - 2^d, see slot_depth).  "Slot"
 //           (j, k) = row k of the three submatrices of local block j (3M doubles).
 //           Slots are grouped 64 at a time (one wavefront); 16-byte chunk c of slot
 //           lane l of group G is at ((G * (3M/2) + c) * 64 + l) * 16 bytes, so every
@@ -57,6 +58,7 @@ struct Geometry {
     int groot;                // L - 1 - kd
     int sub_groups;           // wavefront groups per subtree in the bottom table
     int64_t NT;               // workspace nodes per item
+    int64_t NF;               // k_fused ready flags per item: levels 0..groot, node_offset(groot + 1)
 };
 
 struct ExecArgs {
@@ -68,9 +70,13 @@ struct ExecArgs {
     Geometry geo;
     const double *T;     // [2][s][M]
     const double *B0;    // [M][M]
+    const double *Ptab;  // [2 s + 2 kNearRows]: kNearRows - 1 zeros, then the near-field factor P_d
     const double *ahat_top;
     const double *ahat_bot;
     double *w;           // [batch][NT][2][M]
+    unsigned *flags;     // k_fused: [items][NF] ready flags (value = epoch of the launch)
+    unsigned epoch;      // k_fused: launch number; a flag equal to it marks data of this launch
+    int *status;         // k_fused: bit 0 set when a wait ran out of polls
 };
 
 }  // namespace l2c
@@ -85,6 +91,7 @@ struct l2c_plan_s {
     double *d_bot = nullptr;    // far-field table, levels groot+1..L-1 (subtree-major)
     double *d_T = nullptr;      // [2][s][M]
     double *d_B = nullptr;      // [2][M][M] (B(0), B(1))
+    double *d_P = nullptr;      // near-field factor table, see ExecArgs::Ptab
     double *d_XG = nullptr;     // [M] Chebyshev-Gauss points
     double *d_D = nullptr;      // [M][M] cos(k (m+1/2) pi / M)
     double *d_w = nullptr;
@@ -92,12 +99,23 @@ struct l2c_plan_s {
     int64_t top_bytes = 0, bot_bytes = 0;
     int64_t table_bytes = 0;
     hipEvent_t ev_before = nullptr, ev_after = nullptr;
+    // single-launch path (k_fused)
+    bool fused_ok = false;      // geometry, LDS and co-residency allow it
+    bool fused_on = true;       // caller preference (leg2cheb_plan_set_option)
+    int64_t fused_items = 0;    // items per k_fused launch (all workgroups co-resident)
+    unsigned *d_flags = nullptr;  // [fused_items][NF]
+    int *d_status = nullptr;
+    unsigned epoch = 0;
 };
 
 namespace l2c {
 // l2c_exec.hip
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
                           hipStream_t stream);
+// l2c_fused.hip
+bool fused_supported(int M);
+hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items);
+hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream);
 // l2c_plan.hip
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);
@@ -131,6 +149,59 @@ inline int64_t main_lds_doubles(int L, int M, int s, int kd)
 // Staging registers per k_main thread (column-node w and near-field input).
 constexpr int kMainStageW = 9, kMainStageG = 9;
 
+// k_fused (single launch, one workgroup per level-groot subtree, all co-resident).
+// Waves 0 .. kStreamWaves-1 stream the subtree's far-field table; the other waves
+// ("workers", kWorkThreads threads) do everything else.
+constexpr int kFusedThreads = 512;
+constexpr int kStreamWaves = 2;
+constexpr int kWorkThreads = kFusedThreads - 64 * kStreamWaves;   // 384
+constexpr int kWorkWaves = kWorkThreads / 64;                     // 6
+constexpr int kFusedRows = 11;            // near-field rows per work item (3 items per node and parity at s = 31)
+constexpr int kSpinLimit = 1 << 20;       // polls of one wait before it gives up (~1 s)
+constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per worker thread
+
+// Node offset of depth d in the k_fused w buffer: depth 0 is the subtree root alone;
+// depth d >= 1 holds the subtree's 2^d nodes followed by nodes 0, 1 of the next subtree.
+__host__ __device__ inline int fused_wofs(int d) { return d == 0 ? 0 : (1 << d) + 2 * d - 3; }
+
+// Near-field input of k_fused: per parity, the unit's finest nodes plus two of the next
+// unit (step (1) needs both, the near field one), node stride s + gpad.
+__host__ __device__ inline int fused_gpad(int s) { return (s >= 2 * kFusedRows && !(s & 1)) ? 1 : 0; }
+__host__ __device__ inline int fused_qpad(int s) { return s >= 2 * kFusedRows ? 1 : 0; }
+__host__ __device__ inline int64_t fused_gx(int s, int kd)
+{
+    return (int64_t)(s + fused_gpad(s)) * ((1 << kd) + 2) + 2 * kFusedRows + 4;
+}
+__host__ __device__ inline int64_t fused_nq(int s, int kd)
+{
+    return (int64_t)(2 * s + fused_qpad(s)) * ((1 << kd) + 1) + 3 * (int64_t)s + 2 * kFusedRows;
+}
+
+// The near-field area: input, Q and P during the near field; afterwards the top wave's
+// root reduction (8 + 4 nodes), then its ancestor columns and submatrices.
+__host__ __device__ inline int64_t fused_near_area(int L, int M, int s, int kd)
+{
+    const int64_t NS = 2 * M + 1;
+    const int groot = L - 1 - kd;
+    const int64_t near = 2 * fused_gx(s, kd) + fused_nq(s, kd) + 2 * (int64_t)s + 2 * kFusedRows;
+    const int64_t red = 12 * NS;
+    const int64_t anc = 2 * (int64_t)(groot + 1) * (2 * M + (int64_t)M * M);
+    const int64_t top = red > anc ? red : anc;
+    return near > top ? near : top;
+}
+
+// LDS of k_fused (doubles): B(0), T, the near-field area, w (all depths plus neighbour
+// nodes), own c, the root c, the top wave's scratch, a dummy node pair for stores of
+// out-of-range slots, and 4 words of flags/counters.
+inline int64_t fused_lds_doubles(int L, int M, int s, int kd)
+{
+    const int64_t nodes = int64_t(1) << kd, NS = 2 * M + 1;
+    const int64_t WN = fused_wofs(kd + 1), own = 2 * nodes - 2;
+    const int groot = L - 1 - kd;
+    return (int64_t)M * M + 2 * (int64_t)s * M + fused_near_area(L, M, s, kd) + WN * NS + own * NS + NS +
+           4 * (int64_t)M + (int64_t)(groot + 1) * 2 * M + 2 * NS + 2;
+}
+
 // Subtree depths for a plan with L >= 1 levels.
 inline Geometry make_geometry(int L, int M, int s)
 {
@@ -153,8 +224,23 @@ inline Geometry make_geometry(int L, int M, int s)
     const int64_t slots = (((int64_t)1 << g.kd) - 1) * M;
     g.sub_groups = (int)((slots + 63) / 64);
     g.NT = ((int64_t)1 << (L + 2)) - 4;
+    g.NF = node_offset(g.groot + 1);
     return g;
 }
+
+// Local block j of a subtree (finest depth first) -> depth d (1..kd) and index i within
+// the depth: depth d holds j in [2^kd - 2^d, 2^kd - 2^(d-1)).
+__host__ __device__ inline void slot_depth(int j, int kd, int &d, int &i)
+{
+    const unsigned u = (1u << kd) - (unsigned)j;   // in (2^(d-1), 2^d], >= 2
+    d = 32 - __builtin_clz(u - 1u);
+    i = j - ((1 << kd) - (1 << d));
+}
+
+// The near-field factor table of a plan holds kPLead zeros and then P_d for
+// d = 0 .. 2 s + kPLead; a kernel with R rows per item starts reading at kPLead - (R - 1).
+constexpr int kPLead = 15;
+inline int64_t p_table_len(int s) { return 2 * (int64_t)kPLead + 2 * (int64_t)s + 2; }
 
 // First block of level g in the level-major enumeration.
 __host__ __device__ inline int64_t level_block_offset(int g) { return ((int64_t)1 << (g + 1)) - 2 - g; }

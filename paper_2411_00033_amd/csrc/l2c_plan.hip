@@ -34,7 +34,7 @@ __device__ __forceinline__ double *ahat_addr(double *top, double *bot, const Geo
     if (g <= G.groot) return top + ((level_block_offset(g) + b) * 3 + r) * M * M + k * M + l;
     const int d = g - G.groot;                      // depth below the subtree root
     const int64_t Rn = b >> (d - 1);                // subtree of the block
-    const int64_t j = ((int64_t(1) << (d - 1)) - 1) + (b - (Rn << (d - 1)));
+    const int64_t j = ((int64_t(1) << G.kd) - (int64_t(1) << d)) + (b - (Rn << (d - 1)));   // finest depth first
     const int64_t slot = j * M + k;
     const int64_t grp = Rn * G.sub_groups + slot / 64;
     const int lane = (int)(slot % 64);

@@ -85,3 +85,15 @@ def test_null_plan_calls(lib):
     assert L.leg2cheb_plan_info(None, None) == -1
     assert L.leg2cheb_plan_export(None, 0, None, 0, None) == -1
     assert L.leg2cheb_set_timing_events(None, None, None) == -1
+    assert L.leg2cheb_plan_set_option(None, 1, 1) == -1
+    st = ctypes.c_int(7)
+    assert L.leg2cheb_plan_status(None, ctypes.byref(st)) == -1
+
+
+def test_plan_info_layout_matches_header(lib):
+    """PlanInfo mirrors struct l2c_plan_info field by field (names and order)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"struct l2c_plan_info\s*\{(.*?)\};", text, flags=re.S).group(1)
+    fields = re.findall(r"(int32_t|int64_t)\s+(\w+);", body)
+    ours = [(name, ctypes.sizeof(t)) for name, t in lib.PlanInfo._fields_]
+    assert ours == [(n, 4 if t == "int32_t" else 8) for t, n in fields]

@@ -33,14 +33,22 @@ def l2c():
     return mod
 
 
-def run(l2c, f, direction, leaf=64, rank=18):
+def run(l2c, f, direction, leaf=64, rank=18, single=None):
+    """Execute through the C ABI; single=None keeps the plan's default path, True/False forces
+    the single-launch / three-launch path."""
     import torch
     x = torch.from_numpy(np.ascontiguousarray(f)).cuda()
     batch = 1 if x.dim() == 1 else x.shape[0]
     with l2c.Plan(f.shape[-1], direction, leaf, rank, max_batch=batch) as p:
+        if single is not None and p.info["levels"] > 0:
+            p.set_single_launch(single)
         z = p.execute(x)
         torch.cuda.synchronize()
-        return z.cpu().numpy(), p.info
+        info = p.info
+        assert p.status == 0
+        if single is not None and info["levels"] > 0:
+            assert info["path"] == (l2c.L2C_PATH_SINGLE if single else l2c.L2C_PATH_THREE)
+        return z.cpu().numpy(), info
 
 
 # ----------------------------------------------------------------- plan tables
@@ -65,14 +73,40 @@ def test_plan_tables_match_reference(l2c):
 SIZES = [1, 2, 3, 7, 64, 127, 128, 129, 255, 256, 257, 500, 1000, 1024, 1025, 2049, 4096, 5000, 16384, 40000]
 
 
+def _single_ok(l2c, n, direction=0, leaf=64, rank=18):
+    with l2c.Plan(n, direction, leaf, rank) as p:
+        return p.info["path"] == l2c.L2C_PATH_SINGLE
+
+
+@pytest.mark.parametrize("single", [True, False])
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("direction", [0, 1])
-def test_parity_sizes(l2c, n, direction):
+def test_parity_sizes(l2c, n, direction, single):
     f = inputs.decaying(n, 1.0, inputs.SEED_BASE + 100 + n)
-    z, info = run(l2c, f, direction)
+    if single and not _single_ok(l2c, n, direction):
+        pytest.skip("no single-launch form for n=%d (L <= 1)" % n)
+    z, info = run(l2c, f, direction, single=single if info_levels(l2c, n) > 0 else None)
     err = oracle.einf(z, oracle.transform(f, direction))
-    print("n=%d dir=%d L=%d s=%d E_inf=%.3e" % (n, direction, info["levels"], info["s"], err))
+    print("n=%d dir=%d L=%d s=%d path=%d E_inf=%.3e" % (n, direction, info["levels"], info["s"], info["path"], err))
     assert err <= TOL[(direction, 18)]
+
+
+def info_levels(l2c, n, leaf=64, rank=18):
+    with l2c.Plan(n, 0, leaf, rank) as p:
+        return p.info["levels"]
+
+
+@pytest.mark.parametrize("n", [257, 1024, 5000, 40000, 300000])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_paths_agree(l2c, n, direction):
+    """Single-launch and three-launch paths: same tables, same arithmetic up to summation order."""
+    f = inputs.decaying(n, 0.5, inputs.SEED_BASE + 400 + n)
+    z1, i1 = run(l2c, f, direction, single=True)
+    z3, i3 = run(l2c, f, direction, single=False)
+    assert i1["path"] == l2c.L2C_PATH_SINGLE and i3["path"] == l2c.L2C_PATH_THREE
+    d = np.max(np.abs(z1 - z3)) / np.max(np.abs(z3))
+    print("n=%d dir=%d paths differ by %.3e" % (n, direction, d))
+    assert d <= 1e-14
 
 
 @pytest.mark.parametrize("leaf", [4, 8, 16, 32, 40, 128])
@@ -169,6 +203,38 @@ def test_edge_cases(l2c):
     torch.cuda.synchronize()
 
 
+def test_single_launch_repeats_batches_and_streams(l2c):
+    """Epoch-tagged flags across repeated executes, batches split over several launches
+    (n = 40000: 16 units per item, 16 items per launch), and two plans on two streams."""
+    import torch
+    n, batch = 40000, 40
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 17, batch=batch)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, 0, max_batch=1) as p:
+        assert p.info["path"] == l2c.L2C_PATH_SINGLE
+        z0 = p.execute(x).cpu().numpy()
+        for _ in range(3):
+            assert np.array_equal(p.execute(x).cpu().numpy(), z0)
+        assert p.status == 0
+    for b in (0, 15, 16, 39):
+        assert oracle.einf(z0[b], oracle.leg2cheb(F[b])) <= 1e-13
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    f1, f2 = x[0].clone(), x[1].clone()
+    with l2c.Plan(n, 0) as pa, l2c.Plan(n, 1) as pb:
+        outs = []
+        for _ in range(4):
+            with torch.cuda.stream(s1):
+                outs.append(("a", pa.execute(f1, stream=s1)))
+            with torch.cuda.stream(s2):
+                outs.append(("b", pb.execute(f2, stream=s2)))
+        torch.cuda.synchronize()
+        assert pa.status == 0 and pb.status == 0
+        ra, rb = oracle.leg2cheb(F[0]), oracle.cheb2leg(F[1])
+        for tag, z in outs:
+            ref = ra if tag == "a" else rb
+            assert oracle.einf(z.cpu().numpy(), ref) <= TOL[(0 if tag == "a" else 1, 18)]
+
+
 def test_workspace_grows_with_batch(l2c):
     import torch
     n = 2000
@@ -193,14 +259,15 @@ def _sample_rows(n, info, rng):
     return np.array(sorted(r for r in rows if 0 <= r < n), dtype=np.int64)
 
 
+@pytest.mark.parametrize("single", [True, False])
 @pytest.mark.parametrize("direction", [0, 1])
-def test_config2_million_sampled(l2c, direction):
+def test_config2_million_sampled(l2c, direction, single):
     """N = 10^6, f_j = z_j/sqrt(j+1): sampled rows against the oracle; the full output
     against the independent invariants sum_i z_i = sum_j f_j (x = 1) and the alternating sums (x = -1)."""
     import torch
     n = 10 ** 6
     f = inputs.decaying(n, 0.5, inputs.SEED_BASE + 2)
-    z, info = run(l2c, f, direction)
+    z, info = run(l2c, f, direction, single=single)
     assert (info["levels"], info["s"], info["n_pad"]) == (13, 31, 1015808)
     rows = _sample_rows(n, info, np.random.default_rng(5))
     ref = oracle.transform(f, direction, rows)
