@@ -14,19 +14,21 @@
 //
 // Inside a workgroup the waves specialise.
 //   Streamers (waves 0, 1) read the unit's far-field table (the dominant HBM traffic)
-//   from the first cycle, one 64-slot group (27.6 KiB at M = 18) in flight per wave:
+//   once the workers' staging loads are out, one 64-slot group (27.6 KiB at M = 18) in
+//   flight per wave:
 //   enough to keep HBM busy without queueing requests so deep that every other memory
 //   access of the kernel waits behind them.  The table is laid out finest depth first,
 //   and a group is multiplied (step (3)) as soon as the workers flag its depths ready.
 //   Workers (waves 2..7) stage the input, B(0), T and the near-field tables; step (1)
 //   for the unit's finest nodes (and two of the next unit); step (2) inside the unit,
 //   flagging each depth; publish the root and nodes 0, 1 of every coarser depth; fetch
-//   the next unit's nodes; step (6), the near field.  Then the last worker wave does
-//   step (2) above the units (the leftmost unit below an ancestor reduces the nodes
-//   under it, three levels per exchange, and publishes it), the far-field blocks of the
-//   unit's ancestors (step (3), top table), and the downward chain from level 0 to the
-//   unit root (step (4)).  Workers synchronise through an LDS counter, streamers poll
-//   LDS flags; there is no hardware barrier between the first and the last phase.
+//   the next unit's nodes (one wave); step (6), the near field (four waves).  Meanwhile
+//   the last worker wave does step (2) above the units (the leftmost unit below an
+//   ancestor reduces the nodes under it, three levels per exchange, and publishes it),
+//   then, once the near field is done, the far-field blocks of the unit's ancestors
+//   (step (3), top table), and the downward chain from level 0 to the unit root
+//   (step (4)).  Workers synchronise through LDS counters, streamers poll LDS flags;
+//   there is no hardware barrier between the first and the last phase.
 //   Then all waves: step (4) inside the unit, steps (5) and (7), and the output.
 // A wait that never completes (another kernel holding CUs forever) gives up after
 // kSpinLimit polls and sets a status bit; the launch then ends with a wrong result
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     double *w7 = cR + NS;                             // top wave: z [2 x 2M], canc [(G0+1) x 2M]
     double *dummy = w7 + 4 * M + (G0 + 1) * M2;       // 2 NS: stores of out-of-range slots
     unsigned *sync = reinterpret_cast<unsigned *>(dummy + 2 * NS);
-    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2;
+    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *ndone = sync + 3;
 
     const double *in = a.in + item * a.n;
     double *wg = a.w + item * G.NT * M2;              // published nodes, workspace layout
@@ -268,7 +270,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
     if (streamer) {
-        // ---- streamers: first group in flight (rows r = 0, 1, 2 of 64 slots), then step (3)
+        // ---- streamers: the first group goes in flight after the workers' staging loads
+        //      (issued first, they would queue behind it), then step (3)
+        __syncthreads();                              // with the workers' barrier after staging
         double2 t0[NC3], t1[NC3], t2[NC3];
         if (wv < G.sub_groups) {
 #pragma unroll
@@ -278,7 +282,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 #pragma unroll
             for (int c = 0; c < NC3; ++c) t2[c] = sub[(wv * NCH + 2 * NC3 + c) * 64];
         }
-        __syncthreads();                              // with the workers' barrier after staging
         int grp = wv;
 #pragma unroll 1
         for (; grp + NSW < G.sub_groups; grp += NSW)
@@ -356,6 +359,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             wcnt[0] = 0;
             rdy[0] = (unsigned)kd + 1;                // no depth ready yet
             nbr[0] = 0;
+            ndone[0] = 0;
         }
         __syncthreads();                              // with the streamers' barrier below
         L2C_TS(3, 1);
@@ -365,7 +369,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         //      group are loaded as soon as the same row of this group has been used.
         // ---- step (1): w_k(t, sigma) = sum_m T_k(X_m^sigma) f[2s t + 2m + sigma] (Eq. (wMM))
         //      for the unit's finest nodes and the next unit's first two (its finest-depth
-        //      neighbours).  Worker wave -> (sigma, third of k); lane -> node.  The last
+        //      neighbours).  Worker wave -> (sigma, third of k), so a T value is the same for
+        //      the whole wave (LDS broadcast); lane -> nodes lane and lane + H, H = half the
+        //      node count rounded up, so every T value read feeds two products.  The last
         //      third repeats k = M-1 in its spare slots (no branches in the loop).
         {
             constexpr int KT = (M + 2) / 3;
@@ -374,27 +380,30 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             int kc[KT];
 #pragma unroll
             for (int kk = 0; kk < KT; ++kk) kc[kk] = kb + kk < M ? kb + kk : M - 1;
-            for (int nd = lane; nd < nodes + 2; nd += 64) {
-                double sacc[KT];
+            const int nall = nodes + 2, H = (nall + 1) >> 1;
+            for (int n0 = lane; n0 < H; n0 += 64) {
+                const int n1 = n0 + H < nall ? n0 + H : n0;     // odd count: the last lane repeats
+                double a0[KT], a1[KT];
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk) sacc[kk] = 0.0;
-                const double *fr = gp + sig * GX + nd * GS;
-                int m = 0;
-                for (; m + 2 <= s; m += 2) {
-                    const double f0 = fr[m], f1 = fr[m + 1];
+                for (int kk = 0; kk < KT; ++kk) a0[kk] = a1[kk] = 0.0;
+                const double *f0 = gp + sig * GX + n0 * GS, *f1 = gp + sig * GX + n1 * GS;
+                for (int m = 0; m < s; ++m) {
+                    const double x0 = f0[m], x1 = f1[m];
 #pragma unroll
-                    for (int kk = 0; kk < KT; ++kk)
-                        sacc[kk] = fma(Ts[(m + 1) * M + kc[kk]], f1, fma(Ts[m * M + kc[kk]], f0, sacc[kk]));
+                    for (int kk = 0; kk < KT; ++kk) {
+                        const double t = Ts[m * M + kc[kk]];
+                        a0[kk] = fma(t, x0, a0[kk]);
+                        a1[kk] = fma(t, x1, a1[kk]);
+                    }
                 }
-                if (m < s) {
-                    const double f0 = fr[m];
-#pragma unroll
-                    for (int kk = 0; kk < KT; ++kk) sacc[kk] = fma(Ts[m * M + kc[kk]], f0, sacc[kk]);
-                }
-                double *wo = wl + (fused_wofs(kd) + nd) * NS + sig * M;   // nodes >= 2^kd: neighbour slots
+                double *w0 = wl + (fused_wofs(kd) + n0) * NS + sig * M;   // nodes >= 2^kd: neighbour slots
+                double *w1 = wl + (fused_wofs(kd) + n1) * NS + sig * M;
 #pragma unroll
                 for (int kk = 0; kk < KT; ++kk)
-                    if (kb + kk < M) wo[kb + kk] = sacc[kk];
+                    if (kb + kk < M) {
+                        w0[kb + kk] = a0[kk];
+                        w1[kb + kk] = a1[kk];
+                    }
             }
         }
         worker_sync(wcnt, wtarget, a.status);
@@ -460,7 +469,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         //      over m' in [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig], with P, Q
         //      and g entering through circular register windows; the sums stay in registers
         //      until the leaf evaluation.
-        if (wt < nwork) {
+        if (ww < kNearWaves && wt < nwork) {
             const int nd = wt % nodes, x = wt / nodes;
             const int sig = x & 1, m0 = (x >> 1) * R;
             const double *gs = gp + sig * GX + nd * GS;
@@ -492,7 +501,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
-        worker_sync(wcnt, wtarget, a.status);        // the near-field area is free from here on
+        if (ww < kNearWaves) {
+            wave_lds_done();                          // the near-field area is free once all have counted
+            if (lane == 0) __hip_atomic_fetch_add(ndone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         L2C_TS(3, 4);
         if (ww == kWorkWaves - 1) {
         // ---- top wave; lane (sg, nn) <-> parity and mode
@@ -518,7 +530,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 const int gin = G0 - jdone;                      // input level
                 const int nin = 1 << (jn - jdone);               // input nodes t0 .. t0 + nin - 1
                 const int64_t t0 = (int64_t)X >> jdone;
-                double *src = gp, *dst = gp + nin * NS;          // ping-pong node buffers
+                double *src = Tl, *dst = Tl + nin * NS;          // ping-pong node buffers (T area)
                 {
                     bool done = lane >= nin - 1;                 // lane i waits for node t0 + 1 + i
                     for (int it = 0; it < kSpinLimit; ++it) {
@@ -571,45 +583,69 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 wave_lds_sync();
             }
         }
-        // step (3) for the ancestors a_g = X >> (G0 - g), g = 0..G0 (top table).  Level g
-        // uses column slots 2g (node a_g + 2) and 2g + 1 (node a_g + 3, p = 0 only) and the
-        // submatrices r = 2p, and r = 1 for p = 0.  All loads go out in a few blocks: the
-        // Ahat submatrices first (plan data), then, once every column node is flagged, the
-        // column vectors; the products then read LDS only.
+        // T back into its area (the leaf evaluation needs it) and the ancestors' submatrices
+        // (step (3) below) in one batch of loads; then wait until the near field has
+        // released the near-field area.  Slot sl = 2g + h of level g holds submatrix r = 2p
+        // (h = 0, column node a_g + 2) or r = 1 (h = 1, p = 0 only, column node a_g + 3).
+        const int nsl = 2 * (G0 + 1);
+        auto slot_ok = [&](int sl) -> bool {
+            const int g = sl >> 1;
+            const int64_t an = (int64_t)X >> (G0 - g);
+            return an < (int64_t(1) << (g + 2)) - 2 && ((sl & 1) == 0 || (an & 1) == 0);
+        };
+        auto slot_node = [&](int sl) -> int64_t {
+            const int g = sl >> 1;
+            return node_offset(g) + ((int64_t)X >> (G0 - g)) + 2 + (sl & 1);
+        };
+        constexpr int UAT = (14 * M * M + 63) / 64;   // groot <= 6: at most 14 slots
+        constexpr int UTT = (2 * 33 * M + 63) / 64;   // 2 s M, s <= 33
+        double va[UAT];
         {
-            const int nsl = 2 * (G0 + 1);
+            double vt[UTT];
+#pragma unroll
+            for (int u = 0; u < UTT; ++u) {
+                const int e = u * 64 + lane;
+                vt[u] = e < 2 * s * M ? a.T[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UAT; ++u) {
+                const int idx = u * 64 + lane;
+                const int sl = idx / (M * M), e = idx - sl * (M * M);
+                double x = 0.0;
+                if (idx < nsl * M * M && slot_ok(sl)) {
+                    const int g = sl >> 1;
+                    const int64_t an = (int64_t)X >> (G0 - g);
+                    const int r = (sl & 1) ? 1 : 2 * (int)(an & 1);
+                    x = a.ahat_top[((level_block_offset(g) + (an >> 1)) * 3 + r) * M * M + e];
+                }
+                va[u] = x;
+            }
+#pragma unroll
+            for (int u = 0; u < UTT; ++u) {
+                const int e = u * 64 + lane;
+                if (e < 2 * s * M) Tl[e] = vt[u];
+            }
+            if (lane == 0) {
+                int it = 0;
+                while (lds_flag_get(ndone) < (unsigned)kNearWaves) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++it == kSpinLimit) {
+                        atomicOr(a.status, 2);
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        // step (3) for the ancestors a_g = X >> (G0 - g), g = 0..G0 (top table), from LDS once
+        // every column node is flagged and loaded
+        {
             double *colw = gp;                             // nsl x 2M
             double *atop = gp + nsl * M2;                  // nsl x M x M
-            auto slot_ok = [&](int sl) -> bool {
-                const int g = sl >> 1;
-                const int64_t an = (int64_t)X >> (G0 - g);
-                return an < (int64_t(1) << (g + 2)) - 2 && ((sl & 1) == 0 || (an & 1) == 0);
-            };
-            auto slot_node = [&](int sl) -> int64_t {
-                const int g = sl >> 1;
-                return node_offset(g) + ((int64_t)X >> (G0 - g)) + 2 + (sl & 1);
-            };
-            // Ahat: slot sl holds submatrix r = 2p (sl even) or r = 1 (sl odd) of block a_g >> 1
-            for (int base = 0; base < nsl * M * M; base += 24 * 64) {
-                double v[24];
 #pragma unroll
-                for (int u = 0; u < 24; ++u) {
-                    const int idx = base + u * 64 + lane;
-                    const int sl = idx / (M * M), e = idx - sl * (M * M);
-                    double x = 0.0;
-                    if (idx < nsl * M * M && slot_ok(sl)) {
-                        const int g = sl >> 1;
-                        const int64_t an = (int64_t)X >> (G0 - g);
-                        const int r = (sl & 1) ? 1 : 2 * (int)(an & 1);
-                        x = a.ahat_top[((level_block_offset(g) + (an >> 1)) * 3 + r) * M * M + e];
-                    }
-                    v[u] = x;
-                }
-#pragma unroll
-                for (int u = 0; u < 24; ++u) {
-                    const int idx = base + u * 64 + lane;
-                    if (idx < nsl * M * M) atop[idx] = v[u];
-                }
+            for (int u = 0; u < UAT; ++u) {
+                const int idx = u * 64 + lane;
+                if (idx < nsl * M * M) atop[idx] = va[u];
             }
             // every column node flagged (lane sl polls slot sl)
             {
@@ -703,34 +739,42 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     // ---- steps (5) and (7): z = sum_k T_k(X_m^sig) c(u)[sig][k] (row nodes u < P - 2)
     //      + rs * near; leg2cheb divides by c_i pi/2
     double *out = a.out + item * a.n;
-    if (!streamer && wt < nwork) {
-        const int nd = wt % nodes, x = wt / nodes;
-        const int sig = x & 1, m0 = (x >> 1) * R;
-        const bool far = u0 + nd < P - 2;
-        double cc[M];
-        const double *cs = cfine + nd * NS + sig * M;
+    if (!streamer && ww < kNearWaves && wt < nwork) {
+        auto eval = [&](int nd, int sig, int m0) {
+            const bool far = u0 + nd < P - 2;
+            double cc[M];
+            const double *cs = cfine + nd * NS + sig * M;
 #pragma unroll
-        for (int k = 0; k < M; ++k) cc[k] = cs[k];
+            for (int k = 0; k < M; ++k) cc[k] = cs[k];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int m = m0 + r;
-            if (m < s) {
-                double z = 0.0;
-                if (far) {
-                    const double *tt = Tl + (sig * s + m) * M;
+            for (int r = 0; r < R; ++r) {
+                const int m = m0 + r;
+                if (m < s) {
+                    double z = 0.0;
+                    if (far) {
+                        const double *tt = Tl + (sig * s + m) * M;
 #pragma unroll
-                    for (int k = 0; k < M; ++k) z = fma(tt[k], cc[k], z);
+                        for (int k = 0; k < M; ++k) z = fma(tt[k], cc[k], z);
+                    }
+                    const int64_t i = jb + nd * 2 * s + 2 * m + sig;
+                    double v = acc[r];
+                    if (dir == 1) {
+                        v *= 2.0 * (double)i + 1.0;
+                        if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
+                    }
+                    v += z;
+                    if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
+                    if (i < a.n) out[i] = v;
                 }
-                const int64_t i = jb + nd * 2 * s + 2 * m + sig;
-                double v = acc[r];
-                if (dir == 1) {
-                    v *= 2.0 * (double)i + 1.0;
-                    if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
-                }
-                v += z;
-                if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
-                if (i < a.n) out[i] = v;
             }
+        };
+        if (nodes == 64) {
+            // a wave holds one (parity, row block) for 64 nodes: T rows are wave-uniform
+            const int x = __builtin_amdgcn_readfirstlane(ww);
+            eval(lane, x & 1, (x >> 1) * R);
+        } else {
+            const int x = wt / nodes;
+            eval(wt % nodes, x & 1, (x >> 1) * R);
         }
     }
     L2C_TS(3, 7);
@@ -768,7 +812,9 @@ hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items)
     const Geometry &G = p.geo;
     if (p.L < 2 || G.kd < 1 || !fused_supported(p.M)) return hipSuccess;
     const int nodes = 1 << G.kd, R = kFusedRows;
-    if (nodes * 2 * ((G.s + R - 1) / R) > kWorkThreads) return hipSuccess;              // near-field items
+    if (nodes * 2 * ((G.s + R - 1) / R) > 64 * kNearWaves) return hipSuccess;          // near-field items
+    if (12 * (2 * G.M + 1) > 2 * G.s * G.M) return hipSuccess;                         // hop scratch in T area
+    if (G.s > 33 || G.groot > 6) return hipSuccess;                                      // top wave's load batches
     if (2 * (G.s * (nodes + 2) + R) > kFusedStageG * kWorkThreads) return hipSuccess;  // input staging
     if (2 * G.s * G.M > kFusedStageT * kWorkThreads) return hipSuccess;                // T staging
     if (2 * G.s + 2 * R > kWorkThreads) return hipSuccess;                             // P staging

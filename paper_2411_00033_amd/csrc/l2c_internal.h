@@ -153,10 +153,11 @@ constexpr int kMainStageW = 9, kMainStageG = 9;
 // Waves 0 .. kStreamWaves-1 stream the subtree's far-field table; the other waves
 // ("workers", kWorkThreads threads) do everything else.
 constexpr int kFusedThreads = 512;
-constexpr int kStreamWaves = 2;
-constexpr int kWorkThreads = kFusedThreads - 64 * kStreamWaves;   // 384
-constexpr int kWorkWaves = kWorkThreads / 64;                     // 6
-constexpr int kFusedRows = 11;            // near-field rows per work item (3 items per node and parity at s = 31)
+constexpr int kStreamWaves = 1;
+constexpr int kWorkThreads = kFusedThreads - 64 * kStreamWaves;   // 448
+constexpr int kWorkWaves = kWorkThreads / 64;                     // 7
+constexpr int kFusedRows = 16;            // near-field rows per work item (2 items per node and parity at s = 31)
+constexpr int kNearWaves = 4;             // worker waves that run the near field (one item per thread)
 constexpr int kSpinLimit = 1 << 20;       // polls of one wait before it gives up (~1 s)
 constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per worker thread
 
@@ -165,9 +166,13 @@ constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per wo
 __host__ __device__ inline int fused_wofs(int d) { return d == 0 ? 0 : (1 << d) + 2 * d - 3; }
 
 // Near-field input of k_fused: per parity, the unit's finest nodes plus two of the next
-// unit (step (1) needs both, the near field one), node stride s + gpad.
-__host__ __device__ inline int fused_gpad(int s) { return (s >= 2 * kFusedRows && !(s & 1)) ? 1 : 0; }
-__host__ __device__ inline int fused_qpad(int s) { return s >= 2 * kFusedRows ? 1 : 0; }
+// unit (step (1) needs both, the near field one), node stride s + gpad; Q with node
+// stride 2s + qpad.  A pad keeps the 64 lanes of a wave (64 nodes) on distinct banks.
+// The near-field loop reads column m' < 2s + R - 1 of g (two node boundaries at most
+// when R <= s + 1) and Q offsets c < 3s + 2R - 2 (one boundary when 2R - 3 < s); pads
+// are used only where those bounds hold.
+__host__ __device__ inline int fused_gpad(int s) { return (!(s & 1) && kFusedRows <= s + 1) ? 1 : 0; }
+__host__ __device__ inline int fused_qpad(int s) { return 2 * kFusedRows - 3 < s ? 1 : 0; }
 __host__ __device__ inline int64_t fused_gx(int s, int kd)
 {
     return (int64_t)(s + fused_gpad(s)) * ((1 << kd) + 2) + 2 * kFusedRows + 4;
@@ -178,16 +183,13 @@ __host__ __device__ inline int64_t fused_nq(int s, int kd)
 }
 
 // The near-field area: input, Q and P during the near field; afterwards the top wave's
-// root reduction (8 + 4 nodes), then its ancestor columns and submatrices.
+// ancestor columns and submatrices, 2 (groot+1) x (2M + M^2).
 __host__ __device__ inline int64_t fused_near_area(int L, int M, int s, int kd)
 {
-    const int64_t NS = 2 * M + 1;
     const int groot = L - 1 - kd;
     const int64_t near = 2 * fused_gx(s, kd) + fused_nq(s, kd) + 2 * (int64_t)s + 2 * kFusedRows;
-    const int64_t red = 12 * NS;
     const int64_t anc = 2 * (int64_t)(groot + 1) * (2 * M + (int64_t)M * M);
-    const int64_t top = red > anc ? red : anc;
-    return near > top ? near : top;
+    return near > anc ? near : anc;
 }
 
 // LDS of k_fused (doubles): B(0), T, the near-field area, w (all depths plus neighbour
