@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     double *w7 = cR + NS;                             // top wave: z [2 x 2M], canc [(G0+1) x 2M]
     double *dummy = w7 + 4 * M + (G0 + 1) * M2;       // 2 NS: stores of out-of-range slots
     unsigned *sync = reinterpret_cast<unsigned *>(dummy + 2 * NS);
-    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *ndone = sync + 3;
+    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *ndone = sync + 3, *qdone = sync + 4;
 
     const double *in = a.in + item * a.n;
     double *wg = a.w + item * G.NT * M2;              // published nodes, workspace layout
@@ -312,29 +312,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             vb[u] = e < M * M ? a.B0[e] : 0.0;
         }
         const double vp = wt < nP ? a.Ptab[wt + kPLead - (R - 1)] : 0.0;
-        // Q in runs of 8 consecutive S: the first value from Eq. (tau), then the exact ratio
-        // Q_{S+1}/Q_S: (2S+1)/(2S+2) for leg2cheb (Eq. (Lambdaint)), 2S/(2S+3) for cheb2leg
-        {
-            const int QL = 2 * s * nodes + 3 * s + 2 * R;
-            for (int run = wt; run * 8 < QL; run += NWT) {
-                const int x0 = run * 8;
-                int node = x0 / (2 * s), c = x0 - node * 2 * s;
-                int64_t S = jb + x0;
-                double q = near_Q(dir, S);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if (x0 + i < QL) Ql[node * QS + c] = q;
-                    const double Sd = (double)S;
-                    q = dir == 0 ? q * ((2.0 * Sd + 1.0) / (2.0 * Sd + 2.0))
-                                 : (S == 0 ? near_Q(dir, 1) : q * ((2.0 * Sd) / (2.0 * Sd + 3.0)));
-                    ++S;
-                    if (++c == 2 * s) {
-                        c = 0;
-                        ++node;
-                    }
-                }
-            }
-        }
         if (wt < nP) Pl[wt] = vp;
 #pragma unroll
         for (int u = 0; u < UT; ++u) {
@@ -360,6 +337,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             rdy[0] = (unsigned)kd + 1;                // no depth ready yet
             nbr[0] = 0;
             ndone[0] = 0;
+            qdone[0] = 0;
         }
         __syncthreads();                              // with the streamers' barrier below
         L2C_TS(3, 1);
@@ -387,6 +365,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 #pragma unroll
                 for (int kk = 0; kk < KT; ++kk) a0[kk] = a1[kk] = 0.0;
                 const double *f0 = gp + sig * GX + n0 * GS, *f1 = gp + sig * GX + n1 * GS;
+#pragma unroll 4
                 for (int m = 0; m < s; ++m) {
                     const double x0 = f0[m], x1 = f1[m];
 #pragma unroll
@@ -449,6 +428,46 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             if (wt == 0) set_flag(fl + node_offset(G0) + X, a.epoch);
         }
         L2C_TS(3, 3);
+        // ---- near-field Q table (off the path to the published root), by the near waves
+        if (ww < kNearWaves) {
+            // Q in runs of 8 consecutive S: the first value from Eq. (tau), then the exact ratio
+            // Q_{S+1}/Q_S: (2S+1)/(2S+2) for leg2cheb (Eq. (Lambdaint)), 2S/(2S+3) for cheb2leg
+            {
+                const int QL = 2 * s * nodes + 3 * s + 2 * R;
+                for (int run = wt; run * 8 < QL; run += 64 * kNearWaves) {
+                    const int x0 = run * 8;
+                    int node = x0 / (2 * s), c = x0 - node * 2 * s;
+                    int64_t S = jb + x0;
+                    double q = near_Q(dir, S);
+    #pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        if (x0 + i < QL) Ql[node * QS + c] = q;
+                        const double Sd = (double)S;
+                        q = dir == 0 ? q * ((2.0 * Sd + 1.0) / (2.0 * Sd + 2.0))
+                                     : (S == 0 ? near_Q(dir, 1) : q * ((2.0 * Sd) / (2.0 * Sd + 3.0)));
+                        ++S;
+                        if (++c == 2 * s) {
+                            c = 0;
+                            ++node;
+                        }
+                    }
+                }
+            }
+            // the near waves' own barrier: Q complete before any of them reads it
+            wave_lds_done();
+            if (lane == 0) {
+                __hip_atomic_fetch_add(qdone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                int it = 0;
+                while (lds_flag_get(qdone) < (unsigned)kNearWaves) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++it == kSpinLimit) {
+                        atomicOr(a.status, 2);
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
         // ---- nodes 0, 1 of the next unit at depths 1..kd-1 (one worker wave; the streamers
         //      wait for this only when they reach those depths)
         if (ww == kWorkWaves - 2) {

@@ -156,8 +156,8 @@ constexpr int kFusedThreads = 512;
 constexpr int kStreamWaves = 1;
 constexpr int kWorkThreads = kFusedThreads - 64 * kStreamWaves;   // 448
 constexpr int kWorkWaves = kWorkThreads / 64;                     // 7
-constexpr int kFusedRows = 16;            // near-field rows per work item (2 items per node and parity at s = 31)
-constexpr int kNearWaves = 4;             // worker waves that run the near field (one item per thread)
+constexpr int kFusedRows = 11;            // near-field rows per work item (3 items per node and parity at s = 31)
+constexpr int kNearWaves = 6;             // worker waves that run the near field (one item per thread)
 constexpr int kSpinLimit = 1 << 20;       // polls of one wait before it gives up (~1 s)
 constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per worker thread
 
@@ -194,14 +194,14 @@ __host__ __device__ inline int64_t fused_near_area(int L, int M, int s, int kd)
 
 // LDS of k_fused (doubles): B(0), T, the near-field area, w (all depths plus neighbour
 // nodes), own c, the root c, the top wave's scratch, a dummy node pair for stores of
-// out-of-range slots, and 4 words of flags/counters.
+// out-of-range slots, and 8 words of flags/counters.
 inline int64_t fused_lds_doubles(int L, int M, int s, int kd)
 {
     const int64_t nodes = int64_t(1) << kd, NS = 2 * M + 1;
     const int64_t WN = fused_wofs(kd + 1), own = 2 * nodes - 2;
     const int groot = L - 1 - kd;
     return (int64_t)M * M + 2 * (int64_t)s * M + fused_near_area(L, M, s, kd) + WN * NS + own * NS + NS +
-           4 * (int64_t)M + (int64_t)(groot + 1) * 2 * M + 2 * NS + 2;
+           4 * (int64_t)M + (int64_t)(groot + 1) * 2 * M + 2 * NS + 4;
 }
 
 // Subtree depths for a plan with L >= 1 levels.
