@@ -118,7 +118,7 @@ void free_plan(l2c_plan_s *p)
     (void)hipFree(p->d_XG);
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_w);
-    (void)hipFree(p->d_flags);
+    (void)hipFree(p->d_pub);
     (void)hipFree(p->d_status);
     delete p;
 }
@@ -245,9 +245,10 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             items = 0;
         }
         if (items > 0) {
-            const size_t fbytes = (size_t)items * p->geo.NF * sizeof(unsigned);
-            ok = hipMalloc(&p->d_flags, fbytes) == hipSuccess && hipMalloc(&p->d_status, sizeof(int)) == hipSuccess &&
-                 hipMemsetAsync(p->d_flags, 0, fbytes, st) == hipSuccess &&
+            // both halves of the exchange buffer start out "not written"
+            const size_t pwords = (size_t)2 * items * p->geo.NX * 2 * p->M * 2;
+            ok = hipMalloc(&p->d_pub, pwords * 4) == hipSuccess && hipMalloc(&p->d_status, sizeof(int)) == hipSuccess &&
+                 hipMemsetD32Async((hipDeviceptr_t)p->d_pub, (int)l2c::kPubEmptyHalf, pwords, st) == hipSuccess &&
                  hipMemsetAsync(p->d_status, 0, sizeof(int), st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
             if (!ok) {
                 (void)hipGetLastError();

@@ -183,21 +183,18 @@ __device__ __forceinline__ void down_level(const double *par, double *cur, int c
 // Up: out_n = sum_k b_nk x_k + sum_k (-1)^(n-k) b_nk y_k for children x = w(2T), y = w(2T+1)
 // (the same as B(0) x + B(1) y).  With brow[k] = b_nk (zero for k > n) and the y sums
 // split by the parity of k, out_n = X + (-1)^n (Y_even - Y_odd): no selects in the loop.
+// Four partial sums per product (k mod 4) keep the dependent FMA chains short.
 template <int M>
 __device__ __forceinline__ double up_pair(const double (&brow)[M], const double *x, const double *y, int n)
 {
-    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < M; k += 2) {
-        a0 = fma(brow[k], x[k], a0);
-        b0 = fma(brow[k], y[k], b0);
-        if (k + 1 < M) {
-            a1 = fma(brow[k + 1], x[k + 1], a1);
-            b1 = fma(brow[k + 1], y[k + 1], b1);
-        }
+    for (int k = 0; k < M; ++k) {
+        a[k & 3] = fma(brow[k], x[k], a[k & 3]);
+        b[k & 3] = fma(brow[k], y[k], b[k & 3]);
     }
-    const double ys = b0 - b1;
-    return (a0 + a1) + ((n & 1) ? -ys : ys);
+    const double ys = (b[0] + b[2]) - (b[1] + b[3]);
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((n & 1) ? -ys : ys);
 }
 
 template <int M>

@@ -7,26 +7,27 @@
 //     nodes past its right edge, Eq. (globalij)); at the finest depth it computes them
 //     itself from the input, at coarser depths it reads them, and
 //   * the upward vectors of levels 0..groot, which combine every unit's root.
-// Both travel through the workspace with per-node ready flags.  Every flag holds the
-// number ("epoch") of the launch that last wrote the node, so flags never need clearing.
-// The data are written and read with device-coherent accesses, and a flag is set only
-// after the writes it covers have completed; nothing else crosses workgroups.
+// Both travel through an exchange buffer of two halves, used by alternate launches.  A
+// value not yet written holds a signalling NaN that no arithmetic produces, so a reader
+// polls the data itself: once no value it loaded is that NaN, it has all of them (64-bit
+// device-coherent stores and loads are single-copy atomic).  Each unit resets its own
+// nodes in the other half for the next launch.  Nothing else crosses workgroups.
 //
 // Inside a workgroup the waves specialise.
-//   Streamers (waves 0, 1) read the unit's far-field table (the dominant HBM traffic)
+//   The streamer (wave 0) reads the unit's far-field table (the dominant HBM traffic)
 //   once the workers' staging loads are out, one 64-slot group (27.6 KiB at M = 18) in
-//   flight per wave:
-//   enough to keep HBM busy without queueing requests so deep that every other memory
-//   access of the kernel waits behind them.  The table is laid out finest depth first,
-//   and a group is multiplied (step (3)) as soon as the workers flag its depths ready.
-//   Workers (waves 2..7) stage the input, B(0), T and the near-field tables; step (1)
-//   for the unit's finest nodes (and two of the next unit); step (2) inside the unit,
-//   flagging each depth; publish the root and nodes 0, 1 of every coarser depth; fetch
-//   the next unit's nodes (one wave); step (6), the near field (four waves).  Meanwhile
+//   flight: enough to keep HBM busy without queueing requests so deep that every other
+//   memory access of the kernel waits behind them.  The table is laid out finest depth
+//   first, and a group is multiplied (step (3)) as soon as the workers flag its depths
+//   ready.  Workers (waves 1..7) stage the input, B(0), T and the near-field tables;
+//   step (1) for the unit's finest nodes (and two of the next unit); step (2) inside the
+//   unit, flagging each depth; publish the root and nodes 0, 1 of every coarser depth;
+//   fetch the next unit's nodes (one wave); step (6), the near field (six waves).  Meanwhile
 //   the last worker wave does step (2) above the units (the leftmost unit below an
-//   ancestor reduces the nodes under it, three levels per exchange, and publishes it),
-//   then, once the near field is done, the far-field blocks of the unit's ancestors
-//   (step (3), top table), and the downward chain from level 0 to the unit root
+//   ancestor at most three levels up reduces the roots under it and publishes it) and
+//   collects the tree-top nodes the unit needs; once the near field is done, all worker
+//   waves reduce those, form the far-field blocks of the unit's ancestors (step (3), top
+//   table), and the last one runs the downward chain from level 0 to the unit root
 //   (step (4)).  Workers synchronise through LDS counters, streamers poll LDS flags;
 //   there is no hardware barrier between the first and the last phase.
 //   Then all waves: step (4) inside the unit, steps (5) and (7), and the output.
@@ -48,36 +49,6 @@ __device__ __forceinline__ void store_coherent(double *p, double v)
 __device__ __forceinline__ double load_coherent(const double *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until every store this wave has issued is complete (s_waitcnt vmcnt(0)); the
-// fence keeps the compiler from moving later memory operations above it.
-__device__ __forceinline__ void wave_stores_done()
-{
-    __builtin_amdgcn_s_waitcnt(0x0f70);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-}
-
-__device__ __forceinline__ void set_flag(unsigned *f, unsigned epoch)
-{
-    __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Lane 0 polls the flag until it equals epoch (bounded); the wave continues afterwards.
-__device__ __forceinline__ void wave_wait_flag(const unsigned *f, unsigned epoch, int *status)
-{
-    if ((threadIdx.x & 63) == 0) {
-        bool ok = false;
-        for (int it = 0; it < kSpinLimit; ++it) {
-            if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
-                ok = true;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (!ok) atomicOr(status, 1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // LDS written by some lanes of a wave and then read by other lanes of the same wave:
@@ -209,6 +180,290 @@ __device__ __forceinline__ void stream_group(int grp, int nxt, const double2 *su
     co[NS + M] = c11;
 }
 
+// Exchange nodes hold pub_empty() until the current launch writes them (the buffer half
+// of the next launch is reset to it during this one); any other value is final.
+__device__ __forceinline__ double pub_empty()
+{
+    return __longlong_as_double((long long)(((unsigned long long)kPubEmptyHalf << 32) | kPubEmptyHalf));
+}
+
+__device__ __forceinline__ bool pub_ready(double v)
+{
+    return __double_as_longlong(v) != (long long)(((unsigned long long)kPubEmptyHalf << 32) | kPubEmptyHalf);
+}
+
+// v[u] = p[off(u)] for every u with want(u), loaded again until no such value is empty
+// (bounded; a wave-uniform exit).  Entries without want(u) keep their value.
+template <int NU, class Want, class Off>
+__device__ __forceinline__ void poll_values(double (&v)[NU], const double *p, const Want &want, const Off &off,
+                                            int *status)
+{
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+        if (want(u)) v[u] = pub_empty();
+    for (int it = 0;; ++it) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (want(u) && !pub_ready(v[u])) v[u] = load_coherent(p + off(u));
+        bool ok = true;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) ok = ok && (!want(u) || pub_ready(v[u]));
+        if (__all(ok)) break;
+        if (it == kSpinLimit) {
+            atomicOr(status, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// The far-field blocks of unit X's ancestors a_g = X >> (G0 - g), g = 0..G0 (top table):
+// slot sl = 2g + h holds submatrix r = 2 (a_g & 1) with column node a_g + 2 (h = 0), or
+// r = 1 with column node a_g + 3 (h = 1, a_g even only); a block exists while its column
+// node lies inside level g.  Column nodes at levels g >= gl = G0 - min(3, G0) are exchange
+// nodes; below gl the workgroup reduces each from the 2^(gl-g) level-gl nodes under it.
+// Item i of the workgroup's list is one exchange node; a slot's items are consecutive.
+struct TopSlots {
+    int X, G0, H, gl, nsl;
+    __device__ TopSlots(int X_, int G0_) : X(X_), G0(G0_)
+    {
+        H = G0 < 3 ? G0 : 3;
+        gl = G0 - H;
+        nsl = 2 * (G0 + 1);
+    }
+    __device__ int64_t anc(int g) const { return (int64_t)X >> (G0 - g); }
+    __device__ bool ok(int sl) const
+    {
+        const int64_t an = anc(sl >> 1);
+        return an < (int64_t(1) << ((sl >> 1) + 2)) - 2 && ((sl & 1) == 0 || (an & 1) == 0);
+    }
+    __device__ int64_t col(int sl) const { return anc(sl >> 1) + 2 + (sl & 1); }
+    __device__ int cnt(int sl) const { return (sl >> 1) >= gl ? 1 : 1 << (gl - (sl >> 1)); }
+    __device__ int base(int sl) const      // first item of slot sl
+    {
+        int b = 0;
+        for (int t = 0; t < sl; ++t) b += ok(t) ? cnt(t) : 0;
+        return b;
+    }
+};
+
+// The last worker wave of unit X, up to the point where the workgroup's tree-top items sit
+// in LDS (itm, nitem x NS; the near-field area, free once the near waves have counted):
+//   1. Nodes 0, 1 of the next unit at depths 1..kd-1 into wl (the streamer waits for them
+//      only when it reaches those depths), and step (2) above the units: unit X with
+//      k = min(3, G0, trailing zeros of X) >= 1 is the leftmost unit below its ancestors at
+//      levels G0-1 .. G0-k; it reduces the roots of units X .. X+2^k-1 in the scratch xs and
+//      writes those ancestors to the exchange buffer.  Both inputs come in one poll.
+//   2. The items: wait until every one of them is written, loading it in the same polls.
+template <int M>
+__device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts, int kd, int U, int64_t nbase,
+                                           double *wl, double *xs, double *itm, const double *Bl, double *pubc,
+                                           unsigned *nbr, const unsigned *ndone, int lane)
+{
+    constexpr int M2 = 2 * M, NS = lds_ns<M>();
+    const int X = ts.X, G0 = ts.G0;
+    const bool act = lane < M2;
+    const int sg = lane >= M ? 1 : 0, nn = act ? lane - sg * M : 0;
+    const int kx = X == 0 ? G0 : min(G0, __ffs(X) - 1);
+    const int k = kx < ts.H ? kx : ts.H;
+    const int nin = 1 << k;                           // roots X .. X + nin - 1 (k = 0: none)
+    {
+        constexpr int UN = (12 * M2 + 63) / 64;       // next unit's nodes, kd <= 7
+        constexpr int UL = (8 * M2 + 63) / 64;        // roots
+        const int cntn = X + 1 < U ? 2 * (kd - 1) * M2 : 0;
+        const int nb1 = (int)((nbase + 2 * (kd - 1)) * M2), rb = (int)((node_offset(G0) + X) * M2);
+        double v[UN + UL];
+#pragma unroll
+        for (int u = 0; u < UN + UL; ++u) {
+            const int idx = (u - UN) * 64 + lane;
+            v[u] = (u >= UN && idx < M2) ? wl[idx] : 0.0;   // root X is this unit's
+        }
+        poll_values(
+            v, pubc,
+            [&](int u) {
+                const int idx = (u < UN ? u : u - UN) * 64 + lane;
+                return u < UN ? idx < cntn : (k >= 1 && idx >= M2 && idx < nin * M2);
+            },
+            [&](int u) { return u < UN ? nb1 + u * 64 + lane : rb + (u - UN) * 64 + lane; }, a.status);
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int e = u * 64 + lane;
+            if (e < 2 * (kd - 1) * M2) {
+                const int q = e / M2, r = e - q * M2;
+                const int d = (q >> 1) + 1, kk = q & 1;
+                wl[(fused_wofs(d) + (1 << d) + kk) * NS + r] = v[u];
+            }
+        }
+#pragma unroll
+        for (int u = UN; u < UN + UL; ++u) {
+            const int idx = (u - UN) * 64 + lane;
+            const int r = idx / M2, e = idx - r * M2;
+            if (k >= 1 && idx < nin * M2) xs[r * NS + e] = v[u];
+        }
+        wave_lds_done();
+        if (lane == 0) lds_flag_set(nbr, 1u);
+    }
+    if (k >= 1) {
+        double brow[M];
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) brow[kk] = Bl[nn * M + kk];
+        for (int j = 1; j <= k; ++j) {
+            const int step = 1 << j;                  // parents at nodes 0, step, 2 step, ... (in place)
+            for (int pp = 0; pp < nin; pp += step) {
+                const double *x = xs + pp * NS + sg * M, *y = xs + (pp + (step >> 1)) * NS + sg * M;
+                const double v2 = up_pair<M>(brow, x, y, nn);
+                if (act) xs[pp * NS + lane] = v2;
+                wave_lds_sync();
+            }
+            if (act) store_coherent(pubc + (node_offset(G0 - j) + (X >> j)) * M2 + lane, xs[lane]);
+        }
+    }
+    // 2. items: lane i < nitem finds the exchange node of item i
+    int nitem = 0;
+    for (int sl = 0; sl < ts.nsl; ++sl) nitem += ts.ok(sl) ? ts.cnt(sl) : 0;
+    int mine = 0;
+    if (lane < nitem) {
+        int i = lane, sl = 0;
+        for (; sl < ts.nsl; ++sl) {
+            if (!ts.ok(sl)) continue;
+            const int c = ts.cnt(sl);
+            if (i < c) break;
+            i -= c;
+        }
+        const int g = sl >> 1;
+        mine = g >= ts.gl ? (int)(node_offset(g) + ts.col(sl))
+                          : (int)(node_offset(ts.gl) + (ts.col(sl) << (ts.gl - g)) + i);
+    }
+    constexpr int UC = (36 * M2 + 63) / 64;           // at most 36 items (groot <= 6)
+    double vc[UC];
+    int nid[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int i = (u * 64 + lane) / M2;
+        nid[u] = __shfl(mine, i < 63 ? i : 63);
+        vc[u] = 0.0;
+    }
+    poll_values(
+        vc, pubc, [&](int u) { return (u * 64 + lane) / M2 < nitem; },
+        [&](int u) { return nid[u] * M2 + (u * 64 + lane) % M2; }, a.status);
+    // the near-field area is free once the near waves have counted
+    if (lane == 0) {
+        int it = 0;
+        while (lds_flag_get(ndone) < (unsigned)kNearWaves) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++it == kSpinLimit) {
+                atomicOr(a.status, 2);
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int idx = u * 64 + lane;
+        const int i = idx / M2, e = idx - i * M2;
+        if (i < nitem) itm[i * NS + e] = vc[u];
+    }
+}
+
+// All worker waves, once the items are in LDS (after a worker barrier):
+//   3. the column nodes below level gl, reduced in place (pairwise, level by level; the
+//      pairs of a level are spread over the waves, a barrier between levels);
+//   4. wave g <= G0: canc_g = the ancestor a_g's far-field blocks times their column
+//      nodes (the submatrices ag0, ag1 are this wave's rows nn, loaded beforehand);
+//   5. the top wave: the chain of step (4) from level 0 down to the unit root,
+//      c(a_g) = canc_g + B(p)^T c(a_{g-1}), p = a_g & 1, into cR.
+template <int M>
+__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm, const double *Bl,
+                                            const double (&ag0)[M], const double (&ag1)[M], double *canc,
+                                            double *zb, double *cR, unsigned *wcnt, unsigned &wtarget, int ww,
+                                            bool top, int lane)
+{
+    constexpr int M2 = 2 * M, NS = lds_ns<M>();
+    const bool act = lane < M2;
+    const int sg = lane >= M ? 1 : 0, nn = act ? lane - sg * M : 0;
+    worker_sync(wcnt, wtarget, a.status);             // items in LDS
+    if (ts.gl > 0) {
+        double brow[M];
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) brow[kk] = Bl[nn * M + kk];
+        for (int r = 1; r <= ts.gl; ++r) {
+            const int step = 1 << r;
+            int t = 0, base = 0;
+            for (int sl = 0; sl < ts.nsl; ++sl) {
+                if (!ts.ok(sl)) continue;
+                const int c = ts.cnt(sl);
+                for (int pp = 0; pp + step <= c; pp += step, ++t) {
+                    if (t % kWorkWaves != ww) continue;
+                    const double *x = itm + (base + pp) * NS + sg * M, *y = x + (step >> 1) * NS;
+                    const double v = up_pair<M>(brow, x, y, nn);
+                    if (act) itm[(base + pp) * NS + lane] = v;
+                }
+                base += c;
+            }
+            worker_sync(wcnt, wtarget, a.status);
+        }
+    }
+    if (ww <= ts.G0) {
+        const int g = ww;
+        double c0 = 0.0, c1 = 0.0;
+        if (ts.ok(2 * g)) {
+            const double *x0 = itm + ts.base(2 * g) * NS + sg * M;
+#pragma unroll
+            for (int l = 0; l < M; ++l) c0 = fma(ag0[l], x0[l], c0);
+        }
+        if (ts.ok(2 * g + 1)) {
+            const double *x1 = itm + ts.base(2 * g + 1) * NS + sg * M;
+#pragma unroll
+            for (int l = 0; l < M; ++l) c1 = fma(ag1[l], x1[l], c1);
+        }
+        if (act) canc[g * M2 + lane] = c0 + c1;
+    }
+    worker_sync(wcnt, wtarget, a.status);
+    if (top) {
+        double bcol[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) bcol[k] = Bl[k * M + nn];
+        double cc = act ? canc[lane] : 0.0;
+        for (int g = 1; g <= ts.G0; ++g) {
+            const int p = (int)(ts.anc(g) & 1);
+            if (act) zb[lane] = cc;
+            wave_lds_sync();
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0;       // three chains (latency)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const double v = zb[sg * M + k];
+                const double t = (p && (k & 1)) ? -v : v;
+                if (k % 3 == 0) q0 = fma(bcol[k], t, q0);
+                else if (k % 3 == 1) q1 = fma(bcol[k], t, q1);
+                else q2 = fma(bcol[k], t, q2);
+            }
+            const double acc2 = (q0 + q1) + q2;
+            wave_lds_sync();
+            cc = (act ? canc[g * M2 + lane] : 0.0) + ((p && (nn & 1)) ? -acc2 : acc2);
+        }
+        if (act) cR[lane] = cc;
+    }
+}
+
+// Rows nn of ancestor a_g's two top-table submatrices (zero where the block does not exist).
+template <int M>
+__device__ __forceinline__ void load_anc_rows(const ExecArgs &a, const TopSlots &ts, int g, int lane, double (&ag0)[M],
+                                              double (&ag1)[M])
+{
+    const bool act = lane < 2 * M;
+    const int nn = act ? (lane >= M ? lane - M : lane) : 0;
+    const bool ok0 = g <= ts.G0 && ts.ok(2 * g), ok1 = g <= ts.G0 && ts.ok(2 * g + 1);
+    const int64_t an = ts.anc(g <= ts.G0 ? g : 0);
+    const double *A = a.ahat_top + (level_block_offset(g <= ts.G0 ? g : 0) + (an >> 1)) * 3 * M * M + nn * M;
+    const int r0 = 2 * (int)(an & 1);
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        ag0[l] = ok0 ? A[r0 * M * M + l] : 0.0;
+        ag1[l] = ok1 ? A[M * M + l] : 0.0;
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 {
@@ -242,6 +497,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     const bool streamer = wv < NSW;
     const int wt = tid - 64 * NSW;                    // worker thread index
     const int ww = wv - NSW;                          // worker wave index
+    // the top wave shares a SIMD with the streamer (waves w and w + 4 pair up), so the
+    // near-field waves, which keep the FP64 pipes busy, do not slow its latency-bound chain
+    const bool top = wv == kTopWave, near = !streamer && !top;
+    const int nw = top ? kNearWaves : wv < kTopWave ? wv - NSW : wv - NSW - 1;   // near-field wave
+    const int ntid = nw * 64 + lane;
 
     double *Bl = lds;                                 // M*M
     double *Tl = Bl + M * M;                          // 2 s M
@@ -251,14 +511,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     double *wl = gp + fused_near_area(L, M, s, kd);   // fused_wofs(kd + 1) nodes
     double *cown = wl + fused_wofs(kd + 1) * NS;      // own depths 1..kd at node 2^d - 2
     double *cR = cown + own * NS;                     // c at the unit root (ancestor chain)
-    double *w7 = cR + NS;                             // top wave: z [2 x 2M], canc [(G0+1) x 2M]
-    double *dummy = w7 + 4 * M + (G0 + 1) * M2;       // 2 NS: stores of out-of-range slots
+    double *w7 = cR + NS;                             // top wave: exchange scratch, then z and canc
+    double *dummy = w7 + fused_w7(M, G0);             // 2 NS: stores of out-of-range slots
     unsigned *sync = reinterpret_cast<unsigned *>(dummy + 2 * NS);
     unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *ndone = sync + 3, *qdone = sync + 4;
 
     const double *in = a.in + item * a.n;
-    double *wg = a.w + item * G.NT * M2;              // published nodes, workspace layout
-    unsigned *fl = a.flags + item * G.NF;
+    // exchange nodes: this launch's half, and the next launch's (reset to empty here)
+    double *pubc = a.pub + ((int64_t)(a.epoch & 1u) * a.pub_items + item) * G.NX * M2;
+    double *pubn = a.pub + (int64_t)((a.epoch + 1u) & 1u) * a.pub_items * G.NX * M2;
+    const int64_t nbase = G.NF + (int64_t)X * 2 * (kd - 1);   // this unit's nodes 0, 1 of depths 1..kd-1
     const int64_t jb = u0 * 2 * s;                    // first row of the unit
     const int nslots = (nodes - 1) * M;
     const double2 *sub = reinterpret_cast<const double2 *>(a.ahat_bot) + (int64_t)X * G.sub_groups * NCH * 64 + lane;
@@ -339,6 +601,21 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             ndone[0] = 0;
             qdone[0] = 0;
         }
+        // this unit's exchange nodes in the next launch's half of the buffer: empty again, for
+        // items item, item + batch, ... (the next launch may hold more items than this one)
+        {
+            const int kx = X == 0 ? G0 : min(G0, __ffs(X) - 1);
+            const int nxq = 2 * (kd - 1), nq = 1 + nxq + (kx < 3 ? kx : 3);
+            for (int64_t it = item; it < a.pub_items; it += a.batch) {
+                for (int e = wt; e < nq * M2; e += NWT) {
+                    const int q = e / M2, r = e - q * M2;
+                    const int64_t id = q == 0     ? node_offset(G0) + X
+                                       : q <= nxq ? nbase + (q - 1)
+                                                  : node_offset(G0 - (q - nxq)) + (X >> (q - nxq));
+                    store_coherent(pubn + (it * G.NX + id) * M2 + r, pub_empty());
+                }
+            }
+        }
         __syncthreads();                              // with the streamers' barrier below
         L2C_TS(3, 1);
         // ---- step (3), own blocks.  Slot (j, k) of a group = row k of the three submatrices of
@@ -353,13 +630,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         //      third repeats k = M-1 in its spare slots (no branches in the loop).
         {
             constexpr int KT = (M + 2) / 3;
-            const int sig = ww & 1, kb = (ww >> 1) * KT;
+            const int sig = nw & 1, kb = (nw >> 1) * KT;
             const double *Ts = Tl + sig * s * M;
             int kc[KT];
 #pragma unroll
             for (int kk = 0; kk < KT; ++kk) kc[kk] = kb + kk < M ? kb + kk : M - 1;
             const int nall = nodes + 2, H = (nall + 1) >> 1;
-            for (int n0 = lane; n0 < H; n0 += 64) {
+            for (int n0 = top ? H : lane; n0 < H; n0 += 64) {   // six waves: (sigma, third)
                 const int n1 = n0 + H < nall ? n0 + H : n0;     // odd count: the last lane repeats
                 double a0[KT], a1[KT];
 #pragma unroll
@@ -414,27 +691,24 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         }
         L2C_TS(3, 12);
         // publish the root (level G0, node X) and nodes 0, 1 of depths 1..kd-1 (level G0 + d,
-        // nodes X 2^d, X 2^d + 1), then raise the unit's flag
+        // nodes X 2^d, X 2^d + 1) as exchange nodes
         {
             const int cnt = (2 * kd - 1) * M2;
             for (int e = wt; e < cnt; e += NWT) {
                 const int q = e / M2, r = e - q * M2;
                 const int d = q == 0 ? 0 : (q + 1) >> 1, k = q == 0 ? 0 : (q - 1) & 1;
-                store_coherent(wg + (node_offset(G0 + d) + ((int64_t)X << d) + k) * M2 + r,
-                               wl[(fused_wofs(d) + k) * NS + r]);
+                const int64_t id = q == 0 ? node_offset(G0) + X : nbase + (q - 1);
+                store_coherent(pubc + id * M2 + r, wl[(fused_wofs(d) + k) * NS + r]);
             }
-            wave_stores_done();
-            worker_sync(wcnt, wtarget, a.status);
-            if (wt == 0) set_flag(fl + node_offset(G0) + X, a.epoch);
         }
         L2C_TS(3, 3);
         // ---- near-field Q table (off the path to the published root), by the near waves
-        if (ww < kNearWaves) {
+        if (near) {
             // Q in runs of 8 consecutive S: the first value from Eq. (tau), then the exact ratio
             // Q_{S+1}/Q_S: (2S+1)/(2S+2) for leg2cheb (Eq. (Lambdaint)), 2S/(2S+3) for cheb2leg
             {
                 const int QL = 2 * s * nodes + 3 * s + 2 * R;
-                for (int run = wt; run * 8 < QL; run += 64 * kNearWaves) {
+                for (int run = ntid; run * 8 < QL; run += 64 * kNearWaves) {
                     const int x0 = run * 8;
                     int node = x0 / (2 * s), c = x0 - node * 2 * s;
                     int64_t S = jb + x0;
@@ -468,28 +742,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        // ---- nodes 0, 1 of the next unit at depths 1..kd-1 (one worker wave; the streamers
-        //      wait for this only when they reach those depths)
-        if (ww == kWorkWaves - 2) {
-            const int cnt = 2 * (kd - 1) * M2;
-            const bool have = X + 1 < U;
-            if (have) wave_wait_flag(fl + node_offset(G0) + X + 1, a.epoch, a.status);
-            for (int e = lane; e < cnt; e += 64) {
-                const int q = e / M2, r = e - q * M2;
-                const int d = (q >> 1) + 1, k = q & 1;
-                const double v =
-                    have ? load_coherent(wg + (node_offset(G0 + d) + ((int64_t)(X + 1) << d) + k) * M2 + r) : 0.0;
-                wl[(fused_wofs(d) + (1 << d) + k) * NS + r] = v;
-            }
-            wave_lds_done();
-            if (lane == 0) lds_flag_set(nbr, 1u);
-        }
         // ---- step (6): near field.  Item (node nd, parity sig, rows m0 .. m0+R-1): row m sums
         //      over m' in [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig], with P, Q
         //      and g entering through circular register windows; the sums stay in registers
         //      until the leaf evaluation.
-        if (ww < kNearWaves && wt < nwork) {
-            const int nd = wt % nodes, x = wt / nodes;
+        if (near && ntid < nwork) {
+            const int nd = ntid % nodes, x = ntid / nodes;
             const int sig = x & 1, m0 = (x >> 1) * R;
             const double *gs = gp + sig * GX + nd * GS;
             const double *qs = Ql + nd * QS;
@@ -520,215 +778,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
-        if (ww < kNearWaves) {
+        if (near) {
             wave_lds_done();                          // the near-field area is free once all have counted
             if (lane == 0) __hip_atomic_fetch_add(ndone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         L2C_TS(3, 4);
-        if (ww == kWorkWaves - 1) {
-        // ---- top wave; lane (sg, nn) <-> parity and mode
-        const bool act = lane < M2;
-        const int sg = lane >= M ? 1 : 0, nn = act ? lane - sg * M : 0;
-        double *zb = w7;                              // z0 [2M], z1 [2M]
-        double *canc = w7 + 2 * M2;                   // (G0 + 1) x 2M
-        // step (2) above the units.  Unit X with kown = min(G0, trailing zeros of X) >= 1 is
-        // the leftmost unit below its ancestors at levels G0-1 .. G0-kown and publishes
-        // them.  It reduces kHopLevels levels per exchange: it waits for the other
-        // 2^kHopLevels - 1 nodes of the input level below its next ancestor (published by
-        // their own leftmost units), reduces them in the (now free) near-field area, and
-        // publishes the new nodes.  With groot <= 6 that is at most two exchanges.
-        {
-            constexpr int kHopLevels = 3;
-            const int kown = X == 0 ? G0 : min(G0, __ffs(X) - 1);
-            double brow[M];
-#pragma unroll
-            for (int kk = 0; kk < M; ++kk) brow[kk] = Bl[nn * M + kk];
-            double cur = act ? wl[lane] : 0.0;                  // this unit's node at the input level
-            for (int jdone = 0; jdone < kown;) {
-                const int jn = min(kown, jdone + kHopLevels);
-                const int gin = G0 - jdone;                      // input level
-                const int nin = 1 << (jn - jdone);               // input nodes t0 .. t0 + nin - 1
-                const int64_t t0 = (int64_t)X >> jdone;
-                double *src = Tl, *dst = Tl + nin * NS;          // ping-pong node buffers (T area)
-                {
-                    bool done = lane >= nin - 1;                 // lane i waits for node t0 + 1 + i
-                    for (int it = 0; it < kSpinLimit; ++it) {
-                        if (!done)
-                            done = __hip_atomic_load(fl + node_offset(gin) + t0 + 1 + lane, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
-                        if (__all(done)) break;
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    if (!done) atomicOr(a.status, 1);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                }
-                {
-                    // nin <= 8 nodes of 2M values: UL loads per lane
-                    constexpr int UL = (8 * M2 + 63) / 64;
-                    double v[UL];
-#pragma unroll
-                    for (int u = 0; u < UL; ++u) {
-                        const int idx = u * 64 + lane;
-                        const int r = idx / M2, e = idx - r * M2;
-                        v[u] = (idx < nin * M2 && r > 0) ? load_coherent(wg + (node_offset(gin) + t0 + r) * M2 + e) : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < UL; ++u) {
-                        const int idx = u * 64 + lane;
-                        const int r = idx / M2, e = idx - r * M2;
-                        if (idx < nin * M2 && r > 0) src[r * NS + e] = v[u];
-                    }
-                    if (act) src[lane] = cur;
-                }
-                wave_lds_sync();
-                for (int j = jdone + 1; j <= jn; ++j) {
-                    const int pn = nin >> (j - jdone);
-                    for (int pp = 0; pp < pn; ++pp) {
-                        const double *x = src + (2 * pp) * NS + sg * M;
-                        const double v = up_pair<M>(brow, x, x + NS, nn);
-                        if (act) dst[pp * NS + lane] = v;
-                    }
-                    wave_lds_sync();
-                    cur = act ? dst[lane] : 0.0;
-                    if (act) store_coherent(wg + (node_offset(G0 - j) + (X >> j)) * M2 + lane, cur);
-                    double *t = src;
-                    src = dst;
-                    dst = t;
-                }
-                wave_stores_done();
-                if (lane == 0)
-                    for (int j = jdone + 1; j <= jn; ++j) set_flag(fl + node_offset(G0 - j) + (X >> j), a.epoch);
-                jdone = jn;
-                wave_lds_sync();
-            }
-        }
-        // T back into its area (the leaf evaluation needs it) and the ancestors' submatrices
-        // (step (3) below) in one batch of loads; then wait until the near field has
-        // released the near-field area.  Slot sl = 2g + h of level g holds submatrix r = 2p
-        // (h = 0, column node a_g + 2) or r = 1 (h = 1, p = 0 only, column node a_g + 3).
-        const int nsl = 2 * (G0 + 1);
-        auto slot_ok = [&](int sl) -> bool {
-            const int g = sl >> 1;
-            const int64_t an = (int64_t)X >> (G0 - g);
-            return an < (int64_t(1) << (g + 2)) - 2 && ((sl & 1) == 0 || (an & 1) == 0);
-        };
-        auto slot_node = [&](int sl) -> int64_t {
-            const int g = sl >> 1;
-            return node_offset(g) + ((int64_t)X >> (G0 - g)) + 2 + (sl & 1);
-        };
-        constexpr int UAT = (14 * M * M + 63) / 64;   // groot <= 6: at most 14 slots
-        constexpr int UTT = (2 * 33 * M + 63) / 64;   // 2 s M, s <= 33
-        double va[UAT];
-        {
-            double vt[UTT];
-#pragma unroll
-            for (int u = 0; u < UTT; ++u) {
-                const int e = u * 64 + lane;
-                vt[u] = e < 2 * s * M ? a.T[e] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < UAT; ++u) {
-                const int idx = u * 64 + lane;
-                const int sl = idx / (M * M), e = idx - sl * (M * M);
-                double x = 0.0;
-                if (idx < nsl * M * M && slot_ok(sl)) {
-                    const int g = sl >> 1;
-                    const int64_t an = (int64_t)X >> (G0 - g);
-                    const int r = (sl & 1) ? 1 : 2 * (int)(an & 1);
-                    x = a.ahat_top[((level_block_offset(g) + (an >> 1)) * 3 + r) * M * M + e];
-                }
-                va[u] = x;
-            }
-#pragma unroll
-            for (int u = 0; u < UTT; ++u) {
-                const int e = u * 64 + lane;
-                if (e < 2 * s * M) Tl[e] = vt[u];
-            }
-            if (lane == 0) {
-                int it = 0;
-                while (lds_flag_get(ndone) < (unsigned)kNearWaves) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++it == kSpinLimit) {
-                        atomicOr(a.status, 2);
-                        break;
-                    }
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-        // step (3) for the ancestors a_g = X >> (G0 - g), g = 0..G0 (top table), from LDS once
-        // every column node is flagged and loaded
-        {
-            double *colw = gp;                             // nsl x 2M
-            double *atop = gp + nsl * M2;                  // nsl x M x M
-#pragma unroll
-            for (int u = 0; u < UAT; ++u) {
-                const int idx = u * 64 + lane;
-                if (idx < nsl * M * M) atop[idx] = va[u];
-            }
-            // every column node flagged (lane sl polls slot sl)
-            {
-                bool done = lane >= nsl || !slot_ok(lane);
-                for (int it = 0; it < kSpinLimit; ++it) {
-                    if (!done)
-                        done = __hip_atomic_load(fl + slot_node(lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                               a.epoch;
-                    if (__all(done)) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (!done) atomicOr(a.status, 1);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            }
-            for (int base = 0; base < nsl * M2; base += 8 * 64) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int idx = base + u * 64 + lane;
-                    const int sl = idx / M2, e = idx - sl * M2;
-                    v[u] = (idx < nsl * M2 && slot_ok(sl)) ? load_coherent(wg + slot_node(sl) * M2 + e) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int idx = base + u * 64 + lane;
-                    if (idx < nsl * M2) colw[idx] = v[u];
-                }
-            }
-            wave_lds_sync();
-            for (int g = 0; g <= G0; ++g) {
-                const double *A0 = atop + (2 * g) * M * M + nn * M, *A1 = A0 + M * M;
-                const double *x0 = colw + (2 * g) * M2 + sg * M, *x1 = x0 + M2;
-                double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-                for (int l = 0; l < M; ++l) {
-                    c0 = fma(A0[l], x0[l], c0);
-                    c1 = fma(A1[l], x1[l], c1);
-                }
-                if (act) canc[g * M2 + lane] = c0 + c1;
-            }
-        }
-        wave_lds_sync();
-        // step (4) along the chain: c(a_g) += B(p)^T c(a_{g-1}), p = a_g & 1
-        {
-            double bcol[M];
-#pragma unroll
-            for (int k = 0; k < M; ++k) bcol[k] = Bl[k * M + nn];
-            double cc = act ? canc[lane] : 0.0;
-            for (int g = 1; g <= G0; ++g) {
-                const int p = (int)((X >> (G0 - g)) & 1);
-                if (act) zb[lane] = cc;
-                wave_lds_sync();
-                double acc2 = 0.0;
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const double v = zb[sg * M + k];
-                    acc2 = fma(bcol[k], (p && (k & 1)) ? -v : v, acc2);
-                }
-                wave_lds_sync();
-                cc = (act ? canc[g * M2 + lane] : 0.0) + ((p && (nn & 1)) ? -acc2 : acc2);
-            }
-            if (act) cR[lane] = cc;
-        }
-        }
+        // ---- steps (2)-(4) above the unit (TopSlots, top_gather, top_combine)
+        const TopSlots ts(X, G0);
+        double ag0[M], ag1[M];
+        load_anc_rows<M>(a, ts, ww, lane, ag0, ag1);
+        if (top)
+            top_gather<M>(a, ts, kd, U, nbase, wl, w7, gp, Bl, pubc, nbr, ndone, lane);
+        top_combine<M>(a, ts, gp, Bl, ag0, ag1, w7 + 2 * M2, w7, cR, wcnt, wtarget, ww, top, lane);
     }
     __syncthreads();
     L2C_TS(3, 5);
@@ -758,7 +819,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     // ---- steps (5) and (7): z = sum_k T_k(X_m^sig) c(u)[sig][k] (row nodes u < P - 2)
     //      + rs * near; leg2cheb divides by c_i pi/2
     double *out = a.out + item * a.n;
-    if (!streamer && ww < kNearWaves && wt < nwork) {
+    if (near && ntid < nwork) {
         auto eval = [&](int nd, int sig, int m0) {
             const bool far = u0 + nd < P - 2;
             double cc[M];
@@ -789,11 +850,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         };
         if (nodes == 64) {
             // a wave holds one (parity, row block) for 64 nodes: T rows are wave-uniform
-            const int x = __builtin_amdgcn_readfirstlane(ww);
+            const int x = __builtin_amdgcn_readfirstlane(nw);
             eval(lane, x & 1, (x >> 1) * R);
         } else {
-            const int x = wt / nodes;
-            eval(wt % nodes, x & 1, (x >> 1) * R);
+            const int x = ntid / nodes;
+            eval(ntid % nodes, x & 1, (x >> 1) * R);
         }
     }
     L2C_TS(3, 7);
@@ -832,8 +893,7 @@ hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items)
     if (p.L < 2 || G.kd < 1 || !fused_supported(p.M)) return hipSuccess;
     const int nodes = 1 << G.kd, R = kFusedRows;
     if (nodes * 2 * ((G.s + R - 1) / R) > 64 * kNearWaves) return hipSuccess;          // near-field items
-    if (12 * (2 * G.M + 1) > 2 * G.s * G.M) return hipSuccess;                         // hop scratch in T area
-    if (G.s > 33 || G.groot > 6) return hipSuccess;                                      // top wave's load batches
+    if (G.groot > 6 || G.kd > 7) return hipSuccess;                                      // register batches
     if (2 * (G.s * (nodes + 2) + R) > kFusedStageG * kWorkThreads) return hipSuccess;  // input staging
     if (2 * G.s * G.M > kFusedStageT * kWorkThreads) return hipSuccess;                // T staging
     if (2 * G.s + 2 * R > kWorkThreads) return hipSuccess;                             // P staging
@@ -880,7 +940,8 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
     a.ahat_top = p.d_top;
     a.ahat_bot = p.d_bot;
     a.w = p.d_w;
-    a.flags = p.d_flags;
+    a.pub = p.d_pub;
+    a.pub_items = p.fused_items;
     a.status = p.d_status;
     const size_t lds = fused_lds_bytes(G);
     const unsigned U = 1u << (G.groot + 2);
@@ -900,7 +961,6 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
         c.in = in + b0 * p.n;
         c.out = out + b0 * p.n;
         c.epoch = ++p.epoch;
-        if (c.epoch == 0) c.epoch = ++p.epoch;    // 0 is the value of never-written flags
         const bool timed = p.ev_before && p.ev_after && b0 == 0;
         if (timed) (void)hipEventRecord(p.ev_before, st);
         hipLaunchKernelGGL(k_fused<M>, dim3(U, (unsigned)c.batch), dim3(kFusedThreads), lds, st, c);

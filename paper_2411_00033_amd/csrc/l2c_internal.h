@@ -58,7 +58,8 @@ struct Geometry {
     int groot;                // L - 1 - kd
     int sub_groups;           // wavefront groups per subtree in the bottom table
     int64_t NT;               // workspace nodes per item
-    int64_t NF;               // k_fused ready flags per item: levels 0..groot, node_offset(groot + 1)
+    int64_t NF;               // tree-top nodes, levels 0..groot: node_offset(groot + 1)
+    int64_t NX;               // k_fused exchange nodes per item: NF, then 2 (kd-1) per unit
 };
 
 struct ExecArgs {
@@ -74,8 +75,9 @@ struct ExecArgs {
     const double *ahat_top;
     const double *ahat_bot;
     double *w;           // [batch][NT][2][M]
-    unsigned *flags;     // k_fused: [items][NF] ready flags (value = epoch of the launch)
-    unsigned epoch;      // k_fused: launch number; a flag equal to it marks data of this launch
+    double *pub;         // k_fused: [2][pub_items][NX][2][M] exchange nodes, half (epoch & 1) in use
+    int64_t pub_items;   // k_fused: items of one half of pub
+    unsigned epoch;      // k_fused: launch number
     int *status;         // k_fused: bit 0 set when a wait ran out of polls
 };
 
@@ -103,7 +105,7 @@ struct l2c_plan_s {
     bool fused_ok = false;      // geometry, LDS and co-residency allow it
     bool fused_on = true;       // caller preference (leg2cheb_plan_set_option)
     int64_t fused_items = 0;    // items per k_fused launch (all workgroups co-resident)
-    unsigned *d_flags = nullptr;  // [fused_items][NF]
+    double *d_pub = nullptr;    // ExecArgs::pub, fused_items items per half
     int *d_status = nullptr;
     unsigned epoch = 0;
 };
@@ -158,8 +160,14 @@ constexpr int kWorkThreads = kFusedThreads - 64 * kStreamWaves;   // 448
 constexpr int kWorkWaves = kWorkThreads / 64;                     // 7
 constexpr int kFusedRows = 11;            // near-field rows per work item (3 items per node and parity at s = 31)
 constexpr int kNearWaves = 6;             // worker waves that run the near field (one item per thread)
+constexpr int kTopWave = 4;               // the wave (of the workgroup) that works above the unit
+static_assert(kStreamWaves == 1 && kNearWaves == kWorkWaves - 1 && kTopWave > kStreamWaves && kTopWave < 8,
+              "wave roles: one streamer, one top wave, the rest near-field waves");
 constexpr int kSpinLimit = 1 << 20;       // polls of one wait before it gives up (~1 s)
 constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per worker thread
+// Both 32-bit halves of an exchange node value that the current launch has not written yet
+// (a signalling NaN, which no arithmetic result is).
+constexpr unsigned kPubEmptyHalf = 0x7FF00001u;
 
 // Node offset of depth d in the k_fused w buffer: depth 0 is the subtree root alone;
 // depth d >= 1 holds the subtree's 2^d nodes followed by nodes 0, 1 of the next subtree.
@@ -182,14 +190,32 @@ __host__ __device__ inline int64_t fused_nq(int s, int kd)
     return (int64_t)(2 * s + fused_qpad(s)) * ((1 << kd) + 1) + 3 * (int64_t)s + 2 * kFusedRows;
 }
 
-// The near-field area: input, Q and P during the near field; afterwards the top wave's
-// ancestor columns and submatrices, 2 (groot+1) x (2M + M^2).
+// Load items of the top wave: below level gl = groot - min(3, groot) a column node is
+// reduced from the 2^(gl-g) level-gl nodes under it, at and above gl it is loaded.
+__host__ __device__ inline int fused_top_items(int groot)
+{
+    const int H = groot < 3 ? groot : 3, gl = groot - H;
+    return 2 * ((1 << (gl + 1)) - 2) + 2 * (H + 1);
+}
+
+// The near-field area: input, Q and P during the near field; afterwards the tree-top
+// nodes that the workgroup reduces itself.
 __host__ __device__ inline int64_t fused_near_area(int L, int M, int s, int kd)
 {
     const int groot = L - 1 - kd;
+    const int64_t NS = 2 * M + 1;
     const int64_t near = 2 * fused_gx(s, kd) + fused_nq(s, kd) + 2 * (int64_t)s + 2 * kFusedRows;
-    const int64_t anc = 2 * (int64_t)(groot + 1) * (2 * M + (int64_t)M * M);
+    const int64_t anc = fused_top_items(groot) * NS;
     return near > anc ? near : anc;
+}
+
+// Top-wave scratch of k_fused (doubles): the exchange's 2^min(3, groot) nodes of NS,
+// later the chain's z [2 x 2M] and canc [(groot+1) x 2M].
+__host__ __device__ inline int64_t fused_w7(int M, int groot)
+{
+    const int64_t chain = 4 * (int64_t)M + (int64_t)(groot + 1) * 2 * M;
+    const int64_t exch = (int64_t(1) << (groot < 3 ? groot : 3)) * (2 * (int64_t)M + 1);
+    return chain > exch ? chain : exch;
 }
 
 // LDS of k_fused (doubles): B(0), T, the near-field area, w (all depths plus neighbour
@@ -201,7 +227,7 @@ inline int64_t fused_lds_doubles(int L, int M, int s, int kd)
     const int64_t WN = fused_wofs(kd + 1), own = 2 * nodes - 2;
     const int groot = L - 1 - kd;
     return (int64_t)M * M + 2 * (int64_t)s * M + fused_near_area(L, M, s, kd) + WN * NS + own * NS + NS +
-           4 * (int64_t)M + (int64_t)(groot + 1) * 2 * M + 2 * NS + 4;
+           fused_w7(M, groot) + 2 * NS + 4;
 }
 
 // Subtree depths for a plan with L >= 1 levels.
@@ -227,6 +253,7 @@ inline Geometry make_geometry(int L, int M, int s)
     g.sub_groups = (int)((slots + 63) / 64);
     g.NT = ((int64_t)1 << (L + 2)) - 4;
     g.NF = node_offset(g.groot + 1);
+    g.NX = g.NF + (g.kd >= 1 ? (int64_t(1) << (g.groot + 2)) * 2 * (g.kd - 1) : 0);
     return g;
 }
 
