@@ -75,6 +75,16 @@ __device__ __forceinline__ double near_Q(int dir, int64_t S)
 template <int M>
 __host__ __device__ constexpr int lds_ns() { return 2 * M + 1; }
 
+// Every LDS operand load of a transfer is issued before its first product: left to
+// itself the scheduler interleaves loads and products in small batches and waits for
+// each batch, which makes one transfer several LDS latencies long.
+template <int NLOADS>
+__device__ __forceinline__ void ops_first()
+{
+    __builtin_amdgcn_sched_group_barrier(0x100, NLOADS, 0);   // LDS reads
+    __builtin_amdgcn_sched_group_barrier(0x00a, 256, 0);      // then VALU and matrix-core ops
+}
+
 // Upward transfer of one level (Eq. (wtk) with App. A2): for every parent node and
 // parity, out_n = sum_{k<=n} b_nk z_{(n-k) mod 2, k} with z0 = w(2T) + w(2T+1) and
 // z1 = w(2T) - w(2T+1) (B(1) is B(0) with its odd diagonals negated).
@@ -96,12 +106,17 @@ __device__ __forceinline__ void up_level_h(const double *child, double *par, int
         const int pnode = q >> 1, sig = q & 1;
         const double *wa = child + (2 * pnode) * lds_ns<M>() + sig * M;
         const double *wb = wa + lds_ns<M>();
-        double z0[M], z1[M];
+        double xv[M], yv[M], z0[M], z1[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            const double x = wa[k], y = wb[k];
-            z0[k] = x + y;
-            z1[k] = x - y;
+            xv[k] = wa[k];
+            yv[k] = wb[k];
+        }
+        ops_first<2 * M>();
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            z0[k] = xv[k] + yv[k];
+            z1[k] = xv[k] - yv[k];
         }
         double *po = par + pnode * lds_ns<M>() + sig * M;
 #pragma unroll
@@ -149,7 +164,10 @@ __device__ __forceinline__ void down_level_h(const double *par, double *cur, int
         const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
         double cs[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) cs[k] = (p && (k & 1)) ? -cp[k] : cp[k];
+        for (int k = 0; k < M; ++k) cs[k] = cp[k];
+        ops_first<M>();
+#pragma unroll
+        for (int k = 0; k < M; ++k) cs[k] = (p && (k & 1)) ? -cs[k] : cs[k];
         double *co = cur + v * lds_ns<M>() + sig * M;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
@@ -184,14 +202,22 @@ __device__ __forceinline__ void down_level(const double *par, double *cur, int c
 // (the same as B(0) x + B(1) y).  With brow[k] = b_nk (zero for k > n) and the y sums
 // split by the parity of k, out_n = X + (-1)^n (Y_even - Y_odd): no selects in the loop.
 // Four partial sums per product (k mod 4) keep the dependent FMA chains short.
+
 template <int M>
 __device__ __forceinline__ double up_pair(const double (&brow)[M], const double *x, const double *y, int n)
 {
+    double xv[M], yv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        xv[k] = x[k];
+        yv[k] = y[k];
+    }
+    ops_first<2 * M>();
     double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        a[k & 3] = fma(brow[k], x[k], a[k & 3]);
-        b[k & 3] = fma(brow[k], y[k], b[k & 3]);
+        a[k & 3] = fma(brow[k], xv[k], a[k & 3]);
+        b[k & 3] = fma(brow[k], yv[k], b[k & 3]);
     }
     const double ys = (b[0] + b[2]) - (b[1] + b[3]);
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((n & 1) ? -ys : ys);
@@ -219,13 +245,17 @@ __device__ __forceinline__ void down_level_qn(const double *par, double *cur, in
         const int v = q >> 1, sig = q & 1;
         const int p = pfix >= 0 ? pfix : (v & 1);
         const double *cp = par + (v >> 1) * lds_ns<M>() + sig * M;
+        double cv[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cv[k] = cp[k];
+        ops_first<M>();
         double e0 = 0.0, e1 = 0.0, o0 = 0.0, o1 = 0.0;
 #pragma unroll
         for (int k = 0; k < M; k += 4) {
-            e0 = fma(bcol[k], cp[k], e0);
-            if (k + 1 < M) o0 = fma(bcol[k + 1], cp[k + 1], o0);
-            if (k + 2 < M) e1 = fma(bcol[k + 2], cp[k + 2], e1);
-            if (k + 3 < M) o1 = fma(bcol[k + 3], cp[k + 3], o1);
+            e0 = fma(bcol[k], cv[k], e0);
+            if (k + 1 < M) o0 = fma(bcol[k + 1], cv[k + 1], o0);
+            if (k + 2 < M) e1 = fma(bcol[k + 2], cv[k + 2], e1);
+            if (k + 3 < M) o1 = fma(bcol[k + 3], cv[k + 3], o1);
         }
         const double E = e0 + e1, O = o0 + o1;
         cur[v * lds_ns<M>() + sig * M + n] += p ? ((n & 1) ? O - E : E - O) : E + O;

@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
                     if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
                 }
                 v += z;
-                if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
+                if (dir == 0) v *= (i == 0 ? 1.0 / kPi : 2.0 / kPi);
                 if (i < a.n) out[i] = v;
             }
         }

@@ -41,6 +41,8 @@
 
 namespace l2c {
 
+typedef double d4_t __attribute__((ext_vector_type(4)));   // FP64 MFMA accumulator
+
 __device__ __forceinline__ void store_coherent(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -247,8 +249,8 @@ struct TopSlots {
     }
 };
 
-// The last worker wave of unit X, up to the point where the workgroup's tree-top items sit
-// in LDS (itm, nitem x NS; the near-field area, free once the near waves have counted):
+// The top wave of unit X, while the near field runs, up to the point where the workgroup's
+// tree-top items sit in LDS (itm, nitem x NS, in the T area, which step (1) no longer needs):
 //   1. Nodes 0, 1 of the next unit at depths 1..kd-1 into wl (the streamer waits for them
 //      only when it reaches those depths), and step (2) above the units: unit X with
 //      k = min(3, G0, trailing zeros of X) >= 1 is the leftmost unit below its ancestors at
@@ -258,7 +260,7 @@ struct TopSlots {
 template <int M>
 __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts, int kd, int U, int64_t nbase,
                                            double *wl, double *xs, double *itm, const double *Bl, double *pubc,
-                                           unsigned *nbr, const unsigned *ndone, int lane)
+                                           unsigned *nbr, int lane)
 {
     constexpr int M2 = 2 * M, NS = lds_ns<M>();
     const int X = ts.X, G0 = ts.G0;
@@ -346,18 +348,6 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
     poll_values(
         vc, pubc, [&](int u) { return (u * 64 + lane) / M2 < nitem; },
         [&](int u) { return nid[u] * M2 + (u * 64 + lane) % M2; }, a.status);
-    // the near-field area is free once the near waves have counted
-    if (lane == 0) {
-        int it = 0;
-        while (lds_flag_get(ndone) < (unsigned)kNearWaves) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++it == kSpinLimit) {
-                atomicOr(a.status, 2);
-                break;
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
         const int idx = u * 64 + lane;
@@ -368,16 +358,17 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
 
 // All worker waves, once the items are in LDS (after a worker barrier):
 //   3. the column nodes below level gl, reduced in place (pairwise, level by level; the
-//      pairs of a level are spread over the waves, a barrier between levels);
+//      pairs of a level are spread over the waves, a barrier between levels); a slot's
+//      column node ends up at its first item;
 //   4. wave g <= G0: canc_g = the ancestor a_g's far-field blocks times their column
 //      nodes (the submatrices ag0, ag1 are this wave's rows nn, loaded beforehand);
 //   5. the top wave: the chain of step (4) from level 0 down to the unit root,
 //      c(a_g) = canc_g + B(p)^T c(a_{g-1}), p = a_g & 1, into cR.
 template <int M>
-__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm, const double *Bl,
+__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm,
                                             const double (&ag0)[M], const double (&ag1)[M], double *canc,
-                                            double *zb, double *cR, unsigned *wcnt, unsigned &wtarget, int ww,
-                                            bool top, int lane)
+                                            double *zb, double *cR, const double *Bl, unsigned *wcnt,
+                                            unsigned &wtarget, int ww, bool top, int lane)
 {
     constexpr int M2 = 2 * M, NS = lds_ns<M>();
     const bool act = lane < M2;
@@ -407,16 +398,24 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
     if (ww <= ts.G0) {
         const int g = ww;
         double c0 = 0.0, c1 = 0.0;
-        if (ts.ok(2 * g)) {
-            const double *x0 = itm + ts.base(2 * g) * NS + sg * M;
+        const bool ok0 = ts.ok(2 * g), ok1 = ts.ok(2 * g + 1);
+        const double *x0 = itm + (ok0 ? ts.base(2 * g) : 0) * NS + sg * M;
+        const double *x1 = itm + (ok1 ? ts.base(2 * g + 1) : 0) * NS + sg * M;
+        double xv0[M], xv1[M];
 #pragma unroll
-            for (int l = 0; l < M; ++l) c0 = fma(ag0[l], x0[l], c0);
+        for (int l = 0; l < M; ++l) {
+            xv0[l] = x0[l];
+            xv1[l] = x1[l];
         }
-        if (ts.ok(2 * g + 1)) {
-            const double *x1 = itm + ts.base(2 * g + 1) * NS + sg * M;
+        ops_first<2 * M>();
+        double d0[2] = {0.0, 0.0}, d1[2] = {0.0, 0.0};
 #pragma unroll
-            for (int l = 0; l < M; ++l) c1 = fma(ag1[l], x1[l], c1);
+        for (int l = 0; l < M; ++l) {
+            d0[l & 1] = fma(ag0[l], xv0[l], d0[l & 1]);
+            d1[l & 1] = fma(ag1[l], xv1[l], d1[l & 1]);
         }
+        if (ok0) c0 = d0[0] + d0[1];
+        if (ok1) c1 = d1[0] + d1[1];
         if (act) canc[g * M2 + lane] = c0 + c1;
     }
     worker_sync(wcnt, wtarget, a.status);
@@ -429,10 +428,14 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
             const int p = (int)(ts.anc(g) & 1);
             if (act) zb[lane] = cc;
             wave_lds_sync();
+            double zv[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) zv[k] = zb[sg * M + k];
+            ops_first<M>();
             double q0 = 0.0, q1 = 0.0, q2 = 0.0;       // three chains (latency)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                const double v = zb[sg * M + k];
+                const double v = zv[k];
                 const double t = (p && (k & 1)) ? -v : v;
                 if (k % 3 == 0) q0 = fma(bcol[k], t, q0);
                 else if (k % 3 == 1) q1 = fma(bcol[k], t, q1);
@@ -504,8 +507,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     const int ntid = nw * 64 + lane;
 
     double *Bl = lds;                                 // M*M
-    double *Tl = Bl + M * M;                          // 2 s M
-    double *gp = Tl + 2 * s * M;                      // near-field area: 2 GX input, nQ Q, nP P
+    double *Tl = Bl + M * M;                          // 2 s M (the top wave's items in between)
+    double *gp = Tl + fused_t_area(L, M, s, kd);      // near-field area: 2 GX input, nQ Q, nP P
     double *Ql = gp + 2 * GX;
     double *Pl = Ql + nQ;
     double *wl = gp + fused_near_area(L, M, s, kd);   // fused_wofs(kd + 1) nodes
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     double *w7 = cR + NS;                             // top wave: exchange scratch, then z and canc
     double *dummy = w7 + fused_w7(M, G0);             // 2 NS: stores of out-of-range slots
     unsigned *sync = reinterpret_cast<unsigned *>(dummy + 2 * NS);
-    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *ndone = sync + 3, *qdone = sync + 4;
+    unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *qdone = sync + 4;
 
     const double *in = a.in + item * a.n;
     // exchange nodes: this launch's half, and the next launch's (reset to empty here)
@@ -598,7 +601,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             wcnt[0] = 0;
             rdy[0] = (unsigned)kd + 1;                // no depth ready yet
             nbr[0] = 0;
-            ndone[0] = 0;
             qdone[0] = 0;
         }
         // this unit's exchange nodes in the next launch's half of the buffer: empty again, for
@@ -778,18 +780,30 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
-        if (near) {
-            wave_lds_done();                          // the near-field area is free once all have counted
-            if (lane == 0) __hip_atomic_fetch_add(ndone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
         L2C_TS(3, 4);
         // ---- steps (2)-(4) above the unit (TopSlots, top_gather, top_combine)
         const TopSlots ts(X, G0);
         double ag0[M], ag1[M];
         load_anc_rows<M>(a, ts, ww, lane, ag0, ag1);
+        // T again, for step (5): the near waves load it now and write it once the column
+        // nodes in the T area have been used
+        constexpr int UTR = (kFusedStageT * kWorkThreads + 64 * kNearWaves - 1) / (64 * kNearWaves);
+        double vtr[UTR];
+#pragma unroll
+        for (int u = 0; u < UTR; ++u) {
+            const int e = u * 64 * kNearWaves + ntid;
+            vtr[u] = (near && e < 2 * s * M) ? a.T[e] : 0.0;
+        }
         if (top)
-            top_gather<M>(a, ts, kd, U, nbase, wl, w7, gp, Bl, pubc, nbr, ndone, lane);
-        top_combine<M>(a, ts, gp, Bl, ag0, ag1, w7 + 2 * M2, w7, cR, wcnt, wtarget, ww, top, lane);
+            top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, lane);
+        top_combine<M>(a, ts, Tl, ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget, ww, top, lane);
+        if (near) {
+#pragma unroll
+            for (int u = 0; u < UTR; ++u) {
+                const int e = u * 64 * kNearWaves + ntid;
+                if (e < 2 * s * M) Tl[e] = vtr[u];
+            }
+        }
     }
     __syncthreads();
     L2C_TS(3, 5);
@@ -816,45 +830,95 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     const double *cfine = cown + (nodes - 2) * NS;
     L2C_TS(3, 6);
 
-    // ---- steps (5) and (7): z = sum_k T_k(X_m^sig) c(u)[sig][k] (row nodes u < P - 2)
-    //      + rs * near; leg2cheb divides by c_i pi/2
+    // ---- steps (5) and (7): z = rs * near + sum_k T_k(X_m^sig) c(u)[sig][k] (row nodes
+    //      u < P - 2); leg2cheb divides by c_i pi/2.  The unit's rows are assembled in LDS
+    //      (the near-field area, free by now; node stride 2s+1 against bank conflicts, and
+    //      2 GX > nodes (2s+1) always), then written out in contiguous wave-wide stores.
     double *out = a.out + item * a.n;
+    double *ob = gp;
+    const int OS = 2 * s + 1;
+    // near part (step (7)'s row scale rs for cheb2leg, and its K_00 term)
     if (near && ntid < nwork) {
-        auto eval = [&](int nd, int sig, int m0) {
-            const bool far = u0 + nd < P - 2;
-            double cc[M];
-            const double *cs = cfine + nd * NS + sig * M;
+        const int x = ntid / nodes, nd = ntid % nodes, sig = x & 1, m0 = (x >> 1) * R;
 #pragma unroll
-            for (int k = 0; k < M; ++k) cc[k] = cs[k];
+        for (int r = 0; r < R; ++r) {
+            const int m = m0 + r;
+            if (m < s) {
+                const int64_t i = jb + nd * 2 * s + 2 * m + sig;
+                double v = acc[r];
+                if (dir == 1) {
+                    v *= 2.0 * (double)i + 1.0;
+                    if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
+                }
+                ob[nd * OS + 2 * m + sig] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // far part, step (5): per parity, Z (rows x nodes) = T (rows x M) C (M x nodes) on the
+    // FP64 matrix cores, 16 x 16 tiles, k in steps of 4 (zero padded); lane l supplies
+    // A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4q + l / 16][l % 16], q < 4.
+    {
+        const int mt = (s + 15) / 16, nt = (nodes + 15) / 16, tiles = 2 * mt * nt;
+        const int li = lane & 15, lk = lane >> 4;
+        for (int t = wv; t < tiles; t += NTH / 64) {
+            const int sig = t / (mt * nt), tm = (t / nt) % mt, tn = t % nt;
+            const int ma = tm * 16 + li;                  // A row of this lane
+            const int nb = tn * 16 + li;                  // B column of this lane
+            const bool arow = ma < s, bcol = nb < nodes && u0 + nb < P - 2;
+            const double *ta = Tl + (sig * s + (arow ? ma : 0)) * M;
+            const double *cb = cfine + (bcol ? nb : 0) * NS + sig * M;
+            // operands and the near parts of the tile first (clamped addresses, no branches)
+            constexpr int KS = (M + 3) / 4;
+            double av[KS], bv[KS], ov[4];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int m = m0 + r;
-                if (m < s) {
-                    double z = 0.0;
-                    if (far) {
-                        const double *tt = Tl + (sig * s + m) * M;
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + lk, kc = k < M ? k : M - 1;
+                av[ks] = ta[kc];
+                bv[ks] = cb[kc];
+            }
 #pragma unroll
-                        for (int k = 0; k < M; ++k) z = fma(tt[k], cc[k], z);
-                    }
+            for (int q = 0; q < 4; ++q) {
+                const int m = tm * 16 + 4 * q + lk, nd = tn * 16 + li;
+                ov[q] = ob[(nd < nodes ? nd : 0) * OS + 2 * (m < s ? m : 0) + sig];
+            }
+            ops_first<2 * KS + 4>();
+            d4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bool kin = 4 * ks + lk < M;
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64((arow && kin) ? av[ks] : 0.0, (bcol && kin) ? bv[ks] : 0.0, d,
+                                                         0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = tm * 16 + 4 * q + lk, nd = tn * 16 + li;
+                if (m < s && nd < nodes) {
                     const int64_t i = jb + nd * 2 * s + 2 * m + sig;
-                    double v = acc[r];
-                    if (dir == 1) {
-                        v *= 2.0 * (double)i + 1.0;
-                        if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
-                    }
-                    v += z;
-                    if (dir == 0) v /= (i == 0 ? kPi : 0.5 * kPi);
-                    if (i < a.n) out[i] = v;
+                    double v = ov[q] + d[q];
+                    if (dir == 0) v *= (i == 0 ? 1.0 / kPi : 2.0 / kPi);
+                    ob[nd * OS + 2 * m + sig] = v;
                 }
             }
-        };
-        if (nodes == 64) {
-            // a wave holds one (parity, row block) for 64 nodes: T rows are wave-uniform
-            const int x = __builtin_amdgcn_readfirstlane(nw);
-            eval(lane, x & 1, (x >> 1) * R);
-        } else {
-            const int x = ntid / nodes;
-            eval(ntid % nodes, x & 1, (x >> 1) * R);
+        }
+    }
+    __syncthreads();
+    {
+        // wave wv copies nodes wv, wv + 8, ... (2s <= 64 rows each, one per lane)
+        constexpr int CN = 8;                         // nodes per wave per round (kd <= 7: 128 nodes)
+        for (int nb = wv; nb < nodes; nb += CN * (NTH / 64)) {
+            double v[CN];
+#pragma unroll
+            for (int c = 0; c < CN; ++c) {
+                const int nd = nb + c * (NTH / 64);
+                v[c] = (nd < nodes && lane < 2 * s) ? ob[nd * OS + lane] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < CN; ++c) {
+                const int nd = nb + c * (NTH / 64);
+                const int64_t i = jb + (int64_t)nd * 2 * s + lane;
+                if (nd < nodes && lane < 2 * s && i < a.n) out[i] = v[c];
+            }
         }
     }
     L2C_TS(3, 7);
@@ -894,6 +958,7 @@ hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items)
     const int nodes = 1 << G.kd, R = kFusedRows;
     if (nodes * 2 * ((G.s + R - 1) / R) > 64 * kNearWaves) return hipSuccess;          // near-field items
     if (G.groot > 6 || G.kd > 7) return hipSuccess;                                      // register batches
+    if (2 * G.s > 64) return hipSuccess;                                                 // output copy: a row per lane
     if (2 * (G.s * (nodes + 2) + R) > kFusedStageG * kWorkThreads) return hipSuccess;  // input staging
     if (2 * G.s * G.M > kFusedStageT * kWorkThreads) return hipSuccess;                // T staging
     if (2 * G.s + 2 * R > kWorkThreads) return hipSuccess;                             // P staging

@@ -198,15 +198,21 @@ __host__ __device__ inline int fused_top_items(int groot)
     return 2 * ((1 << (gl + 1)) - 2) + 2 * (H + 1);
 }
 
-// The near-field area: input, Q and P during the near field; afterwards the tree-top
-// nodes that the workgroup reduces itself.
+// The near-field area: input, Q and P during the near field; afterwards the unit's
+// output rows (node stride 2s+1; 2 GX exceeds them).
 __host__ __device__ inline int64_t fused_near_area(int L, int M, int s, int kd)
 {
-    const int groot = L - 1 - kd;
-    const int64_t NS = 2 * M + 1;
-    const int64_t near = 2 * fused_gx(s, kd) + fused_nq(s, kd) + 2 * (int64_t)s + 2 * kFusedRows;
-    const int64_t anc = fused_top_items(groot) * NS;
-    return near > anc ? near : anc;
+    (void)L;
+    (void)M;
+    return 2 * fused_gx(s, kd) + fused_nq(s, kd) + 2 * (int64_t)s + 2 * kFusedRows;
+}
+
+// The T area: T for steps (1) and (5); in between, the tree-top nodes the top wave
+// reduces while the near field runs (T is loaded again afterwards).
+__host__ __device__ inline int64_t fused_t_area(int L, int M, int s, int kd)
+{
+    const int64_t t = 2 * (int64_t)s * M, items = fused_top_items(L - 1 - kd) * (2 * (int64_t)M + 1);
+    return t > items ? t : items;
 }
 
 // Top-wave scratch of k_fused (doubles): the exchange's 2^min(3, groot) nodes of NS,
@@ -226,7 +232,7 @@ inline int64_t fused_lds_doubles(int L, int M, int s, int kd)
     const int64_t nodes = int64_t(1) << kd, NS = 2 * M + 1;
     const int64_t WN = fused_wofs(kd + 1), own = 2 * nodes - 2;
     const int groot = L - 1 - kd;
-    return (int64_t)M * M + 2 * (int64_t)s * M + fused_near_area(L, M, s, kd) + WN * NS + own * NS + NS +
+    return (int64_t)M * M + fused_t_area(L, M, s, kd) + fused_near_area(L, M, s, kd) + WN * NS + own * NS + NS +
            fused_w7(M, groot) + 2 * NS + 4;
 }
 
