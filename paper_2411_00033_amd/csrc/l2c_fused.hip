@@ -257,10 +257,11 @@ struct TopSlots {
 //      levels G0-1 .. G0-k; it reduces the roots of units X .. X+2^k-1 in the scratch xs and
 //      writes those ancestors to the exchange buffer.  Both inputs come in one poll.
 //   2. The items: wait until every one of them is written, loading it in the same polls.
+constexpr int kSchPairs = 3, kSchBase = kSchPairs + 3 * 14;   // reduction schedule (ints)
 template <int M>
 __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts, int kd, int U, int64_t nbase,
                                            double *wl, double *xs, double *itm, const double *Bl, double *pubc,
-                                           unsigned *nbr, int lane)
+                                           unsigned *nbr, int *sch, int lane)
 {
     constexpr int M2 = 2 * M, NS = lds_ns<M>();
     const int X = ts.X, G0 = ts.G0;
@@ -354,9 +355,31 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
         const int i = idx / M2, e = idx - i * M2;
         if (i < nitem) itm[i * NS + e] = vc[u];
     }
+    // 3. the schedule of the reduction (scalar bookkeeping, done once here): per round r the
+    //    item of each pair's left child, and each slot's first item (-1: no block)
+    if (lane == 0) {
+        for (int r = 1; r <= 3; ++r) {
+            const int step = 1 << r;
+            int t = 0, base = 0;
+            for (int sl = 0; sl < ts.nsl; ++sl) {
+                if (!ts.ok(sl)) continue;
+                const int c = ts.cnt(sl);
+                if (r <= ts.gl)
+                    for (int pp = 0; pp + step <= c; pp += step) sch[kSchPairs + 14 * (r - 1) + t++] = base + pp;
+                base += c;
+            }
+            sch[r - 1] = t;
+        }
+        int base = 0;
+        for (int sl = 0; sl < 14; ++sl) {
+            const bool ok = sl < ts.nsl && ts.ok(sl);
+            sch[kSchBase + sl] = ok ? base : -1;
+            base += ok ? ts.cnt(sl) : 0;
+        }
+    }
 }
 
-// All worker waves, once the items are in LDS (after a worker barrier):
+// All worker waves, once the items and the schedule are in LDS (after a worker barrier):
 //   3. the column nodes below level gl, reduced in place (pairwise, level by level; the
 //      pairs of a level are spread over the waves, a barrier between levels); a slot's
 //      column node ends up at its first item;
@@ -365,7 +388,7 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
 //   5. the top wave: the chain of step (4) from level 0 down to the unit root,
 //      c(a_g) = canc_g + B(p)^T c(a_{g-1}), p = a_g & 1, into cR.
 template <int M>
-__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm,
+__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm, const int *sch,
                                             const double (&ag0)[M], const double (&ag1)[M], double *canc,
                                             double *zb, double *cR, const double *Bl, unsigned *wcnt,
                                             unsigned &wtarget, int ww, bool top, int lane)
@@ -373,24 +396,17 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
     constexpr int M2 = 2 * M, NS = lds_ns<M>();
     const bool act = lane < M2;
     const int sg = lane >= M ? 1 : 0, nn = act ? lane - sg * M : 0;
-    worker_sync(wcnt, wtarget, a.status);             // items in LDS
     if (ts.gl > 0) {
         double brow[M];
 #pragma unroll
         for (int kk = 0; kk < M; ++kk) brow[kk] = Bl[nn * M + kk];
         for (int r = 1; r <= ts.gl; ++r) {
-            const int step = 1 << r;
-            int t = 0, base = 0;
-            for (int sl = 0; sl < ts.nsl; ++sl) {
-                if (!ts.ok(sl)) continue;
-                const int c = ts.cnt(sl);
-                for (int pp = 0; pp + step <= c; pp += step, ++t) {
-                    if (t % kWorkWaves != ww) continue;
-                    const double *x = itm + (base + pp) * NS + sg * M, *y = x + (step >> 1) * NS;
-                    const double v = up_pair<M>(brow, x, y, nn);
-                    if (act) itm[(base + pp) * NS + lane] = v;
-                }
-                base += c;
+            const int np = sch[r - 1], half = (1 << (r - 1)) * NS;
+            for (int t = ww; t < np; t += kWorkWaves) {
+                const int xi = sch[kSchPairs + 14 * (r - 1) + t];
+                const double *x = itm + xi * NS + sg * M;
+                const double v = up_pair<M>(brow, x, x + half, nn);
+                if (act) itm[xi * NS + lane] = v;
             }
             worker_sync(wcnt, wtarget, a.status);
         }
@@ -398,9 +414,10 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
     if (ww <= ts.G0) {
         const int g = ww;
         double c0 = 0.0, c1 = 0.0;
-        const bool ok0 = ts.ok(2 * g), ok1 = ts.ok(2 * g + 1);
-        const double *x0 = itm + (ok0 ? ts.base(2 * g) : 0) * NS + sg * M;
-        const double *x1 = itm + (ok1 ? ts.base(2 * g + 1) : 0) * NS + sg * M;
+        const int b0 = sch[kSchBase + 2 * g], b1 = sch[kSchBase + 2 * g + 1];
+        const bool ok0 = b0 >= 0, ok1 = b1 >= 0;
+        const double *x0 = itm + (ok0 ? b0 : 0) * NS + sg * M;
+        const double *x1 = itm + (ok1 ? b1 : 0) * NS + sg * M;
         double xv0[M], xv1[M];
 #pragma unroll
         for (int l = 0; l < M; ++l) {
@@ -503,7 +520,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     // the top wave shares a SIMD with the streamer (waves w and w + 4 pair up), so the
     // near-field waves, which keep the FP64 pipes busy, do not slow its latency-bound chain
     const bool top = wv == kTopWave, near = !streamer && !top;
-    const int nw = top ? kNearWaves : wv < kTopWave ? wv - NSW : wv - NSW - 1;   // near-field wave
+    // near-field wave index; item blocks of 6, 5, 4 window steps (x = nw >> 1) are paired on
+    // the three SIMDs as (0, 4), (1, 5), (2, 3): 10 steps each
+    const int nw = top ? kNearWaves : wv < kTopWave ? wv - NSW : (wv == 7 ? 3 : wv - NSW);
     const int ntid = nw * 64 + lane;
 
     double *Bl = lds;                                 // M*M
@@ -795,8 +814,28 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             vtr[u] = (near && e < 2 * s * M) ? a.T[e] : 0.0;
         }
         if (top)
-            top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, lane);
-        top_combine<M>(a, ts, Tl, ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget, ww, top, lane);
+            top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, reinterpret_cast<int *>(w7), lane);
+        worker_sync(wcnt, wtarget, a.status);         // items and schedule in LDS; near field done
+        // the near part of the unit's output rows (step (7)'s row scale rs for cheb2leg, and
+        // its K_00 term) into the near-field area, now free: node stride 2s+1
+        if (near && ntid < nwork) {
+            const int x = ntid / nodes, nd = ntid % nodes, sig = x & 1, m0 = (x >> 1) * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int m = m0 + r;
+                if (m < s) {
+                    double v = acc[r];
+                    if (dir == 1) {
+                        const int64_t i = jb + nd * 2 * s + 2 * m + sig;
+                        v *= 2.0 * (double)i + 1.0;
+                        if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
+                    }
+                    gp[nd * (2 * s + 1) + 2 * m + sig] = v;
+                }
+            }
+        }
+        top_combine<M>(a, ts, Tl, reinterpret_cast<const int *>(w7), ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget,
+                       ww, top, lane);
         if (near) {
 #pragma unroll
             for (int u = 0; u < UTR; ++u) {
@@ -837,32 +876,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     double *out = a.out + item * a.n;
     double *ob = gp;
     const int OS = 2 * s + 1;
-    // near part (step (7)'s row scale rs for cheb2leg, and its K_00 term)
-    if (near && ntid < nwork) {
-        const int x = ntid / nodes, nd = ntid % nodes, sig = x & 1, m0 = (x >> 1) * R;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int m = m0 + r;
-            if (m < s) {
-                const int64_t i = jb + nd * 2 * s + 2 * m + sig;
-                double v = acc[r];
-                if (dir == 1) {
-                    v *= 2.0 * (double)i + 1.0;
-                    if (i == 0) v += in[0];      // K_00 u_0 = u_0 / 2 = f_0
-                }
-                ob[nd * OS + 2 * m + sig] = v;
-            }
-        }
-    }
-    __syncthreads();
+    // (the near part is already in ob, written after the near field)
     // far part, step (5): per parity, Z (rows x nodes) = T (rows x M) C (M x nodes) on the
     // FP64 matrix cores, 16 x 16 tiles, k in steps of 4 (zero padded); lane l supplies
     // A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4q + l / 16][l % 16], q < 4.
     {
-        const int mt = (s + 15) / 16, nt = (nodes + 15) / 16, tiles = 2 * mt * nt;
+        const int lmt = s > 16 ? 1 : 0, lnt = kd > 4 ? kd - 4 : 0;   // row and node tiles: 2^lmt, 2^lnt
+        const int tiles = 2 << (lmt + lnt);
         const int li = lane & 15, lk = lane >> 4;
         for (int t = wv; t < tiles; t += NTH / 64) {
-            const int sig = t / (mt * nt), tm = (t / nt) % mt, tn = t % nt;
+            const int tn = t & ((1 << lnt) - 1), tm = (t >> lnt) & lmt, sig = t >> (lnt + lmt);
             const int ma = tm * 16 + li;                  // A row of this lane
             const int nb = tn * 16 + li;                  // B column of this lane
             const bool arow = ma < s, bcol = nb < nodes && u0 + nb < P - 2;
@@ -894,9 +917,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             for (int q = 0; q < 4; ++q) {
                 const int m = tm * 16 + 4 * q + lk, nd = tn * 16 + li;
                 if (m < s && nd < nodes) {
-                    const int64_t i = jb + nd * 2 * s + 2 * m + sig;
+                    const bool i0 = X == 0 && nd == 0 && m == 0 && sig == 0;   // global row 0
                     double v = ov[q] + d[q];
-                    if (dir == 0) v *= (i == 0 ? 1.0 / kPi : 2.0 / kPi);
+                    if (dir == 0) v *= (i0 ? 1.0 / kPi : 2.0 / kPi);
                     ob[nd * OS + 2 * m + sig] = v;
                 }
             }
