@@ -484,6 +484,48 @@ __device__ __forceinline__ void load_anc_rows(const ExecArgs &a, const TopSlots 
     }
 }
 
+// Step (6) for one item (node, parity sig, rows m0 .. m0+R-1): row m sums over m' in
+// [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig], with P, Q and g entering
+// through circular register windows (slot t of a step holds m' = mb + t; m0 is a multiple
+// of R).  Each step's operands are loaded before its products.  GPAD, QPAD: the pads of
+// the node strides of g (between nodes) and Q (one, at 2s), known at compile time so that
+// the index arithmetic vanishes where they are zero.
+template <int R, int GPAD, int QPAD>
+__device__ __forceinline__ void near_item(double (&acc)[R], const double *gs, const double *qs, const double *ps,
+                                          int s, int sig, int m0)
+{
+    double pb[R], qb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) pb[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R - 1; ++r) {
+        const int c = sig + 2 * m0 + r;
+        qb[r] = qs[c + (QPAD && c >= 2 * s ? 1 : 0)];
+    }
+    const int steps = ((2 * s - m0) + R - 1) / R;
+    for (int st = 0; st < steps; ++st) {
+        const int mb = m0 + st * R, cb = sig + m0 + mb + R - 1;
+        double pn[R], qn[R], gn[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int mp = mb + t, c = cb + t;
+            pn[t] = ps[mp];
+            qn[t] = qs[c + (QPAD && c >= 2 * s ? 1 : 0)];
+            gn[t] = gs[mp + (GPAD ? (mp >= s ? 1 : 0) + (mp >= 2 * s ? 1 : 0) : 0)];
+        }
+        ops_first<3 * R>();
+        const bool tail = mb + R > 2 * s;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            pb[t] = pn[t];
+            qb[(t + R - 1) % R] = qn[t];
+            const double gv = (tail && mb + t >= 2 * s) ? 0.0 : gn[t];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[r]);
+        }
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 {
@@ -645,42 +687,41 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         //      group are loaded as soon as the same row of this group has been used.
         // ---- step (1): w_k(t, sigma) = sum_m T_k(X_m^sigma) f[2s t + 2m + sigma] (Eq. (wMM))
         //      for the unit's finest nodes and the next unit's first two (its finest-depth
-        //      neighbours).  Worker wave -> (sigma, third of k), so a T value is the same for
-        //      the whole wave (LDS broadcast); lane -> nodes lane and lane + H, H = half the
-        //      node count rounded up, so every T value read feeds two products.  The last
-        //      third repeats k = M-1 in its spare slots (no branches in the loop).
+        //      neighbours): per parity the product W (node x k) = F (node x m) T (m x k), on the
+        //      FP64 matrix cores in 16 x 16 tiles, m in steps of 4 (zero padded); lane l
+        //      supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4q + l / 16][l % 16].
         {
-            constexpr int KT = (M + 2) / 3;
-            const int sig = nw & 1, kb = (nw >> 1) * KT;
-            const double *Ts = Tl + sig * s * M;
-            int kc[KT];
+            constexpr int KTL = (M + 15) / 16;                  // mode tiles
+            const int nall = nodes + 2, ntl = (nall + 15) / 16, tiles = 2 * ntl * KTL;
+            const int li = lane & 15, lk = lane >> 4;
+            for (int t = ww; t < tiles; t += kWorkWaves) {
+                const int kt = t % KTL, rest = t / KTL, ntile = rest % ntl, sig = rest / ntl;
+                const int na = ntile * 16 + li, kb = kt * 16 + li;
+                const bool arow = na < nall, bcol = kb < M;
+                const double *fa = gp + sig * GX + (arow ? na : 0) * GS;
+                const double *tb = Tl + sig * s * M + (bcol ? kb : 0);
+                double av[8], bv[8];                              // s <= 32: at most 8 steps
 #pragma unroll
-            for (int kk = 0; kk < KT; ++kk) kc[kk] = kb + kk < M ? kb + kk : M - 1;
-            const int nall = nodes + 2, H = (nall + 1) >> 1;
-            for (int n0 = top ? H : lane; n0 < H; n0 += 64) {   // six waves: (sigma, third)
-                const int n1 = n0 + H < nall ? n0 + H : n0;     // odd count: the last lane repeats
-                double a0[KT], a1[KT];
+                for (int st = 0; st < 8; ++st) {
+                    const int m = 4 * st + lk, mc = m < s ? m : s - 1;
+                    av[st] = fa[mc];
+                    bv[st] = tb[mc * M];
+                }
+                ops_first<16>();
+                d4_t d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk) a0[kk] = a1[kk] = 0.0;
-                const double *f0 = gp + sig * GX + n0 * GS, *f1 = gp + sig * GX + n1 * GS;
-#pragma unroll 4
-                for (int m = 0; m < s; ++m) {
-                    const double x0 = f0[m], x1 = f1[m];
-#pragma unroll
-                    for (int kk = 0; kk < KT; ++kk) {
-                        const double t = Ts[m * M + kc[kk]];
-                        a0[kk] = fma(t, x0, a0[kk]);
-                        a1[kk] = fma(t, x1, a1[kk]);
+                for (int st = 0; st < 8; ++st) {
+                    if (4 * st < s) {
+                        const bool min = 4 * st + lk < s;
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64((min && arow) ? av[st] : 0.0,
+                                                                 (min && bcol) ? bv[st] : 0.0, d, 0, 0, 0);
                     }
                 }
-                double *w0 = wl + (fused_wofs(kd) + n0) * NS + sig * M;   // nodes >= 2^kd: neighbour slots
-                double *w1 = wl + (fused_wofs(kd) + n1) * NS + sig * M;
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk)
-                    if (kb + kk < M) {
-                        w0[kb + kk] = a0[kk];
-                        w1[kb + kk] = a1[kk];
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const int node = ntile * 16 + 4 * q + lk;     // nodes >= 2^kd: neighbour slots
+                    if (node < nall && bcol) wl[(fused_wofs(kd) + node) * NS + sig * M + kb] = d[q];
+                }
             }
         }
         worker_sync(wcnt, wtarget, a.status);
@@ -773,30 +814,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             const double *gs = gp + sig * GX + nd * GS;
             const double *qs = Ql + nd * QS;
             const double *ps = Pl + (R - 1) - m0;
-            double pb[R], qb[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) pb[r] = 0.0;
-            // window slots are compile-time: slot t of a step holds m' = mb + t (m0 is a multiple of R)
-#pragma unroll
-            for (int r = 0; r < R - 1; ++r) {
-                const int c = sig + 2 * m0 + r;
-                qb[r] = qs[c + (c >= 2 * s ? qpad : 0)];
-            }
-            const int steps = ((2 * s - m0) + R - 1) / R;
-            for (int st = 0; st < steps; ++st) {
-                const int mb = m0 + st * R;
-                const bool tail = mb + R > 2 * s;
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int mp = mb + t;
-                    pb[t] = ps[mp];
-                    const int c = sig + m0 + mp + R - 1;
-                    qb[(t + R - 1) % R] = qs[c + (c >= 2 * s ? qpad : 0)];
-                    double gv = gs[mp + (mp >= s ? gpad : 0) + (mp >= 2 * s ? gpad : 0)];
-                    if (tail && mp >= 2 * s) gv = 0.0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[r]);
-                }
+            switch (gpad * 2 + qpad) {                    // the pads are wave-uniform
+            case 0: near_item<R, 0, 0>(acc, gs, qs, ps, s, sig, m0); break;
+            case 1: near_item<R, 0, 1>(acc, gs, qs, ps, s, sig, m0); break;
+            case 2: near_item<R, 1, 0>(acc, gs, qs, ps, s, sig, m0); break;
+            default: near_item<R, 1, 1>(acc, gs, qs, ps, s, sig, m0); break;
             }
         }
         L2C_TS(3, 4);
