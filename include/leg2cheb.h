@@ -170,6 +170,48 @@ int leg2cheb_plan_status(l2c_plan_t plan, int *status);
  */
 int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after);
 
+/*
+ * Ragged batches: count independent transforms of different lengths and directions
+ * (Alg. 4 for each), planned together and executed as one call.
+ */
+typedef struct l2c_batch_s *l2c_batch_t;
+
+/*
+ * Plan a ragged batch.  Transforms whose sizes give the same levels L and half-leaf s
+ * (Eq. (numlevels)) and the same direction have identical far-field tables (the tables
+ * depend on L, s, M and the kernel only), so they form one group with one set of
+ * tables; a group executes as one launch sequence over its items, each item with its
+ * own length.  L = 0 transforms (Alg. 1 directly) group by direction.
+ *   batch      [out] receives the new handle (NULL on error).
+ *   count      number of transforms, >= 1.
+ *   n          host array [count], each >= 1 (lengths are not limited otherwise).
+ *   direction  host array [count] of L2C_LEG2CHEB / L2C_CHEB2LEG.
+ *   leaf_size, rank, precision   as in leg2cheb_plan_ex, shared by all transforms.
+ *   stream     hipStream_t for the table-building kernels (NULL = null stream).
+ * The call returns after every group's tables are built.  Device memory: one plan per
+ * group plus count entries of lengths and pointers.
+ * Errors: L2C_EINVAL, L2C_EUNSUPPORTED (rank, precision), L2C_ENOMEM, L2C_EHIP.
+ */
+int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction,
+                        int leaf_size, int rank, int precision, void *stream);
+
+/*
+ * out[i][0:n[i]] = T_i(in[i][0:n[i]]) for i < count, T_i the transform of item i.
+ *   in, out  host arrays [count] of device pointers (FP64, n[i] values each); no output
+ *            may overlap any input or another output.
+ *   stream   hipStream_t.
+ * Copies the pointer lists to the device (through pinned memory owned by the batch)
+ * and enqueues every group on stream; allocates nothing.  A later call first waits
+ * for the previous call's pointer copy.  On L2C_EHIP, the outputs are undefined.
+ */
+int leg2cheb_batch_execute(l2c_batch_t batch, const double *const *in, double *const *out, void *stream);
+
+/* Groups of the batch and the total device bytes of their tables. */
+int leg2cheb_batch_info(l2c_batch_t batch, int64_t *groups, int64_t *table_bytes);
+
+/* Release the batch (synchronizes the device first).  NULL is a no-op. */
+int leg2cheb_batch_destroy(l2c_batch_t batch);
+
 /* Non-zero if this build instantiates kernels for rank M. */
 int leg2cheb_rank_supported(int rank);
 

@@ -19,7 +19,8 @@ from ._lib import (  # noqa: F401  (re-exported ABI names)
     L2C_LEG2CHEB, L2C_OK, L2C_OPT_SINGLE_LAUNCH, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_THREE, L2CError,
     TABLE_AHAT, TABLE_B, TABLE_T, leg2cheb_destroy, leg2cheb_execute, leg2cheb_plan, leg2cheb_plan_ex,
     leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
-    leg2cheb_rank_supported, leg2cheb_set_timing_events,
+    leg2cheb_rank_supported, leg2cheb_set_timing_events, leg2cheb_batch_plan, leg2cheb_batch_execute,
+    leg2cheb_batch_info, leg2cheb_batch_destroy,
 )
 
 LEG2CHEB, CHEB2LEG = L2C_LEG2CHEB, L2C_CHEB2LEG
@@ -89,6 +90,64 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "handle", None):
             leg2cheb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class BatchPlan:
+    """A ragged batch: transforms of lengths n[i] and directions direction[i], planned together
+    (one table set per group of equal levels, half-leaf and direction)."""
+
+    def __init__(self, n, direction, leaf_size: int = 64, rank: int = 18, precision: int = L2C_FP64, stream=None):
+        torch = _torch()
+        if len(n) != len(direction) or len(n) == 0:
+            raise ValueError("n and direction must be non-empty and of equal length")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.cuda.current_device()
+        self.n = [int(v) for v in n]
+        self.direction = [int(v) for v in direction]
+        self.handle = leg2cheb_batch_plan(self.n, self.direction, leaf_size, rank, precision, st.cuda_stream)
+
+    @property
+    def info(self) -> dict:
+        return leg2cheb_batch_info(self.handle)
+
+    def execute(self, xs, outs=None, stream=None):
+        """Transform every xs[i] (float64 CUDA tensor of n[i] values) into outs[i]."""
+        torch = _torch()
+        if len(xs) != len(self.n):
+            raise ValueError("expected %d input tensors" % len(self.n))
+        for x, n in zip(xs, self.n):
+            if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != n:
+                raise ValueError("each input must be a contiguous float64 CUDA tensor of its length")
+            if x.device.index != self.device:
+                raise ValueError("inputs must be on cuda:%d" % self.device)
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for o, n in zip(outs, self.n):
+            if o.dtype != torch.float64 or not o.is_cuda or not o.is_contiguous() or o.numel() != n:
+                raise ValueError("each output must be a contiguous float64 CUDA tensor of its length")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        leg2cheb_batch_execute(self.handle, [x.data_ptr() for x in xs], [o.data_ptr() for o in outs],
+                               st.cuda_stream)
+        return outs
+
+    __call__ = execute
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            leg2cheb_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -23,6 +23,7 @@ EXPORTED = (
     "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_destroy", "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
+    "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
 )
 
 
@@ -70,6 +71,11 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_rank_supported.argtypes = [ci]
     lib.leg2cheb_strerror.argtypes = [ci]
     lib.leg2cheb_strerror.restype = ctypes.c_char_p
+    lib.leg2cheb_batch_plan.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(i64), ctypes.POINTER(ci), ci, ci, ci,
+                                        vp]
+    lib.leg2cheb_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.leg2cheb_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.leg2cheb_batch_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name != "leg2cheb_strerror":
             getattr(lib, name).restype = ci
@@ -144,3 +150,33 @@ def leg2cheb_set_timing_events(plan: int, before: int, after: int) -> None:
 
 def leg2cheb_rank_supported(rank: int) -> bool:
     return bool(load().leg2cheb_rank_supported(int(rank)))
+
+
+def leg2cheb_batch_plan(n, direction, leaf_size: int = 64, rank: int = 18, precision: int = L2C_FP64,
+                        stream: int = 0) -> int:
+    count = len(n)
+    na = (ctypes.c_int64 * count)(*[int(v) for v in n])
+    da = (ctypes.c_int * count)(*[int(v) for v in direction])
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_batch_plan(ctypes.byref(h), count, na, da, int(leaf_size), int(rank), int(precision),
+                                      ctypes.c_void_p(stream or None)), "leg2cheb_batch_plan")
+    return h.value
+
+
+def leg2cheb_batch_execute(batch: int, in_ptrs, out_ptrs, stream: int = 0) -> None:
+    count = len(in_ptrs)
+    ia = (ctypes.c_void_p * count)(*[int(p) for p in in_ptrs])
+    oa = (ctypes.c_void_p * count)(*[int(p) for p in out_ptrs])
+    _check(load().leg2cheb_batch_execute(ctypes.c_void_p(batch), ia, oa, ctypes.c_void_p(stream or None)),
+           "leg2cheb_batch_execute")
+
+
+def leg2cheb_batch_info(batch: int) -> dict:
+    g, t = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load().leg2cheb_batch_info(ctypes.c_void_p(batch), ctypes.byref(g), ctypes.byref(t)),
+           "leg2cheb_batch_info")
+    return {"groups": g.value, "table_bytes": t.value}
+
+
+def leg2cheb_batch_destroy(batch: int) -> None:
+    _check(load().leg2cheb_batch_destroy(ctypes.c_void_p(batch)), "leg2cheb_batch_destroy")

@@ -125,6 +125,35 @@ void free_plan(l2c_plan_s *p)
 
 bool use_fused(const l2c_plan_s *p) { return p->fused_ok && p->fused_on; }
 
+}  // namespace
+
+struct l2c_batch_s {
+    int device = 0;
+    int64_t count = 0;
+    std::vector<int64_t> n;                 // caller order
+    std::vector<l2c_plan_s *> plans;        // one per group
+    std::vector<int64_t> gstart;            // group g holds positions [gstart[g], gstart[g+1])
+    std::vector<int64_t> order;             // position -> caller index
+    int64_t *d_n = nullptr;                 // [count] lengths, in position order
+    const double **d_in = nullptr;          // [count] input pointers, in position order
+    double **d_out = nullptr;               // [count] output pointers, in position order
+    void *h_stage = nullptr;                // pinned [2][count] pointers for the copies
+    hipEvent_t staged = nullptr;            // the last pointer copy
+};
+
+namespace {
+
+void free_batch(l2c_batch_s *b)
+{
+    for (l2c_plan_s *p : b->plans) leg2cheb_destroy(p);
+    (void)hipFree(b->d_n);
+    (void)hipFree((void *)b->d_in);
+    (void)hipFree(b->d_out);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+}
+
 int ensure_workspace(l2c_plan_s *p, int64_t batch)
 {
     if (p->L == 0 || batch <= p->ws_batch) return L2C_OK;
@@ -158,6 +187,154 @@ const char *leg2cheb_strerror(int code)
     case L2C_EUNSUPPORTED: return "unsupported configuration";
     default: return "unknown status";
     }
+}
+
+int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction,
+                        int leaf_size, int rank, int precision, void *stream)
+{
+    if (!batch) return L2C_EINVAL;
+    *batch = nullptr;
+    if (count < 1 || !n || !direction) return L2C_EINVAL;
+    for (int64_t i = 0; i < count; ++i)
+        if (n[i] < 1 || (direction[i] != L2C_LEG2CHEB && direction[i] != L2C_CHEB2LEG)) return L2C_EINVAL;
+    if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
+    if (precision != L2C_FP64) return L2C_EUNSUPPORTED;
+    if (!leg2cheb_rank_supported(rank)) return L2C_EUNSUPPORTED;
+    l2c_batch_s *b = new (std::nothrow) l2c_batch_s;
+    if (!b) return L2C_ENOMEM;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return L2C_EHIP;
+    }
+    b->count = count;
+    // group key (L, s, direction); L = 0 transforms: s = 0, one group per direction
+    struct Key {
+        int L, s, dir;
+        int64_t first;
+    };
+    std::vector<Key> keys;
+    std::vector<int> gof(count);
+    for (int64_t i = 0; i < count; ++i) {
+        int L, sz;
+        int64_t np;
+        plan_sizes(n[i], leaf_size, &L, &sz, &np);
+        int g = -1;
+        for (size_t k = 0; k < keys.size(); ++k)
+            if (keys[k].L == L && keys[k].s == sz && keys[k].dir == direction[i]) {
+                g = (int)k;
+                break;
+            }
+        if (g < 0) {
+            keys.push_back({L, sz, direction[i], i});
+            g = (int)keys.size() - 1;
+        }
+        gof[i] = g;
+    }
+    const int G = (int)keys.size();
+    b->gstart.assign(G + 1, 0);
+    for (int64_t i = 0; i < count; ++i) ++b->gstart[gof[i] + 1];
+    for (int g = 0; g < G; ++g) b->gstart[g + 1] += b->gstart[g];
+    b->order.resize(count);
+    std::vector<int64_t> fill(b->gstart.begin(), b->gstart.end() - 1), nord(count);
+    for (int64_t i = 0; i < count; ++i) {
+        b->order[fill[gof[i]]] = i;
+        nord[fill[gof[i]]++] = n[i];
+    }
+    int rc = L2C_OK;
+    for (int g = 0; g < G && rc == L2C_OK; ++g) {
+        int64_t nmax = 0;
+        for (int64_t k = b->gstart[g]; k < b->gstart[g + 1]; ++k) nmax = std::max(nmax, nord[k]);
+        l2c_plan_t pl = nullptr;
+        rc = leg2cheb_plan_ex(&pl, nmax, keys[g].dir, leaf_size, rank, precision, b->gstart[g + 1] - b->gstart[g],
+                              stream);
+        if (rc == L2C_OK) b->plans.push_back(pl);
+    }
+    const size_t cb = (size_t)count * sizeof(void *);
+    if (rc == L2C_OK &&
+        (hipMalloc(&b->d_n, (size_t)count * sizeof(int64_t)) != hipSuccess || hipMalloc(&b->d_in, cb) != hipSuccess ||
+         hipMalloc(&b->d_out, cb) != hipSuccess || hipHostMalloc(&b->h_stage, 2 * cb, hipHostMallocDefault) != hipSuccess ||
+         hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess))
+        rc = L2C_ENOMEM;
+    if (rc == L2C_OK && hipMemcpy(b->d_n, nord.data(), (size_t)count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+        rc = L2C_EHIP;
+    if (rc != L2C_OK) {
+        (void)hipGetLastError();
+        free_batch(b);
+        return rc;
+    }
+    b->n.assign(n, n + count);
+    *batch = b;
+    return L2C_OK;
+}
+
+int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const *out, void *stream)
+{
+    if (!b || !in || !out) return L2C_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
+    if (dev != b->device) return L2C_EINVAL;
+    // every output disjoint from every input and every other output
+    std::vector<std::pair<const char *, const char *>> outs(b->count);
+    for (int64_t i = 0; i < b->count; ++i) {
+        if (!in[i] || !out[i]) return L2C_EINVAL;
+        outs[i] = {(const char *)out[i], (const char *)(out[i] + b->n[i])};
+    }
+    std::sort(outs.begin(), outs.end());
+    for (int64_t i = 1; i < b->count; ++i)
+        if (outs[i].first < outs[i - 1].second) return L2C_EINVAL;
+    for (int64_t i = 0; i < b->count; ++i) {
+        const char *lo = (const char *)in[i], *hi = (const char *)(in[i] + b->n[i]);
+        auto it = std::lower_bound(outs.begin(), outs.end(), std::make_pair(hi, hi));
+        if (it != outs.begin() && std::prev(it)->second > lo) return L2C_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (hipEventSynchronize(b->staged) != hipSuccess) return L2C_EHIP;   // previous pointer copy done
+    const double **si = (const double **)b->h_stage;
+    double **so = (double **)b->h_stage + b->count;
+    for (int64_t k = 0; k < b->count; ++k) {
+        si[k] = in[b->order[k]];
+        so[k] = out[b->order[k]];
+    }
+    const size_t cb = (size_t)b->count * sizeof(void *);
+    if (hipMemcpyAsync(b->d_in, si, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_out, so, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(b->staged, st) != hipSuccess)
+        return L2C_EHIP;
+    for (size_t g = 0; g < b->plans.size(); ++g) {
+        l2c_plan_s *p = b->plans[g];
+        const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
+        const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
+        if (p->L > 0 && use_fused(p)) {
+            const int rc = ensure_workspace(p, std::min(items, p->fused_items));
+            if (rc != L2C_OK) return rc;
+            if (l2c::launch_fused(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+        } else {
+            const int rc = ensure_workspace(p, items);
+            if (rc != L2C_OK) return rc;
+            if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+        }
+    }
+    return L2C_OK;
+}
+
+int leg2cheb_batch_info(l2c_batch_t b, int64_t *groups, int64_t *table_bytes)
+{
+    if (!b) return L2C_EINVAL;
+    if (groups) *groups = (int64_t)b->plans.size();
+    if (table_bytes) {
+        int64_t t = 0;
+        for (l2c_plan_s *p : b->plans) t += p->table_bytes;
+        *table_bytes = t;
+    }
+    return L2C_OK;
+}
+
+int leg2cheb_batch_destroy(l2c_batch_t b)
+{
+    if (!b) return L2C_OK;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    free_batch(b);
+    return ok ? L2C_OK : L2C_EHIP;
 }
 
 int leg2cheb_rank_supported(int rank) { return rank_supported(rank) ? 1 : 0; }

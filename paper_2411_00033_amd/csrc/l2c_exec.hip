@@ -42,7 +42,8 @@ __global__ __launch_bounds__(kThreads) void k_up(ExecArgs a)
     const int lane = tid & 63, wv = wave_id();
 
     // stage the input: zero past n; cheb2leg uses u = c .* f (u_0 = 2 f_0), Sec. 4.1
-    const double *in = a.in + item * a.n;
+    const int64_t n_it = a.item_n ? a.item_n[item] : a.n;
+    const double *in = a.item_in ? a.item_in[item] : a.in + item * a.n;
     const int64_t base = t0 * 2 * s;
     {
         constexpr int U = 8;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void k_up(ExecArgs a)
             for (int u = 0; u < U; ++u) {
                 const int e = b0 + u * kThreads + tid;
                 const int64_t gi = base + e;
-                v[u] = (e < cnt && gi < a.n) ? in[gi] : 0.0;
+                v[u] = (e < cnt && gi < n_it) ? in[gi] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
     double *Ql = gp + 2 * GX;                         // nQ
     double *Pl = Ql + nQ;                             // nP
 
-    const double *in = a.in + item * a.n;
+    const int64_t n_it = a.item_n ? a.item_n[item] : a.n;
+    const double *in = a.item_in ? a.item_in[item] : a.in + item * a.n;
     const double *wgl = a.w + item * G.NT * M2;
     const int64_t jb = u0 * 2 * s;                    // first row of the subtree
 
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
         const int e = u * kMainThreads + tid;              // e = sig * GXL + x
         const int sig = e >= GXL, x = e - sig * GXL;
         const int64_t j = jb + 2 * (int64_t)x + sig;
-        vg[u] = (e < cntg && x < s * (nodes + 1) && j < a.n) ? in[j] : 0.0;
+        vg[u] = (e < cntg && x < s * (nodes + 1) && j < n_it) ? in[j] : 0.0;
     }
     // ---- the wave's first far-field group goes in flight behind them
     const int nslots = (nodes - 1) * M;
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
 
     // ---- steps (5) and (7) for the thread's rows: z = sum_k T_k(X_m^sig) c(u)[sig][k]
     //      (row nodes u < P - 2) + rs * near; leg2cheb divides by c_i pi/2
-    double *out = a.out + item * a.n;
+    double *out = a.item_out ? a.item_out[item] : a.out + item * a.n;
 #pragma unroll
     for (int it = 0; it < kNearItems; ++it) {
         const int wi = lane + 64 * (wv + (kMainThreads / 64) * it);
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
                 }
                 v += z;
                 if (dir == 0) v *= (i == 0 ? 1.0 / kPi : 2.0 / kPi);
-                if (i < a.n) out[i] = v;
+                if (i < n_it) out[i] = v;
             }
         }
     }
@@ -457,14 +459,18 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
 
 // ------------------------------------------------------------------------------------
 // k_direct: plans with L = 0 (n <= leaf): the whole product directly (Alg. 1 per row).
-__global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *out, int64_t n, int dir)
+__global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *out, int64_t nmax, int dir,
+                                                     const int64_t *item_n, const double *const *item_in,
+                                                     double *const *item_out)
 {
     extern __shared__ double lds[];
-    double *gl = lds;          // n
-    double *Ql = gl + n;       // n
-    double *Pl = Ql + n;       // n
+    double *gl = lds;          // nmax
+    double *Ql = gl + nmax;    // nmax
+    double *Pl = Ql + nmax;    // nmax
     const int64_t item = blockIdx.x;
-    const double *x = in + item * n;
+    const int64_t n = item_n ? item_n[item] : nmax;   // ragged batch: this item's length (<= nmax)
+    const double *x = item_in ? item_in[item] : in + item * nmax;
+    double *y = item_out ? item_out[item] : out + item * nmax;
     for (int64_t e = threadIdx.x; e < n; e += kThreads) {
         double v = x[e];
         if (dir == 1) v *= (double)e;
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *o
         } else {
             acc /= (i == 0 ? kPi : 0.5 * kPi);
         }
-        out[item * n + i] = acc;
+        y[i] = acc;
     }
 }
 
@@ -507,11 +513,15 @@ static size_t main_lds_bytes(const Geometry &G)
 }
 
 template <int M>
-static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st)
+static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                      const ItemArrays *ia)
 {
     const Geometry &G = p.geo;
     ExecArgs a;
     a.n = p.n;
+    a.item_n = nullptr;
+    a.item_in = nullptr;
+    a.item_out = nullptr;
     a.dir = p.direction;
     a.geo = G;
     a.T = p.d_T;
@@ -530,8 +540,13 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
     for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
         ExecArgs c = a;
         c.batch = batch - b0 < kMaxItemsPerLaunch ? batch - b0 : kMaxItemsPerLaunch;
-        c.in = in + b0 * p.n;
-        c.out = out + b0 * p.n;
+        c.in = in ? in + b0 * p.n : nullptr;     // null: a ragged batch (item arrays)
+        c.out = out ? out + b0 * p.n : nullptr;
+        if (ia) {
+            c.item_n = ia->n + b0;
+            c.item_in = ia->in + b0;
+            c.item_out = ia->out + b0;
+        }
         c.w = p.d_w + b0 * G.NT * 2 * M;
         const unsigned items = (unsigned)c.batch;
         hipLaunchKernelGGL(k_up<M>, dim3((unsigned)(P >> G.ku), items), dim3(kThreads), up_lds, st, c);
@@ -549,18 +564,20 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st)
+hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                          const ItemArrays *ia)
 {
     if (p.L == 0) {
         if (p.ev_before && p.ev_after) (void)hipEventRecord(p.ev_before, st);
         hipLaunchKernelGGL(k_direct, dim3((unsigned)batch), dim3(kThreads), 3 * sizeof(double) * p.n, st,
-                           in, out, p.n, p.direction);
+                           in, out, p.n, p.direction, ia ? ia->n : nullptr, ia ? ia->in : nullptr,
+                           ia ? ia->out : nullptr);
         if (p.ev_before && p.ev_after) (void)hipEventRecord(p.ev_after, st);
         return hipGetLastError();
     }
     switch (p.M) {
 #define L2C_CASE(MM) \
-    case MM: return run<MM>(p, in, out, batch, st);
+    case MM: return run<MM>(p, in, out, batch, st, ia);
         L2C_FOR_EACH_RANK(L2C_CASE)
 #undef L2C_CASE
     default: return hipErrorInvalidValue;

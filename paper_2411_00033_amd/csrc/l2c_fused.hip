@@ -580,7 +580,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     unsigned *sync = reinterpret_cast<unsigned *>(dummy + 2 * NS);
     unsigned *wcnt = sync, *rdy = sync + 1, *nbr = sync + 2, *qdone = sync + 4;
 
-    const double *in = a.in + item * a.n;
+    const int64_t n_it = a.item_n ? a.item_n[item] : a.n;
+    const double *in = a.item_in ? a.item_in[item] : a.in + item * a.n;
     // exchange nodes: this launch's half, and the next launch's (reset to empty here)
     double *pubc = a.pub + ((int64_t)(a.epoch & 1u) * a.pub_items + item) * G.NX * M2;
     double *pubn = a.pub + (int64_t)((a.epoch + 1u) & 1u) * a.pub_items * G.NX * M2;
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             const int e = u * NWT + wt;
             const int sig = e >= GXL, x = e - sig * GXL;
             const int64_t j = jb + 2 * (int64_t)x + sig;
-            vg[u] = (e < cntg && x < s * (nodes + 2) && j < a.n) ? in[j] : 0.0;
+            vg[u] = (e < cntg && x < s * (nodes + 2) && j < n_it) ? in[j] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < UT; ++u) {
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
     //      u < P - 2); leg2cheb divides by c_i pi/2.  The unit's rows are assembled in LDS
     //      (the near-field area, free by now; node stride 2s+1 against bank conflicts, and
     //      2 GX > nodes (2s+1) always), then written out in contiguous wave-wide stores.
-    double *out = a.out + item * a.n;
+    double *out = a.item_out ? a.item_out[item] : a.out + item * a.n;
     double *ob = gp;
     const int OS = 2 * s + 1;
     // (the near part is already in ob, written after the near field)
@@ -962,7 +963,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             for (int c = 0; c < CN; ++c) {
                 const int nd = nb + c * (NTH / 64);
                 const int64_t i = jb + (int64_t)nd * 2 * s + lane;
-                if (nd < nodes && lane < 2 * s && i < a.n) out[i] = v[c];
+                if (nd < nodes && lane < 2 * s && i < n_it) out[i] = v[c];
             }
         }
     }
@@ -1037,11 +1038,15 @@ FusedOrder g_order[64];
 }  // namespace
 
 template <int M>
-static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st)
+static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                            const ItemArrays *ia)
 {
     const Geometry &G = p.geo;
     ExecArgs a;
     a.n = p.n;
+    a.item_n = nullptr;
+    a.item_in = nullptr;
+    a.item_out = nullptr;
     a.dir = p.direction;
     a.geo = G;
     a.T = p.d_T;
@@ -1068,8 +1073,13 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
     for (int64_t b0 = 0; b0 < batch; b0 += p.fused_items) {
         ExecArgs c = a;
         c.batch = batch - b0 < p.fused_items ? batch - b0 : p.fused_items;
-        c.in = in + b0 * p.n;
-        c.out = out + b0 * p.n;
+        c.in = in ? in + b0 * p.n : nullptr;     // null: a ragged batch (item arrays)
+        c.out = out ? out + b0 * p.n : nullptr;
+        if (ia) {
+            c.item_n = ia->n + b0;
+            c.item_in = ia->in + b0;
+            c.item_out = ia->out + b0;
+        }
         c.epoch = ++p.epoch;
         const bool timed = p.ev_before && p.ev_after && b0 == 0;
         if (timed) (void)hipEventRecord(p.ev_before, st);
@@ -1084,11 +1094,12 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
     return e;
 }
 
-hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st)
+hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                        const ItemArrays *ia)
 {
     switch (p.M) {
 #define L2C_CASE(MM) \
-    case MM: return run_fused<MM>(p, in, out, batch, st);
+    case MM: return run_fused<MM>(p, in, out, batch, st, ia);
         L2C_FOR_EACH_RANK(L2C_CASE)
 #undef L2C_CASE
     default: return hipErrorInvalidValue;

@@ -66,6 +66,11 @@ struct ExecArgs {
     const double *in;
     double *out;
     int64_t n;           // valid length of every item
+    // ragged batches: per item of this launch its length and vectors (null: n, in + item n,
+    // out + item n)
+    const int64_t *item_n;
+    const double *const *item_in;
+    double *const *item_out;
     int64_t batch;
     int dir;             // 0 leg2cheb, 1 cheb2leg
     Geometry geo;
@@ -79,6 +84,13 @@ struct ExecArgs {
     int64_t pub_items;   // k_fused: items of one half of pub
     unsigned epoch;      // k_fused: launch number
     int *status;         // k_fused: bit 0 set when a wait ran out of polls
+};
+
+// Device arrays of a ragged batch, one entry per item of the launch sequence.
+struct ItemArrays {
+    const int64_t *n;
+    const double *const *in;
+    double *const *out;
 };
 
 }  // namespace l2c
@@ -113,11 +125,12 @@ struct l2c_plan_s {
 namespace l2c {
 // l2c_exec.hip
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
-                          hipStream_t stream);
+                          hipStream_t stream, const ItemArrays *ia = nullptr);
 // l2c_fused.hip
 bool fused_supported(int M);
 hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items);
-hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream);
+hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
+                        const ItemArrays *ia = nullptr);
 // l2c_plan.hip
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);

@@ -280,3 +280,93 @@ def test_config2_million_sampled(l2c, direction, single):
         lhs, rhs = float(np.dot(w, z)), float(np.dot(w, f))
         assert abs(lhs - rhs) <= 1e-11 * np.sum(np.abs(f)), (lhs, rhs)
     torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------------- ragged batches
+def test_ragged_batch_small(l2c):
+    """Mixed lengths (direct-only, one and several levels, equal (L, s) with different n) and
+    mixed directions in one batch plan: every output against the oracle and bit-identical to
+    the same transform planned alone."""
+    import torch
+    sizes = [1, 2, 5, 63, 64, 65, 127, 128, 129, 300, 1000, 1024, 2990, 3000, 3007, 4096, 9000, 9001,
+             16384, 20000, 511, 3001]
+    dirs = [i % 2 for i in range(len(sizes))]
+    dirs[12] = dirs[13] = dirs[14] = 0
+    xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 100 + i)).cuda() for i, n in enumerate(sizes)]
+    with l2c.BatchPlan(sizes, dirs) as bp:
+        info = bp.info
+        assert 1 <= info["groups"] < len(sizes) and info["table_bytes"] > 0
+        zs = bp.execute(xs)
+        zs2 = bp.execute(xs)
+        torch.cuda.synchronize()
+    for i, (n, d) in enumerate(zip(sizes, dirs)):
+        z = zs[i].cpu().numpy()
+        assert np.array_equal(z, zs2[i].cpu().numpy())
+        f = xs[i].cpu().numpy()
+        err = oracle.einf(z, oracle.transform(f, d))
+        assert err <= TOL[(d, 18)], (n, d, err)
+        alone, _ = run(l2c, f, d)
+        assert np.array_equal(z, alone), (n, d)
+
+
+def test_ragged_batch_errors(l2c):
+    import torch
+    with pytest.raises(l2c.L2CError) as ei:
+        l2c.leg2cheb_batch_plan([100, 0], [0, 0])
+    assert ei.value.code == l2c.L2C_EINVAL
+    with pytest.raises(l2c.L2CError) as ei:
+        l2c.leg2cheb_batch_plan([100], [2])
+    assert ei.value.code == l2c.L2C_EINVAL
+    with pytest.raises(l2c.L2CError) as ei:
+        l2c.leg2cheb_batch_plan([100], [0], precision=l2c.L2C_FP32)
+    assert ei.value.code == l2c.L2C_EUNSUPPORTED
+    buf = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    p0 = buf.data_ptr()
+    with l2c.BatchPlan([300, 300], [0, 1]) as bp:
+        # an output overlapping another output, and an output overlapping an input
+        for ins, outs in (([p0, p0], [p0 + 8 * 400, p0 + 8 * 500]),
+                          ([p0, p0 + 8 * 300], [p0 + 8 * 600, p0 + 8 * 100])):
+            with pytest.raises(l2c.L2CError) as ei:
+                l2c.leg2cheb_batch_execute(bp.handle, ins, outs)
+            assert ei.value.code == l2c.L2C_EINVAL
+        # shared input, disjoint outputs: allowed
+        l2c.leg2cheb_batch_execute(bp.handle, [p0, p0], [p0 + 8 * 300, p0 + 8 * 600])
+        torch.cuda.synchronize()
+
+
+def test_ragged_batch_2048_sampled(l2c):
+    """2048 transforms, n log-uniform in [128, 262144], directions 50/50, f_j = z_j/(j+1):
+    sampled rows of every output against the oracle, the full outputs against the x = +-1 sums."""
+    import torch
+    sizes, dirs = inputs.ragged_sizes(2048, inputs.SEED_BASE + 4)
+    rng = np.random.default_rng(inputs.SEED_BASE + 5)
+    total = int(sizes.sum())
+    flat = rng.standard_normal(total)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    for i, n in enumerate(sizes):
+        flat[offs[i]:offs[i + 1]] /= np.arange(1, n + 1, dtype=np.float64)
+    x = torch.from_numpy(flat).cuda()
+    y = torch.empty_like(x)
+    xs = [x[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+    ys = [y[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+    with l2c.BatchPlan(sizes.tolist(), dirs.tolist()) as bp:
+        groups = bp.info["groups"]
+        bp.execute(xs, ys)
+        torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    print("ragged batch: %d transforms, %d coefficients, %d groups" % (len(sizes), total, groups))
+    worst = {0: 0.0, 1: 0.0}
+    for i, (n, d) in enumerate(zip(sizes.tolist(), dirs.tolist())):
+        f = flat[offs[i]:offs[i + 1]]
+        z = yh[offs[i]:offs[i + 1]]
+        rows = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 3)]))
+        ref = oracle.transform(f, d, rows)
+        err = np.max(np.abs(z[rows] - ref)) / max(np.max(np.abs(ref)), 1e-300)
+        worst[d] = max(worst[d], err)
+        sgn = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+        for w in (None, sgn):
+            lhs = float(np.sum(z) if w is None else np.dot(w, z))
+            rhs = float(np.sum(f) if w is None else np.dot(w, f))
+            assert abs(lhs - rhs) <= 1e-11 * np.sum(np.abs(f)), (i, n, d, lhs, rhs)
+    print("sampled E_inf: leg2cheb %.2e  cheb2leg %.2e" % (worst[0], worst[1]))
+    assert worst[0] <= TOL[(0, 18)] and worst[1] <= TOL[(1, 18)]
