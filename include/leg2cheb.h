@@ -48,7 +48,8 @@ enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
 enum l2c_path {
     L2C_PATH_DIRECT = 0, /* L = 0: the whole product directly (Alg. 1) */
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
-    L2C_PATH_SINGLE = 2  /* one launch, workgroups exchange tree nodes through ready flags */
+    L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
+    L2C_PATH_BATCHED = 3 /* L2C_FP32 plans: 16 transforms per matrix-core tile, three kernels */
 };
 
 /* Plan options (leg2cheb_plan_set_option). */

@@ -120,10 +120,18 @@ void free_plan(l2c_plan_s *p)
     (void)hipFree(p->d_w);
     (void)hipFree(p->d_pub);
     (void)hipFree(p->d_status);
+    (void)hipFree(p->d_bA);
+    (void)hipFree(p->d_bT);
+    (void)hipFree(p->d_bB);
+    (void)hipFree(p->d_bP);
+    (void)hipFree(p->d_bQ);
+    (void)hipFree(p->d_bw);
     delete p;
 }
 
 bool use_fused(const l2c_plan_s *p) { return p->fused_ok && p->fused_on; }
+bool use_batched(const l2c_plan_s *p) { return p->L > 0 && p->precision == L2C_FP32; }
+size_t elem_bytes(const l2c_plan_s *p) { return p->precision == L2C_FP32 ? sizeof(float) : sizeof(double); }
 
 }  // namespace
 
@@ -173,6 +181,63 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
     return L2C_OK;
 }
 
+// Workspace of the batched form: tiles of 16 items, NT nodes x 2 parities x 256 values.
+int ensure_bworkspace(l2c_plan_s *p, int64_t items)
+{
+    const int64_t tiles = std::min((items + 15) / 16, l2c::kBatMaxTiles);
+    if (tiles <= p->bw_tiles) return L2C_OK;
+    if (p->bw_tiles > 0) {
+        if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
+    }
+    (void)hipFree(p->d_bw);
+    p->d_bw = nullptr;
+    p->bw_tiles = 0;
+    const size_t bytes = (size_t)tiles * p->geo.NT * 2 * 256 * elem_bytes(p);
+    if (hipMalloc(&p->d_bw, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->d_bw = nullptr;
+        return L2C_ENOMEM;
+    }
+    p->bw_tiles = tiles;
+    return L2C_OK;
+}
+
+// Tables of the batched form from the FP64 plan tables, then the FP64 Ahat is released.
+int build_batched_tables(l2c_plan_s *p, const std::vector<double> &T, const std::vector<double> &B,
+                         const std::vector<double> &Ptab, hipStream_t st)
+{
+    const int M = p->M, s = p->s;
+    const int64_t blocks = l2c::level_block_offset(p->L);
+    const int64_t qlen = p->n_pad + 2 * (int64_t)s;
+    std::vector<float> t32(T.begin(), T.end()), b32(B.begin(), B.begin() + (size_t)M * M), p32(2 * (size_t)s);
+    for (int d = 0; d < 2 * s; ++d) p32[d] = (float)Ptab[l2c::kPLead + d];
+    const size_t eb = elem_bytes(p);
+    bool ok = hipMalloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
+              hipMalloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess && hipMalloc(&p->d_bT, t32.size() * eb) == hipSuccess &&
+              hipMalloc(&p->d_bB, b32.size() * eb) == hipSuccess && hipMalloc(&p->d_bP, p32.size() * eb) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return L2C_ENOMEM;
+    }
+    ok = hipMemcpyAsync(p->d_bT, t32.data(), t32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(p->d_bB, b32.data(), b32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(p->d_bP, p32.data(), p32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
+         l2c::batched_build_tables(*p, p->d_bA, p->d_bQ, qlen, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return L2C_EHIP;
+    }
+    (void)hipFree(p->d_top);
+    (void)hipFree(p->d_bot);
+    p->d_top = p->d_bot = nullptr;
+    p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
+    p->bot_bytes = 0;
+    p->table_bytes = p->top_bytes + (int64_t)(qlen + t32.size() + b32.size() + p32.size()) * (int64_t)eb +
+                     (int64_t)(T.size() + B.size() + Ptab.size() + 2 * M + M * M) * 8;
+    return L2C_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -198,8 +263,9 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
     for (int64_t i = 0; i < count; ++i)
         if (n[i] < 1 || (direction[i] != L2C_LEG2CHEB && direction[i] != L2C_CHEB2LEG)) return L2C_EINVAL;
     if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
-    if (precision != L2C_FP64) return L2C_EUNSUPPORTED;
+    if (precision != L2C_FP64 && precision != L2C_FP32) return precision == L2C_BF16X2 ? L2C_EUNSUPPORTED : L2C_EINVAL;
     if (!leg2cheb_rank_supported(rank)) return L2C_EUNSUPPORTED;
+    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
     l2c_batch_s *b = new (std::nothrow) l2c_batch_s;
     if (!b) return L2C_ENOMEM;
     if (hipGetDevice(&b->device) != hipSuccess) {
@@ -304,7 +370,11 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
         l2c_plan_s *p = b->plans[g];
         const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
         const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
-        if (p->L > 0 && use_fused(p)) {
+        if (use_batched(p)) {
+            const int rc = ensure_bworkspace(p, items);
+            if (rc != L2C_OK) return rc;
+            if (l2c::launch_batched(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+        } else if (p->L > 0 && use_fused(p)) {
             const int rc = ensure_workspace(p, std::min(items, p->fused_items));
             if (rc != L2C_OK) return rc;
             if (l2c::launch_fused(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
@@ -349,11 +419,13 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
     if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
     if (rank < 1 || rank > 32) return L2C_EINVAL;
     if (max_batch < 1) return L2C_EINVAL;
-    if (precision != L2C_FP64) {
-        if (precision == L2C_FP32 || precision == L2C_BF16X2) return L2C_EUNSUPPORTED;
+    if (precision != L2C_FP64 && precision != L2C_FP32) {
+        if (precision == L2C_BF16X2) return L2C_EUNSUPPORTED;
         return L2C_EINVAL;
     }
     if (!rank_supported(rank)) return L2C_EUNSUPPORTED;
+    // the batched FP32 form: one 16 x 16 tile per node (M <= 16) and s <= 32
+    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
 
     l2c_plan_s *p = new (std::nothrow) l2c_plan_s();
     if (!p) return L2C_ENOMEM;
@@ -415,6 +487,16 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             free_plan(p);
             return L2C_EHIP;
         }
+        if (precision == L2C_FP32) {
+            int rc = build_batched_tables(p, T, B, Ptab, st);
+            if (rc == L2C_OK) rc = ensure_bworkspace(p, max_batch);
+            if (rc != L2C_OK) {
+                free_plan(p);
+                return rc;
+            }
+            *plan = p;
+            return L2C_OK;
+        }
         // single-launch path: items per launch with every workgroup resident
         int64_t items = 0;
         if (l2c::fused_max_items(*p, &items) != hipSuccess) {
@@ -463,6 +545,12 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
     if (dev != plan->device) return L2C_EINVAL;
+    if (use_batched(plan)) {
+        const int rc = ensure_bworkspace(plan, batch);
+        if (rc != L2C_OK) return rc;
+        if (l2c::launch_batched(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
+        return L2C_OK;
+    }
     if (plan->L > 0 && use_fused(plan)) {
         const int rc = ensure_workspace(plan, std::min(batch, plan->fused_items));
         if (rc != L2C_OK) return rc;
@@ -497,9 +585,13 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
     info->n_blocks = plan->nb;
     info->n_submatrices = plan->nc;
     info->table_bytes = plan->table_bytes;
-    info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double);
+    info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double) +
+                            plan->bw_tiles * plan->geo.NT * 2 * 256 * (int64_t)elem_bytes(plan);
     info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
-    info->path = plan->L == 0 ? L2C_PATH_DIRECT : use_fused(plan) ? L2C_PATH_SINGLE : L2C_PATH_THREE;
+    info->path = plan->L == 0        ? L2C_PATH_DIRECT
+                 : use_batched(plan) ? L2C_PATH_BATCHED
+                 : use_fused(plan)   ? L2C_PATH_SINGLE
+                                     : L2C_PATH_THREE;
     return L2C_OK;
 }
 
@@ -519,6 +611,7 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
     if (bytes != need) return L2C_EINVAL;
     if (table == 1) return hipMemcpy(dst, plan->d_T, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
     if (table == 2) return hipMemcpy(dst, plan->d_B, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
+    if (!plan->d_top) return L2C_EUNSUPPORTED;   // FP32 plans keep Ahat only in the batched layout
     double *tmp = nullptr;
     if (hipMalloc(&tmp, need) != hipSuccess) {
         (void)hipGetLastError();

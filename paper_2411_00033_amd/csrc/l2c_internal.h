@@ -38,6 +38,12 @@ constexpr int kMainThreads = 512;    // k_main: 8 waves, two per SIMD (FP64 issu
 constexpr int kNearItems = 1;        // near-field work items per k_main thread
 constexpr int kMainLds = 160 * 1024; // LDS of one gfx950 CU: k_main runs one workgroup per CU
 constexpr int64_t kMaxItemsPerLaunch = 32768;  // grid.y limit with margin
+// Batched form (l2c_batched.hip): 16 transforms per matrix-core tile, one wave per
+// subtree of 2^depth nodes in each of its three kernels.
+constexpr int kBatUpDepth = 3;
+constexpr int kBatTopDepth = 3;
+constexpr int kBatMainDepth = 3;
+constexpr int64_t kBatMaxTiles = 32768;        // tiles (of 16 items) per launch
 
 __host__ __device__ inline int64_t node_offset(int g) { return (int64_t(1) << (g + 2)) - 4; }
 
@@ -120,6 +126,15 @@ struct l2c_plan_s {
     double *d_pub = nullptr;    // ExecArgs::pub, fused_items items per half
     int *d_status = nullptr;
     unsigned epoch = 0;
+    // batched form (precision L2C_FP32): tables in the form's type and a workspace of
+    // [tiles][NT][2][16 x 16] tiles; the FP64 Ahat tables are released after packing
+    void *d_bA = nullptr;       // Ahat, [blocks][3][64][4] A operands
+    void *d_bT = nullptr;       // [2][s][M]
+    void *d_bB = nullptr;       // [M][M]
+    void *d_bP = nullptr;       // [2s]
+    void *d_bQ = nullptr;       // [n_pad + 2s]
+    void *d_bw = nullptr;
+    int64_t bw_tiles = 0;
 };
 
 namespace l2c {
@@ -131,6 +146,10 @@ bool fused_supported(int M);
 hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items);
 hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                         const ItemArrays *ia = nullptr);
+// l2c_batched.hip
+hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst, int64_t q_len, hipStream_t stream);
+hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
+                          const ItemArrays *ia = nullptr);
 // l2c_plan.hip
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);

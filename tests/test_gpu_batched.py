@@ -1,0 +1,116 @@
+"""GPU parity of the batched FP32 form (16 transforms per matrix-core tile, rank 16).
+
+Tolerance.  The form computes every product in FP32 (unit roundoff u = 2^-24) with FP32
+accumulation; inputs are converted once, outputs are scaled and stored in FP64.  An
+output row is a sum of at most 2s near-field terms plus a far-field value built through
+L upward and L downward transfers of M-term sums, so the rounding error relative to
+max|z| is a small multiple of (2s + 2 L M) u ~ 2e-5 at s = 32, L = 9, M = 16 for a
+worst-case sign pattern; random signs give about its square root.  The bound used here
+is 5e-6 (E_inf, Eq. (Einf)), about 80 u; the rank-16 truncation error (~1e-12) is far below it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_00033_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 5e-6
+
+
+@pytest.fixture(scope="module")
+def l2c():
+    import torch
+    import paper_2411_00033_amd as mod
+    assert torch.cuda.is_available()
+    mod._lib.load()
+    return mod
+
+
+def run32(l2c, F, direction, rank=16, leaf=64):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(F)).cuda()
+    batch = 1 if x.dim() == 1 else x.shape[0]
+    with l2c.Plan(F.shape[-1], direction, leaf, rank, precision=l2c.L2C_FP32, max_batch=batch) as p:
+        info = p.info
+        z = p.execute(x)
+        torch.cuda.synchronize()
+        return z.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("n", [129, 300, 1024, 3000, 20000])
+def test_fp32_parity_sizes(l2c, n, direction):
+    """A batch of 21 (one full tile and a ragged one): every item against the oracle."""
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 40 + n % 97, batch=21)
+    Z, info = run32(l2c, F, direction)
+    assert info["precision"] == l2c.L2C_FP32
+    if info["levels"] > 0:
+        assert info["path"] == l2c.L2C_PATH_BATCHED
+    worst = 0.0
+    for b in range(F.shape[0]):
+        worst = max(worst, oracle.einf(Z[b], oracle.transform(F[b], direction)))
+    print("FP32 n=%d dir=%d L=%d E_inf=%.2e" % (n, direction, info["levels"], worst))
+    assert worst <= TOL32
+
+
+def test_fp32_rank12_and_small_leaf(l2c):
+    n = 5000
+    F = inputs.decaying(n, 0.5, inputs.SEED_BASE + 41, batch=3)
+    for rank, leaf in ((12, 64), (16, 32), (16, 40)):
+        Z, info = run32(l2c, F, 0, rank=rank, leaf=leaf)
+        err = max(oracle.einf(Z[b], oracle.leg2cheb(F[b])) for b in range(3))
+        print("FP32 rank=%d leaf=%d s=%d E_inf=%.2e" % (rank, leaf, info["s"], err))
+        assert err <= (1e-4 if rank == 12 else TOL32)
+
+
+def test_fp32_unsupported(l2c):
+    with pytest.raises(l2c.L2CError) as ei:
+        l2c.Plan(1000, 0, 64, 18, precision=l2c.L2C_FP32)
+    assert ei.value.code == l2c.L2C_EUNSUPPORTED
+    with pytest.raises(l2c.L2CError) as ei:
+        l2c.Plan(1000, 0, 128, 16, precision=l2c.L2C_FP32)
+    assert ei.value.code == l2c.L2C_EUNSUPPORTED
+    with l2c.Plan(1000, 0, 64, 16, precision=l2c.L2C_FP32) as p:
+        with pytest.raises(l2c.L2CError) as ei:
+            p.export(l2c.TABLE_AHAT)
+        assert ei.value.code == l2c.L2C_EUNSUPPORTED
+
+
+def test_fp32_ragged_batch(l2c):
+    """Ragged FP32 batch: mixed lengths and directions, every output against the oracle."""
+    import torch
+    sizes = [1, 70, 128, 129, 1000, 1024, 2990, 3000, 3007, 9000, 9001, 20000] * 2
+    dirs = [0] * 12 + [1] * 12
+    xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 200 + i)).cuda() for i, n in enumerate(sizes)]
+    with l2c.BatchPlan(sizes, dirs, rank=16, precision=l2c.L2C_FP32) as bp:
+        zs = bp.execute(xs)
+        torch.cuda.synchronize()
+    for i, (n, d) in enumerate(zip(sizes, dirs)):
+        err = oracle.einf(zs[i].cpu().numpy(), oracle.transform(xs[i].cpu().numpy(), d))
+        assert err <= TOL32, (n, d, err)
+
+
+def test_config3_fp32_batch_256x65536(l2c):
+    """256 x N = 65536, f = z/(j+1): all 256 against the FP64 GPU path, 8 against the oracle
+    (rows 0, 255 and 6 random)."""
+    import torch
+    n, B = 65536, 256
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 3, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, 0, 64, 16, precision=l2c.L2C_FP32, max_batch=B) as p32, \
+            l2c.Plan(n, 0, 64, 18, max_batch=B) as p64:
+        z32 = p32.execute(x)
+        z64 = p64.execute(x)
+        torch.cuda.synchronize()
+    z32, z64 = z32.cpu().numpy(), z64.cpu().numpy()
+    e64 = max(oracle.einf(z32[b], z64[b]) for b in range(B))
+    rng = np.random.default_rng(inputs.SEED_BASE + 33)
+    worst = 0.0
+    for b in rng.choice(B, 8, replace=False):
+        rows = np.unique(np.concatenate([[0, 255], rng.integers(0, n, 6)]))
+        ref = oracle.leg2cheb(F[b], rows)
+        worst = max(worst, np.max(np.abs(z32[b][rows] - ref)) / np.max(np.abs(ref)))
+    print("cfg3 FP32: E_inf vs FP64 path %.2e, sampled vs oracle %.2e" % (e64, worst))
+    assert e64 <= TOL32 and worst <= TOL32
