@@ -54,11 +54,6 @@ struct Mx<double> {
 };
 
 template <typename T>
-struct BTile {
-    typename Mx<T>::v4 v[2];   // parity sigma = 0, 1
-};
-
-template <typename T>
 struct BatArgs {
     const double *in;
     double *out;
@@ -79,36 +74,19 @@ struct BatArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ BTile<T> tile_zero()
+using v4_t = typename Mx<T>::v4;
+
+template <typename T>
+__device__ __forceinline__ v4_t<T> v4_zero()
 {
-    BTile<T> t;
-    t.v[0] = typename Mx<T>::v4{0, 0, 0, 0};
-    t.v[1] = t.v[0];
-    return t;
+    return v4_t<T>{0, 0, 0, 0};
 }
 
+// Tile (node, parity) of this workgroup row: 64 lanes x 4 values, contiguous.
 template <typename T>
 __device__ __forceinline__ T *tile_ptr(const BatArgs<T> &a, int64_t node, int sig, int lane)
 {
     return a.w + (((int64_t)blockIdx.y * a.NT + node) * 2 + sig) * 256 + lane * 4;
-}
-
-template <typename T>
-__device__ __forceinline__ BTile<T> tile_load(const BatArgs<T> &a, int64_t node, int lane)
-{
-    typedef typename Mx<T>::v4 v4;
-    BTile<T> t;
-    t.v[0] = *reinterpret_cast<const v4 *>(tile_ptr(a, node, 0, lane));
-    t.v[1] = *reinterpret_cast<const v4 *>(tile_ptr(a, node, 1, lane));
-    return t;
-}
-
-template <typename T>
-__device__ __forceinline__ void tile_store(const BatArgs<T> &a, int64_t node, int lane, const BTile<T> &t)
-{
-    typedef typename Mx<T>::v4 v4;
-    *reinterpret_cast<v4 *>(tile_ptr(a, node, 0, lane)) = t.v[0];
-    *reinterpret_cast<v4 *>(tile_ptr(a, node, 1, lane)) = t.v[1];
 }
 
 // The lane's transform: item blockIdx.y * 16 + lane mod 16 (length 0 past the batch).
@@ -131,39 +109,47 @@ __device__ __forceinline__ LaneItem lane_item(const BatArgs<T> &a, int lane)
     return it;
 }
 
-// Eight consecutive input values x[e] = u[j0 + e] (zero past the item's length), with
-// u = c .* f for cheb2leg (u_0 = 2 f_0, Sec. 4.1); times j for the near field's g_j = j u_j.
-__device__ __forceinline__ void load8(const LaneItem &it, int64_t j0, int dir, bool times_j, double (&x)[8])
+// Four input values of one parity, x[kk] = f[j0 + 2 kk] (zero past the item's length).
+// The staging of step (0) (u = c .* f for cheb2leg, u_0 = 2 f_0; g_j = j u_j for the
+// near field) is applied by stage4 once the loads have arrived.
+__device__ __forceinline__ void load4(const LaneItem &it, int64_t j0, double (&x)[4])
 {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = (j0 + e < it.n) ? it.in[j0 + e] : 0.0;
-    if (dir == 1) {
-        if (j0 == 0) x[0] *= 2.0;
-        if (times_j) {
+    for (int kk = 0; kk < 4; ++kk) x[kk] = (j0 + 2 * kk < it.n) ? it.in[j0 + 2 * kk] : 0.0;
+}
+template <typename T>
+__device__ __forceinline__ void stage4(const double (&x)[4], int64_t j0, int dir, bool times_j, T (&y)[4])
+{
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] *= (double)(j0 + e);
+    for (int kk = 0; kk < 4; ++kk) {
+        double v = x[kk];
+        if (dir == 1) {
+            // j < n <= 2^31 wherever x is nonzero
+            const unsigned j = (unsigned)j0 + 2u * (unsigned)kk;
+            if (j0 + 2 * kk == 0) v *= 2.0;
+            if (times_j) v *= (double)j;
         }
+        y[kk] = (T)v;
     }
 }
 
-// t += Bm t_in for one tile and both parities, Bm given as the four A-operand values of
-// the lane (Bm[l mod 16][row(l / 16, kk)]).
+// acc += Am X for one tile, Am given as the lane's four A-operand values
+// (Am[l mod 16][row(l / 16, kk)]) and X in the accumulator layout.
 template <typename T>
-__device__ __forceinline__ void tile_mac(BTile<T> &acc, const T (&am)[4], const BTile<T> &x)
+__device__ __forceinline__ v4_t<T> tile_mac(v4_t<T> acc, const T (&am)[4], const v4_t<T> &x)
 {
 #pragma unroll
-    for (int sg = 0; sg < 2; ++sg) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc.v[sg] = Mx<T>::mma(am[kk], x.v[sg][kk], acc.v[sg]);
-    }
+    for (int kk = 0; kk < 4; ++kk) acc = Mx<T>::mma(am[kk], x[kk], acc);
+    return acc;
 }
 
 // ------------------------------------------------------------------------------------
-// Upward pass.  Leaf tiles come from step (1) (LEAF_STEP1) or from the workspace.
+// Upward pass of one parity over 2^K leaves starting at t0 (level gleaf): leaf tiles from
+// step (1) (LEAF_STEP1) or from the workspace; the loads of leaf i + 1 are issued before
+// the products of leaf i.
 template <typename T, int K, bool LEAF_STEP1>
-__device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gleaf, int lane)
+__device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gleaf, int sg, int lane)
 {
-    typedef typename Mx<T>::v4 v4;
     const int li = lane & 15, q = lane >> 4;
     const int M = a.M, s = a.s;
     // A operands of the parent transfer: B(0) and B(1) = B(0) with odd diagonals negated
@@ -176,43 +162,57 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
         b1a[kk] = ((li - k) & 1) ? -v : v;
     }
     // A operands of step (1): T(sigma)^T, column m = 16 c + 4 q + kk
-    T ta[2][2][4];
+    T ta[2][4];
 #pragma unroll
-    for (int sg = 0; sg < 2; ++sg)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int m = 16 * c + 4 * q + kk;
-                ta[sg][c][kk] = (LEAF_STEP1 && li < M && m < s) ? a.Tm[(sg * s + m) * M + li] : T(0);
-            }
+        for (int kk = 0; kk < 4; ++kk) {
+            const int m = 16 * c + 4 * q + kk;
+            ta[c][kk] = (LEAF_STEP1 && li < M && m < s) ? a.Tm[(sg * s + m) * M + li] : T(0);
+        }
     LaneItem it{nullptr, nullptr, 0};
     if (LEAF_STEP1) it = lane_item(a, lane);
+    const int nch = s > 16 ? 2 : 1;
 
-    BTile<T> stk[K > 0 ? K : 1];
+    // leaf inputs: step (1) reads u[2 s t + 2 m + sigma], m = 16 c + 4 q + kk
+    double xn[2][4];
+    v4_t<T> wn = v4_zero<T>();
+    auto issue = [&](int64_t t) {
+        if (LEAF_STEP1) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (c < nch) load4(it, 2 * s * t + 32 * c + 8 * q + sg, xn[c]);
+        } else {
+            wn = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane));
+        }
+    };
+    issue(t0);
+    v4_t<T> stk[K > 0 ? K : 1];
     for (int i = 0; i < (1 << K); ++i) {
         const int64_t t = t0 + i;
-        BTile<T> cur;
+        v4_t<T> cur;
         if (LEAF_STEP1) {
+            T y[2][4];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (c < nch) stage4<T>(xn[c], 2 * s * t + 32 * c + 8 * q + sg, a.dir, false, y[c]);
+            if (i + 1 < (1 << K)) issue(t + 1);
             // step (1): w_k(t, sigma) = sum_m T_k(X_m^sigma) u[2 s t + 2 m + sigma]
-            cur = tile_zero<T>();
+            cur = v4_zero<T>();
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                if (16 * c < s) {
-                    double x[8];
-                    load8(it, 2 * s * t + 32 * c + 8 * q, a.dir, false, x);
+                if (c < nch) {
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const bool in_node = 16 * c + 4 * q + kk < s;
-#pragma unroll
-                        for (int sg = 0; sg < 2; ++sg)
-                            cur.v[sg] = Mx<T>::mma(ta[sg][c][kk], in_node ? (T)x[2 * kk + sg] : T(0), cur.v[sg]);
+                        cur = Mx<T>::mma(ta[c][kk], in_node ? y[c][kk] : T(0), cur);
                     }
                 }
             }
-            tile_store(a, node_offset(gleaf) + t, lane, cur);
+            *reinterpret_cast<v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane)) = cur;
         } else {
-            cur = tile_load(a, node_offset(gleaf) + t, lane);
+            cur = wn;
+            if (i + 1 < (1 << K)) issue(t + 1);
         }
         // climb while this node is a right child: parent = B(0) left + B(1) right (Eq. (wtk))
         bool done = false;
@@ -223,165 +223,125 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
                     stk[d - 1] = cur;
                     done = true;
                 } else {
-                    BTile<T> par = tile_zero<T>();
-                    tile_mac(par, b0a, stk[d - 1]);
-                    tile_mac(par, b1a, cur);
-                    cur = par;
-                    tile_store(a, node_offset(gleaf - d) + (t >> d), lane, cur);
+                    cur = tile_mac<T>(tile_mac<T>(v4_zero<T>(), b0a, stk[d - 1]), b1a, cur);
+                    *reinterpret_cast<v4_t<T> *>(tile_ptr(a, node_offset(gleaf - d) + (t >> d), sg, lane)) = cur;
                 }
             }
         }
     }
-    (void)sizeof(v4);
 }
 
+// Waves of a workgroup: wave w takes subtree 2 blockIdx.x + w / 2 and parity w mod 2.
 template <typename T, int KU>
 __global__ __launch_bounds__(256) void kb_up(BatArgs<T> a)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t sub = (int64_t)blockIdx.x * 4 + wave_id();
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     const int64_t P = int64_t(1) << (a.L + 1);   // finest nodes
     if ((sub << KU) >= P) return;
-    up_walk<T, KU, true>(a, sub << KU, a.L - 1, lane);
+    up_walk<T, KU, true>(a, sub << KU, a.L - 1, wv & 1, lane);
 }
 
 template <typename T, int KT>
 __global__ __launch_bounds__(256) void kb_top(BatArgs<T> a)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t sub = (int64_t)blockIdx.x * 4 + wave_id();
+    const int lane = threadIdx.x & 63, wv = wave_id();
+    const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     if ((sub << KT) >= (int64_t(1) << (a.gin + 2))) return;
-    up_walk<T, KT, false>(a, sub << KT, a.gin, lane);
+    up_walk<T, KT, false>(a, sub << KT, a.gin, wv & 1, lane);
 }
 
 // ------------------------------------------------------------------------------------
-// Far field of one row node v of level g (step (3), Eq. (cfrompq)): block b = v >> 1,
-// c(2b) = Ahat(0) w(2b+2) + Ahat(1) w(2b+3), c(2b+1) = Ahat(2) w(2b+3); zero when the
-// block lies past the last one of the level (b >= b_g = 2^(g+1) - 1).
+// Far field of one row node v of level g and one parity (step (3), Eq. (cfrompq)):
+// block b = v >> 1, c(2b) = Ahat(0) w(2b+2) + Ahat(1) w(2b+3), c(2b+1) = Ahat(2) w(2b+3);
+// zero when the block lies past the last one of the level (b >= b_g = 2^(g+1) - 1).
+// far_issue loads the operands and far_do multiplies, so loads can run ahead.
 template <typename T>
-__device__ __forceinline__ BTile<T> far_tile(const BatArgs<T> &a, int g, int64_t v, int lane)
+struct FarIn {
+    v4_t<T> A0, A1, W2, W3;
+    int kind;                       // 0: no block, 1: even row node, 2: odd row node
+};
+
+template <typename T>
+__device__ __forceinline__ FarIn<T> far_issue(const BatArgs<T> &a, int g, int64_t v, int sg, int lane)
 {
-    typedef typename Mx<T>::v4 v4;
-    BTile<T> r = tile_zero<T>();
+    FarIn<T> f;
+    f.kind = 0;
+    f.A0 = f.A1 = f.W2 = f.W3 = v4_zero<T>();
     const int64_t b = v >> 1;
-    if (b >= (int64_t(1) << (g + 1)) - 1) return r;
-    const int64_t blk = level_block_offset(g) + b;
-    const T *ab = a.ahat + (blk * 3 * 64 + lane) * 4;
+    if (b >= (int64_t(1) << (g + 1)) - 1) return f;
+    const T *ab = a.ahat + ((level_block_offset(g) + b) * 3 * 64 + lane) * 4;
+    const int64_t cn = node_offset(g) + v + 2;
     if ((v & 1) == 0) {
-        const v4 A0 = *reinterpret_cast<const v4 *>(ab);
-        const v4 A1 = *reinterpret_cast<const v4 *>(ab + 64 * 4);
-        const BTile<T> w2 = tile_load(a, node_offset(g) + v + 2, lane);
-        const BTile<T> w3 = tile_load(a, node_offset(g) + v + 3, lane);
-        const T a0[4] = {A0[0], A0[1], A0[2], A0[3]}, a1[4] = {A1[0], A1[1], A1[2], A1[3]};
-        tile_mac(r, a0, w2);
-        tile_mac(r, a1, w3);
+        f.kind = 1;
+        f.A0 = *reinterpret_cast<const v4_t<T> *>(ab);
+        f.A1 = *reinterpret_cast<const v4_t<T> *>(ab + 64 * 4);
+        f.W2 = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, cn, sg, lane));
+        f.W3 = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, cn + 1, sg, lane));
     } else {
-        const v4 A2 = *reinterpret_cast<const v4 *>(ab + 2 * 64 * 4);
-        const BTile<T> w2 = tile_load(a, node_offset(g) + v + 2, lane);
-        const T a2[4] = {A2[0], A2[1], A2[2], A2[3]};
-        tile_mac(r, a2, w2);
+        f.kind = 2;
+        f.A0 = *reinterpret_cast<const v4_t<T> *>(ab + 2 * 64 * 4);
+        f.W2 = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, cn, sg, lane));
+    }
+    return f;
+}
+
+template <typename T>
+__device__ __forceinline__ v4_t<T> far_do(const FarIn<T> &f)
+{
+    v4_t<T> r = v4_zero<T>();
+    if (f.kind == 0) return r;
+    const T a0[4] = {f.A0[0], f.A0[1], f.A0[2], f.A0[3]};
+    r = tile_mac<T>(r, a0, f.W2);
+    if (f.kind == 1) {
+        const T a1[4] = {f.A1[0], f.A1[1], f.A1[2], f.A1[3]};
+        r = tile_mac<T>(r, a1, f.W3);
     }
     return r;
 }
 
-// Steps (5)-(7) for finest row node u: z = T(sigma) c(u) (row nodes u < P - 2) plus the
-// near field, then the scaling of step (7) and the FP64 store.
-template <typename T>
-__device__ __forceinline__ void leaf_eval(const BatArgs<T> &a, int64_t u, const BTile<T> &cu, const T (&te)[2][2][4],
-                                          const T *Pl, T *Ql, const LaneItem &it, int lane)
-{
-    typedef typename Mx<T>::v4 v4;
-    const int li = lane & 15, q = lane >> 4;
-    const int s = a.s, dir = a.dir;
-    const int64_t P = int64_t(1) << (a.L + 1);
-    const int64_t base = 2 * s * u;                      // first row of the node
-    // Q_S for S = base + [0, 3s): the node's window, through this wave's LDS area
-    for (int e = lane; e < 3 * s; e += 64) Ql[e] = a.Qt[base + e];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nrt = s > 16 ? 2 : 1;
-    v4 acc[2][2];
-#pragma unroll
-    for (int sg = 0; sg < 2; ++sg)
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt) acc[sg][rt] = v4{0, 0, 0, 0};
-    // far part (Eq. (step5)): rows m = 16 rt + l mod 16 of T(sigma), modes row(q, kk)
-    if (u < P - 2) {
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg)
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
-                if (rt < nrt) {
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) acc[sg][rt] = Mx<T>::mma(te[sg][rt][kk], cu.v[sg][kk], acc[sg][rt]);
-                }
-    }
-    // near field (step (6)): row m, column m' = 16 c + 4 q + kk of parity sigma:
-    //   rs_i P_{m'-m} Q_{base + sigma + m + m'} for m <= m' < 2s, times g_{base + 2 m' + sigma}
-    const int nc = (2 * s + 15) / 16;
-    for (int c = 0; c < nc; ++c) {
-        double x[8];
-        load8(it, base + 32 * c + 8 * q, dir, true, x);
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-                if (rt < nrt && c >= rt) {
-                    const int m = 16 * rt + li;
-                    const double rs = dir == 1 ? 2.0 * (double)(base + 2 * m + sg) + 1.0 : 1.0;
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int mp = 16 * c + 4 * q + kk;
-                        const bool nz = m < s && mp >= m && mp < 2 * s;
-                        const T pq = nz ? Pl[nz ? mp - m : 0] * Ql[nz ? sg + m + mp : 0] : T(0);
-                        acc[sg][rt] = Mx<T>::mma(pq * (T)rs, (T)x[2 * kk + sg], acc[sg][rt]);
-                    }
-                }
-            }
-        }
-    }
-    // step (7) and output: lane holds rows m = 16 rt + row(q, r) of item l mod 16
-    if (!it.out) return;
-    const double f0 = (dir == 1 && base == 0 && it.n > 0) ? it.in[0] : 0.0;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        if (rt < nrt) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = 16 * rt + Mx<T>::row(q, r);
-#pragma unroll
-                for (int sg = 0; sg < 2; ++sg) {
-                    const int64_t i = base + 2 * m + sg;
-                    if (m < s && i < it.n) {
-                        double v = (double)acc[sg][rt][r];
-                        if (dir == 0) v *= (i == 0 ? 1.0 / kPi : 2.0 / kPi);
-                        else if (i == 0) v += f0;   // K_00 u_0 = u_0 / 2 = f_0
-                        it.out[i] = v;
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <typename T, int KD>
+// Steps (3)-(7) for one level-groot subtree of 2^KD finest row nodes and one parity.
+// LDS per wave: the far-field tiles of the subtree's own nodes (node idx of depth d at
+// slot 2^d - 2 + idx) and the Q window of its finest nodes.  NC = ceil(2s / 16) column
+// chunks of the near-field band; rows need two 16-row tiles when s > 16 (NC > 2).
+template <typename T, int KD, int NC>
 __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 {
+    constexpr int nc = NC, nrt = NC > 2 ? 2 : 1;
+    constexpr int OWN = (2 << KD) - 2;               // own nodes, depths 1..KD
+    constexpr int QW = 64 * (1 << KD) + 32;          // Q window: 2s 2^KD + s, s <= 32
     __shared__ T Pl[64];
-    __shared__ T Qs[4][96];
+    __shared__ v4_t<T> Fl[4][OWN > 0 ? OWN : 1][64];
+    __shared__ T Ql[4][QW];
     const int lane = threadIdx.x & 63, wv = wave_id();
-    const int li = lane & 15, q = lane >> 4;
-    const int s = a.s, M = a.M;
+    const int li = lane & 15, q = lane >> 4, sg = wv & 1;
+    const int s = a.s, M = a.M, dir = a.dir;
+    L2C_TS(1, 0);
     for (int e = threadIdx.x; e < 2 * s; e += 256) Pl[e] = a.Pt[e];
     __syncthreads();
     const int groot = a.L - 1 - KD;
-    const int64_t Rn = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t Rn = (int64_t)blockIdx.x * 2 + (wv >> 1);
     if (Rn >= (int64_t(1) << (groot + 2))) return;
+    const int64_t u0 = Rn << KD;                      // first finest row node
     const LaneItem it = lane_item(a, lane);
+    T *Qw = Ql[wv];
+    // Q_S for S = 2 s u0 + [0, 2 s 2^KD + s); the rest of the window is zero, so every
+    // read of the leaf loop below is of initialized memory
+    {
+        const int qn = 2 * s * (1 << KD) + s;
+        for (int e = lane; e < QW; e += 64) Qw[e] = e < qn ? a.Qt[2 * s * u0 + e] : T(0);
+    }
+    // near-field inputs of a leaf: g at j = 2 s u + 2 m' + sigma, m' = 16 c + 4 q + kk
+    double xn[4][4];
+    auto issue_near = [&](int64_t u) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nc) load4(it, 2 * s * u + 32 * c + 8 * q + sg, xn[c]);
+    };
+    issue_near(u0);
 
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
-    T bt[2][4], te[2][2][4];
+    T bt[2][4], te[2][4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const int k = Mx<T>::row(q, kk);
@@ -390,40 +350,142 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         bt[1][kk] = ((k - li) & 1) ? -v : v;
     }
 #pragma unroll
-    for (int sg = 0; sg < 2; ++sg)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int kk = 0; kk < 4; ++kk) {
+            const int m = 16 * rt + li, k = Mx<T>::row(q, kk);
+            te[rt][kk] = (m < s && k < M) ? a.Tm[(sg * s + m) * M + k] : T(0);
+        }
+
+    // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
+    // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf
+    T pm[2][4][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int m = 16 * rt + li, k = Mx<T>::row(q, kk);
-                te[sg][rt][kk] = (m < s && k < M) ? a.Tm[(sg * s + m) * M + k] : T(0);
+                const int m = 16 * rt + li, mp = 16 * c + 4 * q + kk;
+                const bool nz = m < s && mp >= m && mp < 2 * s;
+                const T pv = Pl[nz ? mp - m : 0];
+                pm[rt][c][kk] = nz ? pv : T(0);
             }
 
-    // ancestors a_g = Rn >> (groot - g): c(a_0) = far; c(a_g) = far + B(p)^T c(a_{g-1})
-    BTile<T> cp = far_tile(a, 0, Rn >> groot, lane);
-    for (int g = 1; g <= groot; ++g) {
-        const int64_t v = Rn >> (groot - g);
-        BTile<T> cv = far_tile(a, g, v, lane);
-        tile_mac(cv, bt[v & 1], cp);
-        cp = cv;
+    // ancestors a_g = Rn >> (groot - g): c(a_0) = far; c(a_g) = far + B(p)^T c(a_{g-1});
+    // the operands of level g + 1 are loaded while level g is multiplied
+    v4_t<T> cp = v4_zero<T>();
+    {
+        FarIn<T> nx = far_issue(a, 0, Rn >> groot, sg, lane);
+        for (int g = 0; g <= groot; ++g) {
+            const FarIn<T> cu = nx;
+            if (g < groot) nx = far_issue(a, g + 1, Rn >> (groot - g - 1), sg, lane);
+            v4_t<T> cv = far_do(cu);
+            if (g > 0) cv = tile_mac<T>(cv, bt[(Rn >> (groot - g)) & 1], cp);
+            cp = cv;
+        }
     }
-    // depth-first walk over the subtree: stk[d] = c of the current node at depth d
-    BTile<T> stk[KD + 1];
+    L2C_TS(1, 1);
+    // far field of the own nodes (depth-major), pipelined the same way, into LDS
+    if (OWN > 0) {
+        auto own_node = [&](int j, int &d, int64_t &v) {
+            d = 31 - __builtin_clz(j + 2);
+            v = (Rn << d) + (j + 2 - (1 << d));
+        };
+        int d0;
+        int64_t v0;
+        own_node(0, d0, v0);
+        FarIn<T> nx = far_issue(a, groot + d0, v0, sg, lane);
+        for (int j = 0; j < OWN; ++j) {
+            const FarIn<T> cu = nx;
+            if (j + 1 < OWN) {
+                int d1;
+                int64_t v1;
+                own_node(j + 1, d1, v1);
+                nx = far_issue(a, groot + d1, v1, sg, lane);
+            }
+            Fl[wv][j][lane] = far_do(cu);
+        }
+    }
+    // this wave's LDS writes (Q window, far tiles) complete before other lanes read them
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    L2C_TS(1, 2);
+
+    // depth-first walk: stk[d] = c of the current node at depth d; then steps (5)-(7)
+    v4_t<T> stk[KD + 1];
     stk[0] = cp;
     for (int i = 0; i < (1 << KD); ++i) {
-        // depths whose node changes at leaf i: d > KD - ctz(i) (all for i = 0)
-        const int dmin = i == 0 ? 1 : KD - __builtin_ctz(i) ;
+        const int64_t u = u0 + i;
+        const int64_t base = 2 * s * u;
+        T y[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nc) stage4<T>(xn[c], base + 32 * c + 8 * q + sg, dir, true, y[c]);
+        if (i + 1 < (1 << KD)) issue_near(u + 1);
+        const int dmin = i == 0 ? 1 : KD - __builtin_ctz(i);
 #pragma unroll
         for (int d = 1; d <= KD; ++d) {
             if (d >= dmin) {
-                const int64_t v = (Rn << d) + (i >> (KD - d));
-                BTile<T> cv = far_tile(a, groot + d, v, lane);
-                tile_mac(cv, bt[v & 1], stk[d - 1]);
-                stk[d] = cv;
+                const int idx = i >> (KD - d);
+                stk[d] = tile_mac<T>(Fl[wv][(1 << d) - 2 + idx][lane], bt[idx & 1], stk[d - 1]);
             }
         }
-        leaf_eval(a, (Rn << KD) + i, stk[KD], te, Pl, Qs[wv], it, lane);
+        const v4_t<T> cu = stk[KD];
+        v4_t<T> acc[2] = {v4_zero<T>(), v4_zero<T>()};
+        // far part (Eq. (step5)): rows m = 16 rt + l mod 16 of T(sigma).  The last two row
+        // nodes (u >= P - 2) have no far-field block on any level, so their c is zero.
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            if (rt < nrt) acc[rt] = tile_mac<T>(acc[rt], te[rt], cu);
+        // near field (step (6)): row m, column m' = 16 c + 4 q + kk:
+        //   rs_i P_{m'-m} Q_{2 s u + sigma + m + m'} (m <= m' < 2s) times g_{2 s u + 2 m' + sigma}
+        // Q enters through m + m' = 16 (c + rt) + 4 q + kk + l mod 16: 20 values per leaf
+        const T *Qu = Qw + 2 * s * i + sg + 4 * q + li;
+        T qv[5][4];
+#pragma unroll
+        for (int cr = 0; cr < 5; ++cr)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) qv[cr][kk] = Qu[16 * cr + kk];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            if (rt < nrt) {
+                // rs_i = 2i + 1 (cheb2leg), in the form's precision
+                const unsigned i32 = (unsigned)base + 2u * (unsigned)(16 * rt + li) + (unsigned)sg;
+                const T rs = dir == 1 ? (T)(2u * i32 + 1u) : T(1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (c < nc && c >= rt) {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk)
+                            acc[rt] = Mx<T>::mma(pm[rt][c][kk] * (qv[c + rt][kk] * rs), y[c][kk], acc[rt]);
+                    }
+                }
+            }
+        }
+        // step (7) and output: lane holds rows m = 16 rt + row(q, r) of item l mod 16
+        if (it.out) {
+            const double f0 = (dir == 1 && base == 0 && it.n > 0) ? it.in[0] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                if (rt < nrt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = 16 * rt + Mx<T>::row(q, r);
+                        const int64_t iz = base + 2 * m + sg;
+                        if (m < s && iz < it.n) {
+                            double v = (double)acc[rt][r];
+                            if (dir == 0) v *= (iz == 0 ? 1.0 / kPi : 2.0 / kPi);
+                            else if (iz == 0) v += f0;   // K_00 u_0 = u_0 / 2 = f_0
+                            it.out[iz] = v;
+                        }
+                    }
+                }
+            }
+        }
+        if (i == 0) L2C_TS(1, 3);
     }
+    L2C_TS(1, 4);
 }
 
 // ------------------------------------------------------------------------------------
@@ -527,7 +589,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
         a.Qt = (const T *)p.d_bQ;
         a.w = (T *)p.d_bw;
         {
-            const unsigned gx = (unsigned)(((Pn >> ku) + 3) / 4);
+            const unsigned gx = (unsigned)(((Pn >> ku) + 1) / 2);
             switch (ku) {
 #define L2C_UP(KK) \
     case KK: hipLaunchKernelGGL((kb_up<T, KK>), dim3(gx, tiles), dim3(256), 0, st, a); break;
@@ -540,7 +602,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
             const int kt = gin < kBatTopDepth ? gin : kBatTopDepth;
             const int gout = gin - kt;
             a.gin = gin;
-            const unsigned gx = (unsigned)((((int64_t)1 << (gout + 2)) + 3) / 4);
+            const unsigned gx = (unsigned)((((int64_t)1 << (gout + 2)) + 1) / 2);
             switch (kt) {
 #define L2C_TOP(KK) \
     case KK: hipLaunchKernelGGL((kb_top<T, KK>), dim3(gx, tiles), dim3(256), 0, st, a); break;
@@ -552,11 +614,14 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
         }
         {
             const int groot = L - 1 - kd;
-            const unsigned gx = (unsigned)((((int64_t)1 << (groot + 2)) + 3) / 4);
-            switch (kd) {
-#define L2C_MAIN(KK) \
-    case KK: hipLaunchKernelGGL((kb_main<T, KK>), dim3(gx, tiles), dim3(256), 0, st, a); break;
-                L2C_MAIN(0) L2C_MAIN(1) L2C_MAIN(2) L2C_MAIN(3)
+            const unsigned gx = (unsigned)((((int64_t)1 << (groot + 2)) + 1) / 2);
+            const int nc = (2 * p.s + 15) / 16;
+            switch (kd * 8 + nc) {
+#define L2C_MAIN(KK, NN) \
+    case KK * 8 + NN: hipLaunchKernelGGL((kb_main<T, KK, NN>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+#define L2C_MAIN4(KK) L2C_MAIN(KK, 1) L2C_MAIN(KK, 2) L2C_MAIN(KK, 3) L2C_MAIN(KK, 4)
+                L2C_MAIN4(0) L2C_MAIN4(1) L2C_MAIN4(2) L2C_MAIN4(3)
+#undef L2C_MAIN4
 #undef L2C_MAIN
             default: return hipErrorInvalidValue;
             }

@@ -5,7 +5,7 @@ accumulation; inputs are converted once, outputs are scaled and stored in FP64. 
 output row is a sum of at most 2s near-field terms plus a far-field value built through
 L upward and L downward transfers of M-term sums, so the rounding error relative to
 max|z| is a small multiple of (2s + 2 L M) u ~ 2e-5 at s = 32, L = 9, M = 16 for a
-worst-case sign pattern; random signs give about its square root.  The bound used here
+worst-case sign pattern; random signs give about sqrt(2s + 2 L M) u.  The bound used here
 is 5e-6 (E_inf, Eq. (Einf)), about 80 u; the rank-16 truncation error (~1e-12) is far below it.
 """
 import numpy as np
