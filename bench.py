@@ -44,13 +44,17 @@ PMC_FILES = {"k_fused": os.path.join(ROOT, "profiles", "k_fused_pmc_leg2cheb_n1e
 CSRC = os.path.join(ROOT, "paper_2411_00033_amd", "csrc")
 
 
-def source_sha256():
-    """Digest of the HIP sources (kernels, tables and host driver)."""
+# Sources each timed kernel is compiled from: a PMC summary holds only while these are unchanged.
+KERNEL_SOURCES = {"k_fused": ("l2c_fused.hip", "l2c_device.h", "l2c_internal.h", "l2c_math.h"),
+                  "k_main": ("l2c_exec.hip", "l2c_device.h", "l2c_internal.h", "l2c_math.h")}
+
+
+def source_sha256(kernel="k_fused"):
+    """Digest of the HIP sources the kernel is built from."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
+    for name in sorted(KERNEL_SOURCES[kernel]):
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()
 
 
@@ -89,7 +93,7 @@ def pmc_traffic(kernel):
             if ":" in ln and not ln.startswith((" ", "#", "|")):
                 k, v = ln.split(":", 1)
                 rec[k.strip()] = v.strip()
-        if rec.get("source_sha256") != source_sha256():
+        if rec.get("source_sha256") != source_sha256(kernel):
             return None
         return float(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
