@@ -109,28 +109,61 @@ __device__ __forceinline__ LaneItem lane_item(const BatArgs<T> &a, int lane)
     return it;
 }
 
-// Four input values of one parity, x[kk] = f[j0 + 2 kk] (zero past the item's length).
-// The staging of step (0) (u = c .* f for cheb2leg, u_0 = 2 f_0; g_j = j u_j for the
-// near field) is applied by stage4 once the loads have arrived.
-__device__ __forceinline__ void load4(const LaneItem &it, int64_t j0, double (&x)[4])
+// Value of lane r (r uniform) of a per-lane pointer or length.
+template <typename P>
+__device__ __forceinline__ P *lane_ptr(P *p, int r)
 {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) x[kk] = (j0 + 2 * kk < it.n) ? it.in[j0 + 2 * kk] : 0.0;
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), r);
+    return (P *)(((uint64_t)hi << 32) | lo);
 }
-template <typename T>
-__device__ __forceinline__ void stage4(const double (&x)[4], int64_t j0, int dir, bool times_j, T (&y)[4])
+__device__ __forceinline__ int64_t lane_i64(int64_t x, int r)
 {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)x, r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), r);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Transform r (uniform) of the tile: its input row, output row and length, read from
+// lane r (lane r holds transform r).
+__device__ __forceinline__ const double *row_in(const LaneItem &it, int r) { return lane_ptr(it.in, r); }
+__device__ __forceinline__ double *row_out(const LaneItem &it, int r) { return lane_ptr(it.out, r); }
+__device__ __forceinline__ int64_t row_n(const LaneItem &it, int r) { return lane_i64(it.n, r); }
+
+// One node of input for the 16 transforms of the tile, row-coalesced: instruction r reads
+// the node's 2s consecutive values of transform r (lane e: f[2 s t + e]), whole cache
+// lines per instruction.  Zero past a transform's length and for lanes e >= 2s.
+__device__ __forceinline__ void node_load(const LaneItem &it, int64_t t, int s, int lane, double (&x)[16])
+{
+    const int64_t j = 2 * s * t + lane;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        double v = x[kk];
-        if (dir == 1) {
-            // j < n <= 2^31 wherever x is nonzero
-            const unsigned j = (unsigned)j0 + 2u * (unsigned)kk;
-            if (j0 + 2 * kk == 0) v *= 2.0;
-            if (times_j) v *= (double)j;
-        }
-        y[kk] = (T)v;
+    for (int r = 0; r < 16; ++r) {
+        const double *p = row_in(it, r);
+        const int64_t nr = row_n(it, r);
+        x[r] = (lane < 2 * s && j < nr) ? p[j] : 0.0;
     }
+}
+
+// Stage a loaded node into LDS for parity sg: row r (transform), column m = e / 2 for the
+// lanes e of that parity; stage (0) applied (u = c .* f for cheb2leg, u_0 = 2 f_0), and
+// g_j = j u_j for the near field (times_j).  Row stride kBatRow.
+constexpr int kBatRow = 33;
+template <typename T>
+__device__ __forceinline__ void node_stage(T *slot, const double (&x)[16], int64_t t, int s, int lane, int sg, int dir,
+                                           bool times_j)
+{
+    if ((lane & 1) == sg && lane < 2 * s) {
+        const int64_t j = 2 * s * t + lane;
+        double sc = 1.0;
+        if (dir == 1) {
+            if (j == 0) sc = 2.0;
+            if (times_j) sc *= (double)(uint32_t)j;   // j < n <= 2^31 wherever x is nonzero
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) slot[r * kBatRow + (lane >> 1)] = (T)(x[r] * sc);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 // acc += Am X for one tile, Am given as the lane's four A-operand values
@@ -148,7 +181,7 @@ __device__ __forceinline__ v4_t<T> tile_mac(v4_t<T> acc, const T (&am)[4], const
 // step (1) (LEAF_STEP1) or from the workspace; the loads of leaf i + 1 are issued before
 // the products of leaf i.
 template <typename T, int K, bool LEAF_STEP1>
-__device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gleaf, int sg, int lane)
+__device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gleaf, int sg, int lane, T *slot)
 {
     const int li = lane & 15, q = lane >> 4;
     const int M = a.M, s = a.s;
@@ -174,19 +207,16 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
     if (LEAF_STEP1) it = lane_item(a, lane);
     const int nch = s > 16 ? 2 : 1;
 
-    // leaf inputs: step (1) reads u[2 s t + 2 m + sigma], m = 16 c + 4 q + kk
-    double xn[2][4];
+    // leaf inputs: step (1) reads u[2 s t + 2 m + sigma], m = 16 c + 4 q + kk, from the
+    // wave's LDS slot [transform][m]; the next leaf's loads are in flight meanwhile
+    double xn[16];
     v4_t<T> wn = v4_zero<T>();
     auto issue = [&](int64_t t) {
-        if (LEAF_STEP1) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                if (c < nch) load4(it, 2 * s * t + 32 * c + 8 * q + sg, xn[c]);
-        } else {
-            wn = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane));
-        }
+        if (LEAF_STEP1) node_load(it, t, s, lane, xn);
+        else wn = *reinterpret_cast<const v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane));
     };
     issue(t0);
+    if (LEAF_STEP1) node_stage<T>(slot, xn, t0, s, lane, sg, a.dir, false);
     v4_t<T> stk[K > 0 ? K : 1];
     for (int i = 0; i < (1 << K); ++i) {
         const int64_t t = t0 + i;
@@ -195,7 +225,8 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
             T y[2][4];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-                if (c < nch) stage4<T>(xn[c], 2 * s * t + 32 * c + 8 * q + sg, a.dir, false, y[c]);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) y[c][kk] = slot[li * kBatRow + (16 * c + 4 * q + kk)];
             if (i + 1 < (1 << K)) issue(t + 1);
             // step (1): w_k(t, sigma) = sum_m T_k(X_m^sigma) u[2 s t + 2 m + sigma]
             cur = v4_zero<T>();
@@ -210,6 +241,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
                 }
             }
             *reinterpret_cast<v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane)) = cur;
+            if (i + 1 < (1 << K)) node_stage<T>(slot, xn, t + 1, s, lane, sg, a.dir, false);
         } else {
             cur = wn;
             if (i + 1 < (1 << K)) issue(t + 1);
@@ -235,11 +267,12 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
 template <typename T, int KU>
 __global__ __launch_bounds__(256) void kb_up(BatArgs<T> a)
 {
+    __shared__ T slots[4][16 * kBatRow];
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     const int64_t P = int64_t(1) << (a.L + 1);   // finest nodes
     if ((sub << KU) >= P) return;
-    up_walk<T, KU, true>(a, sub << KU, a.L - 1, wv & 1, lane);
+    up_walk<T, KU, true>(a, sub << KU, a.L - 1, wv & 1, lane, slots[wv]);
 }
 
 template <typename T, int KT>
@@ -248,7 +281,7 @@ __global__ __launch_bounds__(256) void kb_top(BatArgs<T> a)
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     if ((sub << KT) >= (int64_t(1) << (a.gin + 2))) return;
-    up_walk<T, KT, false>(a, sub << KT, a.gin, wv & 1, lane);
+    up_walk<T, KT, false>(a, sub << KT, a.gin, wv & 1, lane, nullptr);
 }
 
 // ------------------------------------------------------------------------------------
@@ -301,22 +334,26 @@ __device__ __forceinline__ v4_t<T> far_do(const FarIn<T> &f)
 }
 
 // Steps (3)-(7) for one level-groot subtree of 2^KD finest row nodes and one parity.
-// LDS per wave: the far-field tiles of the subtree's own nodes (node idx of depth d at
-// slot 2^d - 2 + idx) and the Q window of its finest nodes.  NC = ceil(2s / 16) column
-// chunks of the near-field band; rows need two 16-row tiles when s > 16 (NC > 2).
+// NC = ceil(2s / 16) column chunks of the near-field band; rows need two 16-row tiles
+// when s > 16 (NC > 2).  LDS per wave: the far-field tiles of the own nodes above the
+// finest depth (node idx of depth d at slot 2^d - 2 + idx), the Q window of the finest
+// nodes, two input nodes [transform][m] of the wave's parity (row-coalesced loads, the
+// next node in flight) and the output rows of the current node.
 template <typename T, int KD, int NC>
 __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 {
     constexpr int nc = NC, nrt = NC > 2 ? 2 : 1;
-    constexpr int OWN = (2 << KD) - 2;               // own nodes, depths 1..KD
+    constexpr int INNER = (1 << KD) - 2;             // own nodes of depths 1..KD-1
     constexpr int QW = 64 * (1 << KD) + 32;          // Q window: 2s 2^KD + s, s <= 32
+    constexpr int SL = 16 * kBatRow;                 // one staged node
     __shared__ T Pl[64];
-    __shared__ v4_t<T> Fl[4][OWN > 0 ? OWN : 1][64];
+    __shared__ v4_t<T> Fl[4][INNER > 0 ? INNER : 1][64];
     __shared__ T Ql[4][QW];
+    __shared__ T Sl[4][3 * SL];                      // input nodes u, u + 1; output rows
+    L2C_TS(1, 0);
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int li = lane & 15, q = lane >> 4, sg = wv & 1;
     const int s = a.s, M = a.M, dir = a.dir;
-    L2C_TS(1, 0);
     for (int e = threadIdx.x; e < 2 * s; e += 256) Pl[e] = a.Pt[e];
     __syncthreads();
     const int groot = a.L - 1 - KD;
@@ -325,20 +362,18 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
     const int64_t u0 = Rn << KD;                      // first finest row node
     const LaneItem it = lane_item(a, lane);
     T *Qw = Ql[wv];
+    T *in_sl = Sl[wv], *ob = Sl[wv] + 2 * SL;
+    // the first two input nodes
+    double xn[16];
+    node_load(it, u0, s, lane, xn);
     // Q_S for S = 2 s u0 + [0, 2 s 2^KD + s); the rest of the window is zero, so every
     // read of the leaf loop below is of initialized memory
     {
         const int qn = 2 * s * (1 << KD) + s;
         for (int e = lane; e < QW; e += 64) Qw[e] = e < qn ? a.Qt[2 * s * u0 + e] : T(0);
     }
-    // near-field inputs of a leaf: g at j = 2 s u + 2 m' + sigma, m' = 16 c + 4 q + kk
-    double xn[4][4];
-    auto issue_near = [&](int64_t u) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nc) load4(it, 2 * s * u + 32 * c + 8 * q + sg, xn[c]);
-    };
-    issue_near(u0);
+    node_stage<T>(in_sl, xn, u0, s, lane, sg, dir, true);
+    node_load(it, u0 + 1, s, lane, xn);
 
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
     T bt[2][4], te[2][4];
@@ -356,7 +391,6 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             const int m = 16 * rt + li, k = Mx<T>::row(q, kk);
             te[rt][kk] = (m < s && k < M) ? a.Tm[(sg * s + m) * M + k] : T(0);
         }
-
     // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
     // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf
     T pm[2][4][4];
@@ -385,9 +419,10 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             cp = cv;
         }
     }
+    node_stage<T>(in_sl + SL, xn, u0 + 1, s, lane, sg, dir, true);
     L2C_TS(1, 1);
-    // far field of the own nodes (depth-major), pipelined the same way, into LDS
-    if (OWN > 0) {
+    // far field of the own nodes above the finest depth (depth-major), pipelined, into LDS
+    if (INNER > 0) {
         auto own_node = [&](int j, int &d, int64_t &v) {
             d = 31 - __builtin_clz(j + 2);
             v = (Rn << d) + (j + 2 - (1 << d));
@@ -396,9 +431,9 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         int64_t v0;
         own_node(0, d0, v0);
         FarIn<T> nx = far_issue(a, groot + d0, v0, sg, lane);
-        for (int j = 0; j < OWN; ++j) {
+        for (int j = 0; j < INNER; ++j) {
             const FarIn<T> cu = nx;
-            if (j + 1 < OWN) {
+            if (j + 1 < INNER) {
                 int d1;
                 int64_t v1;
                 own_node(j + 1, d1, v1);
@@ -407,31 +442,49 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             Fl[wv][j][lane] = far_do(cu);
         }
     }
-    // this wave's LDS writes (Q window, far tiles) complete before other lanes read them
+    // this wave's LDS writes complete before other lanes read them
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     L2C_TS(1, 2);
 
-    // depth-first walk: stk[d] = c of the current node at depth d; then steps (5)-(7)
+    // depth-first walk: stk[d] = c of the current node at depth d; then steps (5)-(7).
+    // The finest node's far-field operands and the input node u + 2 are loaded one leaf ahead.
     v4_t<T> stk[KD + 1];
     stk[0] = cp;
+    FarIn<T> fnx = far_issue(a, groot + KD, u0, sg, lane);
     for (int i = 0; i < (1 << KD); ++i) {
         const int64_t u = u0 + i;
         const int64_t base = 2 * s * u;
+        const FarIn<T> fcu = fnx;
+        // B operands: g at m' = 16 c + 4 q + kk (node u for m' < s, node u + 1 after)
         T y[4][4];
+        {
+            const T *n0 = in_sl + (i & 1) * SL + li * kBatRow, *n1 = in_sl + ((i + 1) & 1) * SL + li * kBatRow;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nc) stage4<T>(xn[c], base + 32 * c + 8 * q + sg, dir, true, y[c]);
-        if (i + 1 < (1 << KD)) issue_near(u + 1);
-        const int dmin = i == 0 ? 1 : KD - __builtin_ctz(i);
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int d = 1; d <= KD; ++d) {
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int mp = 16 * c + 4 * q + kk;
+                    const T *src = mp < s ? n0 + mp : n1 + (mp < 2 * s ? mp - s : 0);
+                    const T v = *src;
+                    y[c][kk] = (c < nc && mp < 2 * s) ? v : T(0);
+                }
+        }
+        if (i + 1 < (1 << KD)) {
+            fnx = far_issue(a, groot + KD, u + 1, sg, lane);
+            node_load(it, u + 2, s, lane, xn);
+        }
+#pragma unroll
+        for (int d = 1; d < KD; ++d) {
+            const int dmin = i == 0 ? 1 : KD - __builtin_ctz(i);
             if (d >= dmin) {
                 const int idx = i >> (KD - d);
                 stk[d] = tile_mac<T>(Fl[wv][(1 << d) - 2 + idx][lane], bt[idx & 1], stk[d - 1]);
             }
         }
-        const v4_t<T> cu = stk[KD];
+        v4_t<T> cu = far_do(fcu);
+        if (KD > 0) cu = tile_mac<T>(cu, bt[i & 1], stk[KD > 0 ? KD - 1 : 0]);
+        else cu = stk[0];
         v4_t<T> acc[2] = {v4_zero<T>(), v4_zero<T>()};
         // far part (Eq. (step5)): rows m = 16 rt + l mod 16 of T(sigma).  The last two row
         // nodes (u >= P - 2) have no far-field block on any level, so their c is zero.
@@ -463,26 +516,38 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
                 }
             }
         }
-        // step (7) and output: lane holds rows m = 16 rt + row(q, r) of item l mod 16
-        if (it.out) {
-            const double f0 = (dir == 1 && base == 0 && it.n > 0) ? it.in[0] : 0.0;
+        // output rows of this parity through LDS: lane holds rows m = 16 rt + row(q, r) of
+        // transform l mod 16; stored two transforms per instruction, lane -> row
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-                if (rt < nrt) {
+        for (int rt = 0; rt < 2; ++rt)
+            if (rt < nrt) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int m = 16 * rt + Mx<T>::row(q, r);
-                        const int64_t iz = base + 2 * m + sg;
-                        if (m < s && iz < it.n) {
-                            double v = (double)acc[rt][r];
-                            if (dir == 0) v *= (iz == 0 ? 1.0 / kPi : 2.0 / kPi);
-                            else if (iz == 0) v += f0;   // K_00 u_0 = u_0 / 2 = f_0
-                            it.out[iz] = v;
-                        }
-                    }
+                for (int r = 0; r < 4; ++r) ob[li * kBatRow + 16 * rt + Mx<T>::row(q, r)] = acc[rt][r];
+            }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        {
+            const int m = lane & 31;
+            const int64_t iz = base + 2 * m + sg;
+#pragma unroll
+            for (int r2 = 0; r2 < 8; ++r2) {
+                const int tr = 2 * r2 + (lane >> 5);
+                double *o0 = row_out(it, 2 * r2), *o1 = row_out(it, 2 * r2 + 1);
+                const int64_t n0 = row_n(it, 2 * r2), n1 = row_n(it, 2 * r2 + 1);
+                const double *i0 = row_in(it, 2 * r2), *i1 = row_in(it, 2 * r2 + 1);
+                double *o = (lane >> 5) ? o1 : o0;
+                const double *ip = (lane >> 5) ? i1 : i0;
+                const int64_t nr = (lane >> 5) ? n1 : n0;
+                const T zv = ob[tr * kBatRow + m];
+                if (m < s && iz < nr) {
+                    double v = (double)zv;
+                    if (dir == 0) v *= (iz == 0 ? 1.0 / kPi : 2.0 / kPi);
+                    else if (iz == 0) v += ip[0];   // K_00 u_0 = u_0 / 2 = f_0
+                    o[iz] = v;
                 }
             }
         }
+        // the next leaf's second node replaces node u (read above)
+        if (i + 1 < (1 << KD)) node_stage<T>(in_sl + (i & 1) * SL, xn, u + 2, s, lane, sg, dir, true);
         if (i == 0) L2C_TS(1, 3);
     }
     L2C_TS(1, 4);
