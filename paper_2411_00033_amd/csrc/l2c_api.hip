@@ -266,6 +266,9 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
     if (precision != L2C_FP64 && precision != L2C_FP32) return precision == L2C_BF16X2 ? L2C_EUNSUPPORTED : L2C_EINVAL;
     if (!leg2cheb_rank_supported(rank)) return L2C_EUNSUPPORTED;
     if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
+    if (precision == L2C_FP32)
+        for (int64_t i = 0; i < count; ++i)
+            if (n[i] > (int64_t(1) << 28)) return L2C_EUNSUPPORTED;
     l2c_batch_s *b = new (std::nothrow) l2c_batch_s;
     if (!b) return L2C_ENOMEM;
     if (hipGetDevice(&b->device) != hipSuccess) {
@@ -424,8 +427,9 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
         return L2C_EINVAL;
     }
     if (!rank_supported(rank)) return L2C_EUNSUPPORTED;
-    // the batched FP32 form: one 16 x 16 tile per node (M <= 16) and s <= 32
-    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
+    // the batched FP32 form: one 16 x 16 tile per node (M <= 16), s <= 32, rows of at most
+    // 2^28 values (32-bit buffer ranges)
+    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64 || n > (int64_t(1) << 28))) return L2C_EUNSUPPORTED;
 
     l2c_plan_s *p = new (std::nothrow) l2c_plan_s();
     if (!p) return L2C_ENOMEM;

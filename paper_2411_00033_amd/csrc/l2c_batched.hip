@@ -131,17 +131,25 @@ __device__ __forceinline__ const double *row_in(const LaneItem &it, int r) { ret
 __device__ __forceinline__ double *row_out(const LaneItem &it, int r) { return lane_ptr(it.out, r); }
 __device__ __forceinline__ int64_t row_n(const LaneItem &it, int r) { return lane_i64(it.n, r); }
 
+// A transform's row as a raw buffer resource of n values: the hardware range check returns
+// zero for loads past the end and drops stores past it (rows hold at most 2^28 values).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kBufOut = 0xFFFFFFF0u;    // byte offset outside every row
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const double *p, int64_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(n * 8), 0x00020000);
+}
+
 // One node of input for the 16 transforms of the tile, row-coalesced: instruction r reads
 // the node's 2s consecutive values of transform r (lane e: f[2 s t + e]), whole cache
 // lines per instruction.  Zero past a transform's length and for lanes e >= 2s.
 __device__ __forceinline__ void node_load(const LaneItem &it, int64_t t, int s, int lane, double (&x)[16])
 {
-    const int64_t j = 2 * s * t + lane;
+    const unsigned off = lane < 2 * s ? (unsigned)(2 * s * t + lane) * 8u : kBufOut;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const double *p = row_in(it, r);
-        const int64_t nr = row_n(it, r);
-        x[r] = (lane < 2 * s && j < nr) ? p[j] : 0.0;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row_in(it, r), row_n(it, r)), off, 0, 0);
+        x[r] = __builtin_bit_cast(double, v);
     }
 }
 
@@ -333,12 +341,43 @@ __device__ __forceinline__ v4_t<T> far_do(const FarIn<T> &f)
     return r;
 }
 
+// The same for the two parity waves of a subtree sharing one staged node: wave h loads rows
+// 8h .. 8h + 7 and stages both parities, slot[sigma][row][m] (parity stride SL).
+__device__ __forceinline__ void node_load8(const LaneItem &it, int64_t t, int s, int lane, int h, double (&x)[8])
+{
+    const unsigned off = lane < 2 * s ? (unsigned)(2 * s * t + lane) * 8u : kBufOut;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const u32x2 v =
+            __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row_in(it, 8 * h + r), row_n(it, 8 * h + r)), off, 0, 0);
+        x[r] = __builtin_bit_cast(double, v);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void node_stage8(T *slot, int SL, const double (&x)[8], int64_t t, int s, int lane, int h,
+                                            int dir, bool times_j)
+{
+    if (lane < 2 * s) {
+        const int64_t j = 2 * s * t + lane;
+        double sc = 1.0;
+        if (dir == 1) {
+            if (j == 0) sc = 2.0;
+            if (times_j) sc *= (double)(uint32_t)j;   // j < n <= 2^28 wherever x is nonzero
+        }
+        T *dst = slot + (lane & 1) * SL + 8 * h * kBatRow + (lane >> 1);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[r * kBatRow] = (T)(x[r] * sc);
+    }
+}
+
 // Steps (3)-(7) for one level-groot subtree of 2^KD finest row nodes and one parity.
 // NC = ceil(2s / 16) column chunks of the near-field band; rows need two 16-row tiles
 // when s > 16 (NC > 2).  LDS per wave: the far-field tiles of the own nodes above the
-// finest depth (node idx of depth d at slot 2^d - 2 + idx), the Q window of the finest
-// nodes, two input nodes [transform][m] of the wave's parity (row-coalesced loads, the
-// next node in flight) and the output rows of the current node.
+// finest depth (node idx of depth d at slot 2^d - 2 + idx) and the Q window of the finest
+// nodes; per subtree (shared by its two parity waves, two workgroup barriers per leaf):
+// two input nodes [parity][transform][m] (row-coalesced loads, the next node in flight)
+// and the output rows of the current node [transform][2s].  The grid holds an even number
+// of subtrees, so every wave of a workgroup has a subtree and reaches every barrier.
 template <typename T, int KD, int NC>
 __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 {
@@ -346,50 +385,56 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
     constexpr int INNER = (1 << KD) - 2;             // own nodes of depths 1..KD-1
     constexpr int QW = 64 * (1 << KD) + 32;          // Q window: 2s 2^KD + s, s <= 32
     constexpr int SL = 16 * kBatRow;                 // one staged node
-    __shared__ T Pl[64];
     __shared__ v4_t<T> Fl[4][INNER > 0 ? INNER : 1][64];
     __shared__ T Ql[4][QW];
-    __shared__ T Sl[4][3 * SL];                      // input nodes u, u + 1; output rows
+    constexpr int OBS = 65;                          // output row stride (2s <= 64)
+    __shared__ T Sl[2][4 * SL + 16 * OBS];           // per subtree: input nodes u, u + 1; output rows
     L2C_TS(1, 0);
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int li = lane & 15, q = lane >> 4, sg = wv & 1;
     const int s = a.s, M = a.M, dir = a.dir;
-    for (int e = threadIdx.x; e < 2 * s; e += 256) Pl[e] = a.Pt[e];
-    __syncthreads();
     const int groot = a.L - 1 - KD;
-    const int64_t Rn = (int64_t)blockIdx.x * 2 + (wv >> 1);
-    if (Rn >= (int64_t(1) << (groot + 2))) return;
+    const int64_t Rn = (int64_t)blockIdx.x * 2 + (wv >> 1);   // < 2^(groot+2): the grid is exact
     const int64_t u0 = Rn << KD;                      // first finest row node
     const LaneItem it = lane_item(a, lane);
     T *Qw = Ql[wv];
-    T *in_sl = Sl[wv], *ob = Sl[wv] + 2 * SL;
-    // the first two input nodes
-    double xn[16];
-    node_load(it, u0, s, lane, xn);
+    T *in_sl = Sl[wv >> 1], *ob = Sl[wv >> 1] + 4 * SL;
+
+    // Every load of the prologue is issued before the first one is waited for.
+    // The first two input nodes (this wave: rows 8 sg .. 8 sg + 7).
+    double xn[8], xn1[8];
+    node_load8(it, u0, s, lane, sg, xn);
+    node_load8(it, u0 + 1, s, lane, sg, xn1);
     // Q_S for S = 2 s u0 + [0, 2 s 2^KD + s); the rest of the window is zero, so every
     // read of the leaf loop below is of initialized memory
+    constexpr int QR = QW / 64 + 1;
+    T qreg[QR];
     {
         const int qn = 2 * s * (1 << KD) + s;
-        for (int e = lane; e < QW; e += 64) Qw[e] = e < qn ? a.Qt[2 * s * u0 + e] : T(0);
+#pragma unroll
+        for (int k = 0; k < QR; ++k) {
+            const int e = lane + 64 * k;
+            qreg[k] = e < qn ? a.Qt[2 * s * u0 + (e < qn ? e : 0)] : T(0);
+        }
     }
-    node_stage<T>(in_sl, xn, u0, s, lane, sg, dir, true);
-    node_load(it, u0 + 1, s, lane, xn);
-
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
     T bt[2][4], te[2][4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const int k = Mx<T>::row(q, kk);
-        const T v = (li < M && k < M) ? a.B0[k * M + li] : T(0);
-        bt[0][kk] = v;
-        bt[1][kk] = ((k - li) & 1) ? -v : v;
+        const bool ok = li < M && k < M;
+        const T v = a.B0[ok ? k * M + li : 0];
+        bt[0][kk] = ok ? v : T(0);
+        bt[1][kk] = ((k - li) & 1) ? -bt[0][kk] : bt[0][kk];
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int m = 16 * rt + li, k = Mx<T>::row(q, kk);
-            te[rt][kk] = (m < s && k < M) ? a.Tm[(sg * s + m) * M + k] : T(0);
+            const bool ok = m < s && k < M;
+            const T v = a.Tm[ok ? (sg * s + m) * M + k : 0];
+            te[rt][kk] = ok ? v : T(0);
         }
     // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
     // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf
@@ -402,24 +447,32 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             for (int kk = 0; kk < 4; ++kk) {
                 const int m = 16 * rt + li, mp = 16 * c + 4 * q + kk;
                 const bool nz = m < s && mp >= m && mp < 2 * s;
-                const T pv = Pl[nz ? mp - m : 0];
+                const T pv = a.Pt[nz ? mp - m : 0];
                 pm[rt][c][kk] = nz ? pv : T(0);
             }
+    // the first two ancestor levels' far-field operands
+    FarIn<T> n1 = far_issue(a, 0, Rn >> groot, sg, lane);
+    FarIn<T> n2 = groot >= 1 ? far_issue(a, 1, Rn >> (groot - 1), sg, lane) : n1;
+    // now the LDS stores of the Q window and the first input node
+#pragma unroll
+    for (int k = 0; k < QR; ++k) {
+        const int e = lane + 64 * k;
+        if (e < QW) Qw[e] = qreg[k];
+    }
+    node_stage8<T>(in_sl, SL, xn, u0, s, lane, sg, dir, true);
 
     // ancestors a_g = Rn >> (groot - g): c(a_0) = far; c(a_g) = far + B(p)^T c(a_{g-1});
-    // the operands of level g + 1 are loaded while level g is multiplied
+    // the operands of levels g + 1 and g + 2 are in flight while level g is multiplied
     v4_t<T> cp = v4_zero<T>();
-    {
-        FarIn<T> nx = far_issue(a, 0, Rn >> groot, sg, lane);
-        for (int g = 0; g <= groot; ++g) {
-            const FarIn<T> cu = nx;
-            if (g < groot) nx = far_issue(a, g + 1, Rn >> (groot - g - 1), sg, lane);
-            v4_t<T> cv = far_do(cu);
-            if (g > 0) cv = tile_mac<T>(cv, bt[(Rn >> (groot - g)) & 1], cp);
-            cp = cv;
-        }
+    for (int g = 0; g <= groot; ++g) {
+        const FarIn<T> cu = n1;
+        n1 = n2;
+        if (g + 2 <= groot) n2 = far_issue(a, g + 2, Rn >> (groot - g - 2), sg, lane);
+        v4_t<T> cv = far_do(cu);
+        if (g > 0) cv = tile_mac<T>(cv, bt[(Rn >> (groot - g)) & 1], cp);
+        cp = cv;
     }
-    node_stage<T>(in_sl + SL, xn, u0 + 1, s, lane, sg, dir, true);
+    node_stage8<T>(in_sl + 2 * SL, SL, xn1, u0 + 1, s, lane, sg, dir, true);
     L2C_TS(1, 1);
     // far field of the own nodes above the finest depth (depth-major), pipelined, into LDS
     if (INNER > 0) {
@@ -442,9 +495,8 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             Fl[wv][j][lane] = far_do(cu);
         }
     }
-    // this wave's LDS writes complete before other lanes read them
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // LDS writes (far tiles, Q window, staged input of both parity waves) complete
+    __syncthreads();
     L2C_TS(1, 2);
 
     // depth-first walk: stk[d] = c of the current node at depth d; then steps (5)-(7).
@@ -459,7 +511,8 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         // B operands: g at m' = 16 c + 4 q + kk (node u for m' < s, node u + 1 after)
         T y[4][4];
         {
-            const T *n0 = in_sl + (i & 1) * SL + li * kBatRow, *n1 = in_sl + ((i + 1) & 1) * SL + li * kBatRow;
+            const T *n0 = in_sl + (i & 1) * 2 * SL + sg * SL + li * kBatRow;
+            const T *n1 = in_sl + ((i + 1) & 1) * 2 * SL + sg * SL + li * kBatRow;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -472,7 +525,7 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         }
         if (i + 1 < (1 << KD)) {
             fnx = far_issue(a, groot + KD, u + 1, sg, lane);
-            node_load(it, u + 2, s, lane, xn);
+            node_load8(it, u + 2, s, lane, sg, xn);
         }
 #pragma unroll
         for (int d = 1; d < KD; ++d) {
@@ -522,32 +575,31 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         for (int rt = 0; rt < 2; ++rt)
             if (rt < nrt) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ob[li * kBatRow + 16 * rt + Mx<T>::row(q, r)] = acc[rt][r];
+                for (int r = 0; r < 4; ++r) ob[li * OBS + 2 * (16 * rt + Mx<T>::row(q, r)) + sg] = acc[rt][r];
             }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __syncthreads();
         {
-            const int m = lane & 31;
-            const int64_t iz = base + 2 * m + sg;
+            // wave sg stores rows 8 sg .. 8 sg + 7 of the node, lane e -> output 2 s u + e
+            const int64_t iz = base + lane;
+            const unsigned off = lane < 2 * s ? (unsigned)iz * 8u : kBufOut;
+            const double sc = dir == 0 ? (iz == 0 ? 1.0 / kPi : 2.0 / kPi) : 1.0;
 #pragma unroll
-            for (int r2 = 0; r2 < 8; ++r2) {
-                const int tr = 2 * r2 + (lane >> 5);
-                double *o0 = row_out(it, 2 * r2), *o1 = row_out(it, 2 * r2 + 1);
-                const int64_t n0 = row_n(it, 2 * r2), n1 = row_n(it, 2 * r2 + 1);
-                const double *i0 = row_in(it, 2 * r2), *i1 = row_in(it, 2 * r2 + 1);
-                double *o = (lane >> 5) ? o1 : o0;
-                const double *ip = (lane >> 5) ? i1 : i0;
-                const int64_t nr = (lane >> 5) ? n1 : n0;
-                const T zv = ob[tr * kBatRow + m];
-                if (m < s && iz < nr) {
-                    double v = (double)zv;
-                    if (dir == 0) v *= (iz == 0 ? 1.0 / kPi : 2.0 / kPi);
-                    else if (iz == 0) v += ip[0];   // K_00 u_0 = u_0 / 2 = f_0
-                    o[iz] = v;
+            for (int r = 0; r < 8; ++r) {
+                const int tr = 8 * sg + r;
+                const int64_t nr = row_n(it, tr);
+                double v = (double)ob[tr * OBS + (lane < 2 * s ? lane : 0)] * sc;
+                if (dir == 1 && base == 0 && nr > 0) {
+                    const double f0 = row_in(it, tr)[0];
+                    if (iz == 0) v += f0;   // K_00 u_0 = u_0 / 2 = f_0
                 }
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), row_rsrc(row_out(it, tr), nr), off, 0, 0);
             }
         }
-        // the next leaf's second node replaces node u (read above)
-        if (i + 1 < (1 << KD)) node_stage<T>(in_sl + (i & 1) * SL, xn, u + 2, s, lane, sg, dir, true);
+        // the next leaf's second node replaces node u (read above by both parity waves)
+        if (i + 1 < (1 << KD)) {
+            node_stage8<T>(in_sl + (i & 1) * 2 * SL, SL, xn, u + 2, s, lane, sg, dir, true);
+            __syncthreads();
+        }
         if (i == 0) L2C_TS(1, 3);
     }
     L2C_TS(1, 4);
