@@ -40,8 +40,15 @@ typedef struct l2c_plan_s *l2c_plan_t;
 
 enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
 
-/* Arithmetic of the far-field and leaf products (the plan tables and the
- * final accumulation stay FP64).  Only L2C_FP64 is available in this build. */
+/* Arithmetic of the execute.  Inputs and outputs are FP64 in every form, and the
+ * plan builds its tables in FP64.
+ *   L2C_FP64    every product and sum in FP64.
+ *   L2C_FP32    the batched form (not in the paper: it serves batches of transforms):
+ *               tables stored in FP32 and every product of steps (1)-(6) on the matrix
+ *               cores in FP32 with FP32 accumulation, 16 transforms per 16 x 16 tile;
+ *               step (7) scaling in FP64.  Needs rank <= 16, leaf_size <= 64 and
+ *               n <= 2^28; E_inf about 1e-6 (rank 16).
+ *   L2C_BF16X2  reserved (L2C_EUNSUPPORTED in this build). */
 enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
 
 /* Execution path of a plan (l2c_plan_info.path). */
@@ -99,7 +106,8 @@ int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int
 
 /*
  * As leg2cheb_plan, plus:
- *   precision  l2c_precision (only L2C_FP64 in this build, else L2C_EUNSUPPORTED);
+ *   precision  l2c_precision: L2C_FP64, or L2C_FP32 (rank <= 16, leaf_size <= 64,
+ *              n <= 2^28, else L2C_EUNSUPPORTED); L2C_BF16X2 gives L2C_EUNSUPPORTED;
  *   max_batch  workspace is sized for this many items (>= 1); execute grows it on
  *              demand (a synchronizing allocation) when a larger batch arrives;
  *   stream     hipStream_t on which the table-building kernels run (NULL = null stream).
@@ -133,7 +141,8 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info);
  *         2 = B:    B(0) then B(1), 2 x M x M row-major (Eq. (Tky)).
  *   dst   host buffer of at least `bytes` bytes; bytes must equal the table size
  *         (query with dst = NULL: *needed receives the size and nothing is copied).
- * Errors: L2C_EINVAL (bad table id, size mismatch, direct-only plan), L2C_EHIP.
+ * Errors: L2C_EINVAL (bad table id, size mismatch, direct-only plan), L2C_EUNSUPPORTED
+ * (table 0 of an L2C_FP32 plan, which keeps Ahat only in its own layout), L2C_EHIP.
  */
 int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed);
 
