@@ -48,7 +48,10 @@ enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
  *               cores in FP32 with FP32 accumulation, 16 transforms per 16 x 16 tile;
  *               step (7) scaling in FP64.  Needs rank <= 16, leaf_size <= 64 and
  *               n <= 2^28; E_inf about 1e-6 (rank 16).
- *   L2C_BF16X2  reserved (L2C_EUNSUPPORTED in this build). */
+ *   L2C_BF16X2  the same batched form with every FP32 operand x split as hi = bf16(x),
+ *               lo = bf16(x - hi) and each product formed as hi*hi + hi*lo + lo*hi on the
+ *               BF16 matrix cores with FP32 accumulation (products accurate to about
+ *               2^-17); same limits as L2C_FP32. */
 enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
 
 /* Execution path of a plan (l2c_plan_info.path). */
@@ -56,7 +59,7 @@ enum l2c_path {
     L2C_PATH_DIRECT = 0, /* L = 0: the whole product directly (Alg. 1) */
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
     L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
-    L2C_PATH_BATCHED = 3 /* L2C_FP32 plans: 16 transforms per matrix-core tile, three kernels */
+    L2C_PATH_BATCHED = 3 /* L2C_FP32 / L2C_BF16X2 plans: 16 transforms per matrix-core tile */
 };
 
 /* Plan options (leg2cheb_plan_set_option). */
@@ -106,8 +109,8 @@ int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int
 
 /*
  * As leg2cheb_plan, plus:
- *   precision  l2c_precision: L2C_FP64, or L2C_FP32 (rank <= 16, leaf_size <= 64,
- *              n <= 2^28, else L2C_EUNSUPPORTED); L2C_BF16X2 gives L2C_EUNSUPPORTED;
+ *   precision  l2c_precision: L2C_FP64, or L2C_FP32 / L2C_BF16X2 (rank <= 16,
+ *              leaf_size <= 64, n <= 2^28, else L2C_EUNSUPPORTED);
  *   max_batch  workspace is sized for this many items (>= 1); execute grows it on
  *              demand (a synchronizing allocation) when a larger batch arrives;
  *   stream     hipStream_t on which the table-building kernels run (NULL = null stream).
@@ -142,7 +145,8 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info);
  *   dst   host buffer of at least `bytes` bytes; bytes must equal the table size
  *         (query with dst = NULL: *needed receives the size and nothing is copied).
  * Errors: L2C_EINVAL (bad table id, size mismatch, direct-only plan), L2C_EUNSUPPORTED
- * (table 0 of an L2C_FP32 plan, which keeps Ahat only in its own layout), L2C_EHIP.
+ * (table 0 of an L2C_FP32 or L2C_BF16X2 plan, which keeps Ahat only in its own layout),
+ * L2C_EHIP.
  */
 int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed);
 

@@ -130,8 +130,9 @@ void free_plan(l2c_plan_s *p)
 }
 
 bool use_fused(const l2c_plan_s *p) { return p->fused_ok && p->fused_on; }
-bool use_batched(const l2c_plan_s *p) { return p->L > 0 && p->precision == L2C_FP32; }
-size_t elem_bytes(const l2c_plan_s *p) { return p->precision == L2C_FP32 ? sizeof(float) : sizeof(double); }
+bool batched_form(int precision) { return precision == L2C_FP32 || precision == L2C_BF16X2; }
+bool use_batched(const l2c_plan_s *p) { return p->L > 0 && batched_form(p->precision); }
+size_t elem_bytes(const l2c_plan_s *p) { return batched_form(p->precision) ? sizeof(float) : sizeof(double); }
 
 }  // namespace
 
@@ -263,10 +264,10 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
     for (int64_t i = 0; i < count; ++i)
         if (n[i] < 1 || (direction[i] != L2C_LEG2CHEB && direction[i] != L2C_CHEB2LEG)) return L2C_EINVAL;
     if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
-    if (precision != L2C_FP64 && precision != L2C_FP32) return precision == L2C_BF16X2 ? L2C_EUNSUPPORTED : L2C_EINVAL;
+    if (precision != L2C_FP64 && !batched_form(precision)) return L2C_EINVAL;
     if (!leg2cheb_rank_supported(rank)) return L2C_EUNSUPPORTED;
-    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
-    if (precision == L2C_FP32)
+    if (batched_form(precision) && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
+    if (batched_form(precision))
         for (int64_t i = 0; i < count; ++i)
             if (n[i] > (int64_t(1) << 28)) return L2C_EUNSUPPORTED;
     l2c_batch_s *b = new (std::nothrow) l2c_batch_s;
@@ -422,14 +423,11 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
     if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
     if (rank < 1 || rank > 32) return L2C_EINVAL;
     if (max_batch < 1) return L2C_EINVAL;
-    if (precision != L2C_FP64 && precision != L2C_FP32) {
-        if (precision == L2C_BF16X2) return L2C_EUNSUPPORTED;
-        return L2C_EINVAL;
-    }
+    if (precision != L2C_FP64 && !batched_form(precision)) return L2C_EINVAL;
     if (!rank_supported(rank)) return L2C_EUNSUPPORTED;
-    // the batched FP32 form: one 16 x 16 tile per node (M <= 16), s <= 32, rows of at most
+    // the batched forms: one 16 x 16 tile per node (M <= 16), s <= 32, rows of at most
     // 2^28 values (32-bit buffer ranges)
-    if (precision == L2C_FP32 && (rank > 16 || leaf_size > 64 || n > (int64_t(1) << 28))) return L2C_EUNSUPPORTED;
+    if (batched_form(precision) && (rank > 16 || leaf_size > 64 || n > (int64_t(1) << 28))) return L2C_EUNSUPPORTED;
 
     l2c_plan_s *p = new (std::nothrow) l2c_plan_s();
     if (!p) return L2C_ENOMEM;
@@ -491,7 +489,7 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
             free_plan(p);
             return L2C_EHIP;
         }
-        if (precision == L2C_FP32) {
+        if (batched_form(precision)) {
             int rc = build_batched_tables(p, T, B, Ptab, st);
             if (rc == L2C_OK) rc = ensure_bworkspace(p, max_batch);
             if (rc != L2C_OK) {

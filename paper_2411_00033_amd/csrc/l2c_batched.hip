@@ -1,7 +1,8 @@
-// l2c_batched.hip -- the batched execution form (precision L2C_FP32): the modal
-// multipole transform (arXiv 2411.00033, Alg. 4) for 16 transforms at a time, every
-// product of steps (1)-(6) on the gfx950 matrix cores with the batch as the product's
-// column dimension.
+// l2c_batched.hip -- the batched execution forms (precisions L2C_FP32 and L2C_BF16X2):
+// the modal multipole transform (arXiv 2411.00033, Alg. 4) for 16 transforms at a time,
+// every product of steps (1)-(6) on the gfx950 matrix cores with the batch as the
+// product's column dimension (FP32 products, or BF16 hi+lo products with FP32
+// accumulation).
 //
 // A "tile" is the 16 x 16 matrix [k][item] of one tree node and parity for the 16
 // transforms of a workgroup row (blockIdx.y): the upward vectors w of Eq. (wTf) and
@@ -28,6 +29,7 @@
 // form's precision; inputs and outputs stay FP64 (converted on load, scaled by step (7)
 // in FP64 on store).
 #include "l2c_device.h"
+#include "../../include/leg2cheb.h"
 
 namespace l2c {
 
@@ -174,43 +176,138 @@ __device__ __forceinline__ void node_stage(T *slot, const double (&x)[16], int64
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-// acc += Am X for one tile, Am given as the lane's four A-operand values
-// (Am[l mod 16][row(l / 16, kk)]) and X in the accumulator layout.
-template <typename T>
-__device__ __forceinline__ v4_t<T> tile_mac(v4_t<T> acc, const T (&am)[4], const v4_t<T> &x)
+// ------------------------------------------------------------------------------------
+// Forms.  FM = 0: FP32 products, four 16 x 16 x 4 instructions per tile product.
+// FM = 1 (BF16 hi+lo): every FP32 operand x is split as hi = bf16(x), lo = bf16(x - hi),
+// and a product of A and B is ah bh + ah bl + al bh (the al bl term, ~2^-16 relative, is
+// dropped): three 16 x 16 x 16 BF16 instructions with FP32 accumulation.  The BF16
+// instruction takes K = 4q + j (j = 0..3) from lane group q, the same rows the FP32 form
+// takes in its steps kk = j, so both forms use the same per-lane values.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+template <int FM>
+struct Aop;
+template <>
+struct Aop<0> {
+    float v[4];
+};
+template <>
+struct Aop<1> {
+    bf16x4 hi, lo;
+};
+
+__device__ __forceinline__ void split_bf16(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
 {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = Mx<T>::mma(am[kk], x[kk], acc);
+    for (int j = 0; j < 4; ++j) {
+        hi[j] = (__bf16)x[j];
+        lo[j] = (__bf16)(x[j] - (float)hi[j]);
+    }
+}
+
+template <int FM>
+__device__ __forceinline__ Aop<FM> aop(const float (&x)[4])
+{
+    Aop<FM> r;
+    if constexpr (FM == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.v[j] = x[j];
+    } else {
+        split_bf16(x, r.hi, r.lo);
+    }
+    return r;
+}
+
+// The 16 bytes of a packed table entry: four FP32 values, or four hi then four lo BF16 values.
+template <int FM>
+__device__ __forceinline__ Aop<FM> aop_raw(const v4_t<float> &raw)
+{
+    Aop<FM> r;
+    if constexpr (FM == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.v[j] = raw[j];
+    } else {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u4 b = __builtin_bit_cast(u4, raw);
+        r.hi = __builtin_bit_cast(bf16x4, u2{b[0], b[1]});
+        r.lo = __builtin_bit_cast(bf16x4, u2{b[2], b[3]});
+    }
+    return r;
+}
+
+// a1 if c else a0, by value (a runtime index into an array of operands would go to the stack)
+template <int FM>
+__device__ __forceinline__ Aop<FM> pick(const Aop<FM> &a0, const Aop<FM> &a1, bool c)
+{
+    Aop<FM> r;
+    if constexpr (FM == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.v[j] = c ? a1.v[j] : a0.v[j];
+    } else {
+        r.hi = c ? a1.hi : a0.hi;
+        r.lo = c ? a1.lo : a0.lo;
+    }
+    return r;
+}
+
+// acc += A B for one tile, B given as the lane's four values (rows row(q, j) of its column).
+template <int FM>
+__device__ __forceinline__ v4_t<float> mac(v4_t<float> acc, const Aop<FM> &a, const float (&b)[4])
+{
+    if constexpr (FM == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = Mx<float>::mma(a.v[j], b[j], acc);
+    } else {
+        bf16x4 bh, bl;
+        split_bf16(b, bh, bl);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, bh, acc, 0, 0, 0);
+    }
     return acc;
+}
+template <int FM>
+__device__ __forceinline__ v4_t<float> mac_tile(v4_t<float> acc, const Aop<FM> &a, const v4_t<float> &x)
+{
+    const float b[4] = {x[0], x[1], x[2], x[3]};
+    return mac<FM>(acc, a, b);
 }
 
 // ------------------------------------------------------------------------------------
 // Upward pass of one parity over 2^K leaves starting at t0 (level gleaf): leaf tiles from
 // step (1) (LEAF_STEP1) or from the workspace; the loads of leaf i + 1 are issued before
 // the products of leaf i.
-template <typename T, int K, bool LEAF_STEP1>
+template <typename T, int K, bool LEAF_STEP1, int FM>
 __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gleaf, int sg, int lane, T *slot)
 {
     const int li = lane & 15, q = lane >> 4;
     const int M = a.M, s = a.s;
     // A operands of the parent transfer: B(0) and B(1) = B(0) with odd diagonals negated
-    T b0a[4], b1a[4];
+    Aop<FM> b0a, b1a;
+    {
+        float v0[4], v1[4];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        const int k = Mx<T>::row(q, kk);
-        const T v = (li < M && k < M) ? a.B0[li * M + k] : T(0);
-        b0a[kk] = v;
-        b1a[kk] = ((li - k) & 1) ? -v : v;
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = Mx<T>::row(q, kk);
+            const T v = (li < M && k < M) ? a.B0[li * M + k] : T(0);
+            v0[kk] = v;
+            v1[kk] = ((li - k) & 1) ? -v : v;
+        }
+        b0a = aop<FM>(v0);
+        b1a = aop<FM>(v1);
     }
     // A operands of step (1): T(sigma)^T, column m = 16 c + 4 q + kk
-    T ta[2][4];
+    Aop<FM> ta[2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
+        float v[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int m = 16 * c + 4 * q + kk;
-            ta[c][kk] = (LEAF_STEP1 && li < M && m < s) ? a.Tm[(sg * s + m) * M + li] : T(0);
+            v[kk] = (LEAF_STEP1 && li < M && m < s) ? a.Tm[(sg * s + m) * M + li] : T(0);
         }
+        ta[c] = aop<FM>(v);
+    }
     LaneItem it{nullptr, nullptr, 0};
     if (LEAF_STEP1) it = lane_item(a, lane);
     const int nch = s > 16 ? 2 : 1;
@@ -241,11 +338,10 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (c < nch) {
+                    float b[4];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const bool in_node = 16 * c + 4 * q + kk < s;
-                        cur = Mx<T>::mma(ta[c][kk], in_node ? y[c][kk] : T(0), cur);
-                    }
+                    for (int kk = 0; kk < 4; ++kk) b[kk] = 16 * c + 4 * q + kk < s ? y[c][kk] : T(0);
+                    cur = mac<FM>(cur, ta[c], b);
                 }
             }
             *reinterpret_cast<v4_t<T> *>(tile_ptr(a, node_offset(gleaf) + t, sg, lane)) = cur;
@@ -263,7 +359,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
                     stk[d - 1] = cur;
                     done = true;
                 } else {
-                    cur = tile_mac<T>(tile_mac<T>(v4_zero<T>(), b0a, stk[d - 1]), b1a, cur);
+                    cur = mac_tile<FM>(mac_tile<FM>(v4_zero<T>(), b0a, stk[d - 1]), b1a, cur);
                     *reinterpret_cast<v4_t<T> *>(tile_ptr(a, node_offset(gleaf - d) + (t >> d), sg, lane)) = cur;
                 }
             }
@@ -272,7 +368,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
 }
 
 // Waves of a workgroup: wave w takes subtree 2 blockIdx.x + w / 2 and parity w mod 2.
-template <typename T, int KU>
+template <typename T, int KU, int FM>
 __global__ __launch_bounds__(256) void kb_up(BatArgs<T> a)
 {
     __shared__ T slots[4][16 * kBatRow];
@@ -280,16 +376,16 @@ __global__ __launch_bounds__(256) void kb_up(BatArgs<T> a)
     const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     const int64_t P = int64_t(1) << (a.L + 1);   // finest nodes
     if ((sub << KU) >= P) return;
-    up_walk<T, KU, true>(a, sub << KU, a.L - 1, wv & 1, lane, slots[wv]);
+    up_walk<T, KU, true, FM>(a, sub << KU, a.L - 1, wv & 1, lane, slots[wv]);
 }
 
-template <typename T, int KT>
+template <typename T, int KT, int FM>
 __global__ __launch_bounds__(256) void kb_top(BatArgs<T> a)
 {
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
     if ((sub << KT) >= (int64_t(1) << (a.gin + 2))) return;
-    up_walk<T, KT, false>(a, sub << KT, a.gin, wv & 1, lane, nullptr);
+    up_walk<T, KT, false, FM>(a, sub << KT, a.gin, wv & 1, lane, nullptr);
 }
 
 // ------------------------------------------------------------------------------------
@@ -327,17 +423,13 @@ __device__ __forceinline__ FarIn<T> far_issue(const BatArgs<T> &a, int g, int64_
     return f;
 }
 
-template <typename T>
+template <int FM, typename T>
 __device__ __forceinline__ v4_t<T> far_do(const FarIn<T> &f)
 {
     v4_t<T> r = v4_zero<T>();
     if (f.kind == 0) return r;
-    const T a0[4] = {f.A0[0], f.A0[1], f.A0[2], f.A0[3]};
-    r = tile_mac<T>(r, a0, f.W2);
-    if (f.kind == 1) {
-        const T a1[4] = {f.A1[0], f.A1[1], f.A1[2], f.A1[3]};
-        r = tile_mac<T>(r, a1, f.W3);
-    }
+    r = mac_tile<FM>(r, aop_raw<FM>(f.A0), f.W2);
+    if (f.kind == 1) r = mac_tile<FM>(r, aop_raw<FM>(f.A1), f.W3);
     return r;
 }
 
@@ -378,7 +470,7 @@ __device__ __forceinline__ void node_stage8(T *slot, int SL, const double (&x)[8
 // two input nodes [parity][transform][m] (row-coalesced loads, the next node in flight)
 // and the output rows of the current node [transform][2s].  The grid holds an even number
 // of subtrees, so every wave of a workgroup has a subtree and reaches every barrier.
-template <typename T, int KD, int NC>
+template <typename T, int KD, int NC, int FM>
 __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 {
     constexpr int nc = NC, nrt = NC > 2 ? 2 : 1;
@@ -418,14 +510,14 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         }
     }
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
-    T bt[2][4], te[2][4];
+    float btv[2][4], tev[2][4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const int k = Mx<T>::row(q, kk);
         const bool ok = li < M && k < M;
         const T v = a.B0[ok ? k * M + li : 0];
-        bt[0][kk] = ok ? v : T(0);
-        bt[1][kk] = ((k - li) & 1) ? -bt[0][kk] : bt[0][kk];
+        btv[0][kk] = ok ? v : T(0);
+        btv[1][kk] = ((k - li) & 1) ? -btv[0][kk] : btv[0][kk];
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -434,7 +526,7 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             const int m = 16 * rt + li, k = Mx<T>::row(q, kk);
             const bool ok = m < s && k < M;
             const T v = a.Tm[ok ? (sg * s + m) * M + k : 0];
-            te[rt][kk] = ok ? v : T(0);
+            tev[rt][kk] = ok ? v : T(0);
         }
     // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
     // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf
@@ -450,6 +542,8 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
                 const T pv = a.Pt[nz ? mp - m : 0];
                 pm[rt][c][kk] = nz ? pv : T(0);
             }
+    const Aop<FM> bt0 = aop<FM>(btv[0]), bt1 = aop<FM>(btv[1]);
+    const Aop<FM> te[2] = {aop<FM>(tev[0]), aop<FM>(tev[1])};
     // the first two ancestor levels' far-field operands
     FarIn<T> n1 = far_issue(a, 0, Rn >> groot, sg, lane);
     FarIn<T> n2 = groot >= 1 ? far_issue(a, 1, Rn >> (groot - 1), sg, lane) : n1;
@@ -468,8 +562,8 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
         const FarIn<T> cu = n1;
         n1 = n2;
         if (g + 2 <= groot) n2 = far_issue(a, g + 2, Rn >> (groot - g - 2), sg, lane);
-        v4_t<T> cv = far_do(cu);
-        if (g > 0) cv = tile_mac<T>(cv, bt[(Rn >> (groot - g)) & 1], cp);
+        v4_t<T> cv = far_do<FM>(cu);
+        if (g > 0) cv = mac_tile<FM>(cv, pick<FM>(bt0, bt1, (Rn >> (groot - g)) & 1), cp);
         cp = cv;
     }
     node_stage8<T>(in_sl + 2 * SL, SL, xn1, u0 + 1, s, lane, sg, dir, true);
@@ -492,7 +586,7 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
                 own_node(j + 1, d1, v1);
                 nx = far_issue(a, groot + d1, v1, sg, lane);
             }
-            Fl[wv][j][lane] = far_do(cu);
+            Fl[wv][j][lane] = far_do<FM>(cu);
         }
     }
     // LDS writes (far tiles, Q window, staged input of both parity waves) complete
@@ -532,18 +626,18 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
             const int dmin = i == 0 ? 1 : KD - __builtin_ctz(i);
             if (d >= dmin) {
                 const int idx = i >> (KD - d);
-                stk[d] = tile_mac<T>(Fl[wv][(1 << d) - 2 + idx][lane], bt[idx & 1], stk[d - 1]);
+                stk[d] = mac_tile<FM>(Fl[wv][(1 << d) - 2 + idx][lane], pick<FM>(bt0, bt1, idx & 1), stk[d - 1]);
             }
         }
-        v4_t<T> cu = far_do(fcu);
-        if (KD > 0) cu = tile_mac<T>(cu, bt[i & 1], stk[KD > 0 ? KD - 1 : 0]);
+        v4_t<T> cu = far_do<FM>(fcu);
+        if (KD > 0) cu = mac_tile<FM>(cu, pick<FM>(bt0, bt1, i & 1), stk[KD > 0 ? KD - 1 : 0]);
         else cu = stk[0];
         v4_t<T> acc[2] = {v4_zero<T>(), v4_zero<T>()};
         // far part (Eq. (step5)): rows m = 16 rt + l mod 16 of T(sigma).  The last two row
         // nodes (u >= P - 2) have no far-field block on any level, so their c is zero.
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
-            if (rt < nrt) acc[rt] = tile_mac<T>(acc[rt], te[rt], cu);
+            if (rt < nrt) acc[rt] = mac_tile<FM>(acc[rt], te[rt], cu);
         // near field (step (6)): row m, column m' = 16 c + 4 q + kk:
         //   rs_i P_{m'-m} Q_{2 s u + sigma + m + m'} (m <= m' < 2s) times g_{2 s u + 2 m' + sigma}
         // Q enters through m + m' = 16 (c + rt) + 4 q + kk + l mod 16: 20 values per leaf
@@ -562,9 +656,10 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (c < nc && c >= rt) {
+                        float av[4];
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk)
-                            acc[rt] = Mx<T>::mma(pm[rt][c][kk] * (qv[c + rt][kk] * rs), y[c][kk], acc[rt]);
+                        for (int kk = 0; kk < 4; ++kk) av[kk] = pm[rt][c][kk] * (qv[c + rt][kk] * rs);
+                        acc[rt] = mac<FM>(acc[rt], aop<FM>(av), y[c]);
                     }
                 }
             }
@@ -608,8 +703,8 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 // ------------------------------------------------------------------------------------
 // Plan-time helpers: Ahat (FP64 plan tables) -> A-operand order of the form's type;
 // Q_S for S < len.
-template <typename T, int M>
-__global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, T *dst, int64_t blocks)
+template <int M, int FM>
+__global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, void *dst, int64_t blocks)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (blk, r, lane, kk)
     if (e >= blocks * 3 * 256) return;
@@ -622,7 +717,7 @@ __global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, T
         b -= (int64_t(1) << (g + 1)) - 1;
         ++g;
     }
-    const int k = lane & 15, l = Mx<T>::row(lane >> 4, kk);
+    const int k = lane & 15, l = Mx<float>::row(lane >> 4, kk);
     double v = 0.0;
     if (k < M && l < M) {
         if (g <= G.groot) {
@@ -639,7 +734,16 @@ __global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, T
             v = bot[((grp * NCH + el / 2) * 64 + ln) * 2 + (el & 1)];
         }
     }
-    dst[e] = (T)v;
+    if (FM == 0) {
+        ((float *)dst)[e] = (float)v;
+    } else {
+        // 16 bytes per lane entry: four hi then four lo BF16 values
+        const __bf16 hi = (__bf16)(float)v;
+        const __bf16 lo = (__bf16)(float)(v - (double)(float)hi);
+        unsigned short *d16 = (unsigned short *)dst + (e >> 2) * 8 + kk;
+        d16[0] = __builtin_bit_cast(unsigned short, hi);
+        d16[4] = __builtin_bit_cast(unsigned short, lo);
+    }
 }
 
 template <typename T>
@@ -649,13 +753,16 @@ __global__ void kb_q_table(T *Qt, int64_t len, int dir)
     if (S < len) Qt[S] = (T)near_Q(dir, S);
 }
 
-template <typename T, int M>
+template <int M>
 static hipError_t pack(const l2c_plan_s &p, void *dst, hipStream_t st)
 {
     const int64_t blocks = level_block_offset(p.L);
     const int64_t total = blocks * 3 * 256;
-    hipLaunchKernelGGL((kb_pack_ahat<T, M>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, p.d_top,
-                       p.d_bot, p.geo, (T *)dst, blocks);
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (p.precision == L2C_BF16X2)
+        hipLaunchKernelGGL((kb_pack_ahat<M, 1>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks);
+    else
+        hipLaunchKernelGGL((kb_pack_ahat<M, 0>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks);
     return hipGetLastError();
 }
 
@@ -663,8 +770,8 @@ hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst
 {
     hipError_t e;
     switch (p.M) {
-    case 12: e = pack<float, 12>(p, ahat_dst, st); break;
-    case 16: e = pack<float, 16>(p, ahat_dst, st); break;
+    case 12: e = pack<12>(p, ahat_dst, st); break;
+    case 16: e = pack<16>(p, ahat_dst, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -674,7 +781,7 @@ hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst
 }
 
 // ------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int FM>
 static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
                               const ItemArrays *ia)
 {
@@ -709,7 +816,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
             const unsigned gx = (unsigned)(((Pn >> ku) + 1) / 2);
             switch (ku) {
 #define L2C_UP(KK) \
-    case KK: hipLaunchKernelGGL((kb_up<T, KK>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+    case KK: hipLaunchKernelGGL((kb_up<T, KK, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
                 L2C_UP(0) L2C_UP(1) L2C_UP(2) L2C_UP(3)
 #undef L2C_UP
             default: return hipErrorInvalidValue;
@@ -722,7 +829,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
             const unsigned gx = (unsigned)((((int64_t)1 << (gout + 2)) + 1) / 2);
             switch (kt) {
 #define L2C_TOP(KK) \
-    case KK: hipLaunchKernelGGL((kb_top<T, KK>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+    case KK: hipLaunchKernelGGL((kb_top<T, KK, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
                 L2C_TOP(1) L2C_TOP(2) L2C_TOP(3)
 #undef L2C_TOP
             default: return hipErrorInvalidValue;
@@ -737,7 +844,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
             if (timed) (void)hipEventRecord(p.ev_before, st);
             switch (kd * 8 + nc) {
 #define L2C_MAIN(KK, NN) \
-    case KK * 8 + NN: hipLaunchKernelGGL((kb_main<T, KK, NN>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+    case KK * 8 + NN: hipLaunchKernelGGL((kb_main<T, KK, NN, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
 #define L2C_MAIN4(KK) L2C_MAIN(KK, 1) L2C_MAIN(KK, 2) L2C_MAIN(KK, 3) L2C_MAIN(KK, 4)
                 L2C_MAIN4(0) L2C_MAIN4(1) L2C_MAIN4(2) L2C_MAIN4(3)
 #undef L2C_MAIN4
@@ -756,7 +863,8 @@ hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, in
                           const ItemArrays *ia)
 {
     if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
-    return run_batched<float>(p, in, out, batch, st, ia);
+    if (p.precision == L2C_BF16X2) return run_batched<float, 1>(p, in, out, batch, st, ia);
+    return run_batched<float, 0>(p, in, out, batch, st, ia);
 }
 
 }  // namespace l2c

@@ -74,7 +74,7 @@ def test_plan_ex_precision_and_batch_errors(lib):
     L = lib.load()
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 1, 1, None) == -4   # FP32 form: rank <= 16
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 128, 16, 1, 1, None) == -4  # FP32 form: leaf <= 64
-    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 16, 2, 1, None) == -4   # BF16X2 not in this build
+    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 2, 1, None) == -4   # BF16X2 form: rank <= 16
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 9, 1, None) == -1
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 0, 0, None) == -1   # max_batch < 1
     assert L.leg2cheb_plan(None, 100, 0, 64, 18) == -1

@@ -114,3 +114,56 @@ def test_config3_fp32_batch_256x65536(l2c):
         worst = max(worst, np.max(np.abs(z32[b][rows] - ref)) / np.max(np.abs(ref)))
     print("cfg3 FP32: E_inf vs FP64 path %.2e, sampled vs oracle %.2e" % (e64, worst))
     assert e64 <= TOL32 and worst <= TOL32
+
+
+# ----------------------------------------------------------------- BF16 hi+lo form
+# Each product is ah bh + ah bl + al bh with hi/lo BF16 splits: the dropped al bl and the
+# rounding of the lo parts leave about 2^-17 relative error per product (FP32 accumulation
+# adds 2^-24).  With the same (2s + 2 L M)-term error model as above, random signs give
+# about sqrt(352) 2^-17 ~ 1.4e-4; the bound is 5e-4.
+TOLBF = 5e-4
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("n", [129, 1024, 20000])
+def test_bf16x2_parity_sizes(l2c, n, direction):
+    import torch
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 50 + n % 97, batch=21)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 16, precision=l2c.L2C_BF16X2, max_batch=21) as p:
+        info = p.info
+        Z = p.execute(x).cpu().numpy()
+    assert info["precision"] == l2c.L2C_BF16X2
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(21))
+    print("BF16X2 n=%d dir=%d E_inf=%.2e" % (n, direction, worst))
+    assert worst <= TOLBF
+
+
+def test_config3_bf16x2_batch_256x65536(l2c):
+    """256 x N = 65536: the BF16 hi+lo form against the FP64 GPU path on all 256."""
+    import torch
+    n, B = 65536, 256
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 3, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, 0, 64, 16, precision=l2c.L2C_BF16X2, max_batch=B) as pb, \
+            l2c.Plan(n, 0, 64, 18, max_batch=B) as p64:
+        zb = pb.execute(x)
+        z64 = p64.execute(x)
+        torch.cuda.synchronize()
+    zb, z64 = zb.cpu().numpy(), z64.cpu().numpy()
+    e64 = max(oracle.einf(zb[b], z64[b]) for b in range(B))
+    print("cfg3 BF16X2: E_inf vs FP64 path %.2e" % e64)
+    assert e64 <= TOLBF
+
+
+def test_bf16x2_ragged_batch(l2c):
+    import torch
+    sizes = [70, 300, 1024, 3000, 3001, 20000] * 2
+    dirs = [0] * 6 + [1] * 6
+    xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 300 + i)).cuda() for i, n in enumerate(sizes)]
+    with l2c.BatchPlan(sizes, dirs, rank=16, precision=l2c.L2C_BF16X2) as bp:
+        zs = bp.execute(xs)
+        torch.cuda.synchronize()
+    for i, (n, d) in enumerate(zip(sizes, dirs)):
+        err = oracle.einf(zs[i].cpu().numpy(), oracle.transform(xs[i].cpu().numpy(), d))
+        assert err <= TOLBF, (n, d, err)

@@ -318,7 +318,7 @@ def test_ragged_batch_errors(l2c):
         l2c.leg2cheb_batch_plan([100], [2])
     assert ei.value.code == l2c.L2C_EINVAL
     with pytest.raises(l2c.L2CError) as ei:
-        l2c.leg2cheb_batch_plan([100], [0], precision=l2c.L2C_BF16X2)
+        l2c.leg2cheb_batch_plan([100], [0], rank=18, precision=l2c.L2C_BF16X2)
     assert ei.value.code == l2c.L2C_EUNSUPPORTED
     buf = torch.zeros(1000, dtype=torch.float64, device="cuda")
     p0 = buf.data_ptr()
