@@ -186,6 +186,38 @@ def batched_form(l2c, inputs, torch, K, W, flush, flush_sink, with_fp64=True):
     return rec
 
 
+def lines_form(l2c, inputs, torch, K, W, flush, flush_sink):
+    """65536 lines of N = 1024 (a 256 x 256 x 1024 tensor along its last axis), f = z/(k+1):
+    leg2cheb, cold, in the FP64 path and the FP32 form; round-trip error through cheb2leg."""
+    stream = torch.cuda.current_stream()
+    n, lines = 1024, 256 * 256
+    x = torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 5, batch=lines)).cuda()
+    z, g = torch.empty_like(x), torch.empty_like(x)
+    rec = {"workload": "65536 lines of N=1024 (256 x 256 x 1024 FP64 tensor, last axis), f_k = z_k/(k+1); cold HBM"}
+    for tag, prec, rank in (("fp64", l2c.L2C_FP64, 18), ("fp32", l2c.L2C_FP32, 16)):
+        pf = l2c.Plan(n, l2c.LEG2CHEB, 64, rank, precision=prec, max_batch=lines)
+        pb = l2c.Plan(n, l2c.CHEB2LEG, 64, rank, precision=prec, max_batch=lines)
+        for _ in range(W):
+            pf.execute(x, z)
+        torch.cuda.synchronize()
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for i in range(K):
+            torch.sum(flush, dim=0, out=flush_sink)
+            st[i].record(stream)
+            pf.execute(x, z)
+            en[i].record(stream)
+        pb.execute(z, g)
+        torch.cuda.synchronize()
+        ms = float(np.mean([st[i].elapsed_time(en[i]) for i in range(K)]))
+        rt = ((g - x).abs().amax(dim=1) / x.abs().amax(dim=1)).max().item()
+        rec[tag] = {"ms_per_execute": ms, "Gcoeff_s": n * lines / (ms * 1e-3) / 1e9, "round_trip_einf": rt,
+                    "path": pf.info["path"]}
+        pf.close()
+        pb.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +354,7 @@ def main():
         "plan": {"table_bytes": info["table_bytes"], "ahat_bytes_padded": info["ahat_bytes"]},
     }
     rec["batched_fp32_form"] = batched_form(l2c, inputs, torch, min(K, 20), min(W, 5), flush, flush_sink)
+    rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(f, z, 0)
         rec["cpu_baseline"] = base

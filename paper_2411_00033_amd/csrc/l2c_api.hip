@@ -9,6 +9,7 @@
 
 #include "../../include/leg2cheb.h"
 #include "l2c_internal.h"
+#include "l2c_batched.h"
 #include "l2c_math.h"
 
 namespace {
@@ -148,6 +149,14 @@ struct l2c_batch_s {
     double **d_out = nullptr;               // [count] output pointers, in position order
     void *h_stage = nullptr;                // pinned [2][count] pointers for the copies
     hipEvent_t staged = nullptr;            // the last pointer copy
+    // groups run concurrently on side streams (default priority), forked from and joined
+    // back into the caller's stream; group g runs on side stream lane[g] (balanced by work)
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+    std::vector<int> lane;
+    // batched forms: one launch per kernel shape for all groups with L >= 1
+    l2c::BatGrouped *grouped = nullptr;
 };
 
 namespace {
@@ -160,6 +169,12 @@ void free_batch(l2c_batch_s *b)
     (void)hipFree(b->d_out);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    l2c::batched_grouped_free(b->grouped);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (int k = 0; k < l2c_batch_s::kSide; ++k) {
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+    }
     delete b;
 }
 
@@ -315,9 +330,14 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         int64_t nmax = 0;
         for (int64_t k = b->gstart[g]; k < b->gstart[g + 1]; ++k) nmax = std::max(nmax, nord[k]);
         l2c_plan_t pl = nullptr;
-        rc = leg2cheb_plan_ex(&pl, nmax, keys[g].dir, leaf_size, rank, precision, b->gstart[g + 1] - b->gstart[g],
-                              stream);
-        if (rc == L2C_OK) b->plans.push_back(pl);
+        const int64_t items = b->gstart[g + 1] - b->gstart[g];
+        rc = leg2cheb_plan_ex(&pl, nmax, keys[g].dir, leaf_size, rank, precision, items, stream);
+        if (rc == L2C_OK) {
+            b->plans.push_back(pl);
+            // groups run side by side: FP64 groups use the three-launch path
+            pl->fused_on = false;
+            if (!batched_form(precision)) rc = ensure_workspace(pl, items);
+        }
     }
     const size_t cb = (size_t)count * sizeof(void *);
     if (rc == L2C_OK &&
@@ -327,6 +347,40 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         rc = L2C_ENOMEM;
     if (rc == L2C_OK && hipMemcpy(b->d_n, nord.data(), (size_t)count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
         rc = L2C_EHIP;
+    if (rc == L2C_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) rc = L2C_EHIP;
+    for (int k = 0; k < l2c_batch_s::kSide && rc == L2C_OK; ++k)
+        if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess)
+            rc = L2C_EHIP;
+    if (rc == L2C_OK && batched_form(precision)) {
+        std::vector<l2c::ItemArrays> ia(G);
+        std::vector<int64_t> items(G);
+        for (int g = 0; g < G; ++g) {
+            const int64_t k0 = b->gstart[g];
+            ia[g] = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
+            items[g] = b->gstart[g + 1] - k0;
+        }
+        const hipError_t e = l2c::batched_grouped_make(b->plans.data(), ia.data(), items.data(), G, &b->grouped);
+        if (e == hipErrorOutOfMemory) rc = L2C_ENOMEM;
+        else if (e != hipSuccess) b->grouped = nullptr;   // per-group launches instead
+        (void)hipGetLastError();
+    }
+    if (rc == L2C_OK) {
+        // longest work first onto the least-loaded side stream (work ~ items x padded length)
+        std::vector<int> gi(G);
+        std::vector<double> work(G), load(l2c_batch_s::kSide, 0.0);
+        for (int g = 0; g < G; ++g) {
+            gi[g] = g;
+            work[g] = (double)(b->gstart[g + 1] - b->gstart[g]) * (double)std::max<int64_t>(b->plans[g]->n_pad, 1);
+        }
+        std::sort(gi.begin(), gi.end(), [&](int x, int y) { return work[x] > work[y]; });
+        b->lane.assign(G, 0);
+        for (int g : gi) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->lane[g] = k;
+            load[k] += work[g];
+        }
+    }
     if (rc != L2C_OK) {
         (void)hipGetLastError();
         free_batch(b);
@@ -368,26 +422,42 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
     const size_t cb = (size_t)b->count * sizeof(void *);
     if (hipMemcpyAsync(b->d_in, si, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(b->d_out, so, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipEventRecord(b->staged, st) != hipSuccess)
+        hipEventRecord(b->staged, st) != hipSuccess || hipEventRecord(b->fork, st) != hipSuccess)
         return L2C_EHIP;
+    if (b->grouped) {
+        // batched forms: direct groups (L = 0), then every other group in grouped launches
+        for (size_t g = 0; g < b->plans.size(); ++g) {
+            l2c_plan_s *p = b->plans[g];
+            if (p->L != 0) continue;
+            const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
+            const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
+            if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+        }
+        return l2c::batched_grouped_launch(b->grouped, st) == hipSuccess ? L2C_OK : L2C_EHIP;
+    }
+    for (int k = 0; k < l2c_batch_s::kSide; ++k)
+        if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) return L2C_EHIP;
+    // Groups are independent and run concurrently on the side streams.  FP64 groups take the
+    // three-launch path: single-launch kernels need all their workgroups resident and are
+    // never run side by side.
     for (size_t g = 0; g < b->plans.size(); ++g) {
         l2c_plan_s *p = b->plans[g];
+        hipStream_t gs = b->side[b->lane[g]];
         const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
         const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
         if (use_batched(p)) {
             const int rc = ensure_bworkspace(p, items);
             if (rc != L2C_OK) return rc;
-            if (l2c::launch_batched(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
-        } else if (p->L > 0 && use_fused(p)) {
-            const int rc = ensure_workspace(p, std::min(items, p->fused_items));
-            if (rc != L2C_OK) return rc;
-            if (l2c::launch_fused(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+            if (l2c::launch_batched(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
         } else {
             const int rc = ensure_workspace(p, items);
             if (rc != L2C_OK) return rc;
-            if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+            if (l2c::launch_execute(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
         }
     }
+    for (int k = 0; k < l2c_batch_s::kSide; ++k)
+        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess || hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess)
+            return L2C_EHIP;
     return L2C_OK;
 }
 

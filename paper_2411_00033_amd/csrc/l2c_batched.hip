@@ -73,6 +73,7 @@ struct BatArgs {
     const T *Pt;                    // [2s]: P_d
     const T *Qt;                    // [n_pad + 2s]: Q_S
     T *w;                           // [tiles][NT][2][64][4]
+    int64_t tile, bx;               // this workgroup's tile of 16 transforms and its block in the tile row
 };
 
 template <typename T>
@@ -88,10 +89,10 @@ __device__ __forceinline__ v4_t<T> v4_zero()
 template <typename T>
 __device__ __forceinline__ T *tile_ptr(const BatArgs<T> &a, int64_t node, int sig, int lane)
 {
-    return a.w + (((int64_t)blockIdx.y * a.NT + node) * 2 + sig) * 256 + lane * 4;
+    return a.w + ((a.tile * a.NT + node) * 2 + sig) * 256 + lane * 4;
 }
 
-// The lane's transform: item blockIdx.y * 16 + lane mod 16 (length 0 past the batch).
+// The lane's transform: item 16 tile + lane mod 16 (length 0 past the batch).
 struct LaneItem {
     const double *in;
     double *out;
@@ -102,7 +103,7 @@ template <typename T>
 __device__ __forceinline__ LaneItem lane_item(const BatArgs<T> &a, int lane)
 {
     LaneItem it{nullptr, nullptr, 0};
-    const int64_t item = (int64_t)blockIdx.y * 16 + (lane & 15);
+    const int64_t item = a.tile * 16 + (lane & 15);
     if (item < a.batch) {
         it.n = a.item_n ? a.item_n[item] : a.n;
         it.in = a.item_in ? a.item_in[item] : a.in + item * a.n;
@@ -367,23 +368,23 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
     }
 }
 
-// Waves of a workgroup: wave w takes subtree 2 blockIdx.x + w / 2 and parity w mod 2.
+// Waves of a workgroup: wave w takes subtree 2 bx + w / 2 and parity w mod 2.
 template <typename T, int KU, int FM>
-__global__ __launch_bounds__(256) void kb_up(BatArgs<T> a)
+__device__ __forceinline__ void up_body(const BatArgs<T> &a)
 {
     __shared__ T slots[4][16 * kBatRow];
     const int lane = threadIdx.x & 63, wv = wave_id();
-    const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
+    const int64_t sub = a.bx * 2 + (wv >> 1);
     const int64_t P = int64_t(1) << (a.L + 1);   // finest nodes
     if ((sub << KU) >= P) return;
     up_walk<T, KU, true, FM>(a, sub << KU, a.L - 1, wv & 1, lane, slots[wv]);
 }
 
 template <typename T, int KT, int FM>
-__global__ __launch_bounds__(256) void kb_top(BatArgs<T> a)
+__device__ __forceinline__ void top_body(const BatArgs<T> &a)
 {
     const int lane = threadIdx.x & 63, wv = wave_id();
-    const int64_t sub = (int64_t)blockIdx.x * 2 + (wv >> 1);
+    const int64_t sub = a.bx * 2 + (wv >> 1);
     if ((sub << KT) >= (int64_t(1) << (a.gin + 2))) return;
     up_walk<T, KT, false, FM>(a, sub << KT, a.gin, wv & 1, lane, nullptr);
 }
@@ -471,7 +472,7 @@ __device__ __forceinline__ void node_stage8(T *slot, int SL, const double (&x)[8
 // and the output rows of the current node [transform][2s].  The grid holds an even number
 // of subtrees, so every wave of a workgroup has a subtree and reaches every barrier.
 template <typename T, int KD, int NC, int FM>
-__global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
+__device__ __forceinline__ void main_body(const BatArgs<T> &a)
 {
     constexpr int nc = NC, nrt = NC > 2 ? 2 : 1;
     constexpr int INNER = (1 << KD) - 2;             // own nodes of depths 1..KD-1
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
     const int li = lane & 15, q = lane >> 4, sg = wv & 1;
     const int s = a.s, M = a.M, dir = a.dir;
     const int groot = a.L - 1 - KD;
-    const int64_t Rn = (int64_t)blockIdx.x * 2 + (wv >> 1);   // < 2^(groot+2): the grid is exact
+    const int64_t Rn = a.bx * 2 + (wv >> 1);   // < 2^(groot+2): the grid is exact
     const int64_t u0 = Rn << KD;                      // first finest row node
     const LaneItem it = lane_item(a, lane);
     T *Qw = Ql[wv];
@@ -701,6 +702,64 @@ __global__ __launch_bounds__(256) void kb_main(BatArgs<T> a)
 }
 
 // ------------------------------------------------------------------------------------
+// Launches.  Plain: one group, blockIdx.y = tile, blockIdx.x = block in the tile row.
+// Grouped: one launch for many groups of a ragged batch that share the kernel's template
+// shape; blocks [blk0[g], blk0[g+1]) belong to entry g, gx blocks per tile.
+template <typename T>
+struct BatEntry {
+    BatArgs<T> a;
+    int64_t gx;
+};
+
+template <typename T>
+__device__ __forceinline__ BatArgs<T> plain_args(BatArgs<T> a)
+{
+    a.tile = blockIdx.y;
+    a.bx = blockIdx.x;
+    return a;
+}
+
+template <typename T>
+__device__ __forceinline__ BatArgs<T> entry_args(const BatEntry<T> *E, const int64_t *blk0, int n)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n - 1;                      // last entry g with blk0[g] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    BatArgs<T> a = E[lo].a;
+    const int64_t loc = b - blk0[lo];
+    a.tile = loc / E[lo].gx;
+    a.bx = loc - a.tile * E[lo].gx;
+    return a;
+}
+
+template <typename T, int KU, int FM>
+__global__ __launch_bounds__(256) void kb_up(BatArgs<T> a) { up_body<T, KU, FM>(plain_args(a)); }
+template <typename T, int KT, int FM>
+__global__ __launch_bounds__(256) void kb_top(BatArgs<T> a) { top_body<T, KT, FM>(plain_args(a)); }
+template <typename T, int KD, int NC, int FM>
+__global__ __launch_bounds__(256) void kb_main(BatArgs<T> a) { main_body<T, KD, NC, FM>(plain_args(a)); }
+
+template <typename T, int KU, int FM>
+__global__ __launch_bounds__(256) void kbg_up(const BatEntry<T> *E, const int64_t *blk0, int n)
+{
+    up_body<T, KU, FM>(entry_args(E, blk0, n));
+}
+template <typename T, int KT, int FM>
+__global__ __launch_bounds__(256) void kbg_top(const BatEntry<T> *E, const int64_t *blk0, int n)
+{
+    top_body<T, KT, FM>(entry_args(E, blk0, n));
+}
+template <typename T, int KD, int NC, int FM>
+__global__ __launch_bounds__(256) void kbg_main(const BatEntry<T> *E, const int64_t *blk0, int n)
+{
+    main_body<T, KD, NC, FM>(entry_args(E, blk0, n));
+}
+
+// ------------------------------------------------------------------------------------
 // Plan-time helpers: Ahat (FP64 plan tables) -> A-operand order of the form's type;
 // Q_S for S < len.
 template <int M, int FM>
@@ -865,6 +924,164 @@ hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, in
     if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
     if (p.precision == L2C_BF16X2) return run_batched<float, 1>(p, in, out, batch, st, ia);
     return run_batched<float, 0>(p, in, out, batch, st, ia);
+}
+
+}  // namespace l2c
+
+// ------------------------------------------------------------------------------------
+// Grouped launches (ragged batches).
+#include "l2c_batched.h"
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace l2c {
+
+struct BatGrouped {
+    struct Launch {
+        int kind;       // 0 up, 1 top, 2 main
+        int k1, k2;     // KU | KT | (KD, NC)
+        void *E;        // BatEntry<float>[n] (device)
+        int64_t *blk0;  // [n + 1] (device)
+        int n;
+        int64_t blocks;
+    };
+    int fm = 0;
+    std::vector<Launch> launches;
+};
+
+void batched_grouped_free(BatGrouped *g)
+{
+    if (!g) return;
+    for (auto &l : g->launches) {
+        (void)hipFree(l.E);
+        (void)hipFree(l.blk0);
+    }
+    delete g;
+}
+
+hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays *ia, const int64_t *items, int ngroups,
+                                BatGrouped **out)
+{
+    typedef float T;
+    *out = nullptr;
+    // class key (kind, k1, k2, pass) -> entries
+    std::map<std::tuple<int, int, int, int>, std::vector<BatEntry<T>>> cls;
+    int fm = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        const l2c_plan_s &p = *plans[g];
+        if (p.L < 1) continue;
+        if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
+        fm = p.precision == L2C_BF16X2 ? 1 : 0;
+        const int64_t tiles = (items[g] + 15) / 16;
+        if (tiles > p.bw_tiles) return hipErrorInvalidValue;
+        const int L = p.L;
+        const int ku = L - 1 < kBatUpDepth ? L - 1 : kBatUpDepth;
+        const int kd = L - 1 < kBatMainDepth ? L - 1 : kBatMainDepth;
+        const int64_t Pn = int64_t(1) << (L + 1);
+        BatArgs<T> a{};
+        a.in = nullptr;
+        a.out = nullptr;
+        a.n = p.n;
+        a.item_n = ia[g].n;
+        a.item_in = ia[g].in;
+        a.item_out = ia[g].out;
+        a.batch = items[g];
+        a.dir = p.direction;
+        a.L = L;
+        a.s = p.s;
+        a.M = p.M;
+        a.gin = 0;
+        a.NT = p.geo.NT;
+        a.ahat = (const T *)p.d_bA;
+        a.Tm = (const T *)p.d_bT;
+        a.B0 = (const T *)p.d_bB;
+        a.Pt = (const T *)p.d_bP;
+        a.Qt = (const T *)p.d_bQ;
+        a.w = (T *)p.d_bw;
+        a.tile = a.bx = 0;
+        cls[std::make_tuple(0, ku, 0, 0)].push_back({a, ((Pn >> ku) + 1) / 2});
+        int pass = 0;
+        for (int gin = L - 1 - ku; gin > 0; ++pass) {
+            const int kt = gin < kBatTopDepth ? gin : kBatTopDepth;
+            const int gout = gin - kt;
+            BatArgs<T> at = a;
+            at.gin = gin;
+            cls[std::make_tuple(1, kt, 0, pass)].push_back({at, ((int64_t(1) << (gout + 2)) + 1) / 2});
+            gin = gout;
+        }
+        const int groot = L - 1 - kd;
+        cls[std::make_tuple(2, kd, (2 * p.s + 15) / 16, 0)].push_back({a, (int64_t(1) << (groot + 2)) / 2});
+    }
+    BatGrouped *G = new (std::nothrow) BatGrouped;
+    if (!G) return hipErrorOutOfMemory;
+    G->fm = fm;
+    // launch order: every kb_up, then the kb_top passes in pass order, then every kb_main
+    std::vector<std::tuple<int, int, int, int>> keys;
+    for (auto &kv : cls) keys.push_back(kv.first);
+    std::stable_sort(keys.begin(), keys.end(), [](const auto &x, const auto &y) {
+        const int ox = std::get<0>(x) == 1 ? 1 + std::get<3>(x) : (std::get<0>(x) == 0 ? 0 : 1000);
+        const int oy = std::get<0>(y) == 1 ? 1 + std::get<3>(y) : (std::get<0>(y) == 0 ? 0 : 1000);
+        return ox < oy;
+    });
+    for (const auto &k : keys) {
+        const auto &ents = cls[k];
+        std::vector<int64_t> blk0(ents.size() + 1, 0);
+        for (size_t e = 0; e < ents.size(); ++e) {
+            const int64_t tiles = (ents[e].a.batch + 15) / 16;
+            blk0[e + 1] = blk0[e] + ents[e].gx * tiles;
+        }
+        BatGrouped::Launch l{std::get<0>(k), std::get<1>(k), std::get<2>(k), nullptr, nullptr, (int)ents.size(),
+                             blk0.back()};
+        if (l.blocks > 0x7fffffff || hipMalloc(&l.E, ents.size() * sizeof(BatEntry<T>)) != hipSuccess ||
+            hipMalloc(&l.blk0, blk0.size() * sizeof(int64_t)) != hipSuccess ||
+            hipMemcpy(l.E, ents.data(), ents.size() * sizeof(BatEntry<T>), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(l.blk0, blk0.data(), blk0.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            G->launches.push_back(l);
+            batched_grouped_free(G);
+            return hipErrorOutOfMemory;
+        }
+        G->launches.push_back(l);
+    }
+    *out = G;
+    return hipSuccess;
+}
+
+template <int FM>
+static hipError_t grouped_launch_fm(const BatGrouped *G, hipStream_t st)
+{
+    typedef float T;
+    for (const auto &l : G->launches) {
+        if (l.blocks == 0) continue;
+        const BatEntry<T> *E = (const BatEntry<T> *)l.E;
+        const dim3 grid((unsigned)l.blocks), blk(256);
+        switch (l.kind * 64 + l.k1 * 8 + l.k2) {
+#define L2C_GUP(KK) \
+    case 0 * 64 + KK * 8: hipLaunchKernelGGL((kbg_up<T, KK, FM>), grid, blk, 0, st, E, l.blk0, l.n); break;
+            L2C_GUP(0) L2C_GUP(1) L2C_GUP(2) L2C_GUP(3)
+#undef L2C_GUP
+#define L2C_GTOP(KK) \
+    case 1 * 64 + KK * 8: hipLaunchKernelGGL((kbg_top<T, KK, FM>), grid, blk, 0, st, E, l.blk0, l.n); break;
+            L2C_GTOP(1) L2C_GTOP(2) L2C_GTOP(3)
+#undef L2C_GTOP
+#define L2C_GMAIN(KK, NN) \
+    case 2 * 64 + KK * 8 + NN: hipLaunchKernelGGL((kbg_main<T, KK, NN, FM>), grid, blk, 0, st, E, l.blk0, l.n); break;
+#define L2C_GMAIN4(KK) L2C_GMAIN(KK, 1) L2C_GMAIN(KK, 2) L2C_GMAIN(KK, 3) L2C_GMAIN(KK, 4)
+            L2C_GMAIN4(0) L2C_GMAIN4(1) L2C_GMAIN4(2) L2C_GMAIN4(3)
+#undef L2C_GMAIN4
+#undef L2C_GMAIN
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t batched_grouped_launch(const BatGrouped *G, hipStream_t st)
+{
+    return G->fm ? grouped_launch_fm<1>(G, st) : grouped_launch_fm<0>(G, st);
 }
 
 }  // namespace l2c

@@ -167,3 +167,30 @@ def test_bf16x2_ragged_batch(l2c):
     for i, (n, d) in enumerate(zip(sizes, dirs)):
         err = oracle.einf(zs[i].cpu().numpy(), oracle.transform(xs[i].cpu().numpy(), d))
         assert err <= TOLBF, (n, d, err)
+
+
+# ----------------------------------------------------------------- 3-D line batch
+def test_lines_3d_round_trip(l2c):
+    """A 256 x 256 x 1024 tensor, f_k = z/(k+1) along the last axis (65536 lines of
+    N = 1024): leg2cheb then cheb2leg along that axis, in the FP64 path and the FP32
+    form.  Round trip against the input on every line; each direction against the
+    oracle on 64 seeded lines."""
+    import torch
+    n, lines = 1024, 256 * 256
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 5, batch=lines)
+    x = torch.from_numpy(F).cuda()
+    rng = np.random.default_rng(inputs.SEED_BASE + 55)
+    pick = rng.choice(lines, 64, replace=False)
+    for prec, rank, tol, tol_rt in ((l2c.L2C_FP64, 18, (1e-13, 1e-12), 1e-12),
+                                    (l2c.L2C_FP32, 16, (TOL32, TOL32), 2 * TOL32)):
+        with l2c.Plan(n, 0, 64, rank, precision=prec, max_batch=lines) as pf, \
+                l2c.Plan(n, 1, 64, rank, precision=prec, max_batch=lines) as pb:
+            z = pf.execute(x)
+            g = pb.execute(z)
+            torch.cuda.synchronize()
+        rt = ((g - x).abs().amax(dim=1) / x.abs().amax(dim=1)).max().item()
+        zh = z[torch.from_numpy(pick).cuda()].cpu().numpy()
+        e_f = max(oracle.einf(zh[i], oracle.leg2cheb(F[b])) for i, b in enumerate(pick))
+        e_b = max(oracle.einf(g[int(b)].cpu().numpy(), oracle.cheb2leg(zh[i])) for i, b in enumerate(pick))
+        print("lines 3-D precision %d: leg2cheb %.2e cheb2leg %.2e round trip %.2e" % (prec, e_f, e_b, rt))
+        assert e_f <= tol[0] and e_b <= tol[1] and rt <= tol_rt
