@@ -197,6 +197,9 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
     return L2C_OK;
 }
 
+int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
+              void *stream, bool full_leaf);
+
 // Workspace of the batched form: tiles of 16 items, NT nodes x 2 parities x 256 values.
 int ensure_bworkspace(l2c_plan_s *p, int64_t items)
 {
@@ -292,46 +295,53 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         return L2C_EHIP;
     }
     b->count = count;
-    // group key (L, s, direction); L = 0 transforms: s = 0, one group per direction
+    // Groups: one per (L, direction); L = 0 transforms form one group per direction.  Every
+    // group is planned with the full half-leaf s = leaf/2 (the same L as Eq. (numlevels)
+    // gives, with more padding), so that few groups cover the batch and the batched forms
+    // fill their 16-transform tiles.
     struct Key {
         int L, s, dir;
-        int64_t first;
     };
-    std::vector<Key> keys;
-    std::vector<int> gof(count);
+    std::vector<int> Ls(count), Ss(count);
     for (int64_t i = 0; i < count; ++i) {
-        int L, sz;
         int64_t np;
-        plan_sizes(n[i], leaf_size, &L, &sz, &np);
-        int g = -1;
-        for (size_t k = 0; k < keys.size(); ++k)
-            if (keys[k].L == L && keys[k].s == sz && keys[k].dir == direction[i]) {
-                g = (int)k;
-                break;
+        plan_sizes(n[i], leaf_size, &Ls[i], &Ss[i], &np);
+    }
+    std::vector<Key> keys;
+    std::vector<int64_t> ord(count);
+    for (int64_t i = 0; i < count; ++i) Ss[i] = Ls[i] > 0 ? leaf_size / 2 : 0;   // full half-leaf
+    {
+        std::vector<int> gof(count);
+        for (int64_t i = 0; i < count; ++i) {
+            int g = -1;
+            for (size_t k = 0; k < keys.size(); ++k)
+                if (keys[k].L == Ls[i] && keys[k].s == Ss[i] && keys[k].dir == direction[i]) {
+                    g = (int)k;
+                    break;
+                }
+            if (g < 0) {
+                keys.push_back({Ls[i], Ss[i], direction[i]});
+                g = (int)keys.size() - 1;
             }
-        if (g < 0) {
-            keys.push_back({L, sz, direction[i], i});
-            g = (int)keys.size() - 1;
+            gof[i] = g;
         }
-        gof[i] = g;
+        b->gstart.assign(keys.size() + 1, 0);
+        for (int64_t i = 0; i < count; ++i) ++b->gstart[gof[i] + 1];
+        for (size_t g = 0; g < keys.size(); ++g) b->gstart[g + 1] += b->gstart[g];
+        std::vector<int64_t> fill(b->gstart.begin(), b->gstart.end() - 1);
+        for (int64_t i = 0; i < count; ++i) ord[fill[gof[i]]++] = i;
     }
     const int G = (int)keys.size();
-    b->gstart.assign(G + 1, 0);
-    for (int64_t i = 0; i < count; ++i) ++b->gstart[gof[i] + 1];
-    for (int g = 0; g < G; ++g) b->gstart[g + 1] += b->gstart[g];
-    b->order.resize(count);
-    std::vector<int64_t> fill(b->gstart.begin(), b->gstart.end() - 1), nord(count);
-    for (int64_t i = 0; i < count; ++i) {
-        b->order[fill[gof[i]]] = i;
-        nord[fill[gof[i]]++] = n[i];
-    }
+    b->order = ord;
+    std::vector<int64_t> nord(count);
+    for (int64_t k = 0; k < count; ++k) nord[k] = n[ord[k]];
     int rc = L2C_OK;
     for (int g = 0; g < G && rc == L2C_OK; ++g) {
         int64_t nmax = 0;
         for (int64_t k = b->gstart[g]; k < b->gstart[g + 1]; ++k) nmax = std::max(nmax, nord[k]);
         l2c_plan_t pl = nullptr;
         const int64_t items = b->gstart[g + 1] - b->gstart[g];
-        rc = leg2cheb_plan_ex(&pl, nmax, keys[g].dir, leaf_size, rank, precision, items, stream);
+        rc = plan_impl(&pl, nmax, keys[g].dir, leaf_size, rank, precision, items, stream, true);
         if (rc == L2C_OK) {
             b->plans.push_back(pl);
             // groups run side by side: FP64 groups use the three-launch path
@@ -483,8 +493,28 @@ int leg2cheb_batch_destroy(l2c_batch_t b)
 
 int leg2cheb_rank_supported(int rank) { return rank_supported(rank) ? 1 : 0; }
 
+}  // extern "C"
+
+namespace {
+// full_leaf: s = leaf_size / 2 instead of the smallest s of Eq. (numlevels) that covers n
+// (same L; more padding), so that transforms of one L share every table.
+int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
+              void *stream, bool full_leaf);
+}  // namespace
+
+extern "C" {
+
 int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
                      int64_t max_batch, void *stream)
+{
+    return plan_impl(plan, n, direction, leaf_size, rank, precision, max_batch, stream, false);
+}
+
+}  // extern "C"
+
+namespace {
+int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
+              void *stream, bool full_leaf)
 {
     if (!plan) return L2C_EINVAL;
     *plan = nullptr;
@@ -511,6 +541,10 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
         return L2C_EHIP;
     }
     plan_sizes(n, leaf_size, &p->L, &p->s, &p->n_pad);
+    if (full_leaf && p->L > 0) {
+        p->s = leaf_size / 2;
+        p->n_pad = (int64_t)p->s << (p->L + 2);
+    }
     if (p->L >= L2C_MAX_LEVELS - 1) {
         delete p;
         return L2C_EINVAL;
@@ -598,6 +632,9 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
     *plan = p;
     return L2C_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank)
 {

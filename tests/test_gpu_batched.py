@@ -194,3 +194,36 @@ def test_lines_3d_round_trip(l2c):
         e_b = max(oracle.einf(g[int(b)].cpu().numpy(), oracle.cheb2leg(zh[i])) for i, b in enumerate(pick))
         print("lines 3-D precision %d: leg2cheb %.2e cheb2leg %.2e round trip %.2e" % (prec, e_f, e_b, rt))
         assert e_f <= tol[0] and e_b <= tol[1] and rt <= tol_rt
+
+
+def test_ragged_2048_fp32_sampled(l2c):
+    """The 2048-transform ragged batch (n log-uniform in [128, 262144], directions 50/50,
+    f_j = z_j/(j+1)) in the FP32 form: sampled rows of every output against the oracle and
+    the x = +-1 sums of every full output."""
+    import torch
+    sizes, dirs = inputs.ragged_sizes(2048, inputs.SEED_BASE + 4)
+    rng = np.random.default_rng(inputs.SEED_BASE + 6)
+    total = int(sizes.sum())
+    flat = rng.standard_normal(total)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    for i, n in enumerate(sizes):
+        flat[offs[i]:offs[i + 1]] /= np.arange(1, n + 1, dtype=np.float64)
+    x = torch.from_numpy(flat).cuda()
+    y = torch.empty_like(x)
+    xs = [x[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+    ys = [y[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+    with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), rank=16, precision=l2c.L2C_FP32) as bp:
+        bp.execute(xs, ys)
+        torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    worst = 0.0
+    for i, (n, d) in enumerate(zip(sizes.tolist(), dirs.tolist())):
+        f, z = flat[offs[i]:offs[i + 1]], yh[offs[i]:offs[i + 1]]
+        rows = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 2)]))
+        ref = oracle.transform(f, d, rows)
+        worst = max(worst, np.max(np.abs(z[rows] - ref)) / np.max(np.abs(ref)))
+        sgn = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+        for w in (np.ones(n), sgn):
+            assert abs(float(np.dot(w, z)) - float(np.dot(w, f))) <= 1e-4 * np.sum(np.abs(f)), (i, n, d)
+    print("ragged 2048 FP32 sampled E_inf %.2e" % worst)
+    assert worst <= TOL32

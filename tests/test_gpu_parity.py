@@ -284,9 +284,10 @@ def test_config2_million_sampled(l2c, direction, single):
 
 # ----------------------------------------------------------------- ragged batches
 def test_ragged_batch_small(l2c):
-    """Mixed lengths (direct-only, one and several levels, equal (L, s) with different n) and
-    mixed directions in one batch plan: every output against the oracle and bit-identical to
-    the same transform planned alone on the three-launch path (which ragged groups use)."""
+    """Mixed lengths (direct-only, one and several levels, equal L with different n) and
+    mixed directions in one batch plan: every output against the oracle, repeatable bit for
+    bit, and within the tolerance of the same transform planned alone (a ragged group uses
+    the full half-leaf s = 32, a single plan the smallest s that covers n)."""
     import torch
     sizes = [1, 2, 5, 63, 64, 65, 127, 128, 129, 300, 1000, 1024, 2990, 3000, 3007, 4096, 9000, 9001,
              16384, 20000, 511, 3001]
@@ -296,6 +297,8 @@ def test_ragged_batch_small(l2c):
     with l2c.BatchPlan(sizes, dirs) as bp:
         info = bp.info
         assert 1 <= info["groups"] < len(sizes) and info["table_bytes"] > 0
+        # groups are (levels, direction): n = 1..64 direct, then L = 1..7
+        assert info["groups"] == len({(l2c.Plan(n, 0).info["levels"], d) for n, d in zip(sizes, dirs)})
         zs = bp.execute(xs)
         zs2 = bp.execute(xs)
         torch.cuda.synchronize()
@@ -305,8 +308,8 @@ def test_ragged_batch_small(l2c):
         f = xs[i].cpu().numpy()
         err = oracle.einf(z, oracle.transform(f, d))
         assert err <= TOL[(d, 18)], (n, d, err)
-        alone, _ = run(l2c, f, d, single=False)
-        assert np.array_equal(z, alone), (n, d)
+        alone, _ = run(l2c, f, d)
+        assert oracle.einf(z, alone) <= 2 * TOL[(d, 18)], (n, d)
 
 
 def test_ragged_batch_errors(l2c):
