@@ -59,7 +59,9 @@ enum l2c_path {
     L2C_PATH_DIRECT = 0, /* L = 0: the whole product directly (Alg. 1) */
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
     L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
-    L2C_PATH_BATCHED = 3 /* L2C_FP32 / L2C_BF16X2 plans: 16 transforms per matrix-core tile */
+    L2C_PATH_BATCHED = 3, /* L2C_FP32 / L2C_BF16X2 plans: 16 transforms per matrix-core tile */
+    L2C_PATH_DENSE = 4    /* FP64 plans with n <= 4096 and max_batch >= 64: Alg. 1 as dense
+                             per-parity products on the FP64 matrix cores */
 };
 
 /* Plan options (leg2cheb_plan_set_option). */

@@ -127,6 +127,7 @@ void free_plan(l2c_plan_s *p)
     (void)hipFree(p->d_bP);
     (void)hipFree(p->d_bQ);
     (void)hipFree(p->d_bw);
+    (void)hipFree(p->d_dense);
     delete p;
 }
 
@@ -459,6 +460,8 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
             const int rc = ensure_bworkspace(p, items);
             if (rc != L2C_OK) return rc;
             if (l2c::launch_batched(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
+        } else if (p->d_dense) {
+            if (l2c::launch_dense(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
         } else {
             const int rc = ensure_workspace(p, items);
             if (rc != L2C_OK) return rc;
@@ -603,6 +606,18 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             *plan = p;
             return L2C_OK;
         }
+        // batches of short transforms: the direct product on the matrix cores
+        if (n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
+            const int64_t HP = l2c::dense_hp(n);
+            ok = hipMalloc(&p->d_dense, (size_t)2 * HP * HP * sizeof(double)) == hipSuccess &&
+                 l2c::dense_build(*p, p->d_dense, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+            if (!ok) {
+                (void)hipGetLastError();
+                free_plan(p);
+                return L2C_ENOMEM;
+            }
+            p->table_bytes += 2 * HP * HP * (int64_t)sizeof(double);
+        }
         // single-launch path: items per launch with every workgroup resident
         int64_t items = 0;
         if (l2c::fused_max_items(*p, &items) != hipSuccess) {
@@ -654,6 +669,10 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
     if (dev != plan->device) return L2C_EINVAL;
+    if (plan->d_dense) {
+        if (l2c::launch_dense(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
+        return L2C_OK;
+    }
     if (use_batched(plan)) {
         const int rc = ensure_bworkspace(plan, batch);
         if (rc != L2C_OK) return rc;
@@ -698,6 +717,7 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
                             plan->bw_tiles * plan->geo.NT * 2 * 256 * (int64_t)elem_bytes(plan);
     info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
     info->path = plan->L == 0        ? L2C_PATH_DIRECT
+                 : plan->d_dense     ? L2C_PATH_DENSE
                  : use_batched(plan) ? L2C_PATH_BATCHED
                  : use_fused(plan)   ? L2C_PATH_SINGLE
                                      : L2C_PATH_THREE;

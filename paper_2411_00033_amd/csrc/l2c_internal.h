@@ -135,6 +135,9 @@ struct l2c_plan_s {
     void *d_bQ = nullptr;       // [n_pad + 2s]
     void *d_bw = nullptr;
     int64_t bw_tiles = 0;
+    // FP64 batches of short transforms (l2c_dense.hip): per parity the dense coefficient
+    // matrix of Alg. 1, [2][HP][HP]
+    double *d_dense = nullptr;
 };
 
 namespace l2c {
@@ -150,6 +153,12 @@ hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t ba
 hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst, int64_t q_len, hipStream_t stream);
 hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                           const ItemArrays *ia = nullptr);
+// l2c_dense.hip: FP64 plans with L >= 1, n <= kDenseMaxN and max_batch >= kDenseMinBatch
+constexpr int64_t kDenseMaxN = 4096, kDenseMinBatch = 64;
+int64_t dense_hp(int64_t n);
+hipError_t dense_build(const l2c_plan_s &p, double *D, hipStream_t stream);
+hipError_t launch_dense(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
+                        const ItemArrays *ia = nullptr);
 // l2c_plan.hip
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);

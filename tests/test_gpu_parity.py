@@ -373,3 +373,26 @@ def test_ragged_batch_2048_sampled(l2c):
             assert abs(lhs - rhs) <= 1e-11 * np.sum(np.abs(f)), (i, n, d, lhs, rhs)
     print("sampled E_inf: leg2cheb %.2e  cheb2leg %.2e" % (worst[0], worst[1]))
     assert worst[0] <= TOL[(0, 18)] and worst[1] <= TOL[(1, 18)]
+
+
+# ----------------------------------------------------------------- dense path (short transforms)
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("n", [129, 300, 999, 1000, 1024, 4096])
+def test_dense_batches_of_short_transforms(l2c, n, direction):
+    """FP64 plans for n <= 4096 made for batches of 64 or more apply Alg. 1 as dense
+    per-parity products on the matrix cores: every output against the oracle (the direct
+    product is exact up to rounding), a ragged tail of transforms past a 64-transform tile,
+    and the plain (batch 1) execute of the same plan."""
+    import torch
+    B = 70
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 60 + n % 89, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 18, max_batch=B) as p:
+        assert p.info["path"] == l2c.L2C_PATH_DENSE
+        Z = p.execute(x).cpu().numpy()
+        z1 = p.execute(x[B - 1]).cpu().numpy()
+        torch.cuda.synchronize()
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(B))
+    print("dense n=%d dir=%d E_inf=%.2e" % (n, direction, worst))
+    assert worst <= 1e-14
+    assert np.array_equal(z1, Z[B - 1])
