@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched-form and line-batch measurements (profiling the N=10^6 kernel alone)")
     ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch"],
                     help="fp32_batch: only the batched FP32 form (256 x 65536), e.g. under a profiler")
     args = ap.parse_args()
@@ -358,8 +360,9 @@ def main():
         "cheb2leg_ms_per_step": c2l_ms,
         "plan": {"table_bytes": info["table_bytes"], "ahat_bytes_padded": info["ahat_bytes"], "plan_ms": plan_ms},
     }
-    rec["batched_fp32_form"] = batched_form(l2c, inputs, torch, min(K, 20), min(W, 5), flush, flush_sink)
-    rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
+    if not args.no_extra:
+        rec["batched_fp32_form"] = batched_form(l2c, inputs, torch, min(K, 20), min(W, 5), flush, flush_sink)
+        rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(f, z, 0)
         rec["cpu_baseline"] = base
