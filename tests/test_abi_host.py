@@ -99,3 +99,34 @@ def test_plan_info_layout_matches_header(lib):
     fields = re.findall(r"(int32_t|int64_t)\s+(\w+);", body)
     ours = [(name, ctypes.sizeof(t)) for name, t in lib.PlanInfo._fields_]
     assert ours == [(n, 4 if t == "int32_t" else 8) for t, n in fields]
+
+
+def test_batch_plan_argument_errors(lib):
+    """Ragged-batch argument checks that the library makes on the host, before any device
+    call: every case returns its error code and leaves the handle NULL."""
+    L = lib.load()
+    i64, ci = ctypes.c_int64, ctypes.c_int
+
+    def plan(ns, dirs, leaf=64, rank=18, precision=0):
+        h = ctypes.c_void_p(1)
+        na = (i64 * max(len(ns), 1))(*ns)
+        da = (ci * max(len(dirs), 1))(*dirs)
+        rc = L.leg2cheb_batch_plan(ctypes.byref(h), len(ns), na, da, leaf, rank, precision, None)
+        assert h.value is None
+        return rc
+
+    assert plan([], []) == -1                       # count < 1
+    assert plan([100, 0], [0, 0]) == -1             # n < 1
+    assert plan([100], [2]) == -1                   # direction
+    assert plan([100], [0], leaf=3) == -1           # leaf size
+    assert plan([100], [0], leaf=130) == -1
+    assert plan([100], [0], leaf=63) == -1          # odd leaf size
+    assert plan([100], [0], precision=7) == -1      # precision code
+    assert plan([100], [0], rank=17) == -4          # rank without kernels
+    assert plan([100], [0], rank=18, precision=1) == -4   # batched forms: rank <= 16
+    assert plan([100], [0], leaf=128, rank=16, precision=2) == -4   # batched forms: leaf <= 64
+    assert plan([(1 << 28) + 1], [0], rank=16, precision=1) == -4   # batched forms: n <= 2^28
+    assert L.leg2cheb_batch_plan(None, 1, None, None, 64, 18, 0, None) == -1
+    assert L.leg2cheb_batch_execute(None, None, None, None) == -1
+    assert L.leg2cheb_batch_info(None, None, None) == -1
+    assert L.leg2cheb_batch_destroy(None) == 0
