@@ -193,11 +193,15 @@ int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after);
 typedef struct l2c_batch_s *l2c_batch_t;
 
 /*
- * Plan a ragged batch.  Transforms whose sizes give the same levels L and half-leaf s
- * (Eq. (numlevels)) and the same direction have identical far-field tables (the tables
- * depend on L, s, M and the kernel only), so they form one group with one set of
- * tables; a group executes as one launch sequence over its items, each item with its
- * own length.  L = 0 transforms (Alg. 1 directly) group by direction.
+ * Plan a ragged batch.  Transforms with the same levels L (Eq. (numlevels)) and the same
+ * direction form one group with one set of tables (the tables depend on L, s, M and the
+ * kernel only): every group is planned with the full half-leaf s = leaf_size / 2, so its
+ * shorter transforms only see more zero padding, and each item keeps its own length.
+ * Results therefore agree with a separately planned transform (whose s may be smaller)
+ * to the method's accuracy, not bit for bit.  L = 0 transforms (Alg. 1 directly) group
+ * by direction.  FP64 groups execute concurrently on side streams of the batch (the
+ * three-launch path, or the dense path for n <= 4096 with 64 or more items); the
+ * batched forms execute all groups in one launch per kernel shape.
  *   batch      [out] receives the new handle (NULL on error).
  *   count      number of transforms, >= 1.
  *   n          host array [count], each >= 1 (lengths are not limited otherwise).
@@ -217,8 +221,10 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
  *            may overlap any input or another output.
  *   stream   hipStream_t.
  * Copies the pointer lists to the device (through pinned memory owned by the batch)
- * and enqueues every group on stream; allocates nothing.  A later call first waits
- * for the previous call's pointer copy.  On L2C_EHIP, the outputs are undefined.
+ * and enqueues every group; work on the batch's side streams is ordered after the
+ * copies on stream, and stream waits for it before anything enqueued later.  Allocates
+ * nothing.  A later call first waits for the previous call's pointer copy.  On
+ * L2C_EHIP, the outputs are undefined.
  */
 int leg2cheb_batch_execute(l2c_batch_t batch, const double *const *in, double *const *out, void *stream);
 

@@ -347,7 +347,7 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
             b->plans.push_back(pl);
             // groups run side by side: FP64 groups use the three-launch path
             pl->fused_on = false;
-            if (!batched_form(precision)) rc = ensure_workspace(pl, items);
+            if (!batched_form(precision) && !pl->d_dense) rc = ensure_workspace(pl, items);
         }
     }
     const size_t cb = (size_t)count * sizeof(void *);

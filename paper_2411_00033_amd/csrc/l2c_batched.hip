@@ -971,7 +971,7 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
     for (int g = 0; g < ngroups; ++g) {
         const l2c_plan_s &p = *plans[g];
         if (p.L < 1) continue;
-        if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
+        if (p.s > 32 || p.M > 16) return hipErrorInvalidValue;
         fm = p.precision == L2C_BF16X2 ? 1 : 0;
         const int64_t tiles = (items[g] + 15) / 16;
         if (tiles > p.bw_tiles) return hipErrorInvalidValue;
