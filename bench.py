@@ -233,7 +233,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the transform is a single-GPU kernel path "
-              "(multi-GPU sharding is described in DESIGN.md but not built); got --gpus %d" % args.gpus,
+              "(multi-GPU sharding is designed but not built); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
