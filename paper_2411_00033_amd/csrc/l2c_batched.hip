@@ -45,15 +45,6 @@ struct Mx<float> {
     // accumulator register r of lane group q holds row 4q + r
     static __host__ __device__ constexpr int row(int q, int r) { return 4 * q + r; }
 };
-template <>
-struct Mx<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 mma(double a, double b, v4 c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __host__ __device__ constexpr int row(int q, int r) { return q + 4 * r; }
-};
 
 template <typename T>
 struct BatArgs {
