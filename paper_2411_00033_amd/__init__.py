@@ -145,6 +145,16 @@ class BatchPlan:
 
     __call__ = execute
 
+    def execute_ptrs(self, in_ptrs, out_ptrs, stream=None) -> None:
+        """As execute, for callers that hold the device pointers (ints, FP64, n[i] values each)
+        already: no per-tensor checks here; the library still rejects null pointers and
+        overlapping outputs."""
+        torch = _torch()
+        if len(in_ptrs) != len(self.n) or len(out_ptrs) != len(self.n):
+            raise ValueError("expected %d input and output pointers" % len(self.n))
+        st = stream if stream is not None else torch.cuda.current_stream()
+        leg2cheb_batch_execute(self.handle, in_ptrs, out_ptrs, st.cuda_stream)
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             leg2cheb_batch_destroy(self.handle)

@@ -86,10 +86,13 @@ def test_fp32_ragged_batch(l2c):
     xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 200 + i)).cuda() for i, n in enumerate(sizes)]
     with l2c.BatchPlan(sizes, dirs, rank=16, precision=l2c.L2C_FP32) as bp:
         zs = bp.execute(xs)
+        zp = [torch.empty_like(x) for x in xs]
+        bp.execute_ptrs([x.data_ptr() for x in xs], [z.data_ptr() for z in zp])
         torch.cuda.synchronize()
     for i, (n, d) in enumerate(zip(sizes, dirs)):
         err = oracle.einf(zs[i].cpu().numpy(), oracle.transform(xs[i].cpu().numpy(), d))
         assert err <= TOL32, (n, d, err)
+        assert torch.equal(zs[i], zp[i])
 
 
 def test_config3_fp32_batch_256x65536(l2c):
