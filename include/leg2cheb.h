@@ -237,6 +237,19 @@ int leg2cheb_batch_destroy(l2c_batch_t batch);
 /* Non-zero if this build instantiates kernels for rank M. */
 int leg2cheb_rank_supported(int rank);
 
+/*
+ * Test hook for the error paths (no paper passage: the method allocates nothing itself).
+ * Every device and pinned host allocation the library makes (plans, workspaces, batches,
+ * plan_export's staging) counts down a process-wide counter: with fail_at = k >= 1 the
+ * k-th allocation after this call fails as if memory were exhausted, and the call that
+ * made it returns L2C_ENOMEM having released everything it had allocated; fail_at = 0
+ * disarms the hook; fail_at = -1 only queries.
+ *   pending  [out, may be NULL] the countdown before this call (0: disarmed or fired).
+ *   live     [out, may be NULL] allocations the library holds now (for leak checks).
+ * Errors: L2C_EINVAL (fail_at < -1).
+ */
+int leg2cheb_debug_alloc_hook(int64_t fail_at, int64_t *pending, int64_t *live);
+
 /* Static description of a status code. */
 const char *leg2cheb_strerror(int code);
 

@@ -24,6 +24,7 @@ EXPORTED = (
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
     "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
+    "leg2cheb_debug_alloc_hook",
 )
 
 
@@ -76,6 +77,7 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.leg2cheb_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.leg2cheb_batch_destroy.argtypes = [vp]
+    lib.leg2cheb_debug_alloc_hook.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for name in EXPORTED:
         if name != "leg2cheb_strerror":
             getattr(lib, name).restype = ci
@@ -150,6 +152,15 @@ def leg2cheb_set_timing_events(plan: int, before: int, after: int) -> None:
 
 def leg2cheb_rank_supported(rank: int) -> bool:
     return bool(load().leg2cheb_rank_supported(int(rank)))
+
+
+def leg2cheb_debug_alloc_hook(fail_at: int = -1):
+    """Arm (fail_at >= 1), disarm (0) or only query (-1) the allocation-failure hook.
+    Returns (countdown before the call, allocations the library holds)."""
+    pend, live = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load().leg2cheb_debug_alloc_hook(int(fail_at), ctypes.byref(pend), ctypes.byref(live)),
+           "leg2cheb_debug_alloc_hook")
+    return pend.value, live.value
 
 
 def leg2cheb_batch_plan(n, direction, leaf_size: int = 64, rank: int = 18, precision: int = L2C_FP64,

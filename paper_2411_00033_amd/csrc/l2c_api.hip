@@ -1,5 +1,6 @@
 // l2c_api.hip -- C ABI (include/leg2cheb.h): argument checking, plan sizes and host-side
 // constant tables, device memory ownership, and dispatch to the kernels.
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -8,12 +9,62 @@
 #include <vector>
 
 #include "../../include/leg2cheb.h"
+#include "l2c_alloc.h"
 #include "l2c_internal.h"
 #include "l2c_batched.h"
 #include "l2c_math.h"
 
-namespace {
+namespace l2c {
 
+// Allocation-failure hook: the k-th allocation from the arming call fails (0: disarmed).
+static std::atomic<int64_t> g_fail_at{0};
+static std::atomic<int64_t> g_live{0};   // allocations made here and not yet released
+
+static bool injected_failure()
+{
+    int64_t k = g_fail_at.load();
+    while (k > 0)
+        if (g_fail_at.compare_exchange_weak(k, k - 1)) return k == 1;
+    return false;
+}
+
+hipError_t dev_alloc_raw(void **ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (injected_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) *ptr = nullptr;
+    else if (*ptr) ++g_live;
+    return e;
+}
+
+void dev_free(const void *ptr)
+{
+    if (!ptr) return;
+    (void)hipFree(const_cast<void *>(ptr));
+    --g_live;
+}
+
+hipError_t host_alloc(void **ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (injected_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipHostMalloc(ptr, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) *ptr = nullptr;
+    else if (*ptr) ++g_live;
+    return e;
+}
+
+void host_free(void *ptr)
+{
+    if (!ptr) return;
+    (void)hipHostFree(ptr);
+    --g_live;
+}
+
+}  // namespace l2c
+
+namespace {
 
 // Sizes of Eq. (numlevels): s_hat = leaf/2, L = ceil(log2(n/s_hat)) - 2,
 // s = ceil(n / 2^(L+2)), N = s 2^(L+2).  L <= 0: the plan applies Alg. 1 directly.
@@ -111,23 +162,23 @@ bool rank_supported(int M)
 void free_plan(l2c_plan_s *p)
 {
     if (!p) return;
-    (void)hipFree(p->d_top);
-    (void)hipFree(p->d_bot);
-    (void)hipFree(p->d_T);
-    (void)hipFree(p->d_B);
-    (void)hipFree(p->d_P);
-    (void)hipFree(p->d_XG);
-    (void)hipFree(p->d_D);
-    (void)hipFree(p->d_w);
-    (void)hipFree(p->d_pub);
-    (void)hipFree(p->d_status);
-    (void)hipFree(p->d_bA);
-    (void)hipFree(p->d_bT);
-    (void)hipFree(p->d_bB);
-    (void)hipFree(p->d_bP);
-    (void)hipFree(p->d_bQ);
-    (void)hipFree(p->d_bw);
-    (void)hipFree(p->d_dense);
+    l2c::dev_free(p->d_top);
+    l2c::dev_free(p->d_bot);
+    l2c::dev_free(p->d_T);
+    l2c::dev_free(p->d_B);
+    l2c::dev_free(p->d_P);
+    l2c::dev_free(p->d_XG);
+    l2c::dev_free(p->d_D);
+    l2c::dev_free(p->d_w);
+    l2c::dev_free(p->d_pub);
+    l2c::dev_free(p->d_status);
+    l2c::dev_free(p->d_bA);
+    l2c::dev_free(p->d_bT);
+    l2c::dev_free(p->d_bB);
+    l2c::dev_free(p->d_bP);
+    l2c::dev_free(p->d_bQ);
+    l2c::dev_free(p->d_bw);
+    l2c::dev_free(p->d_dense);
     delete p;
 }
 
@@ -165,10 +216,10 @@ namespace {
 void free_batch(l2c_batch_s *b)
 {
     for (l2c_plan_s *p : b->plans) leg2cheb_destroy(p);
-    (void)hipFree(b->d_n);
-    (void)hipFree((void *)b->d_in);
-    (void)hipFree(b->d_out);
-    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    l2c::dev_free(b->d_n);
+    l2c::dev_free((void *)b->d_in);
+    l2c::dev_free(b->d_out);
+    l2c::host_free(b->h_stage);
     if (b->staged) (void)hipEventDestroy(b->staged);
     l2c::batched_grouped_free(b->grouped);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -185,11 +236,11 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
     if (p->ws_batch > 0) {
         if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
     }
-    (void)hipFree(p->d_w);
+    l2c::dev_free(p->d_w);
     p->d_w = nullptr;
     p->ws_batch = 0;
     const size_t bytes = (size_t)batch * p->geo.NT * 2 * p->M * sizeof(double);
-    if (hipMalloc(&p->d_w, bytes) != hipSuccess) {
+    if (l2c::dev_alloc(&p->d_w, bytes) != hipSuccess) {
         (void)hipGetLastError();
         p->d_w = nullptr;
         return L2C_ENOMEM;
@@ -209,11 +260,11 @@ int ensure_bworkspace(l2c_plan_s *p, int64_t items)
     if (p->bw_tiles > 0) {
         if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
     }
-    (void)hipFree(p->d_bw);
+    l2c::dev_free(p->d_bw);
     p->d_bw = nullptr;
     p->bw_tiles = 0;
     const size_t bytes = (size_t)tiles * p->geo.NT * 2 * 256 * elem_bytes(p);
-    if (hipMalloc(&p->d_bw, bytes) != hipSuccess) {
+    if (l2c::dev_alloc(&p->d_bw, bytes) != hipSuccess) {
         (void)hipGetLastError();
         p->d_bw = nullptr;
         return L2C_ENOMEM;
@@ -232,9 +283,11 @@ int build_batched_tables(l2c_plan_s *p, const std::vector<double> &T, const std:
     std::vector<float> t32(T.begin(), T.end()), b32(B.begin(), B.begin() + (size_t)M * M), p32(2 * (size_t)s);
     for (int d = 0; d < 2 * s; ++d) p32[d] = (float)Ptab[l2c::kPLead + d];
     const size_t eb = elem_bytes(p);
-    bool ok = hipMalloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
-              hipMalloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess && hipMalloc(&p->d_bT, t32.size() * eb) == hipSuccess &&
-              hipMalloc(&p->d_bB, b32.size() * eb) == hipSuccess && hipMalloc(&p->d_bP, p32.size() * eb) == hipSuccess;
+    bool ok = l2c::dev_alloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bT, t32.size() * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bB, b32.size() * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bP, p32.size() * eb) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         return L2C_ENOMEM;
@@ -248,8 +301,8 @@ int build_batched_tables(l2c_plan_s *p, const std::vector<double> &T, const std:
         (void)hipGetLastError();
         return L2C_EHIP;
     }
-    (void)hipFree(p->d_top);
-    (void)hipFree(p->d_bot);
+    l2c::dev_free(p->d_top);
+    l2c::dev_free(p->d_bot);
     p->d_top = p->d_bot = nullptr;
     p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
     p->bot_bytes = 0;
@@ -352,8 +405,9 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
     }
     const size_t cb = (size_t)count * sizeof(void *);
     if (rc == L2C_OK &&
-        (hipMalloc(&b->d_n, (size_t)count * sizeof(int64_t)) != hipSuccess || hipMalloc(&b->d_in, cb) != hipSuccess ||
-         hipMalloc(&b->d_out, cb) != hipSuccess || hipHostMalloc(&b->h_stage, 2 * cb, hipHostMallocDefault) != hipSuccess ||
+        (l2c::dev_alloc(&b->d_n, (size_t)count * sizeof(int64_t)) != hipSuccess ||
+         l2c::dev_alloc(&b->d_in, cb) != hipSuccess || l2c::dev_alloc(&b->d_out, cb) != hipSuccess ||
+         l2c::host_alloc(&b->h_stage, 2 * cb) != hipSuccess ||
          hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess))
         rc = L2C_ENOMEM;
     if (rc == L2C_OK && hipMemcpy(b->d_n, nord.data(), (size_t)count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
@@ -496,6 +550,15 @@ int leg2cheb_batch_destroy(l2c_batch_t b)
 
 int leg2cheb_rank_supported(int rank) { return rank_supported(rank) ? 1 : 0; }
 
+int leg2cheb_debug_alloc_hook(int64_t fail_at, int64_t *pending, int64_t *live)
+{
+    if (fail_at < -1) return L2C_EINVAL;
+    const int64_t before = fail_at >= 0 ? l2c::g_fail_at.exchange(fail_at) : l2c::g_fail_at.load();
+    if (pending) *pending = before;
+    if (live) *live = l2c::g_live.load();
+    return L2C_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -570,13 +633,13 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         for (int k = 0; k < M; ++k)
             for (int m = 0; m < M; ++m) Dm[(size_t)k * M + m] = std::cos(k * (m + 0.5) * M_PI / M);
 
-        bool ok = hipMalloc(&p->d_top, p->top_bytes) == hipSuccess &&
-                  (p->bot_bytes == 0 || hipMalloc(&p->d_bot, p->bot_bytes) == hipSuccess) &&
-                  hipMalloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&p->d_P, Ptab.size() * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&p->d_D, Dm.size() * sizeof(double)) == hipSuccess;
+        bool ok = l2c::dev_alloc(&p->d_top, p->top_bytes) == hipSuccess &&
+                  (p->bot_bytes == 0 || l2c::dev_alloc(&p->d_bot, p->bot_bytes) == hipSuccess) &&
+                  l2c::dev_alloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_P, Ptab.size() * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_D, Dm.size() * sizeof(double)) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);
@@ -609,7 +672,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         // batches of short transforms: the direct product on the matrix cores
         if (n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
             const int64_t HP = l2c::dense_hp(n);
-            ok = hipMalloc(&p->d_dense, (size_t)2 * HP * HP * sizeof(double)) == hipSuccess &&
+            ok = l2c::dev_alloc(&p->d_dense, (size_t)2 * HP * HP * sizeof(double)) == hipSuccess &&
                  l2c::dense_build(*p, p->d_dense, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
             if (!ok) {
                 (void)hipGetLastError();
@@ -627,7 +690,8 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         if (items > 0) {
             // both halves of the exchange buffer start out "not written"
             const size_t pwords = (size_t)2 * items * p->geo.NX * 2 * p->M * 2;
-            ok = hipMalloc(&p->d_pub, pwords * 4) == hipSuccess && hipMalloc(&p->d_status, sizeof(int)) == hipSuccess &&
+            ok = l2c::dev_alloc(&p->d_pub, pwords * 4) == hipSuccess &&
+                 l2c::dev_alloc(&p->d_status, sizeof(int)) == hipSuccess &&
                  hipMemsetD32Async((hipDeviceptr_t)p->d_pub, (int)l2c::kPubEmptyHalf, pwords, st) == hipSuccess &&
                  hipMemsetAsync(p->d_status, 0, sizeof(int), st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
             if (!ok) {
@@ -742,13 +806,13 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
     if (table == 2) return hipMemcpy(dst, plan->d_B, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
     if (!plan->d_top) return L2C_EUNSUPPORTED;   // FP32 plans keep Ahat only in the batched layout
     double *tmp = nullptr;
-    if (hipMalloc(&tmp, need) != hipSuccess) {
+    if (l2c::dev_alloc(&tmp, need) != hipSuccess) {
         (void)hipGetLastError();
         return L2C_ENOMEM;
     }
     bool ok = l2c::launch_export_ahat(*plan, tmp, nullptr) == hipSuccess &&
               hipMemcpy(dst, tmp, need, hipMemcpyDeviceToHost) == hipSuccess;
-    (void)hipFree(tmp);
+    l2c::dev_free(tmp);
     return ok ? L2C_OK : L2C_EHIP;
 }
 

@@ -921,6 +921,7 @@ hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, in
 
 // ------------------------------------------------------------------------------------
 // Grouped launches (ragged batches).
+#include "l2c_alloc.h"
 #include "l2c_batched.h"
 #include <map>
 #include <tuple>
@@ -945,8 +946,8 @@ void batched_grouped_free(BatGrouped *g)
 {
     if (!g) return;
     for (auto &l : g->launches) {
-        (void)hipFree(l.E);
-        (void)hipFree(l.blk0);
+        dev_free(l.E);
+        dev_free(l.blk0);
     }
     delete g;
 }
@@ -1024,8 +1025,8 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
         }
         BatGrouped::Launch l{std::get<0>(k), std::get<1>(k), std::get<2>(k), nullptr, nullptr, (int)ents.size(),
                              blk0.back()};
-        if (l.blocks > 0x7fffffff || hipMalloc(&l.E, ents.size() * sizeof(BatEntry<T>)) != hipSuccess ||
-            hipMalloc(&l.blk0, blk0.size() * sizeof(int64_t)) != hipSuccess ||
+        if (l.blocks > 0x7fffffff || dev_alloc(&l.E, ents.size() * sizeof(BatEntry<T>)) != hipSuccess ||
+            dev_alloc(&l.blk0, blk0.size() * sizeof(int64_t)) != hipSuccess ||
             hipMemcpy(l.E, ents.data(), ents.size() * sizeof(BatEntry<T>), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(l.blk0, blk0.data(), blk0.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipGetLastError();

@@ -130,3 +130,16 @@ def test_batch_plan_argument_errors(lib):
     assert L.leg2cheb_batch_execute(None, None, None, None) == -1
     assert L.leg2cheb_batch_info(None, None, None) == -1
     assert L.leg2cheb_batch_destroy(None) == 0
+
+
+def test_alloc_hook_host_logic(lib):
+    """The allocation-failure hook's countdown is host state: arming, querying and disarming
+    make no device call, and a countdown no allocation reached is reported back."""
+    assert lib.leg2cheb_debug_alloc_hook(0) == (0, 0)
+    assert lib.leg2cheb_debug_alloc_hook(3) == (0, 0)
+    assert lib.leg2cheb_debug_alloc_hook(-1) == (3, 0)
+    assert lib.leg2cheb_debug_alloc_hook(0) == (3, 0)
+    assert lib.leg2cheb_debug_alloc_hook(-1) == (0, 0)
+    with pytest.raises(lib.L2CError) as ei:
+        lib.leg2cheb_debug_alloc_hook(-2)
+    assert ei.value.code == lib.L2C_EINVAL
