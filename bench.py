@@ -218,6 +218,50 @@ def lines_form(l2c, inputs, torch, K, W, flush, flush_sink):
     return rec
 
 
+def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink):
+    """The n = 1024 single transform (latency, cold) and the 2048-transform ragged batch
+    (n log-uniform in [128, 262144], directions 50/50) through BatchPlan.execute_ptrs."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k, cold=True):
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        for i in range(k):
+            if cold:
+                torch.sum(flush, dim=0, out=flush_sink)
+            st[i].record(stream)
+            fn()
+            en[i].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([st[i].elapsed_time(en[i]) for i in range(k)]))
+
+    rec = {}
+    x1 = torch.from_numpy(inputs.decaying(1024, 1.0, inputs.SEED_BASE + 1)).cuda()
+    y1 = torch.empty_like(x1)
+    with l2c.Plan(1024, l2c.LEG2CHEB, 64, 18) as p1:
+        rec["n1024_single"] = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
+                               "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
+                               "path": p1.info["path"]}
+    sizes, dirs = inputs.ragged_sizes(2048, inputs.SEED_BASE + 4)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    x = torch.randn(int(offs[-1]), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ip = [x.data_ptr() + 8 * int(o) for o in offs[:-1]]
+    op = [y.data_ptr() + 8 * int(o) for o in offs[:-1]]
+    rg = {"workload": "2048 transforms, n log-uniform in [128, 262144] (%d coefficients), directions 50/50"
+                      % int(offs[-1])}
+    for tag, prec, rank in (("fp64", l2c.L2C_FP64, 18), ("fp32", l2c.L2C_FP32, 16)):
+        with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), rank=rank, precision=prec) as bp:
+            ms = timed(lambda: bp.execute_ptrs(ip, op), max(2, K // 4))
+            rg[tag] = {"ms_per_execute": ms, "Gcoeff_s": float(offs[-1]) / (ms * 1e-3) / 1e9,
+                       "groups": bp.info["groups"]}
+    rec["ragged_2048"] = rg
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +367,11 @@ def main():
         ce[i].record(stream)
     torch.cuda.synchronize()
     c2l_ms = float(np.mean([cs[i].elapsed_time(ce[i]) for i in range(K)]))
+    # round trip at the same size: cheb2leg of the leg2cheb output against the input
+    back = torch.empty_like(x)
+    plan_c.execute(out, back)
+    torch.cuda.synchronize()
+    round_trip = ((back - x).abs().max() / x.abs().max()).item()
 
     z = out.cpu().numpy()
     ahat_alg = 8.0 * RANK * RANK * info["n_submatrices"]          # Ahat, one M x M table per submatrix
@@ -358,11 +407,13 @@ def main():
         "warm_ms_per_step": warm_ms,
         "cold_wall_ms_per_step_incl_flush": wall_cold,
         "cheb2leg_ms_per_step": c2l_ms,
+        "round_trip_einf": round_trip,
         "plan": {"table_bytes": info["table_bytes"], "ahat_bytes_padded": info["ahat_bytes"], "plan_ms": plan_ms},
     }
     if not args.no_extra:
         rec["batched_fp32_form"] = batched_form(l2c, inputs, torch, min(K, 20), min(W, 5), flush, flush_sink)
         rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
+        rec.update(small_and_ragged(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink))
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(f, z, 0)
         rec["cpu_baseline"] = base
