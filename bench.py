@@ -242,9 +242,14 @@ def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink):
     x1 = torch.from_numpy(inputs.decaying(1024, 1.0, inputs.SEED_BASE + 1)).cuda()
     y1 = torch.empty_like(x1)
     with l2c.Plan(1024, l2c.LEG2CHEB, 64, 18) as p1:
-        rec["n1024_single"] = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
-                               "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
-                               "path": p1.info["path"]}
+        one = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
+               "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
+               "path": p1.info["path"]}
+        p1.set_direct(False)   # the same transform by Alg. 4
+        one["multipole"] = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
+                            "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
+                            "path": p1.info["path"]}
+        rec["n1024_single"] = one
     sizes, dirs = inputs.ragged_sizes(2048, inputs.SEED_BASE + 4)
     offs = np.concatenate([[0], np.cumsum(sizes)])
     x = torch.randn(int(offs[-1]), dtype=torch.float64, device="cuda")

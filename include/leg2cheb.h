@@ -56,7 +56,8 @@ enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
 
 /* Execution path of a plan (l2c_plan_info.path). */
 enum l2c_path {
-    L2C_PATH_DIRECT = 0, /* L = 0: the whole product directly (Alg. 1) */
+    L2C_PATH_DIRECT = 0, /* the whole product directly, row by row (Alg. 1): plans with
+                            L = 0, and short FP64 plans (L2C_OPT_DIRECT) */
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
     L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
     L2C_PATH_BATCHED = 3, /* L2C_FP32 / L2C_BF16X2 plans: 16 transforms per matrix-core tile */
@@ -66,7 +67,8 @@ enum l2c_path {
 
 /* Plan options (leg2cheb_plan_set_option). */
 enum l2c_option {
-    L2C_OPT_SINGLE_LAUNCH = 1 /* 1: single-launch path when the plan allows it (default); 0: three launches */
+    L2C_OPT_SINGLE_LAUNCH = 1, /* 1: single-launch path when the plan allows it (default); 0: three launches */
+    L2C_OPT_DIRECT = 2         /* 1: Alg. 1 directly for short FP64 plans (default); 0: Alg. 4 */
 };
 
 enum l2c_status {
@@ -160,12 +162,19 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
  *       unit).  The workgroups exchange only subtree roots, the two boundary nodes of
  *       each depth, and the upward vectors above the subtrees.  Value 0 selects the
  *       three-launch path.  Both paths use the same plan tables and agree to rounding.
+ *   L2C_OPT_DIRECT  value 1 (default) runs short FP64 transforms (L >= 1, n <= 8192
+ *       and max_batch n^2 <= 2^26) as Alg. 1, every output row one sum over its band,
+ *       on many small workgroups: at these lengths a multipole launch is dominated by
+ *       its dependency chain.  An execute with batch n^2 > 2^26 takes Alg. 4 instead.
+ *       Value 0 selects Alg. 4 (the path L2C_OPT_SINGLE_LAUNCH chooses).  The plan
+ *       builds the multipole tables either way.  Plans on the dense path (n <= 4096,
+ *       max_batch >= 64) use it regardless.
  * Single-launch kernels of one device are ordered by the library (a launch on another
  * stream waits for the previous one), so they never compete for compute units; other
  * work may delay but not block them.  A plan must not be executed on two streams at
  * the same time.
  * Errors: L2C_EINVAL (plan, option or value), L2C_EUNSUPPORTED (value 1 on a plan whose
- * geometry has no single-launch form).
+ * geometry has no single-launch form, or that is not a short FP64 plan).
  */
 int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value);
 

@@ -669,6 +669,8 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             *plan = p;
             return L2C_OK;
         }
+        // short transforms: Alg. 1 row by row (the multipole tables stay available)
+        p->direct_ok = n <= l2c::kDirectMaxN && max_batch <= l2c::kDirectMaxWork / (n * n);
         // batches of short transforms: the direct product on the matrix cores
         if (n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
             const int64_t HP = l2c::dense_hp(n);
@@ -737,6 +739,10 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
         if (l2c::launch_dense(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
     }
+    if (plan->L > 0 && plan->direct_ok && plan->direct_on && batch <= l2c::kDirectMaxWork / (plan->n * plan->n)) {
+        if (l2c::launch_direct(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
+        return L2C_OK;
+    }
     if (use_batched(plan)) {
         const int rc = ensure_bworkspace(plan, batch);
         if (rc != L2C_OK) return rc;
@@ -780,11 +786,12 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
     info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double) +
                             plan->bw_tiles * plan->geo.NT * 2 * 256 * (int64_t)elem_bytes(plan);
     info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
-    info->path = plan->L == 0        ? L2C_PATH_DIRECT
-                 : plan->d_dense     ? L2C_PATH_DENSE
-                 : use_batched(plan) ? L2C_PATH_BATCHED
-                 : use_fused(plan)   ? L2C_PATH_SINGLE
-                                     : L2C_PATH_THREE;
+    info->path = plan->L == 0                           ? L2C_PATH_DIRECT
+                 : plan->d_dense                        ? L2C_PATH_DENSE
+                 : use_batched(plan)                    ? L2C_PATH_BATCHED
+                 : plan->direct_ok && plan->direct_on   ? L2C_PATH_DIRECT
+                 : use_fused(plan)                      ? L2C_PATH_SINGLE
+                                                        : L2C_PATH_THREE;
     return L2C_OK;
 }
 
@@ -824,6 +831,11 @@ int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value)
         if (value != 0 && value != 1) return L2C_EINVAL;
         if (value == 1 && !plan->fused_ok) return L2C_EUNSUPPORTED;
         plan->fused_on = value == 1;
+        return L2C_OK;
+    case L2C_OPT_DIRECT:
+        if (value != 0 && value != 1) return L2C_EINVAL;
+        if (value == 1 && !plan->direct_ok) return L2C_EUNSUPPORTED;
+        plan->direct_on = value == 1;
         return L2C_OK;
     default: return L2C_EINVAL;
     }

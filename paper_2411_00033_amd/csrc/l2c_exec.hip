@@ -14,7 +14,7 @@
 //           downward spreading of step (4) from level 0, the leaf evaluation of
 //           Eq. (step5), the near-diagonal direct part of step (6), the scaling of
 //           step (7), and the output.  Nothing but w crosses kernel boundaries.
-// Plans with L = 0 use k_direct (Alg. 1 for every row).
+// Plans with L = 0, and short transforms, use k_direct (Alg. 1 for every row).
 #include "l2c_device.h"
 
 namespace l2c {
@@ -458,38 +458,83 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
 }
 
 // ------------------------------------------------------------------------------------
-// k_direct: plans with L = 0 (n <= leaf): the whole product directly (Alg. 1 per row).
+// k_direct: Alg. 1, each output row as one sum over its band j >= i, j - i even, with the
+// factorisation a_ij = rs_i P_{(j-i)/2} Q_{(i+j)/2} g_j of the near field applied to the
+// whole row.  Used by plans with L = 0 and, up to kDirectMaxN, by short transforms,
+// where a multipole launch is pure latency.
+// Workgroup (row block rb, parity sg) of one item: rows i = 2 i' + sg, i' in
+// [16 rb, 16 rb + 16); 16 lanes per row take j' = i' + lane, i' + lane + 16, ...
+// (j = 2 j' + sg) and a butterfly over the 16 lanes adds their partial sums.  The
+// block's g, P and Q are evaluated into LDS first: with c = j' - 16 rb, g[c] = g_{2j'+sg},
+// P[c] = P_c, Q[c] = Q_{32 rb + sg + c}, and row r of the block reads P[c - r] Q[c + r] g[c].
+constexpr int kDirRows = 16;
+
 __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *out, int64_t nmax, int dir,
                                                      const int64_t *item_n, const double *const *item_in,
                                                      double *const *item_out)
 {
     extern __shared__ double lds[];
-    double *gl = lds;          // nmax
-    double *Ql = gl + nmax;    // nmax
-    double *Pl = Ql + nmax;    // nmax
-    const int64_t item = blockIdx.x;
-    const int64_t n = item_n ? item_n[item] : nmax;   // ragged batch: this item's length (<= nmax)
+    const int64_t HPm = (nmax + 1) / 2;
+    double *gl = lds, *Pl = gl + HPm, *Ql = Pl + HPm;   // HPm, HPm and HPm + kDirRows doubles
+    const int sg = blockIdx.x & 1;
+    const int64_t i0 = (int64_t)(blockIdx.x >> 1) * kDirRows;
+    const int64_t item = blockIdx.y;
+    const int64_t n = item_n ? item_n[item] : nmax;     // ragged batch: this item's length (<= nmax)
+    const int64_t H = (n - sg + 1) / 2;                 // rows (and columns) of parity sg
+    if (i0 >= H) return;
     const double *x = item_in ? item_in[item] : in + item * nmax;
     double *y = item_out ? item_out[item] : out + item * nmax;
-    for (int64_t e = threadIdx.x; e < n; e += kThreads) {
-        double v = x[e];
-        if (dir == 1) v *= (double)e;
-        gl[e] = v;
-        Ql[e] = near_Q(dir, e);
-        Pl[e] = near_P(dir, e);
+    const int64_t C = H - i0;                           // columns j' in [i0, H)
+    for (int64_t c = threadIdx.x; c < C + kDirRows; c += kThreads) {
+        if (c < C) {
+            const int64_t j = 2 * (i0 + c) + sg;
+            double v = x[j];
+            if (dir == 1) v *= (double)j;
+            gl[c] = v;
+            Pl[c] = near_P(dir, c);
+        }
+        Ql[c] = near_Q(dir, 2 * i0 + sg + c);
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
-        double acc = 0.0;
-        for (int64_t j = i; j < n; j += 2) acc = fma(Pl[(j - i) / 2] * Ql[(i + j) / 2], gl[j], acc);
+    const int r = threadIdx.x >> 4, k = threadIdx.x & 15;
+    const int64_t ip = i0 + r;
+    double acc = 0.0;
+    if (ip < H)
+        for (int64_t c = r + k; c < C; c += 16) acc = fma(Pl[c - r] * Ql[c + r], gl[c], acc);
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    if (k == 0 && ip < H) {
+        const int64_t i = 2 * ip + sg;
         if (dir == 1) {
             acc *= 2.0 * (double)i + 1.0;
-            if (i == 0) acc += x[0];
+            if (i == 0) acc += x[0];   // K_00 u_0 = f_0
         } else {
             acc /= (i == 0 ? kPi : 0.5 * kPi);
         }
         y[i] = acc;
     }
+}
+
+hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                         const ItemArrays *ia)
+{
+    const int64_t HPm = (p.n + 1) / 2;
+    const size_t lds = sizeof(double) * (size_t)(3 * HPm + kDirRows);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const unsigned blocks = (unsigned)(2 * ((HPm + kDirRows - 1) / kDirRows));
+    for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
+        const int64_t nb = batch - b0 < kMaxItemsPerLaunch ? batch - b0 : kMaxItemsPerLaunch;
+        const bool timed = p.ev_before && p.ev_after && b0 == 0;
+        if (timed) (void)hipEventRecord(p.ev_before, st);
+        hipLaunchKernelGGL(k_direct, dim3(blocks, (unsigned)nb), dim3(kThreads), lds, st,
+                           ia ? nullptr : in + b0 * p.n, ia ? nullptr : out + b0 * p.n, p.n, p.direction,
+                           ia ? ia->n + b0 : nullptr, ia ? ia->in + b0 : nullptr, ia ? ia->out + b0 : nullptr);
+        if (timed) (void)hipEventRecord(p.ev_after, st);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------------------------
@@ -567,14 +612,7 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
                           const ItemArrays *ia)
 {
-    if (p.L == 0) {
-        if (p.ev_before && p.ev_after) (void)hipEventRecord(p.ev_before, st);
-        hipLaunchKernelGGL(k_direct, dim3((unsigned)batch), dim3(kThreads), 3 * sizeof(double) * p.n, st,
-                           in, out, p.n, p.direction, ia ? ia->n : nullptr, ia ? ia->in : nullptr,
-                           ia ? ia->out : nullptr);
-        if (p.ev_before && p.ev_after) (void)hipEventRecord(p.ev_after, st);
-        return hipGetLastError();
-    }
+    if (p.L == 0) return launch_direct(p, in, out, batch, st, ia);
     switch (p.M) {
 #define L2C_CASE(MM) \
     case MM: return run<MM>(p, in, out, batch, st, ia);

@@ -138,10 +138,21 @@ struct l2c_plan_s {
     // FP64 batches of short transforms (l2c_dense.hip): per parity the dense coefficient
     // matrix of Alg. 1, [2][HP][HP]
     double *d_dense = nullptr;
+    // short FP64 transforms (n <= kDirectMaxN, max_batch n^2 <= kDirectMaxWork): Alg. 1 row
+    // by row (k_direct) instead of the multipole kernels for executes within the same
+    // work bound, unless switched off (leg2cheb_plan_set_option)
+    bool direct_ok = false;
+    bool direct_on = true;
 };
 
 namespace l2c {
 // l2c_exec.hip
+// k_direct is faster than Alg. 4 (by measurement) while n <= kDirectMaxN and
+// batch n^2 <= kDirectMaxWork: its work grows as n^2 per transform, and every workgroup
+// evaluates the lambda products of its band itself
+constexpr int64_t kDirectMaxN = 8192, kDirectMaxWork = int64_t(1) << 26;
+hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
+                         const ItemArrays *ia = nullptr);
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
                           hipStream_t stream, const ItemArrays *ia = nullptr);
 // l2c_fused.hip

@@ -41,6 +41,7 @@ def run(l2c, f, direction, leaf=64, rank=18, single=None):
     batch = 1 if x.dim() == 1 else x.shape[0]
     with l2c.Plan(f.shape[-1], direction, leaf, rank, max_batch=batch) as p:
         if single is not None and p.info["levels"] > 0:
+            p.set_direct(False)
             p.set_single_launch(single)
         z = p.execute(x)
         torch.cuda.synchronize()
@@ -75,6 +76,8 @@ SIZES = [1, 2, 3, 7, 64, 127, 128, 129, 255, 256, 257, 500, 1000, 1024, 1025, 20
 
 def _single_ok(l2c, n, direction=0, leaf=64, rank=18):
     with l2c.Plan(n, direction, leaf, rank) as p:
+        if p.info["levels"] > 0:
+            p.set_direct(False)
         return p.info["path"] == l2c.L2C_PATH_SINGLE
 
 
@@ -396,3 +399,56 @@ def test_dense_batches_of_short_transforms(l2c, n, direction):
     print("dense n=%d dir=%d E_inf=%.2e" % (n, direction, worst))
     assert worst <= 1e-14
     assert np.array_equal(z1, Z[B - 1])
+
+
+@pytest.mark.parametrize("n", [129, 255, 256, 257, 1000, 1024, 1025, 2049, 4096, 5000, 8191, 8192])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_direct_short_transforms(l2c, n, direction):
+    """FP64 plans for n <= 8192 (L >= 1) and batch n^2 <= 2^26 apply Alg. 1 row by row:
+    every output of a batch of up to three against the oracle (the direct product is exact
+    up to rounding), the batch-1 execute of the same plan bit for bit, agreement with the
+    multipole path of the same plan to the multipole tolerance, and a batch past the work
+    bound that runs the multipole path."""
+    import torch
+    B = max(1, min(3, (1 << 26) // (n * n)))
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 70 + n % 97, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 18, max_batch=B) as p:
+        assert p.info["levels"] > 0 and p.info["path"] == l2c.L2C_PATH_DIRECT
+        Z = p.execute(x).cpu().numpy()
+        z1 = p.execute(x[B - 1]).cpu().numpy()
+        # a batch past the work bound runs Alg. 4: same result to the multipole tolerance
+        nb = (1 << 26) // (n * n) + 1
+        xb = x[torch.arange(nb) % B].contiguous()
+        Zb = p.execute(xb).cpu().numpy()
+        p.set_direct(False)
+        assert p.info["path"] in (l2c.L2C_PATH_SINGLE, l2c.L2C_PATH_THREE)
+        Zm = p.execute(x).cpu().numpy()
+        p.set_direct(True)
+        assert p.info["path"] == l2c.L2C_PATH_DIRECT
+        torch.cuda.synchronize()
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(B))
+    dm = max(oracle.einf(Zm[b], Z[b]) for b in range(B))
+    assert max(oracle.einf(Zb[b], Zm[b]) for b in range(B)) <= 1e-15
+    print("direct n=%d dir=%d E_inf=%.2e, multipole differs by %.2e" % (n, direction, worst, dm))
+    # both sides sum the same FP64 terms in different orders; cheb2leg rows cancel more
+    # (their terms grow like (2i+1) j), hence the looser bound
+    assert worst <= (1e-14 if direction == 0 else 5e-14)
+    assert np.array_equal(z1, Z[B - 1])
+    assert dm <= TOL[(direction, 18)]
+
+
+def test_direct_option_errors(l2c):
+    """L2C_OPT_DIRECT = 1 only on short FP64 plans with L >= 1."""
+    with l2c.Plan(20000, 0) as p:
+        assert p.info["path"] != l2c.L2C_PATH_DIRECT
+        p.set_direct(False)
+        with pytest.raises(l2c.L2CError) as ei:
+            p.set_direct(True)
+        assert ei.value.code == l2c.L2C_EUNSUPPORTED
+        with pytest.raises(l2c.L2CError) as ei:
+            l2c.leg2cheb_plan_set_option(p.handle, l2c.L2C_OPT_DIRECT, 2)
+        assert ei.value.code == l2c.L2C_EINVAL
+    with l2c.Plan(1024, 0, 64, 16, precision=l2c.L2C_FP32) as p:
+        with pytest.raises(l2c.L2CError):
+            p.set_direct(True)
