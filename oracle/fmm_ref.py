@@ -11,7 +11,8 @@ order and notation, with no blocking, fusion or reordering:
 * T(sigma):        the Vandermonde matrix of Eqs. (matveczs), (Xs)
 * B(l):            W^{-1} V(l) W of App. A3, in exact rational arithmetic
 * execute:         steps (1)-(7) of Alg. 4, with step (6) as the direct product over
-                   the entries that no far-field submatrix covers.
+                   the entries that no far-field submatrix covers; stage_input and
+                   upward are its steps (0) and (1)-(2), exposed for phase tests.
 
 It is slow (Python loops over blocks, mpmath for every kernel sample) and meant
 for n up to a few thousand.  Alg. 4 is an approximation of the direct product;
@@ -211,30 +212,45 @@ def near_field_mask(P: dict) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------- execute
-def execute(P: dict, f: np.ndarray) -> np.ndarray:
-    """Alg. 4 (Leg2Cheb; the same steps for Cheb2Leg with the reverse kernel)."""
-    n, N, direction = P["n"], P["N"], P["direction"]
+def stage_input(P: dict, f: np.ndarray) -> np.ndarray:
+    """Step (0): the input zero-padded to N; for Cheb2Leg C is applied first (u = c .* f)."""
+    n, N = P["n"], P["N"]
     f = np.asarray(f, dtype=np.float64)
     assert f.shape == (n,)
     u = np.zeros(N)
     u[:n] = f
-    if direction == CHEB2LEG:
+    if P["direction"] == CHEB2LEG:
         u[0] *= 2.0  # c .* f: C applied first, its pi/2 lives in the kernel
+    return u
+
+
+def upward(P: dict, u: np.ndarray, sig: int) -> list:
+    """Steps (1)-(2) of Alg. 4 for parity sig: w[g] of shape (b_g, 2, M), where w[g][b, q]
+    is the upward vector of column node 2b + q + 2 of level g (Eq. (globalij))."""
+    L, s, M, T, B, bg = P["L"], P["s"], P["M"], P["T"], P["B"], P["b"]
+    w = [np.zeros((bg[g], 2, M)) for g in range(L)]
+    # step (1): w(L-1) = f^sigma(L-1) T(sigma), f(L-1) = f[4 h_{L-1}:] as (b, 2, 2s)
+    fL = u[4 * s:].reshape(bg[L - 1], 2, 2 * s)[:, :, sig::2]
+    w[L - 1] = np.einsum("bqm,mk->bqk", fL, T[sig])
+    # step (2): upward, Eq. (wtk)
+    for g in range(L - 1, 0, -1):
+        for b in range(1, bg[g]):
+            b0, q0 = divmod(b - 1, 2)
+            w[g - 1][b0, q0] = B[0] @ w[g][b, 0] + B[1] @ w[g][b, 1]
+    return w
+
+
+def execute(P: dict, f: np.ndarray) -> np.ndarray:
+    """Alg. 4 (Leg2Cheb; the same steps for Cheb2Leg with the reverse kernel)."""
+    n, N, direction = P["n"], P["N"], P["direction"]
+    u = stage_input(P, f)
     z = np.zeros(N)
     if not P["direct"]:
         L, s, M, T, B, A = P["L"], P["s"], P["M"], P["T"], P["B"], P["Ahat"]
         bg = P["b"]
         for sig in (0, 1):
-            w = [np.zeros((bg[g], 2, M)) for g in range(L)]
+            w = upward(P, u, sig)
             c = [np.zeros((bg[g], 2, M)) for g in range(L)]
-            # step (1): w(L-1) = f^sigma(L-1) T(sigma), f(L-1) = f[4 h_{L-1}:] as (b, 2, 2s)
-            fL = u[4 * s:].reshape(bg[L - 1], 2, 2 * s)[:, :, sig::2]
-            w[L - 1] = np.einsum("bqm,mk->bqk", fL, T[sig])
-            # step (2): upward, Eq. (wtk)
-            for g in range(L - 1, 0, -1):
-                for b in range(1, bg[g]):
-                    b0, q0 = divmod(b - 1, 2)
-                    w[g - 1][b0, q0] = B[0] @ w[g][b, 0] + B[1] @ w[g][b, 1]
             # step (3): far-field products
             for g in range(L):
                 for b in range(bg[g]):

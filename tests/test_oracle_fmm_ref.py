@@ -170,3 +170,31 @@ def test_alg4_matches_direct_oracle(n, leaf, direction):
     P = F.plan(n, direction, leaf, 18)
     z = F.execute(P, f)
     assert oracle.einf(z, oracle.transform(f, direction)) <= 2e-15
+
+
+@pytest.mark.parametrize("n", [300, 1000, 3000])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_upward_vectors_are_chebyshev_moments(n, direction):
+    """Steps (1)-(2): the upward vector of every column node equals the node's Chebyshev
+    moments taken directly, w_k = sum_e T_k(-1 + e/h_g) u[2 h_g t + e] over the node's 2 h_g
+    entries e of parity sigma (h_g = s 2^(L-g-1)).  The B(l) re-expansion of Eq. (Tky) is
+    exact for degree < M, so the two agree to rounding; a wrong B, child order, parity or
+    level offset breaks it."""
+    sz = F.sizes(n, 64, 18)
+    P = dict(sz, direction=direction, T=F.vandermonde(sz["s"], 18), B=F.b_matrices(18))
+    f = np.random.default_rng(n + direction).standard_normal(n)
+    u = F.stage_input(P, f)
+    L, s = P["L"], P["s"]
+    for sig in (0, 1):
+        w = F.upward(P, u, sig)
+        for g in range(L):
+            hg = s << (L - g - 1)
+            e = np.arange(sig, 2 * hg, 2)
+            V = np.polynomial.chebyshev.chebvander(-1.0 + e / hg, 17)   # [entry][k]
+            ref = np.zeros_like(w[g])
+            for b in range(P["b"][g]):
+                for q in (0, 1):
+                    t = 2 * b + q + 2
+                    ref[b, q] = u[2 * hg * t + e] @ V
+            scale = np.max(np.abs(ref))
+            assert np.max(np.abs(w[g] - ref)) <= 1e-13 * scale, (sig, g)
