@@ -145,12 +145,19 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info);
  *   table 0 = Ahat: [level][block][r][k][l], levels 0..L-1, b_gamma = 2^(gamma+1)-1
  *                   blocks each, r = p + q(q+1)/2 (Eq. (cfrompq)), M x M row-major;
  *         1 = T:    [sigma][m][k] = T_k(-1 + (2m+sigma)/s), 2 x s x M (Eq. (Xs));
- *         2 = B:    B(0) then B(1), 2 x M x M row-major (Eq. (Tky)).
+ *         2 = B:    B(0) then B(1), 2 x M x M row-major (Eq. (Tky));
+ *         3 = w:    the upward vectors of steps (1)-(2) (Eqs. (wMM), (wtk)) of the first
+ *                   item of the last execute on the three-launch path, as its workspace
+ *                   holds them: [node][sigma][k], every node of every level, level g
+ *                   (2^(g+2) nodes) starting at node 2^(g+2) - 4, 2^(L+2) - 4 nodes in
+ *                   all.  Column node 2b + q + 2 of level g is the w(g, b, q) of the
+ *                   paper.  After executes on other paths the contents are unspecified.
  *   dst   host buffer of at least `bytes` bytes; bytes must equal the table size
  *         (query with dst = NULL: *needed receives the size and nothing is copied).
+ *         Copies are synchronous on the null stream.
  * Errors: L2C_EINVAL (bad table id, size mismatch, direct-only plan), L2C_EUNSUPPORTED
- * (table 0 of an L2C_FP32 or L2C_BF16X2 plan, which keeps Ahat only in its own layout),
- * L2C_EHIP.
+ * (table 0 of an L2C_FP32 or L2C_BF16X2 plan, which keeps Ahat only in its own layout;
+ * table 3 of a plan without an FP64 workspace), L2C_EHIP.
  */
 int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, int64_t *needed);
 

@@ -804,11 +804,16 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
     case 0: need = plan->nc * M * M * 8; break;
     case 1: need = (int64_t)2 * plan->s * M * 8; break;
     case 2: need = (int64_t)2 * M * M * 8; break;
+    case 3: need = plan->geo.NT * 2 * M * 8; break;
     default: return L2C_EINVAL;
     }
     if (needed) *needed = need;
     if (!dst) return L2C_OK;
     if (bytes != need) return L2C_EINVAL;
+    if (table == 3) {
+        if (!plan->d_w) return L2C_EUNSUPPORTED;   // no FP64 workspace on this plan's paths
+        return hipMemcpy(dst, plan->d_w, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
+    }
     if (table == 1) return hipMemcpy(dst, plan->d_T, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
     if (table == 2) return hipMemcpy(dst, plan->d_B, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
     if (!plan->d_top) return L2C_EUNSUPPORTED;   // FP32 plans keep Ahat only in the batched layout

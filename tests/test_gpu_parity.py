@@ -70,6 +70,44 @@ def test_plan_tables_match_reference(l2c):
             torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n", [300, 1024, 3000])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_upward_phase_matches_reference(l2c, n, direction):
+    """Steps (0)-(2) on the GPU (k_up, k_top of the three-launch path) against the host
+    reference of the same phase: every level's upward vectors of the first item, read
+    from the plan's workspace, within rounding of fmm_ref.upward."""
+    import torch
+    f = inputs.decaying(n, 1.0, inputs.SEED_BASE + 80 + n)
+    x = torch.from_numpy(f).cuda()
+    with l2c.Plan(n, direction, 64, 18) as p:
+        p.set_direct(False)
+        p.set_single_launch(False)
+        p.execute(x)
+        torch.cuda.synchronize()
+        info = p.info
+        W = p.export(l2c.TABLE_W).reshape(-1, 2, 18)
+    sz = fmm_ref.sizes(n, 64, 18)
+    assert (info["levels"], info["s"]) == (sz["L"], sz["s"])
+    P = dict(sz, direction=direction, T=fmm_ref.vandermonde(sz["s"], 18), B=fmm_ref.b_matrices(18))
+    u = fmm_ref.stage_input(P, f)
+    L = P["L"]
+    assert W.shape[0] == (1 << (L + 2)) - 4
+    for sig in (0, 1):
+        w = fmm_ref.upward(P, u, sig)
+        for g in range(L):
+            t = 2 * np.arange(P["b"][g])[:, None] + np.arange(2)[None, :] + 2     # column nodes
+            got = W[(1 << (g + 2)) - 4 + t, sig]                                  # (b, q, k)
+            err = np.max(np.abs(got - w[g])) / np.max(np.abs(w[g]))
+            assert err <= 1e-14, (sig, g, err)
+
+
+def test_workspace_export_errors(l2c):
+    with l2c.Plan(65536, 0, 64, 16, precision=l2c.L2C_FP32) as p:
+        with pytest.raises(l2c.L2CError) as ei:
+            p.export(l2c.TABLE_W)
+        assert ei.value.code == l2c.L2C_EUNSUPPORTED
+
+
 # ----------------------------------------------------------------- end to end vs oracle
 SIZES = [1, 2, 3, 7, 64, 127, 128, 129, 255, 256, 257, 500, 1000, 1024, 1025, 2049, 4096, 5000, 16384, 40000]
 
