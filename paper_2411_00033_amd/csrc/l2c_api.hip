@@ -384,6 +384,11 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         for (size_t g = 0; g < keys.size(); ++g) b->gstart[g + 1] += b->gstart[g];
         std::vector<int64_t> fill(b->gstart.begin(), b->gstart.end() - 1);
         for (int64_t i = 0; i < count; ++i) ord[fill[gof[i]]++] = i;
+        // longest first inside each group: tiles of 16 transforms of the batched forms then
+        // hold similar lengths, and workgroups past a tile's longest transform end at once
+        for (size_t g = 0; g < keys.size(); ++g)
+            std::stable_sort(ord.begin() + b->gstart[g], ord.begin() + b->gstart[g + 1],
+                             [&](int64_t x, int64_t y) { return n[x] > n[y]; });
     }
     const int G = (int)keys.size();
     b->order = ord;

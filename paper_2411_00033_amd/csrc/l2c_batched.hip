@@ -481,6 +481,15 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
     const int64_t Rn = a.bx * 2 + (wv >> 1);   // < 2^(groot+2): the grid is exact
     const int64_t u0 = Rn << KD;                      // first finest row node
     const LaneItem it = lane_item(a, lane);
+    // a workgroup whose rows all lie past every transform of its tile writes nothing and
+    // ends before any barrier (ragged batches order each group longest first, so tiles of
+    // short transforms skip the end of the group's padded length)
+    {
+        double nm = (double)it.n;
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) nm = fmax(nm, __shfl_xor(nm, m, 16));
+        if ((double)(2 * (int64_t)s * ((a.bx * 2) << KD)) >= nm) return;
+    }
     T *Qw = Ql[wv];
     T *in_sl = Sl[wv >> 1], *ob = Sl[wv >> 1] + 4 * SL;
 

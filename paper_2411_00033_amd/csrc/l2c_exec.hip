@@ -158,6 +158,9 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
     const int64_t item = blockIdx.y;
     const int64_t Rn = blockIdx.x;                    // subtree root, level groot
     const int64_t u0 = Rn << kd;                      // first finest row node
+    // a subtree whose rows all lie past its item's length (in a ragged batch, items shorter
+    // than the group's padded length) writes nothing: the workgroup ends before any barrier
+    if (u0 * 2 * s >= (a.item_n ? a.item_n[item] : a.n)) return;
     const int64_t P = int64_t(1) << (L + 1);
     const int gpad = near_gpad(s);                    // g: node stride s + gpad
     const int GS = s + gpad;
