@@ -277,8 +277,9 @@ def main():
                     help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-form and line-batch measurements (profiling the N=10^6 kernel alone)")
-    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch"],
-                    help="fp32_batch: only the batched FP32 form (256 x 65536), e.g. under a profiler")
+    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d"],
+                    help="fp32_batch: only the batched FP32 form (256 x 65536); lines_3d: only the "
+                         "65536 lines of n = 1024 (FP64 dense path and FP32 form); e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the transform is a single-GPU kernel path "
@@ -310,6 +311,10 @@ def main():
     if args.workload == "fp32_batch":
         rec = batched_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink, with_fp64=False)
         print(json.dumps({"workload": "fp32_batch", "steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
+        return
+    if args.workload == "lines_3d":
+        rec = lines_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)
+        print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
         return
 
     plan = l2c.Plan(N, l2c.LEG2CHEB, LEAF, RANK)
