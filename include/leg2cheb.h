@@ -76,7 +76,7 @@ enum l2c_status {
     L2C_EINVAL = -1,      /* invalid argument (null pointer, bad size, overlap, ...) */
     L2C_ENOMEM = -2,      /* device or host allocation failed */
     L2C_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
-    L2C_EUNSUPPORTED = -4 /* valid request that this build does not implement */
+    L2C_EUNSUPPORTED = -4 /* valid request that the library does not implement */
 };
 
 struct l2c_plan_info {
@@ -103,8 +103,8 @@ struct l2c_plan_info {
  *   leaf_size  side 2*s_hat of the smallest far-field submatrices (Eq. (numlevels)
  *              uses s_hat); even, 4 <= leaf_size <= 128.  The paper uses s = 32,
  *              i.e. leaf_size 64 (Sec. 5).  The effective s lies in [s_hat/2, s_hat].
- *   rank       M, number of Chebyshev modes per axis; one of the ranks this build
- *              instantiates (leg2cheb_rank_supported).  The paper uses 18.
+ *   rank       M, number of Chebyshev modes per axis; one of the ranks the library
+ *              has kernels for (leg2cheb_rank_supported).  The paper uses 18.
  * The device tables are built with kernels on the current device and stream 0;
  * the call returns after they are complete.
  * Errors: L2C_EINVAL, L2C_EUNSUPPORTED (rank), L2C_ENOMEM, L2C_EHIP.
@@ -250,7 +250,7 @@ int leg2cheb_batch_info(l2c_batch_t batch, int64_t *groups, int64_t *table_bytes
 /* Release the batch (synchronizes the device first).  NULL is a no-op. */
 int leg2cheb_batch_destroy(l2c_batch_t batch);
 
-/* Non-zero if this build instantiates kernels for rank M. */
+/* Non-zero if the library has kernels for rank M. */
 int leg2cheb_rank_supported(int rank);
 
 /*
