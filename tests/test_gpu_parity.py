@@ -195,19 +195,41 @@ def test_table1_sizes_uniform_input(l2c):
         assert e1 <= 4 * float(row[1]) and e2 <= 4 * float(row[3])
 
 
-def test_batch_matches_single_and_is_deterministic(l2c):
+@pytest.mark.parametrize("single", [None, True, False])
+def test_batch_matches_single_and_is_deterministic(l2c, single):
+    """Every path (None: the plan's default, the direct product at this size; True / False:
+    the single-launch / three-launch multipole paths) gives bit-identical results on a
+    repeat and for each item of a batch executed alone: the reduction order is fixed."""
     import torch
     n, batch = 3000, 5
     F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 7, batch=batch)
     for direction in (0, 1):
-        Z, _ = run(l2c, F, direction)
-        Z2, _ = run(l2c, F, direction)
+        Z, info = run(l2c, F, direction, single=single)
+        Z2, _ = run(l2c, F, direction, single=single)
         assert np.array_equal(Z, Z2)
         for b in range(batch):
-            zb, _ = run(l2c, F[b], direction)
+            zb, ib = run(l2c, F[b], direction, single=single)
+            assert ib["path"] == info["path"]
             assert np.array_equal(Z[b], zb)
             assert oracle.einf(zb, oracle.transform(F[b], direction)) <= TOL[(direction, 18)]
     torch.cuda.synchronize()
+
+
+def test_single_launch_is_deterministic_at_1e6(l2c):
+    """The single-launch kernel at N = 10^6 (256 workgroups exchanging tree nodes through
+    the grid-wide buffer): repeated executes of one plan, and a second plan, agree bit for
+    bit."""
+    import torch
+    n = 1_000_000
+    x = torch.from_numpy(inputs.decaying(n, 0.5, inputs.SEED_BASE + 2)).cuda()
+    with l2c.Plan(n, 0) as p, l2c.Plan(n, 0) as q:
+        assert p.info["path"] == l2c.L2C_PATH_SINGLE
+        z0 = p.execute(x)
+        zs = [p.execute(x) for _ in range(3)] + [q.execute(x)]
+        torch.cuda.synchronize()
+        assert p.status == 0 and q.status == 0
+    for z in zs:
+        assert torch.equal(z, z0)
 
 
 def test_round_trip(l2c):
