@@ -33,15 +33,17 @@ def l2c():
     return mod
 
 
-def run(l2c, f, direction, leaf=64, rank=18, single=None):
+def run(l2c, f, direction, leaf=64, rank=18, single=None, direct=None):
     """Execute through the C ABI; single=None keeps the plan's default path, True/False forces
-    the single-launch / three-launch path."""
+    the single-launch / three-launch path (Alg. 4); direct=False keeps Alg. 4 (the plan's
+    multipole path) where short transforms would take the direct product."""
     import torch
     x = torch.from_numpy(np.ascontiguousarray(f)).cuda()
     batch = 1 if x.dim() == 1 else x.shape[0]
     with l2c.Plan(f.shape[-1], direction, leaf, rank, max_batch=batch) as p:
-        if single is not None and p.info["levels"] > 0:
+        if (single is not None or direct is False) and p.info["levels"] > 0:
             p.set_direct(False)
+        if single is not None and p.info["levels"] > 0:
             p.set_single_launch(single)
         z = p.execute(x)
         torch.cuda.synchronize()
@@ -155,7 +157,8 @@ def test_paths_agree(l2c, n, direction):
 def test_parity_leaf_sizes(l2c, leaf, direction):
     n = 3001
     f = inputs.decaying(n, 0.5, inputs.SEED_BASE + 200 + leaf)
-    z, info = run(l2c, f, direction, leaf=leaf)
+    z, info = run(l2c, f, direction, leaf=leaf, direct=False)
+    assert info["levels"] == 0 or info["path"] in (l2c.L2C_PATH_SINGLE, l2c.L2C_PATH_THREE)
     err = oracle.einf(z, oracle.transform(f, direction))
     print("leaf=%d dir=%d L=%d s=%d E_inf=%.3e" % (leaf, direction, info["levels"], info["s"], err))
     assert err <= TOL[(direction, 18)] * (10 if leaf <= 8 else 1)
@@ -172,11 +175,14 @@ def test_parity_ranks(l2c, rank, direction):
     assert err <= TOL[(direction, rank)]
 
 
-def test_config1_leg2cheb_1024(l2c):
-    """N = 1024, f_j = z_j/(j+1), leaf 64, rank 18; all rows against the oracle."""
+@pytest.mark.parametrize("direct", [None, False])
+def test_config1_leg2cheb_1024(l2c, direct):
+    """N = 1024, f_j = z_j/(j+1), leaf 64, rank 18; all rows against the oracle, on the
+    plan's default path (the direct product) and on Alg. 4."""
     f = inputs.decaying(1024, 1.0, inputs.SEED_BASE + 1)
-    z, info = run(l2c, f, 0)
+    z, info = run(l2c, f, 0, direct=direct)
     assert (info["levels"], info["s"], info["n_pad"]) == (3, 32, 1024)
+    assert info["path"] == (l2c.L2C_PATH_DIRECT if direct is None else l2c.L2C_PATH_SINGLE)
     assert oracle.einf(z, oracle.leg2cheb(f)) <= 1e-13
 
 
@@ -187,8 +193,8 @@ def test_table1_sizes_uniform_input(l2c):
     for row in rows[:6]:
         n = int(row[0])
         f = inputs.uniform01(n, 1)
-        z1, _ = run(l2c, f, 0)
-        z2, _ = run(l2c, f, 1)
+        z1, _ = run(l2c, f, 0, direct=False)    # Alg. 4, the method Table 1 measures
+        z2, _ = run(l2c, f, 1, direct=False)
         e1 = oracle.einf(z1, oracle.leg2cheb(f))
         e2 = oracle.einf(z2, oracle.cheb2leg(f))
         print("N=%d L2C %.2e (paper %s)  C2L %.2e (paper %s)" % (n, e1, row[1], e2, row[3]))
@@ -261,7 +267,7 @@ def test_edge_cases(l2c):
         with pytest.raises(l2c.L2CError):
             l2c.leg2cheb_execute(p.handle, buf.data_ptr(), buf.data_ptr(), 1, 0)
     # zero input gives zero output
-    z, _ = run(l2c, np.zeros(5000), 1)
+    z, _ = run(l2c, np.zeros(5000), 1, direct=False)
     assert np.all(z == 0.0)
     torch.cuda.synchronize()
 
