@@ -179,6 +179,7 @@ void free_plan(l2c_plan_s *p)
     l2c::dev_free(p->d_bQ);
     l2c::dev_free(p->d_bw);
     l2c::dev_free(p->d_dense);
+    l2c::dev_free(p->d_dir);
     delete p;
 }
 
@@ -270,6 +271,21 @@ int ensure_bworkspace(l2c_plan_s *p, int64_t items)
         return L2C_ENOMEM;
     }
     p->bw_tiles = tiles;
+    return L2C_OK;
+}
+
+// k_direct's P and Q tables (plans with L = 0 and short FP64 plans).
+int build_direct_tables(l2c_plan_s *p, hipStream_t st)
+{
+    if (l2c::dev_alloc(&p->d_dir, (size_t)l2c::direct_table_len(p->n) * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return L2C_ENOMEM;
+    }
+    if (l2c::direct_build(*p, p->d_dir, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return L2C_EHIP;
+    }
+    p->table_bytes += l2c::direct_table_len(p->n) * (int64_t)sizeof(double);
     return L2C_OK;
 }
 
@@ -676,6 +692,13 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         }
         // short transforms: Alg. 1 row by row (the multipole tables stay available)
         p->direct_ok = n <= l2c::kDirectMaxN && max_batch <= l2c::kDirectMaxWork / (n * n);
+        if (p->direct_ok) {
+            const int rc = build_direct_tables(p, st);
+            if (rc != L2C_OK) {
+                free_plan(p);
+                return rc;
+            }
+        }
         // batches of short transforms: the direct product on the matrix cores
         if (n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
             const int64_t HP = l2c::dense_hp(n);
@@ -710,6 +733,12 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             p->fused_items = items;
         }
         const int rc = ensure_workspace(p, use_fused(p) ? std::min(max_batch, p->fused_items) : max_batch);
+        if (rc != L2C_OK) {
+            free_plan(p);
+            return rc;
+        }
+    } else {
+        const int rc = build_direct_tables(p, st);   // L = 0: Alg. 1 only
         if (rc != L2C_OK) {
             free_plan(p);
             return rc;

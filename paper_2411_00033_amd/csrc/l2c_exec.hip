@@ -468,13 +468,32 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
 // Workgroup (row block rb, parity sg) of one item: rows i = 2 i' + sg, i' in
 // [16 rb, 16 rb + 16); 16 lanes per row take j' = i' + lane, i' + lane + 16, ...
 // (j = 2 j' + sg) and a butterfly over the 16 lanes adds their partial sums.  The
-// block's g, P and Q are evaluated into LDS first: with c = j' - 16 rb, g[c] = g_{2j'+sg},
+// block's g, P and Q are staged in LDS first: with c = j' - 16 rb, g[c] = g_{2j'+sg},
 // P[c] = P_c, Q[c] = Q_{32 rb + sg + c}, and row r of the block reads P[c - r] Q[c + r] g[c].
+// P and Q come from the plan's tables (k_direct_tables), built once with the same device
+// functions that the near field uses.
 constexpr int kDirRows = 16;
+
+int64_t direct_table_len(int64_t n) { return (n + 1) / 2 + n + 17; }
+
+__global__ void k_direct_tables(double *tab, int64_t n, int dir)
+{
+    const int64_t HP = (n + 1) / 2;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < HP) tab[e] = near_P(dir, e);
+    else if (e < HP + n + 17) tab[e] = near_Q(dir, e - HP);
+}
+
+hipError_t direct_build(const l2c_plan_s &p, double *tab, hipStream_t st)
+{
+    const int64_t len = direct_table_len(p.n);
+    hipLaunchKernelGGL(k_direct_tables, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, tab, p.n, p.direction);
+    return hipGetLastError();
+}
 
 __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *out, int64_t nmax, int dir,
                                                      const int64_t *item_n, const double *const *item_in,
-                                                     double *const *item_out)
+                                                     double *const *item_out, const double *tab)
 {
     extern __shared__ double lds[];
     const int64_t HPm = (nmax + 1) / 2;
@@ -488,15 +507,16 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *o
     const double *x = item_in ? item_in[item] : in + item * nmax;
     double *y = item_out ? item_out[item] : out + item * nmax;
     const int64_t C = H - i0;                           // columns j' in [i0, H)
+    const double *Pt = tab, *Qt = tab + HPm + 2 * i0 + sg;   // Q_S for S < nmax + 17
     for (int64_t c = threadIdx.x; c < C + kDirRows; c += kThreads) {
         if (c < C) {
             const int64_t j = 2 * (i0 + c) + sg;
             double v = x[j];
             if (dir == 1) v *= (double)j;
             gl[c] = v;
-            Pl[c] = near_P(dir, c);
+            Pl[c] = Pt[c];
         }
-        Ql[c] = near_Q(dir, 2 * i0 + sg + c);
+        Ql[c] = Qt[c];
     }
     __syncthreads();
     const int r = threadIdx.x >> 4, k = threadIdx.x & 15;
@@ -521,6 +541,7 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *o
 hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
                          const ItemArrays *ia)
 {
+    if (!p.d_dir) return hipErrorInvalidValue;
     const int64_t HPm = (p.n + 1) / 2;
     const size_t lds = sizeof(double) * (size_t)(3 * HPm + kDirRows);
     if (lds > 64 * 1024)
@@ -532,7 +553,8 @@ hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int
         if (timed) (void)hipEventRecord(p.ev_before, st);
         hipLaunchKernelGGL(k_direct, dim3(blocks, (unsigned)nb), dim3(kThreads), lds, st,
                            ia ? nullptr : in + b0 * p.n, ia ? nullptr : out + b0 * p.n, p.n, p.direction,
-                           ia ? ia->n + b0 : nullptr, ia ? ia->in + b0 : nullptr, ia ? ia->out + b0 : nullptr);
+                           ia ? ia->n + b0 : nullptr, ia ? ia->in + b0 : nullptr, ia ? ia->out + b0 : nullptr,
+                           (const double *)p.d_dir);
         if (timed) (void)hipEventRecord(p.ev_after, st);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

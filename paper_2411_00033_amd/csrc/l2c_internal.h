@@ -143,6 +143,9 @@ struct l2c_plan_s {
     // work bound, unless switched off (leg2cheb_plan_set_option)
     bool direct_ok = false;
     bool direct_on = true;
+    // k_direct's factor tables: P_d for d < ceil(n/2), then Q_S for S < n + 17 (plans with
+    // L = 0, and plans with direct_ok)
+    double *d_dir = nullptr;
 };
 
 namespace l2c {
@@ -151,6 +154,8 @@ namespace l2c {
 // batch n^2 <= kDirectMaxWork: its work grows as n^2 per transform, and every workgroup
 // evaluates the lambda products of its band itself
 constexpr int64_t kDirectMaxN = 8192, kDirectMaxWork = int64_t(1) << 26;
+int64_t direct_table_len(int64_t n);
+hipError_t direct_build(const l2c_plan_s &p, double *tab, hipStream_t stream);
 hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                          const ItemArrays *ia = nullptr);
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
