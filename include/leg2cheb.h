@@ -170,9 +170,10 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
  *       each depth, and the upward vectors above the subtrees.  Value 0 selects the
  *       three-launch path.  Both paths use the same plan tables and agree to rounding.
  *   L2C_OPT_DIRECT  value 1 (default) runs short FP64 transforms (L >= 1, n <= 8192
- *       and max_batch n^2 <= 2^26) as Alg. 1, every output row one sum over its band,
- *       on many small workgroups: at these lengths a multipole launch is dominated by
- *       its dependency chain.  An execute with batch n^2 > 2^26 takes Alg. 4 instead.
+ *       and max_batch n^2 <= W, W = 2^27 for n <= 4096 and 2^26 above) as Alg. 1, every
+ *       output row one sum over its band, on many small workgroups: at these lengths a
+ *       multipole launch is dominated by its dependency chain.  An execute with
+ *       batch n^2 > W takes Alg. 4 instead.
  *       Value 0 selects Alg. 4 (the path L2C_OPT_SINGLE_LAUNCH chooses).  The plan
  *       builds the multipole tables either way.  Plans on the dense path (n <= 4096,
  *       max_batch >= 64) use it regardless.

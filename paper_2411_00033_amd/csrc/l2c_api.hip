@@ -691,7 +691,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             return L2C_OK;
         }
         // short transforms: Alg. 1 row by row (the multipole tables stay available)
-        p->direct_ok = n <= l2c::kDirectMaxN && max_batch <= l2c::kDirectMaxWork / (n * n);
+        p->direct_ok = n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n);
         if (p->direct_ok) {
             const int rc = build_direct_tables(p, st);
             if (rc != L2C_OK) {
@@ -773,7 +773,8 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
         if (l2c::launch_dense(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
     }
-    if (plan->L > 0 && plan->direct_ok && plan->direct_on && batch <= l2c::kDirectMaxWork / (plan->n * plan->n)) {
+    if (plan->L > 0 && plan->direct_ok && plan->direct_on &&
+        batch <= l2c::direct_max_work(plan->n) / (plan->n * plan->n)) {
         if (l2c::launch_direct(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
     }

@@ -138,7 +138,7 @@ struct l2c_plan_s {
     // FP64 batches of short transforms (l2c_dense.hip): per parity the dense coefficient
     // matrix of Alg. 1, [2][HP][HP]
     double *d_dense = nullptr;
-    // short FP64 transforms (n <= kDirectMaxN, max_batch n^2 <= kDirectMaxWork): Alg. 1 row
+    // short FP64 transforms (n <= kDirectMaxN, max_batch n^2 <= direct_max_work(n)): Alg. 1 row
     // by row (k_direct) instead of the multipole kernels for executes within the same
     // work bound, unless switched off (leg2cheb_plan_set_option)
     bool direct_ok = false;
@@ -151,9 +151,10 @@ struct l2c_plan_s {
 namespace l2c {
 // l2c_exec.hip
 // k_direct is faster than Alg. 4 (by measurement) while n <= kDirectMaxN and
-// batch n^2 <= kDirectMaxWork: its work grows as n^2 per transform, and every workgroup
-// evaluates the lambda products of its band itself
-constexpr int64_t kDirectMaxN = 8192, kDirectMaxWork = int64_t(1) << 26;
+// batch n^2 <= direct_max_work(n): its work grows as n^2 per transform, and above
+// n = 4096 its LDS band (3 n / 2 doubles) leaves room for one workgroup per CU
+constexpr int64_t kDirectMaxN = 8192;
+inline int64_t direct_max_work(int64_t n) { return n <= 4096 ? int64_t(1) << 27 : int64_t(1) << 26; }
 int64_t direct_table_len(int64_t n);
 hipError_t direct_build(const l2c_plan_s &p, double *tab, hipStream_t stream);
 hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,

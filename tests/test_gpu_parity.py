@@ -470,13 +470,15 @@ def test_dense_batches_of_short_transforms(l2c, n, direction):
 @pytest.mark.parametrize("n", [129, 255, 256, 257, 1000, 1024, 1025, 2049, 4096, 5000, 8191, 8192])
 @pytest.mark.parametrize("direction", [0, 1])
 def test_direct_short_transforms(l2c, n, direction):
-    """FP64 plans for n <= 8192 (L >= 1) and batch n^2 <= 2^26 apply Alg. 1 row by row:
+    """FP64 plans for n <= 8192 (L >= 1) and batch n^2 <= W (2^27 up to n = 4096, 2^26
+    above) apply Alg. 1 row by row:
     every output of a batch of up to three against the oracle (the direct product is exact
     up to rounding), the batch-1 execute of the same plan bit for bit, agreement with the
     multipole path of the same plan to the multipole tolerance, and a batch past the work
     bound that runs the multipole path."""
     import torch
-    B = max(1, min(3, (1 << 26) // (n * n)))
+    W = (1 << 27) if n <= 4096 else (1 << 26)
+    B = max(1, min(3, W // (n * n)))
     F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 70 + n % 97, batch=B)
     x = torch.from_numpy(F).cuda()
     with l2c.Plan(n, direction, 64, 18, max_batch=B) as p:
@@ -484,7 +486,7 @@ def test_direct_short_transforms(l2c, n, direction):
         Z = p.execute(x).cpu().numpy()
         z1 = p.execute(x[B - 1]).cpu().numpy()
         # a batch past the work bound runs Alg. 4: same result to the multipole tolerance
-        nb = (1 << 26) // (n * n) + 1
+        nb = W // (n * n) + 1
         xb = x[torch.arange(nb) % B].contiguous()
         Zb = p.execute(xb).cpu().numpy()
         p.set_direct(False)
