@@ -60,18 +60,24 @@ __global__ __launch_bounds__(256) void kd_dense(const double *in, double *out, i
         rn = item_n ? item_n[lit] : n;
         rowp = item_in ? item_in[lit] : in + lit * n;
     }
-    const int64_t kc0 = 4 * ob, kcN = HP / 16;     // chunks of 16 j'; j' >= i' >= 64 ob
+    const int kc0 = 4 * (int)ob, kcN = (int)(HP / 16);   // chunks of 16 j'; j' >= i' >= 64 ob
+    // this thread's D rows (one per parity), from column 4 lp on
+    const double *drow0 = D + (64 * ob + lr) * HP + 4 * lp, *drow1 = drow0 + HP * HP;
     double fv[8], dv[2][4];
-    auto load = [&](int64_t kc) {
+    auto load = [&](int kc) {
+        const int64_t j0 = 32 * kc + 8 * lp;         // both parities of j' = 16 kc + 4 lp + e/2
+        if (j0 + 8 <= rn) {                           // the whole segment inside the row
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t j = 32 * kc + 8 * lp + e;   // both parities of j' = 16 kc + 4 lp + e/2
-            fv[e] = (j < rn) ? rowp[j] : 0.0;
+            for (int e = 0; e < 8; ++e) fv[e] = rowp[j0 + e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) fv[e] = (j0 + e < rn) ? rowp[j0 + e] : 0.0;
         }
 #pragma unroll
-        for (int sg = 0; sg < 2; ++sg)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) dv[sg][e] = D[(sg * HP + 64 * ob + lr) * HP + 16 * kc + 4 * lp + e];
+        for (int e = 0; e < 4; ++e) {
+            dv[0][e] = drow0[16 * kc + e];
+            dv[1][e] = drow1[16 * kc + e];
+        }
     };
     d4v acc[2][4];
 #pragma unroll
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(256) void kd_dense(const double *in, double *out, i
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[sg][ct] = d4v{0.0, 0.0, 0.0, 0.0};
     if (kc0 < kcN) load(kc0);
-    for (int64_t kc = kc0; kc < kcN; ++kc) {
+    for (int kc = kc0; kc < kcN; ++kc) {
         __syncthreads();                            // the previous chunk's reads are done
 #pragma unroll
         for (int e = 0; e < 8; ++e) Fs[e & 1][lr][4 * lp + (e >> 1)] = fv[e];
