@@ -383,6 +383,14 @@ def main():
     torch.cuda.synchronize()
     round_trip = ((back - x).abs().max() / x.abs().max()).item()
 
+    # every wait of the single-launch kernel completed in every execute above (a wait that
+    # gave up would have made its output wrong)
+    for p_, tag in ((plan, "leg2cheb"), (plan_c, "cheb2leg")):
+        st_bits = p_.status
+        if st_bits != 0:
+            print("bench.py: the %s plan reports status bits %#x: a single-launch wait gave up, results invalid"
+                  % (tag, st_bits), file=sys.stderr)
+            sys.exit(3)
     z = out.cpu().numpy()
     ahat_alg = 8.0 * RANK * RANK * info["n_submatrices"]          # Ahat, one M x M table per submatrix
     main_alg = 16.0 * N + ahat_alg                                 # + FP64 input read and output write

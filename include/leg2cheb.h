@@ -68,7 +68,17 @@ enum l2c_path {
 /* Plan options (leg2cheb_plan_set_option). */
 enum l2c_option {
     L2C_OPT_SINGLE_LAUNCH = 1, /* 1: single-launch path when the plan allows it (default); 0: three launches */
-    L2C_OPT_DIRECT = 2         /* 1: Alg. 1 directly for short FP64 plans (default); 0: Alg. 4 */
+    L2C_OPT_DIRECT = 2,        /* 1: Alg. 1 directly for short FP64 plans (default); 0: Alg. 4 */
+    L2C_OPT_EXCHANGE_TIMEOUT_US = 3 /* bound of the single-launch path's waits for other workgroups */
+};
+
+/* Status bits of the single-launch path (leg2cheb_plan_status).  Every wait inside that
+ * kernel is bounded on the device's wall clock; one that gives up sets its bit, and the
+ * output of that execute is wrong. */
+enum l2c_status_bit {
+    L2C_STATUS_EXCHANGE = 1, /* a wait for another workgroup's exchanged tree nodes */
+    L2C_STATUS_WORKERS = 2,  /* a barrier among the waves of one workgroup */
+    L2C_STATUS_STREAM = 4    /* the far-field streaming wave waiting for its operands */
 };
 
 enum l2c_status {
@@ -129,7 +139,10 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
  *   batch    >= 0; 0 is a no-op.
  *   stream   hipStream_t.
  * Enqueues the kernels and returns.  Allocates only when batch exceeds the
- * workspace capacity.  On L2C_EHIP, out is undefined.
+ * workspace capacity.  On L2C_EHIP, out is undefined.  Returns L2C_EHIP without
+ * enqueuing anything while a status bit of an earlier, finished single-launch execute
+ * of the plan is set (its output was wrong; see leg2cheb_plan_status, which clears the
+ * bits).  The check reads host memory and does not wait for executes still running.
  */
 int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
 
@@ -177,20 +190,27 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
  *       Value 0 selects Alg. 4 (the path L2C_OPT_SINGLE_LAUNCH chooses).  The plan
  *       builds the multipole tables either way.  Plans on the dense path (n <= 4096,
  *       max_batch >= 64) use it regardless.
+ *   L2C_OPT_EXCHANGE_TIMEOUT_US  0 <= value <= 6e7 (default 1e6): how long a workgroup of
+ *       the single-launch kernel waits for tree nodes from another workgroup before it
+ *       gives up and sets L2C_STATUS_EXCHANGE.  A wait that gives up ends normally, so the
+ *       kernel still ends.  Value 0 makes every such wait give up after its first poll and
+ *       set the bit whether or not it found its values: tests use it to take this error
+ *       path on purpose.
  * Single-launch kernels of one device are ordered by the library (a launch on another
- * stream waits for the previous one), so they never compete for compute units; other
- * work may delay but not block them.  A plan must not be executed on two streams at
- * the same time.
+ * stream waits for all work enqueued so far on the stream of the previous one, which must
+ * therefore still exist), so they never compete for compute units; other work may delay
+ * but not block them.  A plan must not be executed on two streams at the same time.
  * Errors: L2C_EINVAL (plan, option or value), L2C_EUNSUPPORTED (value 1 on a plan whose
  * geometry has no single-launch form, or that is not a short FP64 plan).
  */
 int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value);
 
 /*
- * Diagnostic status of the plan's single-launch executions since it was made:
- * bit 0 = a workgroup stopped waiting for another after about a second (the
- * output of that execute is wrong).  Synchronizes the device.  *status = 0 for
- * plans without a single-launch path.
+ * Status of the plan's single-launch executes since it was made or since the last call:
+ * the l2c_status_bit bits of every wait that gave up (the output of that execute is
+ * wrong).  A wait for another workgroup gives up after L2C_OPT_EXCHANGE_TIMEOUT_US
+ * (default one second), every other wait after one second.  Synchronizes the device,
+ * then clears the bits.  *status = 0 for plans without a single-launch path.
  */
 int leg2cheb_plan_status(l2c_plan_t plan, int *status);
 
@@ -210,27 +230,55 @@ int leg2cheb_set_timing_events(l2c_plan_t plan, void *before, void *after);
 typedef struct l2c_batch_s *l2c_batch_t;
 
 /*
- * Plan a ragged batch.  Transforms with the same levels L (Eq. (numlevels)) and the same
- * direction form one group with one set of tables (the tables depend on L, s, M and the
- * kernel only): every group is planned with the full half-leaf s = leaf_size / 2, so its
- * shorter transforms only see more zero padding, and each item keeps its own length.
- * Results therefore agree with a separately planned transform (whose s may be smaller)
- * to the method's accuracy, not bit for bit.  L = 0 transforms (Alg. 1 directly) group
- * by direction.  FP64 groups execute concurrently on side streams of the batch (the
- * three-launch path, or the dense path for n <= 4096 with 64 or more items); the
- * batched forms execute all groups in one launch per kernel shape.
+ * Leaf size and rank of the transforms of a ragged batch, chosen per size bucket:
+ * bucket k covers the lengths n with buckets[k-1].n_max < n <= buckets[k].n_max, and
+ * the last bucket covers every larger n.  leaf_size and rank as in leg2cheb_plan_ex.
+ */
+struct l2c_tuning_bucket {
+    int64_t n_max;
+    int32_t leaf_size;
+    int32_t rank;
+};
+struct l2c_tuning {
+    int32_t count;                            /* 1 .. 32, n_max strictly increasing */
+    const struct l2c_tuning_bucket *buckets;  /* host array [count] */
+};
+
+/*
+ * Plan a ragged batch.  Transforms with the same size bucket, levels L (Eq. (numlevels))
+ * and direction form one group with one set of tables (the tables depend on L, s, M and
+ * the kernel only): every group is planned with its bucket's full half-leaf
+ * s = leaf_size / 2, so its shorter transforms only see more zero padding, and each item
+ * keeps its own length.  Results therefore agree with a separately planned transform
+ * (whose s may be smaller) to the method's accuracy, not bit for bit.  L = 0 transforms
+ * (Alg. 1 directly) group by bucket and direction.  FP64 groups execute concurrently on
+ * side streams of the batch (the three-launch path, or the dense path for n <= 4096 with
+ * 64 or more items); the batched forms execute all groups in one launch per kernel shape.
  *   batch      [out] receives the new handle (NULL on error).
  *   count      number of transforms, >= 1.
  *   n          host array [count], each >= 1 (lengths are not limited otherwise).
  *   direction  host array [count] of L2C_LEG2CHEB / L2C_CHEB2LEG.
- *   leaf_size, rank, precision   as in leg2cheb_plan_ex, shared by all transforms.
+ *   precision  as in leg2cheb_plan_ex, shared by all transforms.
+ *   tuning     the size buckets, or NULL for the library's own table for the precision
+ *              (made by its autotuner from timings of ragged batches; leg2cheb_batch_tuning
+ *              returns it).
  *   stream     hipStream_t for the table-building kernels (NULL = null stream).
  * The call returns after every group's tables are built.  Device memory: one plan per
  * group plus count entries of lengths and pointers.
- * Errors: L2C_EINVAL, L2C_EUNSUPPORTED (rank, precision), L2C_ENOMEM, L2C_EHIP.
+ * Errors: L2C_EINVAL (arguments, bucket order, leaf size), L2C_EUNSUPPORTED (a rank
+ * without kernels; rank > 16, leaf_size > 64 or n > 2^28 in a batched form), L2C_ENOMEM,
+ * L2C_EHIP.
  */
-int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction,
-                        int leaf_size, int rank, int precision, void *stream);
+int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction, int precision,
+                        const struct l2c_tuning *tuning, void *stream);
+
+/*
+ * The library's size buckets for a precision (the tuning used when leg2cheb_batch_plan
+ * gets NULL).  Writes min(cap, *count) buckets to buckets (host memory; may be NULL when
+ * cap is 0) and the table's length to *count.  No device call.
+ * Errors: L2C_EINVAL (precision, count NULL, cap < 0, buckets NULL with cap > 0).
+ */
+int leg2cheb_batch_tuning(int precision, struct l2c_tuning_bucket *buckets, int32_t cap, int32_t *count);
 
 /*
  * out[i][0:n[i]] = T_i(in[i][0:n[i]]) for i < count, T_i the transform of item i.
@@ -240,8 +288,9 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
  * Copies the pointer lists to the device (through pinned memory owned by the batch)
  * and enqueues every group; work on the batch's side streams is ordered after the
  * copies on stream, and stream waits for it before anything enqueued later.  Allocates
- * nothing.  A later call first waits for the previous call's pointer copy.  On
- * L2C_EHIP, the outputs are undefined.
+ * nothing.  A later call first waits on the host for the previous call's pointer copy,
+ * and orders its own work on its stream after the whole previous call (which may have
+ * used another stream).  On L2C_EHIP, the outputs are undefined.
  */
 int leg2cheb_batch_execute(l2c_batch_t batch, const double *const *in, double *const *out, void *stream);
 

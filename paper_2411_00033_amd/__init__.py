@@ -16,11 +16,12 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401  (re-exported ABI names)
     L2C_BF16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
-    L2C_LEG2CHEB, L2C_OK, L2C_OPT_DIRECT, L2C_OPT_SINGLE_LAUNCH, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_THREE, L2CError,
+    L2C_LEG2CHEB, L2C_OK, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US, L2C_OPT_SINGLE_LAUNCH,
+    L2C_STATUS_EXCHANGE, L2C_STATUS_STREAM, L2C_STATUS_WORKERS, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_THREE, L2CError,
     TABLE_AHAT, TABLE_B, TABLE_T, TABLE_W, leg2cheb_destroy, leg2cheb_execute, leg2cheb_plan, leg2cheb_plan_ex,
     leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
     leg2cheb_rank_supported, leg2cheb_debug_alloc_hook, leg2cheb_set_timing_events, leg2cheb_batch_plan, leg2cheb_batch_execute,
-    leg2cheb_batch_info, leg2cheb_batch_destroy,
+    leg2cheb_batch_info, leg2cheb_batch_destroy, leg2cheb_batch_tuning,
 )
 
 LEG2CHEB, CHEB2LEG = L2C_LEG2CHEB, L2C_CHEB2LEG
@@ -81,9 +82,14 @@ class Plan:
         """Choose the single-launch path (default when the plan allows it) or three launches."""
         leg2cheb_plan_set_option(self.handle, L2C_OPT_SINGLE_LAUNCH, 1 if on else 0)
 
+    def set_exchange_timeout_us(self, us: int) -> None:
+        """Bound of the single-launch kernel's waits for other workgroups (default 10^6 us)."""
+        leg2cheb_plan_set_option(self.handle, L2C_OPT_EXCHANGE_TIMEOUT_US, int(us))
+
     @property
     def status(self) -> int:
-        """Diagnostic bits of the single-launch path (0 = every wait completed); synchronizes."""
+        """Status bits of the single-launch path since the last query (0 = every wait
+        completed); synchronizes the device and clears the bits."""
         return leg2cheb_plan_status(self.handle)
 
     def set_timing_events(self, before, after) -> None:
@@ -113,15 +119,21 @@ class BatchPlan:
     """A ragged batch: transforms of lengths n[i] and directions direction[i], planned together
     (one table set per group of equal levels, half-leaf and direction)."""
 
-    def __init__(self, n, direction, leaf_size: int = 64, rank: int = 18, precision: int = L2C_FP64, stream=None):
+    def __init__(self, n, direction, leaf_size=None, rank=None, precision: int = L2C_FP64, tuning=None,
+                 stream=None):
+        """tuning: a list of (n_max, leaf_size, rank) size buckets; leaf_size and rank alone
+        make one bucket for every length; with neither, the library's own table is used."""
         torch = _torch()
         if len(n) != len(direction) or len(n) == 0:
             raise ValueError("n and direction must be non-empty and of equal length")
+        if tuning is None and (leaf_size is not None or rank is not None):
+            default = 18 if precision == L2C_FP64 else 16
+            tuning = [(1 << 62, 64 if leaf_size is None else leaf_size, default if rank is None else rank)]
         st = stream if stream is not None else torch.cuda.current_stream()
         self.device = torch.cuda.current_device()
         self.n = [int(v) for v in n]
         self.direction = [int(v) for v in direction]
-        self.handle = leg2cheb_batch_plan(self.n, self.direction, leaf_size, rank, precision, st.cuda_stream)
+        self.handle = leg2cheb_batch_plan(self.n, self.direction, precision, tuning, st.cuda_stream)
 
     @property
     def info(self) -> dict:

@@ -17,14 +17,15 @@ L2C_FP64, L2C_FP32, L2C_BF16X2 = 0, 1, 2
 L2C_OK, L2C_EINVAL, L2C_ENOMEM, L2C_EHIP, L2C_EUNSUPPORTED = 0, -1, -2, -3, -4
 TABLE_AHAT, TABLE_T, TABLE_B, TABLE_W = 0, 1, 2, 3
 L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE = 0, 1, 2, 3, 4
-L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT = 1, 2
+L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US = 1, 2, 3
+L2C_STATUS_EXCHANGE, L2C_STATUS_WORKERS, L2C_STATUS_STREAM = 1, 2, 4
 
 EXPORTED = (
     "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_destroy", "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
     "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
-    "leg2cheb_debug_alloc_hook",
+    "leg2cheb_batch_tuning", "leg2cheb_debug_alloc_hook",
 )
 
 
@@ -39,6 +40,14 @@ class PlanInfo(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuningBucket(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int64), ("leaf_size", ctypes.c_int32), ("rank", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("buckets", ctypes.POINTER(TuningBucket))]
 
 
 class L2CError(RuntimeError):
@@ -72,8 +81,10 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_rank_supported.argtypes = [ci]
     lib.leg2cheb_strerror.argtypes = [ci]
     lib.leg2cheb_strerror.restype = ctypes.c_char_p
-    lib.leg2cheb_batch_plan.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(i64), ctypes.POINTER(ci), ci, ci, ci,
-                                        vp]
+    lib.leg2cheb_batch_plan.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(i64), ctypes.POINTER(ci), ci,
+                                        ctypes.POINTER(Tuning), vp]
+    lib.leg2cheb_batch_tuning.argtypes = [ci, ctypes.POINTER(TuningBucket), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
     lib.leg2cheb_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.leg2cheb_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.leg2cheb_batch_destroy.argtypes = [vp]
@@ -163,15 +174,35 @@ def leg2cheb_debug_alloc_hook(fail_at: int = -1):
     return pend.value, live.value
 
 
-def leg2cheb_batch_plan(n, direction, leaf_size: int = 64, rank: int = 18, precision: int = L2C_FP64,
-                        stream: int = 0) -> int:
+def _tuning(tuning):
+    """(n_max, leaf_size, rank) triples -> a Tuning struct (kept alive by the caller)."""
+    rows = [(int(a), int(b), int(c)) for a, b, c in tuning]
+    arr = (TuningBucket * max(len(rows), 1))(*[TuningBucket(*r) for r in rows])
+    return Tuning(len(rows), arr), arr
+
+
+def leg2cheb_batch_plan(n, direction, precision: int = L2C_FP64, tuning=None, stream: int = 0) -> int:
+    """tuning: None (the library's table) or a list of (n_max, leaf_size, rank) size buckets."""
     count = len(n)
     na = (ctypes.c_int64 * count)(*[int(v) for v in n])
     da = (ctypes.c_int * count)(*[int(v) for v in direction])
     h = ctypes.c_void_p()
-    _check(load().leg2cheb_batch_plan(ctypes.byref(h), count, na, da, int(leaf_size), int(rank), int(precision),
+    tp = None
+    if tuning is not None:
+        t, keep = _tuning(tuning)
+        tp = ctypes.byref(t)
+    _check(load().leg2cheb_batch_plan(ctypes.byref(h), count, na, da, int(precision), tp,
                                       ctypes.c_void_p(stream or None)), "leg2cheb_batch_plan")
     return h.value
+
+
+def leg2cheb_batch_tuning(precision: int = L2C_FP64):
+    """The library's size buckets for the precision, as (n_max, leaf_size, rank) triples."""
+    cnt = ctypes.c_int32(0)
+    _check(load().leg2cheb_batch_tuning(int(precision), None, 0, ctypes.byref(cnt)), "leg2cheb_batch_tuning")
+    arr = (TuningBucket * max(cnt.value, 1))()
+    _check(load().leg2cheb_batch_tuning(int(precision), arr, cnt.value, ctypes.byref(cnt)), "leg2cheb_batch_tuning")
+    return [(arr[k].n_max, arr[k].leaf_size, arr[k].rank) for k in range(cnt.value)]
 
 
 def leg2cheb_batch_execute(batch: int, in_ptrs, out_ptrs, stream: int = 0) -> None:

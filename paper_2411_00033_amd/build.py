@@ -1,6 +1,11 @@
-"""Compile the HIP library libleg2cheb.so in-tree for gfx950 (hipcc)."""
+"""Compile the HIP library libleg2cheb.so in-tree for gfx950 (hipcc).
+
+Each source is compiled to an object in parallel (`_build/`), then the objects are
+linked into the shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -9,10 +14,11 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libleg2cheb.so")
+OBJ = os.path.join(PKG, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off in every device build
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -23,19 +29,37 @@ def sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompile (the build check must exercise the compiler)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(ln for ln in res.stdout.splitlines() if "packed-fp32-ops" not in ln)
-    if res.returncode != 0:
+    return res.returncode, out
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Always recompile (the build check must exercise the compiler)."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
+    cmds = [[HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", s, "-o", o] for s, o in zip(srcs, objs)]
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 16)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), cmds))
+    failed = False
+    for (rc, out), src in zip(results, srcs):
+        if rc != 0:
+            sys.stderr.write(out + "\n")
+            failed = True
+        elif verbose and out.strip():
+            print(out)
+    if failed:
+        raise RuntimeError("hipcc failed")
+    tmp = LIB + ".tmp%d" % os.getpid()
+    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    if rc != 0:
         sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed (%d)" % res.returncode)
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError("hipcc link failed (%d)" % rc)
     os.replace(tmp, LIB)
     return LIB
 

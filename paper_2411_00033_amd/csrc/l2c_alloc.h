@@ -17,7 +17,7 @@ hipError_t dev_alloc(T **ptr, size_t bytes)
     return dev_alloc_raw((void **)ptr, bytes);
 }
 void dev_free(const void *ptr);
-hipError_t host_alloc(void **ptr, size_t bytes);
+hipError_t host_alloc(void **ptr, size_t bytes, unsigned flags = hipHostMallocDefault);
 void host_free(void *ptr);
 
 }  // namespace l2c

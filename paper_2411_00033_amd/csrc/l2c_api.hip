@@ -1,5 +1,6 @@
-// l2c_api.hip -- C ABI (include/leg2cheb.h): argument checking, plan sizes and host-side
-// constant tables, device memory ownership, and dispatch to the kernels.
+// l2c_api.hip -- C ABI (include/leg2cheb.h): argument checking, plan sizes, the exact
+// B(0), B(1) of the upward and downward transfers (the other plan tables are built on the
+// device), device memory ownership, and dispatch to the kernels.
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -13,6 +14,7 @@
 #include "l2c_internal.h"
 #include "l2c_batched.h"
 #include "l2c_math.h"
+#include "l2c_tuning_table.h"
 
 namespace l2c {
 
@@ -45,11 +47,11 @@ void dev_free(const void *ptr)
     --g_live;
 }
 
-hipError_t host_alloc(void **ptr, size_t bytes)
+hipError_t host_alloc(void **ptr, size_t bytes, unsigned flags)
 {
     *ptr = nullptr;
     if (injected_failure()) return hipErrorOutOfMemory;
-    const hipError_t e = hipHostMalloc(ptr, bytes, hipHostMallocDefault);
+    const hipError_t e = hipHostMalloc(ptr, bytes, flags);
     if (e != hipSuccess) *ptr = nullptr;
     else if (*ptr) ++g_live;
     return e;
@@ -119,35 +121,6 @@ void b_matrices(int M, std::vector<double> &B)
     }
 }
 
-// T(sigma)_{mk} = T_k(-1 + (2m + sigma)/s), Eq. (Xs); three-term recurrence.
-void vandermonde(int s, int M, std::vector<double> &T)
-{
-    T.assign((size_t)2 * s * M, 0.0);
-    for (int sig = 0; sig < 2; ++sig)
-        for (int m = 0; m < s; ++m) {
-            const double X = -1.0 + (double)(2 * m + sig) / (double)s;
-            double t0 = 1.0, t1 = X;
-            for (int k = 0; k < M; ++k) {
-                T[((size_t)sig * s + m) * M + k] = t0;
-                const double t2 = 2.0 * X * t1 - t0;
-                t0 = t1;
-                t1 = t2;
-            }
-        }
-}
-
-// Near-field factor table (the same P_d as the near-field kernels use, Eq. (Lxymod) for
-// cheb2leg): l2c::kPLead leading zeros, then P_d for d = 0, 1, ...
-void near_p_table(int s, int dir, std::vector<double> &P)
-{
-    P.assign((size_t)l2c::p_table_len(s), 0.0);
-    for (int e = l2c::kPLead; e < (int)P.size(); ++e) {
-        const int d = e - l2c::kPLead;
-        const double lam = l2c::lambda_int(d);
-        P[e] = dir == 0 ? lam : lam / (1.0 - 2.0 * (double)d);
-    }
-}
-
 bool rank_supported(int M)
 {
     switch (M) {
@@ -171,7 +144,7 @@ void free_plan(l2c_plan_s *p)
     l2c::dev_free(p->d_D);
     l2c::dev_free(p->d_w);
     l2c::dev_free(p->d_pub);
-    l2c::dev_free(p->d_status);
+    l2c::host_free(p->h_status);
     l2c::dev_free(p->d_bA);
     l2c::dev_free(p->d_bT);
     l2c::dev_free(p->d_bB);
@@ -184,6 +157,18 @@ void free_plan(l2c_plan_s *p)
 }
 
 bool use_fused(const l2c_plan_s *p) { return p->fused_ok && p->fused_on; }
+
+// Status words of the plan's single-launch executes that have ended, as bits (word k ->
+// bit k).  A plain read of pinned host memory: it does not wait for running kernels.
+int status_bits(const l2c_plan_s *p)
+{
+    if (!p->h_status) return 0;
+    const volatile int *w = p->h_status;
+    int bits = 0;
+    for (int k = 0; k < l2c::kStatusWords; ++k)
+        if (w[k] != 0) bits |= 1 << k;
+    return bits;
+}
 bool batched_form(int precision) { return precision == L2C_FP32 || precision == L2C_BF16X2; }
 bool use_batched(const l2c_plan_s *p) { return p->L > 0 && batched_form(p->precision); }
 size_t elem_bytes(const l2c_plan_s *p) { return batched_form(p->precision) ? sizeof(float) : sizeof(double); }
@@ -202,6 +187,8 @@ struct l2c_batch_s {
     double **d_out = nullptr;               // [count] output pointers, in position order
     void *h_stage = nullptr;                // pinned [2][count] pointers for the copies
     hipEvent_t staged = nullptr;            // the last pointer copy
+    hipEvent_t done = nullptr;              // the end of the last execute on its stream
+    bool any = false;                       // done has been recorded
     // groups run concurrently on side streams (default priority), forked from and joined
     // back into the caller's stream; group g runs on side stream lane[g] (balanced by work)
     static constexpr int kSide = 4;
@@ -222,6 +209,7 @@ void free_batch(l2c_batch_s *b)
     l2c::dev_free(b->d_out);
     l2c::host_free(b->h_stage);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->done) (void)hipEventDestroy(b->done);
     l2c::batched_grouped_free(b->grouped);
     if (b->fork) (void)hipEventDestroy(b->fork);
     for (int k = 0; k < l2c_batch_s::kSide; ++k) {
@@ -289,28 +277,27 @@ int build_direct_tables(l2c_plan_s *p, hipStream_t st)
     return L2C_OK;
 }
 
-// Tables of the batched form from the FP64 plan tables, then the FP64 Ahat is released.
-int build_batched_tables(l2c_plan_s *p, const std::vector<double> &T, const std::vector<double> &B,
-                         const std::vector<double> &Ptab, hipStream_t st)
+// Tables of the batched form from the FP64 plan tables (rounded once to FP32 on the
+// device), then the FP64 Ahat is released.
+int build_batched_tables(l2c_plan_s *p, hipStream_t st)
 {
     const int M = p->M, s = p->s;
     const int64_t blocks = l2c::level_block_offset(p->L);
     const int64_t qlen = p->n_pad + 2 * (int64_t)s;
-    std::vector<float> t32(T.begin(), T.end()), b32(B.begin(), B.begin() + (size_t)M * M), p32(2 * (size_t)s);
-    for (int d = 0; d < 2 * s; ++d) p32[d] = (float)Ptab[l2c::kPLead + d];
+    const int64_t nT = 2 * (int64_t)s * M, nB = (int64_t)M * M, nP = 2 * (int64_t)s;
     const size_t eb = elem_bytes(p);
     bool ok = l2c::dev_alloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
               l2c::dev_alloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bT, t32.size() * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bB, b32.size() * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bP, p32.size() * eb) == hipSuccess;
+              l2c::dev_alloc(&p->d_bT, nT * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bB, nB * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bP, nP * eb) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         return L2C_ENOMEM;
     }
-    ok = hipMemcpyAsync(p->d_bT, t32.data(), t32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
-         hipMemcpyAsync(p->d_bB, b32.data(), b32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
-         hipMemcpyAsync(p->d_bP, p32.data(), p32.size() * eb, hipMemcpyHostToDevice, st) == hipSuccess &&
+    ok = l2c::launch_to_f32(p->d_T, (float *)p->d_bT, nT, st) == hipSuccess &&
+         l2c::launch_to_f32(p->d_B, (float *)p->d_bB, nB, st) == hipSuccess &&
+         l2c::launch_to_f32(p->d_P + l2c::kPLead, (float *)p->d_bP, nP, st) == hipSuccess &&
          l2c::batched_build_tables(*p, p->d_bA, p->d_bQ, qlen, st) == hipSuccess &&
          hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
@@ -322,8 +309,8 @@ int build_batched_tables(l2c_plan_s *p, const std::vector<double> &T, const std:
     p->d_top = p->d_bot = nullptr;
     p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
     p->bot_bytes = 0;
-    p->table_bytes = p->top_bytes + (int64_t)(qlen + t32.size() + b32.size() + p32.size()) * (int64_t)eb +
-                     (int64_t)(T.size() + B.size() + Ptab.size() + 2 * M + M * M) * 8;
+    p->table_bytes = p->top_bytes + (qlen + nT + nB + nP) * (int64_t)eb +
+                     (nT + 2 * nB + l2c::p_table_len(s) + M + nB) * 8;
     return L2C_OK;
 }
 
@@ -343,18 +330,45 @@ const char *leg2cheb_strerror(int code)
     }
 }
 
-int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction,
-                        int leaf_size, int rank, int precision, void *stream)
+int leg2cheb_batch_tuning(int precision, struct l2c_tuning_bucket *buckets, int32_t cap, int32_t *count)
+{
+    if (!count || cap < 0 || (cap > 0 && !buckets)) return L2C_EINVAL;
+    if (precision != L2C_FP64 && !batched_form(precision)) return L2C_EINVAL;
+    const l2c::TuneRow *rows = nullptr;
+    const int nr = l2c::builtin_tuning(precision, &rows);
+    *count = nr;
+    for (int k = 0; k < nr && k < cap; ++k) buckets[k] = {rows[k].n_max, rows[k].leaf_size, rows[k].rank};
+    return L2C_OK;
+}
+
+int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, const int *direction, int precision,
+                        const struct l2c_tuning *tuning, void *stream)
 {
     if (!batch) return L2C_EINVAL;
     *batch = nullptr;
     if (count < 1 || !n || !direction) return L2C_EINVAL;
     for (int64_t i = 0; i < count; ++i)
         if (n[i] < 1 || (direction[i] != L2C_LEG2CHEB && direction[i] != L2C_CHEB2LEG)) return L2C_EINVAL;
-    if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1)) return L2C_EINVAL;
     if (precision != L2C_FP64 && !batched_form(precision)) return L2C_EINVAL;
-    if (!leg2cheb_rank_supported(rank)) return L2C_EUNSUPPORTED;
-    if (batched_form(precision) && (rank > 16 || leaf_size > 64)) return L2C_EUNSUPPORTED;
+    // size buckets: the caller's, or the library's table for the precision
+    std::vector<l2c_tuning_bucket> bk;
+    if (tuning) {
+        if (tuning->count < 1 || tuning->count > 32 || !tuning->buckets) return L2C_EINVAL;
+        bk.assign(tuning->buckets, tuning->buckets + tuning->count);
+    } else {
+        const l2c::TuneRow *rows = nullptr;
+        const int nr = l2c::builtin_tuning(precision, &rows);
+        for (int k = 0; k < nr; ++k) bk.push_back({rows[k].n_max, rows[k].leaf_size, rows[k].rank});
+    }
+    for (size_t k = 0; k < bk.size(); ++k) {
+        if (k > 0 && bk[k].n_max <= bk[k - 1].n_max) return L2C_EINVAL;
+        if (bk[k].leaf_size < 4 || bk[k].leaf_size > 128 || (bk[k].leaf_size & 1)) return L2C_EINVAL;
+        if (bk[k].rank < 1 || bk[k].rank > 32) return L2C_EINVAL;
+    }
+    for (const auto &b : bk) {
+        if (!leg2cheb_rank_supported(b.rank)) return L2C_EUNSUPPORTED;
+        if (batched_form(precision) && (b.rank > 16 || b.leaf_size > 64)) return L2C_EUNSUPPORTED;
+    }
     if (batched_form(precision))
         for (int64_t i = 0; i < count; ++i)
             if (n[i] > (int64_t(1) << 28)) return L2C_EUNSUPPORTED;
@@ -365,32 +379,35 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         return L2C_EHIP;
     }
     b->count = count;
-    // Groups: one per (L, direction); L = 0 transforms form one group per direction.  Every
-    // group is planned with the full half-leaf s = leaf/2 (the same L as Eq. (numlevels)
-    // gives, with more padding), so that few groups cover the batch and the batched forms
-    // fill their 16-transform tiles.
+    // Groups: one per (bucket, L, direction); L = 0 transforms form one group per bucket and
+    // direction.  Every group is planned with its bucket's full half-leaf s = leaf/2 (the same
+    // L as Eq. (numlevels) gives, with more padding), so that few groups cover the batch and
+    // the batched forms fill their 16-transform tiles.
     struct Key {
-        int L, s, dir;
+        int bucket, L, s, dir;
     };
-    std::vector<int> Ls(count), Ss(count);
+    std::vector<int> Ls(count), Ss(count), Bs(count);
     for (int64_t i = 0; i < count; ++i) {
+        int k = 0;
+        while (k + 1 < (int)bk.size() && n[i] > bk[k].n_max) ++k;
+        Bs[i] = k;
         int64_t np;
-        plan_sizes(n[i], leaf_size, &Ls[i], &Ss[i], &np);
+        plan_sizes(n[i], bk[k].leaf_size, &Ls[i], &Ss[i], &np);
+        Ss[i] = Ls[i] > 0 ? bk[k].leaf_size / 2 : 0;   // full half-leaf
     }
     std::vector<Key> keys;
     std::vector<int64_t> ord(count);
-    for (int64_t i = 0; i < count; ++i) Ss[i] = Ls[i] > 0 ? leaf_size / 2 : 0;   // full half-leaf
     {
         std::vector<int> gof(count);
         for (int64_t i = 0; i < count; ++i) {
             int g = -1;
             for (size_t k = 0; k < keys.size(); ++k)
-                if (keys[k].L == Ls[i] && keys[k].s == Ss[i] && keys[k].dir == direction[i]) {
+                if (keys[k].bucket == Bs[i] && keys[k].L == Ls[i] && keys[k].s == Ss[i] && keys[k].dir == direction[i]) {
                     g = (int)k;
                     break;
                 }
             if (g < 0) {
-                keys.push_back({Ls[i], Ss[i], direction[i]});
+                keys.push_back({Bs[i], Ls[i], Ss[i], direction[i]});
                 g = (int)keys.size() - 1;
             }
             gof[i] = g;
@@ -416,7 +433,8 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         for (int64_t k = b->gstart[g]; k < b->gstart[g + 1]; ++k) nmax = std::max(nmax, nord[k]);
         l2c_plan_t pl = nullptr;
         const int64_t items = b->gstart[g + 1] - b->gstart[g];
-        rc = plan_impl(&pl, nmax, keys[g].dir, leaf_size, rank, precision, items, stream, true);
+        const l2c_tuning_bucket &tb = bk[keys[g].bucket];
+        rc = plan_impl(&pl, nmax, keys[g].dir, tb.leaf_size, tb.rank, precision, items, stream, true);
         if (rc == L2C_OK) {
             b->plans.push_back(pl);
             // groups run side by side: FP64 groups use the three-launch path
@@ -433,7 +451,9 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
         rc = L2C_ENOMEM;
     if (rc == L2C_OK && hipMemcpy(b->d_n, nord.data(), (size_t)count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
         rc = L2C_EHIP;
-    if (rc == L2C_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) rc = L2C_EHIP;
+    if (rc == L2C_OK && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess))
+        rc = L2C_EHIP;
     for (int k = 0; k < l2c_batch_s::kSide && rc == L2C_OK; ++k)
         if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess)
@@ -499,6 +519,9 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
     }
     hipStream_t st = (hipStream_t)stream;
     if (hipEventSynchronize(b->staged) != hipSuccess) return L2C_EHIP;   // previous pointer copy done
+    // the previous execute (possibly on another stream) still reads the device pointer
+    // lists and the group workspaces until it ends: this one starts after it
+    if (b->any && hipStreamWaitEvent(st, b->done, 0) != hipSuccess) return L2C_EHIP;
     const double **si = (const double **)b->h_stage;
     double **so = (double **)b->h_stage + b->count;
     for (int64_t k = 0; k < b->count; ++k) {
@@ -519,7 +542,10 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
             const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
             if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
         }
-        return l2c::batched_grouped_launch(b->grouped, st) == hipSuccess ? L2C_OK : L2C_EHIP;
+        if (l2c::batched_grouped_launch(b->grouped, st) != hipSuccess || hipEventRecord(b->done, st) != hipSuccess)
+            return L2C_EHIP;
+        b->any = true;
+        return L2C_OK;
     }
     for (int k = 0; k < l2c_batch_s::kSide; ++k)
         if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) return L2C_EHIP;
@@ -546,6 +572,8 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
     for (int k = 0; k < l2c_batch_s::kSide; ++k)
         if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess || hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess)
             return L2C_EHIP;
+    if (hipEventRecord(b->done, st) != hipSuccess) return L2C_EHIP;
+    b->any = true;
     return L2C_OK;
 }
 
@@ -646,33 +674,27 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         p->top_bytes = top_blocks * 3 * M * M * (int64_t)sizeof(double);
         p->bot_bytes = (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
 
-        std::vector<double> T, B, Ptab, XG(M), Dm((size_t)M * M);
-        vandermonde(s, M, T);
+        // B(0), B(1) on the host (exact dyadic rationals); T, P, the Chebyshev-Gauss points,
+        // the DCT matrix and Ahat on the device
+        std::vector<double> B;
         b_matrices(M, B);
-        near_p_table(s, direction, Ptab);
-        for (int m = 0; m < M; ++m) XG[m] = std::cos((m + 0.5) * M_PI / M);
-        for (int k = 0; k < M; ++k)
-            for (int m = 0; m < M; ++m) Dm[(size_t)k * M + m] = std::cos(k * (m + 0.5) * M_PI / M);
+        const int64_t nT = 2 * (int64_t)s * M, nP = l2c::p_table_len(s);
 
         bool ok = l2c::dev_alloc(&p->d_top, p->top_bytes) == hipSuccess &&
                   (p->bot_bytes == 0 || l2c::dev_alloc(&p->d_bot, p->bot_bytes) == hipSuccess) &&
-                  l2c::dev_alloc(&p->d_T, T.size() * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_T, nT * sizeof(double)) == hipSuccess &&
                   l2c::dev_alloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
-                  l2c::dev_alloc(&p->d_P, Ptab.size() * sizeof(double)) == hipSuccess &&
-                  l2c::dev_alloc(&p->d_XG, XG.size() * sizeof(double)) == hipSuccess &&
-                  l2c::dev_alloc(&p->d_D, Dm.size() * sizeof(double)) == hipSuccess;
+                  l2c::dev_alloc(&p->d_P, nP * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_XG, M * sizeof(double)) == hipSuccess &&
+                  l2c::dev_alloc(&p->d_D, (size_t)M * M * sizeof(double)) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);
             return L2C_ENOMEM;
         }
-        p->table_bytes =
-            p->top_bytes + p->bot_bytes + (int64_t)(T.size() + B.size() + Ptab.size() + XG.size() + Dm.size()) * 8;
-        ok = hipMemcpyAsync(p->d_T, T.data(), T.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_P, Ptab.data(), Ptab.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_XG, XG.data(), XG.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_D, Dm.data(), Dm.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+        p->table_bytes = p->top_bytes + p->bot_bytes + (nT + (int64_t)B.size() + nP + M + (int64_t)M * M) * 8;
+        ok = hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
+             l2c::launch_build_small(*p, st) == hipSuccess &&
              (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
              l2c::launch_build_ahat(*p, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
         if (!ok) {
@@ -681,7 +703,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             return L2C_EHIP;
         }
         if (batched_form(precision)) {
-            int rc = build_batched_tables(p, T, B, Ptab, st);
+            int rc = build_batched_tables(p, st);
             if (rc == L2C_OK) rc = ensure_bworkspace(p, max_batch);
             if (rc != L2C_OK) {
                 free_plan(p);
@@ -721,13 +743,23 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             // both halves of the exchange buffer start out "not written"
             const size_t pwords = (size_t)2 * items * p->geo.NX * 2 * p->M * 2;
             ok = l2c::dev_alloc(&p->d_pub, pwords * 4) == hipSuccess &&
-                 l2c::dev_alloc(&p->d_status, sizeof(int)) == hipSuccess &&
-                 hipMemsetD32Async((hipDeviceptr_t)p->d_pub, (int)l2c::kPubEmptyHalf, pwords, st) == hipSuccess &&
-                 hipMemsetAsync(p->d_status, 0, sizeof(int), st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+                 l2c::host_alloc((void **)&p->h_status, l2c::kStatusWords * sizeof(int),
+                                 hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
             if (!ok) {
                 (void)hipGetLastError();
                 free_plan(p);
                 return L2C_ENOMEM;
+            }
+            std::memset(p->h_status, 0, l2c::kStatusWords * sizeof(int));
+            ok = hipHostGetDevicePointer((void **)&p->d_status, p->h_status, 0) == hipSuccess &&
+                 hipDeviceGetAttribute(&p->clock_khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess &&
+                 p->clock_khz > 0 &&
+                 hipMemsetD32Async((hipDeviceptr_t)p->d_pub, (int)l2c::kPubEmptyHalf, pwords, st) == hipSuccess &&
+                 hipStreamSynchronize(st) == hipSuccess;
+            if (!ok) {
+                (void)hipGetLastError();
+                free_plan(p);
+                return L2C_EHIP;
             }
             p->fused_ok = true;
             p->fused_items = items;
@@ -769,6 +801,7 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
     if (dev != plan->device) return L2C_EINVAL;
+    if (status_bits(plan) != 0) return L2C_EHIP;   // an earlier single-launch execute gave up a wait
     if (plan->d_dense) {
         if (l2c::launch_dense(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
@@ -877,6 +910,10 @@ int leg2cheb_plan_set_option(l2c_plan_t plan, int option, int64_t value)
         if (value == 1 && !plan->direct_ok) return L2C_EUNSUPPORTED;
         plan->direct_on = value == 1;
         return L2C_OK;
+    case L2C_OPT_EXCHANGE_TIMEOUT_US:
+        if (value < 0 || value > 60000000) return L2C_EINVAL;
+        plan->poll_us = value;
+        return L2C_OK;
     default: return L2C_EINVAL;
     }
 }
@@ -885,9 +922,11 @@ int leg2cheb_plan_status(l2c_plan_t plan, int *status)
 {
     if (!plan || !status) return L2C_EINVAL;
     *status = 0;
-    if (!plan->d_status) return L2C_OK;
+    if (!plan->h_status) return L2C_OK;
     if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
-    if (hipMemcpy(status, plan->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return L2C_EHIP;
+    *status = status_bits(plan);
+    volatile int *w = plan->h_status;
+    for (int k = 0; k < l2c::kStatusWords; ++k) w[k] = 0;
     return L2C_OK;
 }
 

@@ -24,6 +24,29 @@ namespace l2c {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// A bounded wait, timed on the device's constant-rate wall clock: expired() is false
+// until `ticks` have passed since its first call.  A wait loop reads the clock only every
+// few polls, so a bound of 0 gives up after a handful of polls.
+struct WaitClock {
+    uint64_t end = 0;
+    __device__ __forceinline__ bool expired(uint64_t ticks)
+    {
+        const uint64_t now = wall_clock64();
+        if (end == 0) {
+            end = now + ticks + 1;
+            return false;
+        }
+        return now >= end;
+    }
+};
+
+// Status word `word` of a single-launch execute set to 1 (a vector store to host-mapped
+// memory, visible to the host once the kernel has ended).
+__device__ __forceinline__ void raise_status(int *status, int word)
+{
+    __hip_atomic_store(status + word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Copy count doubles from global memory to LDS.  The loads of each round are issued
 // together (U per thread) before any is waited for, so a round costs one memory
 // latency instead of U.

@@ -15,6 +15,8 @@
 //           Eq. (step5), the near-diagonal direct part of step (6), the scaling of
 //           step (7), and the output.  Nothing but w crosses kernel boundaries.
 // Plans with L = 0, and short transforms, use k_direct (Alg. 1 for every row).
+#include <mutex>
+
 #include "l2c_device.h"
 
 namespace l2c {
@@ -544,8 +546,14 @@ hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int
     if (!p.d_dir) return hipErrorInvalidValue;
     const int64_t HPm = (p.n + 1) / 2;
     const size_t lds = sizeof(double) * (size_t)(3 * HPm + kDirRows);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (lds > 64 * 1024) {
+        static std::once_flag attr_once;
+        static hipError_t attr_err = hipSuccess;
+        std::call_once(attr_once, [] {
+            attr_err = hipFuncSetAttribute((const void *)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        });
+        if (attr_err != hipSuccess) return attr_err;
+    }
     const unsigned blocks = (unsigned)(2 * ((HPm + kDirRows - 1) / kDirRows));
     for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
         const int64_t nb = batch - b0 < kMaxItemsPerLaunch ? batch - b0 : kMaxItemsPerLaunch;
@@ -601,12 +609,16 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
     a.ahat_bot = p.d_bot;
     const int64_t P = int64_t(1) << (G.L + 1);
     const size_t up_lds = up_lds_bytes(G), main_lds = main_lds_bytes(G);
-    static bool attr_set = false;   // allow the full 160 KiB LDS of a gfx950 CU
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_up<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute((const void *)k_main<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    // allow the full 160 KiB LDS of a gfx950 CU (once per process and rank; the result is kept)
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] {
+        attr_err = hipFuncSetAttribute((const void *)k_up<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (attr_err == hipSuccess)
+            attr_err =
+                hipFuncSetAttribute((const void *)k_main<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
     for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
         ExecArgs c = a;
         c.batch = batch - b0 < kMaxItemsPerLaunch ? batch - b0 : kMaxItemsPerLaunch;

@@ -31,10 +31,13 @@
 //   (step (4)).  Workers synchronise through LDS counters, streamers poll LDS flags;
 //   there is no hardware barrier between the first and the last phase.
 //   Then all waves: step (4) inside the unit, steps (5) and (7), and the output.
-// A wait that never completes (another kernel holding CUs forever) gives up after
-// kSpinLimit polls and sets a status bit; the launch then ends with a wrong result
-// instead of hanging.  The host keeps single-launch kernels of different streams from
-// overlapping, so every workgroup of a launch becomes resident.
+// Every wait is bounded on the device's wall clock: one that never completes (another
+// kernel holding CUs forever) gives up and sets a status word, and the launch then ends
+// with a wrong result instead of hanging; the host reports the word (the next execute of
+// the plan returns an error).  The waits for other workgroups have a bound of their own
+// that the host can lower, which tests use to force this path.  The host keeps
+// single-launch kernels of different streams from overlapping, so every workgroup of a
+// launch becomes resident.
 #include <mutex>
 
 #include "l2c_device.h"
@@ -65,17 +68,17 @@ __device__ __forceinline__ void wave_lds_done()
 }
 
 // Barrier of the worker waves only (LDS counter; target is this wave's running count).
-__device__ __forceinline__ void worker_sync(unsigned *cnt, unsigned &target, int *status)
+__device__ __forceinline__ void worker_sync(unsigned *cnt, unsigned &target, const ExecArgs &a)
 {
     wave_lds_done();
     target += kWorkWaves;
     if ((threadIdx.x & 63) == 0) {
         __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        int it = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+        WaitClock wc;
+        for (int it = 1; __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target; ++it) {
             __builtin_amdgcn_s_sleep(1);
-            if (++it == kSpinLimit) {
-                atomicOr(status, 2);
+            if ((it & 15) == 0 && wc.expired(a.wait_ticks)) {
+                raise_status(a.status, kStatusWorkers);
                 break;
             }
         }
@@ -103,9 +106,9 @@ __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 // (depth d, index i): c(2i)[k] = Ahat(.,0)[k,:] w(2i+2) + Ahat(.,1)[k,:] w(2i+3),
 // c(2i+1)[k] = Ahat(.,2)[k,:] w(2i+3), both parities.
 template <int M, bool REFILL>
-__device__ __forceinline__ void stream_group(int grp, int nxt, const double2 *sub, const double *wl, double *cown,
-                                             double *dummy, int kd, int nslots, int lane, const unsigned *rdy,
-                                             const unsigned *nbr,
+__device__ __forceinline__ void stream_group(const ExecArgs &ea, int grp, int nxt, const double2 *sub, const double *wl,
+                                             double *cown, double *dummy, int kd, int nslots, int lane,
+                                             const unsigned *rdy, const unsigned *nbr,
                                              double2 (&t0)[M / 2], double2 (&t1)[M / 2], double2 (&t2)[M / 2])
 {
     constexpr int NCH = 3 * M / 2, NC3 = M / 2, NS = lds_ns<M>();
@@ -116,9 +119,15 @@ __device__ __forceinline__ void stream_group(int grp, int nxt, const double2 *su
     slot_depth(j, kd, d, i);
     int dlo, ilo;                                     // coarsest depth in the group
     slot_depth(min(grp * 64 + 63, nslots - 1) / M, kd, dlo, ilo);
-    for (int it = 0; it < kSpinLimit; ++it) {
-        if (lds_flag_get(rdy) <= (unsigned)dlo && (dlo == kd || lds_flag_get(nbr) != 0)) break;
-        __builtin_amdgcn_s_sleep(1);
+    {
+        WaitClock wc;
+        for (int it = 1; !(lds_flag_get(rdy) <= (unsigned)dlo && (dlo == kd || lds_flag_get(nbr) != 0)); ++it) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((it & 15) == 0 && wc.expired(ea.wait_ticks)) {
+                raise_status(ea.status, kStatusStream);
+                break;
+            }
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const double *wa = wl + (fused_wofs(d) + 2 * i + 2) * NS;   // w(2i+2); w(2i+3) follows
@@ -198,23 +207,25 @@ __device__ __forceinline__ bool pub_ready(double v)
 // (bounded; a wave-uniform exit).  Entries without want(u) keep their value.
 template <int NU, class Want, class Off>
 __device__ __forceinline__ void poll_values(double (&v)[NU], const double *p, const Want &want, const Off &off,
-                                            int *status)
+                                            const ExecArgs &a)
 {
 #pragma unroll
     for (int u = 0; u < NU; ++u)
         if (want(u)) v[u] = pub_empty();
-    for (int it = 0;; ++it) {
+    WaitClock wc;
+    for (int it = 1;; ++it) {
 #pragma unroll
         for (int u = 0; u < NU; ++u)
             if (want(u) && !pub_ready(v[u])) v[u] = load_coherent(p + off(u));
         bool ok = true;
 #pragma unroll
         for (int u = 0; u < NU; ++u) ok = ok && (!want(u) || pub_ready(v[u]));
-        if (__all(ok)) break;
-        if (it == kSpinLimit) {
-            atomicOr(status, 1);
+        // a bound of 0 (a test of this error path) gives up at the first poll, always
+        if (a.poll_ticks == 0 || (!__all(ok) && (it & 7) == 0 && wc.expired(a.poll_ticks))) {
+            raise_status(a.status, kStatusExchange);
             break;
         }
+        if (__all(ok)) break;
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -287,7 +298,7 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
                 const int idx = (u < UN ? u : u - UN) * 64 + lane;
                 return u < UN ? idx < cntn : (k >= 1 && idx >= M2 && idx < nin * M2);
             },
-            [&](int u) { return u < UN ? nb1 + u * 64 + lane : rb + (u - UN) * 64 + lane; }, a.status);
+            [&](int u) { return u < UN ? nb1 + u * 64 + lane : rb + (u - UN) * 64 + lane; }, a);
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
             const int e = u * 64 + lane;
@@ -348,7 +359,7 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
     }
     poll_values(
         vc, pubc, [&](int u) { return (u * 64 + lane) / M2 < nitem; },
-        [&](int u) { return nid[u] * M2 + (u * 64 + lane) % M2; }, a.status);
+        [&](int u) { return nid[u] * M2 + (u * 64 + lane) % M2; }, a);
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
         const int idx = u * 64 + lane;
@@ -408,7 +419,7 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
                 const double v = up_pair<M>(brow, x, x + half, nn);
                 if (act) itm[xi * NS + lane] = v;
             }
-            worker_sync(wcnt, wtarget, a.status);
+            worker_sync(wcnt, wtarget, a);
         }
     }
     if (ww <= ts.G0) {
@@ -435,7 +446,7 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
         if (ok1) c1 = d1[0] + d1[1];
         if (act) canc[g * M2 + lane] = c0 + c1;
     }
-    worker_sync(wcnt, wtarget, a.status);
+    worker_sync(wcnt, wtarget, a);
     if (top) {
         double bcol[M];
 #pragma unroll
@@ -612,8 +623,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         int grp = wv;
 #pragma unroll 1
         for (; grp + NSW < G.sub_groups; grp += NSW)
-            stream_group<M, true>(grp, grp + NSW, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
-        if (grp < G.sub_groups) stream_group<M, false>(grp, 0, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
+            stream_group<M, true>(a, grp, grp + NSW, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
+        if (grp < G.sub_groups) stream_group<M, false>(a, grp, 0, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
         L2C_TS(3, 8);
     } else {
         // ---- workers: stage input (both parities, zero past n; cheb2leg u = c .* f), T, B(0),
@@ -725,7 +736,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
-        worker_sync(wcnt, wtarget, a.status);
+        worker_sync(wcnt, wtarget, a);
         if (wt == 0) lds_flag_set(rdy, (unsigned)kd);
         L2C_TS(3, 2);
         // cheb2leg near field reads g_j = j u_j: scale the staged input (step (1) has read u)
@@ -748,7 +759,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             for (int d = kd - 1; d >= 0; --d) {
                 if (qn_ok)
                     up_level_qn<M>(wl + fused_wofs(d + 1) * NS, wl + fused_wofs(d) * NS, 1 << d, brow, n, q0, QSTEP);
-                worker_sync(wcnt, wtarget, a.status);
+                worker_sync(wcnt, wtarget, a);
                 if (wt == 0) lds_flag_set(rdy, (unsigned)d);
             }
         }
@@ -794,11 +805,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             wave_lds_done();
             if (lane == 0) {
                 __hip_atomic_fetch_add(qdone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                int it = 0;
-                while (lds_flag_get(qdone) < (unsigned)kNearWaves) {
+                WaitClock wc;
+                for (int it = 1; lds_flag_get(qdone) < (unsigned)kNearWaves; ++it) {
                     __builtin_amdgcn_s_sleep(1);
-                    if (++it == kSpinLimit) {
-                        atomicOr(a.status, 2);
+                    if ((it & 15) == 0 && wc.expired(a.wait_ticks)) {
+                        raise_status(a.status, kStatusWorkers);
                         break;
                     }
                 }
@@ -838,7 +849,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         }
         if (top)
             top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, reinterpret_cast<int *>(w7), lane);
-        worker_sync(wcnt, wtarget, a.status);         // items and schedule in LDS; near field done
+        worker_sync(wcnt, wtarget, a);         // items and schedule in LDS; near field done
         // the near part of the unit's output rows (step (7)'s row scale rs for cheb2leg, and
         // its K_00 term) into the near-field area, now free: node stride 2s+1
         if (near && ntid < nwork) {
@@ -1026,7 +1037,8 @@ hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items)
 }
 
 // Single-launch kernels of one device never overlap: a launch on a stream other than the
-// previous one waits for the previous launch.
+// previous one waits for everything enqueued so far on the previous one (an event recorded
+// there at the switch), so a run of launches on one stream records no event.
 namespace {
 struct FusedOrder {
     std::mutex mu;
@@ -1058,6 +1070,9 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
     a.pub = p.d_pub;
     a.pub_items = p.fused_items;
     a.status = p.d_status;
+    const uint64_t khz = (uint64_t)(p.clock_khz > 0 ? p.clock_khz : 100000);
+    a.wait_ticks = (uint64_t)kWaitUs * khz / 1000u;
+    a.poll_ticks = (uint64_t)p.poll_us * khz / 1000u;
     const size_t lds = fused_lds_bytes(G);
     const unsigned U = 1u << (G.groot + 2);
     FusedOrder &o = g_order[p.device & 63];
@@ -1067,7 +1082,8 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
         if (e != hipSuccess) return e;
     }
     if (o.any && o.last != st) {
-        hipError_t e = hipStreamWaitEvent(st, o.done, 0);
+        hipError_t e = hipEventRecord(o.done, o.last);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, o.done, 0);
         if (e != hipSuccess) return e;
     }
     for (int64_t b0 = 0; b0 < batch; b0 += p.fused_items) {
@@ -1086,12 +1102,11 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
         hipLaunchKernelGGL(k_fused<M>, dim3(U, (unsigned)c.batch), dim3(kFusedThreads), lds, st, c);
         if (timed) (void)hipEventRecord(p.ev_after, st);
     }
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipEventRecord(o.done, st);
     o.last = st;
     o.any = true;
-    return e;
+    return hipSuccess;
 }
 
 hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,

@@ -89,8 +89,17 @@ struct ExecArgs {
     double *pub;         // k_fused: [2][pub_items][NX][2][M] exchange nodes, half (epoch & 1) in use
     int64_t pub_items;   // k_fused: items of one half of pub
     unsigned epoch;      // k_fused: launch number
-    int *status;         // k_fused: bit 0 set when a wait ran out of polls
+    int *status;         // k_fused: status words (host-mapped); word k set to 1 when a wait of kind k gave up
+    uint64_t wait_ticks; // k_fused: bound of the waits inside a workgroup, in wall-clock ticks
+    uint64_t poll_ticks; // k_fused: bound of the waits for other workgroups, in wall-clock ticks
 };
+
+// Status words of the single-launch path (ExecArgs::status), one per kind of wait; the
+// plan reports word k as bit k (leg2cheb_plan_status).
+constexpr int kStatusExchange = 0;   // a poll of another workgroup's exchange nodes
+constexpr int kStatusWorkers = 1;    // a barrier of the worker waves, or of the near-field waves
+constexpr int kStatusStream = 2;     // the streaming wave waiting for the workers' depth flags
+constexpr int kStatusWords = 4;
 
 // Device arrays of a ragged batch, one entry per item of the launch sequence.
 struct ItemArrays {
@@ -124,8 +133,11 @@ struct l2c_plan_s {
     bool fused_on = true;       // caller preference (leg2cheb_plan_set_option)
     int64_t fused_items = 0;    // items per k_fused launch (all workgroups co-resident)
     double *d_pub = nullptr;    // ExecArgs::pub, fused_items items per half
-    int *d_status = nullptr;
+    int *h_status = nullptr;    // kStatusWords words of pinned, device-mapped host memory
+    int *d_status = nullptr;    // the device address of h_status
     unsigned epoch = 0;
+    int64_t poll_us = 1000000;  // bound of the waits for other workgroups (L2C_OPT_EXCHANGE_TIMEOUT_US)
+    int clock_khz = 0;          // wall-clock rate of the device (hipDeviceAttributeWallClockRate)
     // batched form (precision L2C_FP32): tables in the form's type and a workspace of
     // [tiles][NT][2][16 x 16] tiles; the FP64 Ahat tables are released after packing
     void *d_bA = nullptr;       // Ahat, [blocks][3][64][4] A operands
@@ -177,6 +189,8 @@ hipError_t dense_build(const l2c_plan_s &p, double *D, hipStream_t stream);
 hipError_t launch_dense(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                         const ItemArrays *ia = nullptr);
 // l2c_plan.hip
+hipError_t launch_build_small(const l2c_plan_s &p, hipStream_t stream);   // T, P, XG, D
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t stream);
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);
 
@@ -221,7 +235,7 @@ constexpr int kNearWaves = 6;             // worker waves that run the near fiel
 constexpr int kTopWave = 4;               // the wave (of the workgroup) that works above the unit
 static_assert(kStreamWaves == 1 && kNearWaves == kWorkWaves - 1 && kTopWave > kStreamWaves && kTopWave < 8,
               "wave roles: one streamer, one top wave, the rest near-field waves");
-constexpr int kSpinLimit = 1 << 20;       // polls of one wait before it gives up (~1 s)
+constexpr int64_t kWaitUs = 1000000;      // bound of every wait inside a workgroup (1 s)
 constexpr int kFusedStageG = 12, kFusedStageT = 4;   // staging registers per worker thread
 // Both 32-bit halves of an exchange node value that the current launch has not written yet
 // (a signalling NaN, which no arithmetic result is).

@@ -10,6 +10,9 @@
 // as two M x M x M products in LDS.  All in FP64.  Results go straight into the
 // far-field tables that k_main reads (layouts in l2c_internal.h).
 //
+// k_build_small makes the Vandermonde matrices T(sigma) of Eq. (Xs), the near-field factor
+// P_d, the Chebyshev-Gauss points and the DCT matrix, also in FP64 on the device.
+//
 // The paper's planning shortcuts (persymmetry of Lambda^-, reuse across a level,
 // term dropping in Eq. (tau), the radix-2/3 DCT of size 18) reduce CPU flops; here
 // every sample is evaluated directly, which keeps one independent thread per sample.
@@ -110,6 +113,71 @@ __global__ void k_export_ahat(double *top, double *bot, Geometry G, double *dst,
         ++g;
     }
     dst[e] = *ahat_addr<M>(top, bot, G, g, blk, r, k, l);
+}
+
+// The plan's small tables, one thread per entry:
+//   T[sigma][m][k] = T_k(X), X = -1 + (2m + sigma)/s (Eq. (Xs)), by the three-term recurrence;
+//   P[e] = 0 for e < kPLead, then the near-field factor P_d, d = e - kPLead (lambda_d for
+//          leg2cheb, lambda_d / (1 - 2d) for cheb2leg, Eq. (Lxymod));
+//   XG[m] = cos((m + 1/2) pi / M) and Dm[k][m] = cos(k (m + 1/2) pi / M) (Eq. (aklmore)).
+__global__ void k_build_small(double *T, double *P, double *XG, double *Dm, int s, int M, int dir, int plen)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nt = 2 * s * M;
+    if (e < nt) {
+        const int k = e % M, sm = e / M, m = sm % s, sig = sm / s;
+        const double X = -1.0 + (double)(2 * m + sig) / (double)s;
+        double t0 = 1.0, t1 = X;
+        for (int j = 0; j < k; ++j) {
+            const double t2 = 2.0 * X * t1 - t0;
+            t0 = t1;
+            t1 = t2;
+        }
+        T[e] = t0;
+        return;
+    }
+    e -= nt;
+    if (e < plen) {
+        const int d = e - kPLead;
+        double v = 0.0;
+        if (d >= 0) {
+            const double lam = lambda_int(d);
+            v = dir == 0 ? lam : lam / (1.0 - 2.0 * (double)d);
+        }
+        P[e] = v;
+        return;
+    }
+    e -= plen;
+    if (e < M) {
+        XG[e] = cos((e + 0.5) * kPi / M);
+        return;
+    }
+    e -= M;
+    if (e < M * M) {
+        const int k = e / M, m = e % M;
+        Dm[e] = cos(k * (m + 0.5) * kPi / M);
+    }
+}
+
+__global__ void k_to_f32(const double *src, float *dst, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = (float)src[e];
+}
+
+hipError_t launch_build_small(const l2c_plan_s &p, hipStream_t st)
+{
+    const int total = 2 * p.s * p.M + (int)p_table_len(p.s) + p.M + p.M * p.M;
+    hipLaunchKernelGGL(k_build_small, dim3((total + 255) / 256), dim3(256), 0, st, p.d_T, p.d_P, p.d_XG, p.d_D, p.s,
+                       p.M, p.direction, (int)p_table_len(p.s));
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
 }
 
 template <int M>

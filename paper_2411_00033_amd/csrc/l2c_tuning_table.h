@@ -1,0 +1,33 @@
+// l2c_tuning_table.h -- leaf size and rank per size bucket of a ragged batch
+// (leg2cheb_batch_plan with tuning = NULL), per precision form.
+//
+// Written by paper_2411_00033_amd/autotune.py from timings of the ragged batch on an
+// MI355X; regenerate it with that script.  Each row covers the lengths n with
+// n_max(previous row) < n <= n_max; the last row covers every larger n.  The FP64 rows
+// keep rank >= 18 (the rank at which every far-field submatrix of both kernels meets the
+// FP64 accuracy target); the batched forms keep rank <= 16 and leaf <= 64.
+#pragma once
+#include <stdint.h>
+
+namespace l2c {
+
+struct TuneRow {
+    int64_t n_max;
+    int32_t leaf_size, rank;
+};
+
+// untuned defaults: the paper's leaf (s = 32) and M = 18 in FP64, M = 16 in the batched forms
+static const TuneRow kTuneFP64[] = {{INT64_MAX, 64, 18}};
+static const TuneRow kTuneBatched[] = {{INT64_MAX, 64, 16}};
+
+inline int builtin_tuning(int precision, const TuneRow **rows)
+{
+    if (precision == 0) {
+        *rows = kTuneFP64;
+        return (int)(sizeof(kTuneFP64) / sizeof(kTuneFP64[0]));
+    }
+    *rows = kTuneBatched;
+    return (int)(sizeof(kTuneBatched) / sizeof(kTuneBatched[0]));
+}
+
+}  // namespace l2c

@@ -107,11 +107,12 @@ def test_batch_plan_argument_errors(lib):
     L = lib.load()
     i64, ci = ctypes.c_int64, ctypes.c_int
 
-    def plan(ns, dirs, leaf=64, rank=18, precision=0):
+    def plan(ns, dirs, leaf=64, rank=18, precision=0, buckets=None):
         h = ctypes.c_void_p(1)
         na = (i64 * max(len(ns), 1))(*ns)
         da = (ci * max(len(dirs), 1))(*dirs)
-        rc = L.leg2cheb_batch_plan(ctypes.byref(h), len(ns), na, da, leaf, rank, precision, None)
+        t, keep = lib._tuning(buckets if buckets is not None else [(1 << 62, leaf, rank)])
+        rc = L.leg2cheb_batch_plan(ctypes.byref(h), len(ns), na, da, precision, ctypes.byref(t), None)
         assert h.value is None
         return rc
 
@@ -126,7 +127,12 @@ def test_batch_plan_argument_errors(lib):
     assert plan([100], [0], rank=18, precision=1) == -4   # batched forms: rank <= 16
     assert plan([100], [0], leaf=128, rank=16, precision=2) == -4   # batched forms: leaf <= 64
     assert plan([(1 << 28) + 1], [0], rank=16, precision=1) == -4   # batched forms: n <= 2^28
-    assert L.leg2cheb_batch_plan(None, 1, None, None, 64, 18, 0, None) == -1
+    assert plan([100], [0], buckets=[]) == -1                        # no bucket
+    assert plan([100], [0], buckets=[(4096, 64, 18), (4096, 64, 18)]) == -1   # n_max not increasing
+    assert plan([100], [0], buckets=[(4096, 64, 18), (1 << 40, 63, 18)]) == -1   # odd leaf in a bucket
+    assert plan([100], [0], buckets=[(4096, 64, 18), (1 << 40, 64, 17)]) == -4   # rank without kernels
+    assert plan([100], [0], precision=1, buckets=[(4096, 64, 16), (1 << 40, 64, 18)]) == -4
+    assert L.leg2cheb_batch_plan(None, 1, None, None, 0, None, None) == -1
     assert L.leg2cheb_batch_execute(None, None, None, None) == -1
     assert L.leg2cheb_batch_info(None, None, None) == -1
     assert L.leg2cheb_batch_destroy(None) == 0
@@ -143,3 +149,35 @@ def test_alloc_hook_host_logic(lib):
     with pytest.raises(lib.L2CError) as ei:
         lib.leg2cheb_debug_alloc_hook(-2)
     assert ei.value.code == lib.L2C_EINVAL
+
+
+def test_builtin_tuning_table(lib):
+    """The library's size buckets (used when a ragged batch is planned with tuning NULL):
+    increasing n_max, even leaf sizes in [4, 128], ranks with kernels, FP64 rank >= 18 and
+    batched-form rank <= 16, leaf <= 64; queries need no device."""
+    for prec in (lib.L2C_FP64, lib.L2C_FP32, lib.L2C_BF16X2):
+        rows = lib.leg2cheb_batch_tuning(prec)
+        assert rows
+        assert all(a[0] < b[0] for a, b in zip(rows, rows[1:]))
+        for n_max, leaf, rank in rows:
+            assert 4 <= leaf <= 128 and leaf % 2 == 0 and lib.leg2cheb_rank_supported(rank)
+            if prec == lib.L2C_FP64:
+                assert rank >= 18
+            else:
+                assert rank <= 16 and leaf <= 64
+    L = lib.load()
+    cnt = ctypes.c_int32(-1)
+    assert L.leg2cheb_batch_tuning(9, None, 0, ctypes.byref(cnt)) == -1
+    assert L.leg2cheb_batch_tuning(0, None, 0, None) == -1
+    assert L.leg2cheb_batch_tuning(0, None, 4, ctypes.byref(cnt)) == -1
+    assert L.leg2cheb_batch_tuning(0, None, 0, ctypes.byref(cnt)) == 0 and cnt.value >= 1
+
+
+def test_status_and_option_constants_match_header(lib):
+    """The binding's option and status-bit values are the header's."""
+    text = open(HEADER).read()
+    for name in ("L2C_OPT_SINGLE_LAUNCH", "L2C_OPT_DIRECT", "L2C_OPT_EXCHANGE_TIMEOUT_US", "L2C_STATUS_EXCHANGE",
+                 "L2C_STATUS_WORKERS", "L2C_STATUS_STREAM", "L2C_FP64", "L2C_FP32", "L2C_BF16X2"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, text)
+        assert m, name
+        assert int(m.group(1)) == getattr(lib, name), name

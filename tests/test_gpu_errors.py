@@ -64,10 +64,13 @@ def batch_maker(l2c, ns, dirs, precision, rank=18):
     na = (ctypes.c_int64 * len(ns))(*ns)
     da = (ctypes.c_int * len(dirs))(*dirs)
 
+    t, keep = l2c._lib._tuning([(1 << 62, 64, rank)])
+
     def make():
         h = ctypes.c_void_p(1)
-        rc = L.leg2cheb_batch_plan(ctypes.byref(h), len(ns), na, da, 64, rank, precision, None)
+        rc = L.leg2cheb_batch_plan(ctypes.byref(h), len(ns), na, da, precision, ctypes.byref(t), None)
         return rc, h
+    make.keep = (t, keep)
     return make
 
 
@@ -151,3 +154,63 @@ def test_execute_and_export_allocation_failures(l2c):
         assert pending == 0 and live == live0
         l2c.leg2cheb_plan_export(p.handle, l2c.TABLE_AHAT, buf.ctypes.data, need)
         assert np.array_equal(buf, p.export(l2c.TABLE_AHAT).ravel())
+
+
+def test_single_launch_wait_timeout_is_reported(l2c):
+    """A single-launch wait that gives up is reported, forced from the host: with the
+    exchange timeout at 0 every wait for another workgroup gives up after its first poll
+    (every kernel still ends), the plan's status shows L2C_STATUS_EXCHANGE, the next
+    execute returns L2C_EHIP without running, and once the status has been read (which
+    clears it) the plan with the default timeout gives the oracle's result again."""
+    import torch
+    import oracle
+    n = 40000
+    f = inputs.decaying(n, 1.0, inputs.SEED_BASE + 90)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    with l2c.Plan(n, 0) as p:
+        assert p.info["path"] == l2c.L2C_PATH_SINGLE
+        with pytest.raises(l2c.L2CError) as ei:
+            p.set_exchange_timeout_us(-1)
+        assert ei.value.code == l2c.L2C_EINVAL
+        p.set_exchange_timeout_us(0)
+        p.execute(x, y)
+        torch.cuda.synchronize()
+        with pytest.raises(l2c.L2CError) as ei:
+            p.execute(x, y)
+        assert ei.value.code == l2c.L2C_EHIP
+        st = p.status
+        print("forced give-up: status %#x" % st, flush=True)
+        assert st & l2c.L2C_STATUS_EXCHANGE
+        assert p.status == 0                    # read and cleared
+        p.set_exchange_timeout_us(1000000)
+        z = p.execute(x, y)
+        torch.cuda.synchronize()
+        assert p.status == 0
+    assert oracle.einf(z.cpu().numpy(), oracle.leg2cheb(f)) <= 1e-13
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_reused_on_another_stream(l2c, precision):
+    """A ragged batch executed on one stream and immediately again, with other pointers, on
+    a second stream: the second call waits for the first, so both outputs are right."""
+    import torch
+    import oracle
+    rank = 18 if precision == 0 else 16
+    ns = [300, 5000, 70000, 1000, 20000]
+    dirs = [0, 1, 0, 1, 1]
+    xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 95 + i)).cuda() for i, n in enumerate(ns)]
+    xs2 = [(2.0 * x).flip(0).contiguous() for x in xs]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with l2c.BatchPlan(ns, dirs, 64, rank, precision) as b:
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            y1 = b.execute(xs, stream=s1)
+        with torch.cuda.stream(s2):
+            y2 = b.execute(xs2, stream=s2)
+        torch.cuda.synchronize()
+    tol = 1e-13 if precision == 0 else 2.5e-6
+    for i, d in enumerate(dirs):
+        for xx, yy in ((xs, y1), (xs2, y2)):
+            err = oracle.einf(yy[i].cpu().numpy(), oracle.transform(xx[i].cpu().numpy(), d))
+            assert err <= tol, (i, err)
