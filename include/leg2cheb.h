@@ -146,6 +146,23 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
  */
 int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
 
+/*
+ * leg2cheb_execute for callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid it): the same transform, with no hipMalloc, hipFree
+ * or other allocation in the call.  FP64 plans only.  Plans on the dense or direct path
+ * run as in leg2cheb_execute (those kernels use no workspace); every other plan runs the
+ * three-launch path of Alg. 4 with its upward vectors in a workspace of 64 MiB that the
+ * library holds in a fixed device array per device for the life of the process, instead
+ * of the plan's own workspace.  That array is shared by every call on the device: calls
+ * that overlap on one device (other streams, other threads) race and must not be made.
+ * The output agrees bit for bit with leg2cheb_execute on the three-launch path.
+ *   in, out, batch, stream  as in leg2cheb_execute.
+ * Errors: L2C_EINVAL as leg2cheb_execute, and when batch x (2^(L+2) - 4) x 2 x rank x 8
+ * bytes exceeds 64 MiB (at n = 10^6, rank 18: batch > 7); L2C_EUNSUPPORTED (a plan of a
+ * batched precision form); L2C_EHIP as leg2cheb_execute.
+ */
+int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
+
 /* Release the plan and its device memory (synchronizes the device first). NULL is a no-op. */
 int leg2cheb_destroy(l2c_plan_t plan);
 

@@ -21,7 +21,8 @@ L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US = 1, 2, 3
 L2C_STATUS_EXCHANGE, L2C_STATUS_WORKERS, L2C_STATUS_STREAM = 1, 2, 4
 
 EXPORTED = (
-    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_destroy", "leg2cheb_plan_info",
+    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
+    "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
     "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
@@ -72,6 +73,7 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_plan.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci]
     lib.leg2cheb_plan_ex.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, vp]
     lib.leg2cheb_execute.argtypes = [vp, vp, vp, i64, vp]
+    lib.leg2cheb_execute_noalloc.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_destroy.argtypes = [vp]
     lib.leg2cheb_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.leg2cheb_plan_export.argtypes = [vp, ci, vp, i64, ctypes.POINTER(i64)]
@@ -125,6 +127,12 @@ def leg2cheb_execute(plan: int, in_ptr: int, out_ptr: int, batch: int, stream: i
     _check(load().leg2cheb_execute(ctypes.c_void_p(plan), ctypes.c_void_p(in_ptr or None),
                                    ctypes.c_void_p(out_ptr or None), int(batch), ctypes.c_void_p(stream or None)),
            "leg2cheb_execute")
+
+
+def leg2cheb_execute_noalloc(plan: int, in_ptr: int, out_ptr: int, batch: int, stream: int = 0) -> None:
+    _check(load().leg2cheb_execute_noalloc(ctypes.c_void_p(plan), ctypes.c_void_p(in_ptr or None),
+                                           ctypes.c_void_p(out_ptr or None), int(batch),
+                                           ctypes.c_void_p(stream or None)), "leg2cheb_execute_noalloc")
 
 
 def leg2cheb_destroy(plan: int) -> None:

@@ -788,10 +788,12 @@ int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int
     return leg2cheb_plan_ex(plan, n, direction, leaf_size, rank, L2C_FP64, 1, nullptr);
 }
 
-int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream)
+}  // extern "C"
+
+namespace {
+// Argument checks shared by leg2cheb_execute and leg2cheb_execute_noalloc (batch >= 1).
+int check_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch)
 {
-    if (!plan || batch < 0) return L2C_EINVAL;
-    if (batch == 0) return L2C_OK;
     if (!in || !out) return L2C_EINVAL;
     const int64_t len = batch * plan->n;
     if (batch > (int64_t(1) << 40) / plan->n) return L2C_EINVAL;
@@ -802,12 +804,51 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
     if (dev != plan->device) return L2C_EINVAL;
     if (status_bits(plan) != 0) return L2C_EHIP;   // an earlier single-launch execute gave up a wait
+    return L2C_OK;
+}
+
+bool direct_now(const l2c_plan_s *plan, int64_t batch)
+{
+    return plan->L > 0 && plan->direct_ok && plan->direct_on &&
+           batch <= l2c::direct_max_work(plan->n) / (plan->n * plan->n);
+}
+}  // namespace
+
+extern "C" {
+
+int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream)
+{
+    if (!plan || batch < 0) return L2C_EINVAL;
+    if (batch == 0) return L2C_OK;
+    if (plan->precision != L2C_FP64) return L2C_EUNSUPPORTED;
+    const int rc = check_execute(plan, in, out, batch);
+    if (rc != L2C_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // the dense and direct paths use no workspace and allocate nothing
+    if (plan->d_dense) return l2c::launch_dense(*plan, in, out, batch, st) == hipSuccess ? L2C_OK : L2C_EHIP;
+    if (plan->L == 0 || direct_now(plan, batch))
+        return l2c::launch_direct(*plan, in, out, batch, st) == hipSuccess ? L2C_OK : L2C_EHIP;
+    const int64_t per_item = plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double);
+    if (batch > (int64_t)l2c::kNoallocScratchBytes / per_item) return L2C_EINVAL;
+    double *w = nullptr;
+    if (l2c::noalloc_scratch(plan->device, &w) != hipSuccess) {
+        (void)hipGetLastError();
+        return L2C_EHIP;
+    }
+    return l2c::launch_execute_scratch(*plan, in, out, batch, st, w) == hipSuccess ? L2C_OK : L2C_EHIP;
+}
+
+int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream)
+{
+    if (!plan || batch < 0) return L2C_EINVAL;
+    if (batch == 0) return L2C_OK;
+    const int crc = check_execute(plan, in, out, batch);
+    if (crc != L2C_OK) return crc;
     if (plan->d_dense) {
         if (l2c::launch_dense(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
     }
-    if (plan->L > 0 && plan->direct_ok && plan->direct_on &&
-        batch <= l2c::direct_max_work(plan->n) / (plan->n * plan->n)) {
+    if (direct_now(plan, batch)) {
         if (l2c::launch_direct(*plan, in, out, batch, (hipStream_t)stream) != hipSuccess) return L2C_EHIP;
         return L2C_OK;
     }

@@ -592,7 +592,7 @@ static size_t main_lds_bytes(const Geometry &G)
 
 template <int M>
 static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
-                      const ItemArrays *ia)
+                      const ItemArrays *ia, double *w)
 {
     const Geometry &G = p.geo;
     ExecArgs a;
@@ -629,7 +629,7 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
             c.item_in = ia->in + b0;
             c.item_out = ia->out + b0;
         }
-        c.w = p.d_w + b0 * G.NT * 2 * M;
+        c.w = w + b0 * G.NT * 2 * M;
         const unsigned items = (unsigned)c.batch;
         hipLaunchKernelGGL(k_up<M>, dim3((unsigned)(P >> G.ku), items), dim3(kThreads), up_lds, st, c);
         for (int gin = G.L - 1 - G.ku; gin > 0;) {
@@ -652,7 +652,50 @@ hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, in
     if (p.L == 0) return launch_direct(p, in, out, batch, st, ia);
     switch (p.M) {
 #define L2C_CASE(MM) \
-    case MM: return run<MM>(p, in, out, batch, st, ia);
+    case MM: return run<MM>(p, in, out, batch, st, ia, p.d_w);
+        L2C_FOR_EACH_RANK(L2C_CASE)
+#undef L2C_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Workspace of leg2cheb_execute_noalloc: the upward vectors w of the three-launch path in
+// a fixed device array instead of the plan's workspace, for callers that cannot allocate.
+// Each device holds its own copy for the life of the process.  Nothing in it needs to
+// start at zero (k_up and k_top write every node that k_main reads), and calls that
+// overlap on one device race for it.
+static __device__ __align__(256) double scratch[kNoallocScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {};   // device address of scratch, per device
+}  // namespace
+
+// The device address of scratch on `device` (the current device), resolved once per device.
+hipError_t noalloc_scratch(int device, double **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        double *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!q) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = q;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_execute_scratch(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
+                                  double *w)
+{
+    if (p.L == 0 || !w) return hipErrorInvalidValue;
+    switch (p.M) {
+#define L2C_CASE(MM) \
+    case MM: return run<MM>(p, in, out, batch, st, nullptr, w);
         L2C_FOR_EACH_RANK(L2C_CASE)
 #undef L2C_CASE
     default: return hipErrorInvalidValue;

@@ -173,6 +173,12 @@ hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int
                          const ItemArrays *ia = nullptr);
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
                           hipStream_t stream, const ItemArrays *ia = nullptr);
+// leg2cheb_execute_noalloc: the three-launch path with w in a fixed device array of
+// kNoallocScratchBytes (resolved per device by noalloc_scratch)
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(int device, double **ptr);
+hipError_t launch_execute_scratch(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
+                                  hipStream_t stream, double *w);
 // l2c_fused.hip
 bool fused_supported(int M);
 hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items);

@@ -83,6 +83,7 @@ def test_plan_ex_precision_and_batch_errors(lib):
 def test_null_plan_calls(lib):
     L = lib.load()
     assert L.leg2cheb_execute(None, None, None, 1, None) == -1
+    assert L.leg2cheb_execute_noalloc(None, None, None, 1, None) == -1
     assert L.leg2cheb_destroy(None) == 0
     assert L.leg2cheb_plan_info(None, None) == -1
     assert L.leg2cheb_plan_export(None, 0, None, 0, None) == -1
