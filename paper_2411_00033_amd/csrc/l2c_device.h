@@ -5,14 +5,19 @@
 #include "l2c_internal.h"
 #include "l2c_math.h"
 
-// Phase timestamps for performance analysis: compiled in only with L2C_PHASE_TIMING
-// (the product build defines nothing and the macro expands to nothing).
+// Phase timestamps for performance analysis, compiled in only with L2C_PHASE_TIMING (the
+// product build defines nothing and the macro expands to nothing; paper_2411_00033_amd/
+// phase_timing.py builds and reads the instrumented variant).  Slot (kern, unit, phase)
+// keeps the latest wall-clock time at which lane 0 of any wave of the unit's workgroup
+// passed the point (first item of the launch, units < 4096).  Each source file has its
+// own copy of the table.
 #ifdef L2C_PHASE_TIMING
-extern __device__ unsigned long long l2c_phase_ts[];
-#define L2C_TS(kern, ph)                                                                          \
-    do {                                                                                          \
-        if (threadIdx.x == 0 && blockIdx.y == 0 && blockIdx.x < 4096)                             \
-            l2c_phase_ts[((kern) * 4096 + blockIdx.x) * 16 + (ph)] = wall_clock64();              \
+constexpr int kPhaseKernels = 4, kPhaseUnits = 4096, kPhaseSlots = 16;
+static __device__ unsigned long long l2c_phase_ts[kPhaseKernels * kPhaseUnits * kPhaseSlots];
+#define L2C_TS(kern, ph)                                                                               \
+    do {                                                                                               \
+        if ((threadIdx.x & 63) == 0 && blockIdx.y == 0 && blockIdx.x < kPhaseUnits)                    \
+            atomicMax(&l2c_phase_ts[((kern) * kPhaseUnits + blockIdx.x) * kPhaseSlots + (ph)], wall_clock64()); \
     } while (0)
 #else
 #define L2C_TS(kern, ph) \

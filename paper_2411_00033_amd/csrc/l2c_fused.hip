@@ -847,8 +847,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             const int e = u * 64 * kNearWaves + ntid;
             vtr[u] = (near && e < 2 * s * M) ? a.T[e] : 0.0;
         }
-        if (top)
+        if (top) {
             top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, reinterpret_cast<int *>(w7), lane);
+            L2C_TS(3, 9);
+        }
         worker_sync(wcnt, wtarget, a);         // items and schedule in LDS; near field done
         // the near part of the unit's output rows (step (7)'s row scale rs for cheb2leg, and
         // its K_00 term) into the near-field area, now free: node stride 2s+1
@@ -870,6 +872,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         }
         top_combine<M>(a, ts, Tl, reinterpret_cast<const int *>(w7), ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget,
                        ww, top, lane);
+        if (top) L2C_TS(3, 10);
         if (near) {
 #pragma unroll
             for (int u = 0; u < UTR; ++u) {
@@ -1122,3 +1125,21 @@ hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t ba
 }
 
 }  // namespace l2c
+
+#ifdef L2C_PHASE_TIMING
+// Instrumented builds only: copy (and optionally clear) this file's phase table (kernel 3
+// is k_fused; phases in the order of L2C_TS above).
+extern "C" int l2c_debug_phase_ts(unsigned long long *dst, int64_t count, int clear)
+{
+    const size_t bytes = sizeof(unsigned long long) * (size_t)kPhaseKernels * kPhaseUnits * kPhaseSlots;
+    if (count * (int64_t)sizeof(unsigned long long) != (int64_t)bytes) return -1;
+    if (dst && hipMemcpyFromSymbol(dst, HIP_SYMBOL(l2c_phase_ts), bytes, 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return -3;
+    if (clear) {
+        static unsigned long long zero[kPhaseKernels * kPhaseUnits * kPhaseSlots];
+        if (hipMemcpyToSymbol(HIP_SYMBOL(l2c_phase_ts), zero, bytes, 0, hipMemcpyHostToDevice) != hipSuccess)
+            return -3;
+    }
+    return 0;
+}
+#endif
