@@ -16,7 +16,9 @@ Timing protocol
     roofline.achieved.  A separate loop, so that those events add nothing to the step.
   * Warm: K further steps back to back, no flush (warm_ms_per_step).
 The CPU baseline times the direct oracle on a bounded sample of rows of the same
-transform and extrapolates by term count to the full transform.
+transform and extrapolates by term count to the full transform, and times the
+single-threaded CPU FMM of Alg. 4 on the whole transform (fastest of 2^(26 - log2 N)
+executes, the protocol of Sec. 5.2).
 
 Prints one JSON line.
 """
@@ -116,6 +118,19 @@ def cpu_baseline(f, z_gpu, direction):
             "sample": "rows i = 0 mod 3 of the N=10^6 %s (%d rows, %.3g of %.3g terms, %.1f s), "
                       "extrapolated by term count" % (("leg2cheb", "cheb2leg")[direction], rows.size, terms_sample,
                                                       terms_full, dt)}
+    # the single-threaded CPU FMM of Alg. 4 (FP64, leaf 64, rank 18), fastest of
+    # 2^(26 - log2 N) executes as in Sec. 5.2
+    from oracle import cpu_fmm
+    reps = 2 ** max(0, 26 - int(round(np.log2(n))))
+    with cpu_fmm.CpuFmm(n, direction, LEAF, RANK) as p:
+        t = p.fastest_seconds(f, reps)
+        zc = p.execute(f)
+        plan_s = p.plan_s
+    base["fmm"] = {"value": n / t / 1e9, "unit": "Gcoeff/s", "cores": 1, "kind": "cpu_fmm",
+                   "ms_per_transform": t * 1e3, "plan_s": plan_s,
+                   "einf_vs_gpu": float(np.max(np.abs(zc - z_gpu)) / np.max(np.abs(z_gpu))),
+                   "sample": "the whole N=10^6 %s, fastest of %d executes on one host core (single-threaded "
+                             "C++ Alg. 4, oracle/cpu_fmm.cpp)" % (("leg2cheb", "cheb2leg")[direction], reps)}
     return base, err
 
 

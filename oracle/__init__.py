@@ -13,6 +13,9 @@ Contents
 * ``fmm_ref``: the plan tables and the seven steps of Alg. 4 written out in
   numpy in the paper's order and notation (an approximation of the direct
   product; pinned against it in the tests).
+* ``cpu_fmm`` (``cpu_fmm.cpp``): a single-threaded C++ implementation of Alg. 4, the
+  CPU baseline that the benchmark times beside the GPU path; not an oracle, pinned
+  against the direct oracle in ``tests/test_cpu_fmm.py``.
 
 Every function here is pinned in ``tests/test_oracle_*.py`` against exact
 rational arithmetic, library routines and invariants.
