@@ -188,14 +188,20 @@ def batched_form(l2c, inputs, torch, K, W, flush, flush_sink, with_fp64=True):
     msb = timed(pb, yb)
     pb.close()
     rec.update({"bf16x2_ms_per_execute": msb, "bf16x2_Gcoeff_s": coeffs / (msb * 1e-3) / 1e9})
+    yh = torch.empty_like(x)
+    ph = l2c.Plan(BATCH_N, l2c.LEG2CHEB, 64, 16, precision=l2c.L2C_FP16X2, max_batch=BATCH_B)
+    msh = timed(ph, yh)
+    ph.close()
+    rec.update({"fp16x2_ms_per_execute": msh, "fp16x2_Gcoeff_s": coeffs / (msh * 1e-3) / 1e9})
     if with_fp64:
         y64 = torch.empty_like(x)
         p64 = l2c.Plan(BATCH_N, l2c.LEG2CHEB, 64, 18, max_batch=BATCH_B)
         ms64 = timed(p64, y64)
         d = (y32 - y64).abs().max().item() / y64.abs().max().item()
         db = (yb - y64).abs().max().item() / y64.abs().max().item()
+        dh = (yh - y64).abs().max().item() / y64.abs().max().item()
         rec.update({"fp64_path_ms_per_execute": ms64, "fp64_path_Gcoeff_s": coeffs / (ms64 * 1e-3) / 1e9,
-                    "einf_fp32_vs_fp64_path": d, "einf_bf16x2_vs_fp64_path": db})
+                    "einf_fp32_vs_fp64_path": d, "einf_bf16x2_vs_fp64_path": db, "einf_fp16x2_vs_fp64_path": dh})
         p64.close()
     p32.close()
     return rec

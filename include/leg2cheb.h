@@ -51,8 +51,14 @@ enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
  *   L2C_BF16X2  the same batched form with every FP32 operand x split as hi = bf16(x),
  *               lo = bf16(x - hi) and each product formed as hi*hi + hi*lo + lo*hi on the
  *               BF16 matrix cores with FP32 accumulation (products accurate to about
- *               2^-17); same limits as L2C_FP32. */
-enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2 };
+ *               2^-17); same limits as L2C_FP32.
+ *   L2C_FP16X2  the same with FP16 hi + lo operands (about 2^-22 per product) on the FP16
+ *               matrix cores with FP32 accumulation.  FP16 spans only 2^-24 .. 2^16, so
+ *               each Ahat submatrix is stored scaled by a power of two (undone after its
+ *               product) and each column of every runtime operand (one transform) is
+ *               scaled by a power of two from its largest magnitude before it is split;
+ *               same limits as L2C_FP32. */
+enum l2c_precision { L2C_FP64 = 0, L2C_FP32 = 1, L2C_BF16X2 = 2, L2C_FP16X2 = 3 };
 
 /* Execution path of a plan (l2c_plan_info.path). */
 enum l2c_path {
@@ -60,7 +66,7 @@ enum l2c_path {
                             L = 0, and short FP64 plans (L2C_OPT_DIRECT) */
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
     L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
-    L2C_PATH_BATCHED = 3, /* L2C_FP32 / L2C_BF16X2 plans: 16 transforms per matrix-core tile */
+    L2C_PATH_BATCHED = 3, /* L2C_FP32 / L2C_BF16X2 / L2C_FP16X2 plans: 16 transforms per matrix-core tile */
     L2C_PATH_DENSE = 4    /* FP64 plans with n <= 4096 and max_batch >= 64: Alg. 1 as dense
                              per-parity products on the FP64 matrix cores */
 };
@@ -123,7 +129,7 @@ int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int
 
 /*
  * As leg2cheb_plan, plus:
- *   precision  l2c_precision: L2C_FP64, or L2C_FP32 / L2C_BF16X2 (rank <= 16,
+ *   precision  l2c_precision: L2C_FP64, or L2C_FP32 / L2C_BF16X2 / L2C_FP16X2 (rank <= 16,
  *              leaf_size <= 64, n <= 2^28, else L2C_EUNSUPPORTED);
  *   max_batch  workspace is sized for this many items (>= 1); execute grows it on
  *              demand (a synchronizing allocation) when a larger batch arrives;

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (  # noqa: F401  (re-exported ABI names)
-    L2C_BF16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
+    L2C_BF16X2, L2C_FP16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
     L2C_LEG2CHEB, L2C_OK, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US, L2C_OPT_SINGLE_LAUNCH,
     L2C_STATUS_EXCHANGE, L2C_STATUS_STREAM, L2C_STATUS_WORKERS, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_THREE, L2CError,
     TABLE_AHAT, TABLE_B, TABLE_T, TABLE_W, leg2cheb_destroy, leg2cheb_execute, leg2cheb_execute_noalloc, leg2cheb_plan, leg2cheb_plan_ex,

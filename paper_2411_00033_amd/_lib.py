@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libleg2cheb.so")
 
 L2C_LEG2CHEB, L2C_CHEB2LEG = 0, 1
-L2C_FP64, L2C_FP32, L2C_BF16X2 = 0, 1, 2
+L2C_FP64, L2C_FP32, L2C_BF16X2, L2C_FP16X2 = 0, 1, 2, 3
 L2C_OK, L2C_EINVAL, L2C_ENOMEM, L2C_EHIP, L2C_EUNSUPPORTED = 0, -1, -2, -3, -4
 TABLE_AHAT, TABLE_T, TABLE_B, TABLE_W = 0, 1, 2, 3
 L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE = 0, 1, 2, 3, 4

@@ -151,6 +151,7 @@ void free_plan(l2c_plan_s *p)
     l2c::dev_free(p->d_bP);
     l2c::dev_free(p->d_bQ);
     l2c::dev_free(p->d_bw);
+    l2c::dev_free(p->d_bS);
     l2c::dev_free(p->d_dense);
     l2c::dev_free(p->d_dir);
     delete p;
@@ -169,7 +170,10 @@ int status_bits(const l2c_plan_s *p)
         if (w[k] != 0) bits |= 1 << k;
     return bits;
 }
-bool batched_form(int precision) { return precision == L2C_FP32 || precision == L2C_BF16X2; }
+bool batched_form(int precision)
+{
+    return precision == L2C_FP32 || precision == L2C_BF16X2 || precision == L2C_FP16X2;
+}
 bool use_batched(const l2c_plan_s *p) { return p->L > 0 && batched_form(p->precision); }
 size_t elem_bytes(const l2c_plan_s *p) { return batched_form(p->precision) ? sizeof(float) : sizeof(double); }
 
@@ -290,7 +294,8 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
               l2c::dev_alloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess &&
               l2c::dev_alloc(&p->d_bT, nT * eb) == hipSuccess &&
               l2c::dev_alloc(&p->d_bB, nB * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bP, nP * eb) == hipSuccess;
+              l2c::dev_alloc(&p->d_bP, nP * eb) == hipSuccess &&
+              (p->precision != L2C_FP16X2 || l2c::dev_alloc(&p->d_bS, (size_t)blocks * 3 * sizeof(float)) == hipSuccess);
     if (!ok) {
         (void)hipGetLastError();
         return L2C_ENOMEM;
@@ -310,7 +315,8 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
     p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
     p->bot_bytes = 0;
     p->table_bytes = p->top_bytes + (qlen + nT + nB + nP) * (int64_t)eb +
-                     (nT + 2 * nB + l2c::p_table_len(s) + M + nB) * 8;
+                     (nT + 2 * nB + l2c::p_table_len(s) + M + nB) * 8 +
+                     (p->d_bS ? blocks * 3 * (int64_t)sizeof(float) : 0);
     return L2C_OK;
 }
 

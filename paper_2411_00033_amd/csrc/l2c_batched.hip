@@ -1,7 +1,7 @@
-// l2c_batched.hip -- the batched execution forms (precisions L2C_FP32 and L2C_BF16X2):
-// the modal multipole transform (arXiv 2411.00033, Alg. 4) for 16 transforms at a time,
-// every product of steps (1)-(6) on the gfx950 matrix cores with the batch as the
-// product's column dimension (FP32 products, or BF16 hi+lo products with FP32
+// l2c_batched.hip -- the batched execution forms (precisions L2C_FP32, L2C_BF16X2 and
+// L2C_FP16X2): the modal multipole transform (arXiv 2411.00033, Alg. 4) for 16 transforms
+// at a time, every product of steps (1)-(6) on the gfx950 matrix cores with the batch as
+// the product's column dimension (FP32 products, or BF16 or FP16 hi+lo products with FP32
 // accumulation).
 //
 // A "tile" is the 16 x 16 matrix [k][item] of one tree node and parity for the 16
@@ -59,6 +59,7 @@ struct BatArgs {
     int gin;                        // kb_top: level of the loaded nodes
     int64_t NT;                     // workspace nodes per tile
     const T *ahat;                  // [blocks][3][64 lanes][4]: A operands, level-major blocks
+    const float *ahat_inv;          // FP16X2: [blocks][3] factor that undoes a submatrix's scaling
     const T *Tm;                    // [2][s][M]
     const T *B0;                    // [M][M]
     const T *Pt;                    // [2s]: P_d
@@ -175,7 +176,18 @@ __device__ __forceinline__ void node_stage(T *slot, const double (&x)[16], int64
 // dropped): three 16 x 16 x 16 BF16 instructions with FP32 accumulation.  The BF16
 // instruction takes K = 4q + j (j = 0..3) from lane group q, the same rows the FP32 form
 // takes in its steps kk = j, so both forms use the same per-lane values.
+// FM = 2 (FP16 hi+lo): the same three products with FP16 operands, which keep 22 bits
+// (about 2^-22 relative per product) but span only 2^-24 .. 2^16.  So every operand is
+// scaled by a power of two before it is split: the A operands of the plan's Ahat per
+// submatrix (the table spans about 16 decades; the factor that undoes the scaling is
+// stored beside it), the near-field band per leaf from its largest magnitude, the other A
+// operands (T, B(0), B(1), of magnitude <= 1) not at all, and every B operand per column,
+// i.e. per transform, from the
+// largest magnitude in that column (a reduction over the column's four lanes), so that
+// transforms of any scale share a tile.  A product is then (A' B') / (s_A s_B), scaled back
+// in FP32 before it joins the accumulator.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 template <int FM>
 struct Aop;
 template <>
@@ -186,6 +198,21 @@ template <>
 struct Aop<1> {
     bf16x4 hi, lo;
 };
+template <>
+struct Aop<2> {
+    f16x4 hi, lo;
+    float inv;   // the operand is (hi + lo) inv
+};
+
+__device__ __forceinline__ void split_f16(const float (&x)[4], float sc, f16x4 &hi, f16x4 &lo)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float v = x[j] * sc;
+        hi[j] = (_Float16)v;
+        lo[j] = (_Float16)(v - (float)hi[j]);
+    }
+}
 
 __device__ __forceinline__ void split_bf16(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
 {
@@ -203,15 +230,19 @@ __device__ __forceinline__ Aop<FM> aop(const float (&x)[4])
     if constexpr (FM == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) r.v[j] = x[j];
-    } else {
+    } else if constexpr (FM == 1) {
         split_bf16(x, r.hi, r.lo);
+    } else {
+        split_f16(x, 1.0f, r.hi, r.lo);
+        r.inv = 1.0f;
     }
     return r;
 }
 
 // The 16 bytes of a packed table entry: four FP32 values, or four hi then four lo BF16 values.
+// (FP16X2: four hi then four lo FP16 values of the scaled submatrix; inv undoes the scaling.)
 template <int FM>
-__device__ __forceinline__ Aop<FM> aop_raw(const v4_t<float> &raw)
+__device__ __forceinline__ Aop<FM> aop_raw(const v4_t<float> &raw, float inv = 1.0f)
 {
     Aop<FM> r;
     if constexpr (FM == 0) {
@@ -221,8 +252,14 @@ __device__ __forceinline__ Aop<FM> aop_raw(const v4_t<float> &raw)
         typedef unsigned int u4 __attribute__((ext_vector_type(4)));
         typedef unsigned int u2 __attribute__((ext_vector_type(2)));
         const u4 b = __builtin_bit_cast(u4, raw);
-        r.hi = __builtin_bit_cast(bf16x4, u2{b[0], b[1]});
-        r.lo = __builtin_bit_cast(bf16x4, u2{b[2], b[3]});
+        if constexpr (FM == 1) {
+            r.hi = __builtin_bit_cast(bf16x4, u2{b[0], b[1]});
+            r.lo = __builtin_bit_cast(bf16x4, u2{b[2], b[3]});
+        } else {
+            r.hi = __builtin_bit_cast(f16x4, u2{b[0], b[1]});
+            r.lo = __builtin_bit_cast(f16x4, u2{b[2], b[3]});
+            r.inv = inv;
+        }
     }
     return r;
 }
@@ -238,6 +275,7 @@ __device__ __forceinline__ Aop<FM> pick(const Aop<FM> &a0, const Aop<FM> &a1, bo
     } else {
         r.hi = c ? a1.hi : a0.hi;
         r.lo = c ? a1.lo : a0.lo;
+        if constexpr (FM == 2) r.inv = c ? a1.inv : a0.inv;
     }
     return r;
 }
@@ -249,12 +287,30 @@ __device__ __forceinline__ v4_t<float> mac(v4_t<float> acc, const Aop<FM> &a, co
     if constexpr (FM == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = Mx<float>::mma(a.v[j], b[j], acc);
-    } else {
+    } else if constexpr (FM == 1) {
         bf16x4 bh, bl;
         split_bf16(b, bh, bl);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bh, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, bl, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, bh, acc, 0, 0, 0);
+    } else {
+        // the column (transform l mod 16) scaled so that its largest magnitude lies in
+        // [2^13, 2^14): the four lanes l, l + 16, l + 32, l + 48 hold it
+        float m = fmaxf(fmaxf(fabsf(b[0]), fabsf(b[1])), fmaxf(fabsf(b[2]), fabsf(b[3])));
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        int e = 0;
+        (void)frexpf(m, &e);                          // m = f 2^e, f in [1/2, 1)
+        const int sh = m > 0.0f ? min(14 - e, 100) : 0;
+        f16x4 bh, bl;
+        split_f16(b, ldexpf(1.0f, sh), bh, bl);
+        v4_t<float> p = {0.0f, 0.0f, 0.0f, 0.0f};
+        p = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, bh, p, 0, 0, 0);
+        p = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, bl, p, 0, 0, 0);
+        p = __builtin_amdgcn_mfma_f32_16x16x16f16(a.lo, bh, p, 0, 0, 0);
+        const float inv = ldexpf(a.inv, -sh);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fmaf(p[j], inv, acc[j]);
     }
     return acc;
 }
@@ -388,6 +444,7 @@ __device__ __forceinline__ void top_body(const BatArgs<T> &a)
 template <typename T>
 struct FarIn {
     v4_t<T> A0, A1, W2, W3;
+    float i0, i1;                   // FP16X2: the factors that undo the scaling of A0, A1
     int kind;                       // 0: no block, 1: even row node, 2: odd row node
 };
 
@@ -397,10 +454,16 @@ __device__ __forceinline__ FarIn<T> far_issue(const BatArgs<T> &a, int g, int64_
     FarIn<T> f;
     f.kind = 0;
     f.A0 = f.A1 = f.W2 = f.W3 = v4_zero<T>();
+    f.i0 = f.i1 = 1.0f;
     const int64_t b = v >> 1;
     if (b >= (int64_t(1) << (g + 1)) - 1) return f;
     const T *ab = a.ahat + ((level_block_offset(g) + b) * 3 * 64 + lane) * 4;
     const int64_t cn = node_offset(g) + v + 2;
+    if (a.ahat_inv) {
+        const float *iv = a.ahat_inv + (level_block_offset(g) + b) * 3;
+        f.i0 = (v & 1) == 0 ? iv[0] : iv[2];
+        f.i1 = iv[1];
+    }
     if ((v & 1) == 0) {
         f.kind = 1;
         f.A0 = *reinterpret_cast<const v4_t<T> *>(ab);
@@ -420,8 +483,8 @@ __device__ __forceinline__ v4_t<T> far_do(const FarIn<T> &f)
 {
     v4_t<T> r = v4_zero<T>();
     if (f.kind == 0) return r;
-    r = mac_tile<FM>(r, aop_raw<FM>(f.A0), f.W2);
-    if (f.kind == 1) r = mac_tile<FM>(r, aop_raw<FM>(f.A1), f.W3);
+    r = mac_tile<FM>(r, aop_raw<FM>(f.A0, f.i0), f.W2);
+    if (f.kind == 1) r = mac_tile<FM>(r, aop_raw<FM>(f.A1, f.i1), f.W3);
     return r;
 }
 
@@ -648,6 +711,32 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         for (int cr = 0; cr < 5; ++cr)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) qv[cr][kk] = Qu[16 * cr + kk];
+        // FP16X2: the band is scaled by one power of two per leaf, from its largest magnitude
+        // (its entries P Q rs fall off by about 3 decades across a node, and with Q and rs
+        // they reach far below FP16's normal range for large S)
+        float bsc = 1.0f, binv = 1.0f;
+        if constexpr (FM == 2) {
+            float bm = 0.0f;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                if (rt < nrt) {
+                    const unsigned i32 = (unsigned)base + 2u * (unsigned)(16 * rt + li) + (unsigned)sg;
+                    const T rs = dir == 1 ? (T)(2u * i32 + 1u) : T(1);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (c < nc && c >= rt)
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) bm = fmaxf(bm, fabsf(pm[rt][c][kk] * (qv[c + rt][kk] * rs)));
+                }
+            }
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) bm = fmaxf(bm, __shfl_xor(bm, m));
+            int e = 0;
+            (void)frexpf(bm, &e);
+            const int sh = bm > 0.0f ? min(13 - e, 100) : 0;
+            bsc = ldexpf(1.0f, sh);
+            binv = ldexpf(1.0f, -sh);
+        }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             if (rt < nrt) {
@@ -659,8 +748,10 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
                     if (c < nc && c >= rt) {
                         float av[4];
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) av[kk] = pm[rt][c][kk] * (qv[c + rt][kk] * rs);
-                        acc[rt] = mac<FM>(acc[rt], aop<FM>(av), y[c]);
+                        for (int kk = 0; kk < 4; ++kk) av[kk] = pm[rt][c][kk] * (qv[c + rt][kk] * rs) * bsc;
+                        Aop<FM> ab = aop<FM>(av);
+                        if constexpr (FM == 2) ab.inv = binv;
+                        acc[rt] = mac<FM>(acc[rt], ab, y[c]);
                     }
                 }
             }
@@ -762,43 +853,69 @@ __global__ __launch_bounds__(256) void kbg_main(const BatEntry<T> *E, const int6
 // ------------------------------------------------------------------------------------
 // Plan-time helpers: Ahat (FP64 plan tables) -> A-operand order of the form's type;
 // Q_S for S < len.
+// Ahat entry (k, l) of submatrix r of level-major block b (zero outside M x M).
+template <int M>
+__device__ __forceinline__ double ahat_entry(const double *top, const double *bot, const Geometry &G, int64_t b, int r,
+                                             int k, int l)
+{
+    if (k >= M || l >= M) return 0.0;
+    int g = 0;
+    while (b >= (int64_t(1) << (g + 1)) - 1) {
+        b -= (int64_t(1) << (g + 1)) - 1;
+        ++g;
+    }
+    if (g <= G.groot) return top[((level_block_offset(g) + b) * 3 + r) * M * M + k * M + l];
+    constexpr int NCH = 3 * M / 2;
+    const int d = g - G.groot;
+    const int64_t Rn = b >> (d - 1);
+    const int64_t j = ((int64_t(1) << G.kd) - (int64_t(1) << d)) + (b - (Rn << (d - 1)));
+    const int64_t slot = j * M + k;
+    const int64_t grp = Rn * G.sub_groups + slot / 64;
+    const int ln = (int)(slot % 64);
+    const int el = r * M + l;
+    return bot[((grp * NCH + el / 2) * 64 + ln) * 2 + (el & 1)];
+}
+
+// FP16X2: per submatrix (block-major, r fastest) the power of two 2^-e that undoes its
+// scaling: the scaled entries have magnitude < 2^13.
+template <int M>
+__global__ void kb_ahat_scale(const double *top, const double *bot, Geometry G, float *inv, int64_t nsub)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nsub) return;
+    double m = 0.0;
+    for (int k = 0; k < M && k < 16; ++k)
+        for (int l = 0; l < M && l < 16; ++l) m = fmax(m, fabs(ahat_entry<M>(top, bot, G, e / 3, (int)(e % 3), k, l)));
+    int ex = 0;
+    (void)frexp(m, &ex);                       // m = f 2^ex, f in [1/2, 1)
+    inv[e] = m > 0.0 ? ldexpf(1.0f, ex - 13) : 1.0f;
+}
+
 template <int M, int FM>
-__global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, void *dst, int64_t blocks)
+__global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, void *dst, int64_t blocks,
+                             const float *inv)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (blk, r, lane, kk)
     if (e >= blocks * 3 * 256) return;
     const int kk = (int)(e & 3), lane = (int)((e >> 2) & 63);
     const int64_t br = e >> 8;
     const int r = (int)(br % 3);
-    int64_t b = br / 3;
-    int g = 0;
-    while (b >= (int64_t(1) << (g + 1)) - 1) {
-        b -= (int64_t(1) << (g + 1)) - 1;
-        ++g;
-    }
     const int k = lane & 15, l = Mx<float>::row(lane >> 4, kk);
-    double v = 0.0;
-    if (k < M && l < M) {
-        if (g <= G.groot) {
-            v = top[((level_block_offset(g) + b) * 3 + r) * M * M + k * M + l];
-        } else {
-            constexpr int NCH = 3 * M / 2;
-            const int d = g - G.groot;
-            const int64_t Rn = b >> (d - 1);
-            const int64_t j = ((int64_t(1) << G.kd) - (int64_t(1) << d)) + (b - (Rn << (d - 1)));
-            const int64_t slot = j * M + k;
-            const int64_t grp = Rn * G.sub_groups + slot / 64;
-            const int ln = (int)(slot % 64);
-            const int el = r * M + l;
-            v = bot[((grp * NCH + el / 2) * 64 + ln) * 2 + (el & 1)];
-        }
-    }
+    const double v = ahat_entry<M>(top, bot, G, br / 3, r, k, l);
     if (FM == 0) {
         ((float *)dst)[e] = (float)v;
-    } else {
+    } else if (FM == 1) {
         // 16 bytes per lane entry: four hi then four lo BF16 values
         const __bf16 hi = (__bf16)(float)v;
         const __bf16 lo = (__bf16)(float)(v - (double)(float)hi);
+        unsigned short *d16 = (unsigned short *)dst + (e >> 2) * 8 + kk;
+        d16[0] = __builtin_bit_cast(unsigned short, hi);
+        d16[4] = __builtin_bit_cast(unsigned short, lo);
+    } else {
+        // four hi then four lo FP16 values of the entry scaled by 1 / inv (a power of two)
+        const double vs = v / (double)inv[br];
+        const _Float16 hi = (_Float16)vs;
+        const _Float16 lo = (_Float16)(vs - (double)hi);
         unsigned short *d16 = (unsigned short *)dst + (e >> 2) * 8 + kk;
         d16[0] = __builtin_bit_cast(unsigned short, hi);
         d16[4] = __builtin_bit_cast(unsigned short, lo);
@@ -818,10 +935,19 @@ static hipError_t pack(const l2c_plan_s &p, void *dst, hipStream_t st)
     const int64_t blocks = level_block_offset(p.L);
     const int64_t total = blocks * 3 * 256;
     const dim3 grid((unsigned)((total + 255) / 256));
-    if (p.precision == L2C_BF16X2)
-        hipLaunchKernelGGL((kb_pack_ahat<M, 1>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks);
-    else
-        hipLaunchKernelGGL((kb_pack_ahat<M, 0>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks);
+    if (p.precision == L2C_FP16X2) {
+        if (!p.d_bS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((kb_ahat_scale<M>), dim3((unsigned)((blocks * 3 + 255) / 256)), dim3(256), 0, st, p.d_top,
+                           p.d_bot, p.geo, p.d_bS, blocks * 3);
+        hipLaunchKernelGGL((kb_pack_ahat<M, 2>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks,
+                           (const float *)p.d_bS);
+    } else if (p.precision == L2C_BF16X2) {
+        hipLaunchKernelGGL((kb_pack_ahat<M, 1>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks,
+                           (const float *)nullptr);
+    } else {
+        hipLaunchKernelGGL((kb_pack_ahat<M, 0>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks,
+                           (const float *)nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -866,6 +992,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
         a.gin = 0;
         a.NT = p.geo.NT;
         a.ahat = (const T *)p.d_bA;
+        a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
         a.Pt = (const T *)p.d_bP;
@@ -922,6 +1049,7 @@ hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, in
                           const ItemArrays *ia)
 {
     if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
+    if (p.precision == L2C_FP16X2) return run_batched<float, 2>(p, in, out, batch, st, ia);
     if (p.precision == L2C_BF16X2) return run_batched<float, 1>(p, in, out, batch, st, ia);
     return run_batched<float, 0>(p, in, out, batch, st, ia);
 }
@@ -973,7 +1101,7 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
         const l2c_plan_s &p = *plans[g];
         if (p.L < 1) continue;
         if (p.s > 32 || p.M > 16) return hipErrorInvalidValue;
-        fm = p.precision == L2C_BF16X2 ? 1 : 0;
+        fm = p.precision == L2C_FP16X2 ? 2 : p.precision == L2C_BF16X2 ? 1 : 0;
         const int64_t tiles = (items[g] + 15) / 16;
         if (tiles > p.bw_tiles) return hipErrorInvalidValue;
         const int L = p.L;
@@ -995,6 +1123,7 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
         a.gin = 0;
         a.NT = p.geo.NT;
         a.ahat = (const T *)p.d_bA;
+        a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
         a.Pt = (const T *)p.d_bP;
@@ -1082,7 +1211,7 @@ static hipError_t grouped_launch_fm(const BatGrouped *G, hipStream_t st)
 
 hipError_t batched_grouped_launch(const BatGrouped *G, hipStream_t st)
 {
-    return G->fm ? grouped_launch_fm<1>(G, st) : grouped_launch_fm<0>(G, st);
+    return G->fm == 2 ? grouped_launch_fm<2>(G, st) : G->fm == 1 ? grouped_launch_fm<1>(G, st) : grouped_launch_fm<0>(G, st);
 }
 
 }  // namespace l2c

@@ -146,6 +146,7 @@ struct l2c_plan_s {
     void *d_bP = nullptr;       // [2s]
     void *d_bQ = nullptr;       // [n_pad + 2s]
     void *d_bw = nullptr;
+    float *d_bS = nullptr;      // FP16X2: [blocks][3] factors undoing each submatrix's scaling
     int64_t bw_tiles = 0;
     // FP64 batches of short transforms (l2c_dense.hip): per parity the dense coefficient
     // matrix of Alg. 1, [2][HP][HP]

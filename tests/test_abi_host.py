@@ -75,6 +75,7 @@ def test_plan_ex_precision_and_batch_errors(lib):
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 1, 1, None) == -4   # FP32 form: rank <= 16
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 128, 16, 1, 1, None) == -4  # FP32 form: leaf <= 64
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 2, 1, None) == -4   # BF16X2 form: rank <= 16
+    assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 3, 1, None) == -4   # FP16X2 form: rank <= 16
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 9, 1, None) == -1
     assert L.leg2cheb_plan_ex(ctypes.byref(h), 100, 0, 64, 18, 0, 0, None) == -1   # max_batch < 1
     assert L.leg2cheb_plan(None, 100, 0, 64, 18) == -1
@@ -156,7 +157,7 @@ def test_builtin_tuning_table(lib):
     """The library's size buckets (used when a ragged batch is planned with tuning NULL):
     increasing n_max, even leaf sizes in [4, 128], ranks with kernels, FP64 rank >= 18 and
     batched-form rank <= 16, leaf <= 64; queries need no device."""
-    for prec in (lib.L2C_FP64, lib.L2C_FP32, lib.L2C_BF16X2):
+    for prec in (lib.L2C_FP64, lib.L2C_FP32, lib.L2C_BF16X2, lib.L2C_FP16X2):
         rows = lib.leg2cheb_batch_tuning(prec)
         assert rows
         assert all(a[0] < b[0] for a, b in zip(rows, rows[1:]))
@@ -178,7 +179,7 @@ def test_status_and_option_constants_match_header(lib):
     """The binding's option and status-bit values are the header's."""
     text = open(HEADER).read()
     for name in ("L2C_OPT_SINGLE_LAUNCH", "L2C_OPT_DIRECT", "L2C_OPT_EXCHANGE_TIMEOUT_US", "L2C_STATUS_EXCHANGE",
-                 "L2C_STATUS_WORKERS", "L2C_STATUS_STREAM", "L2C_FP64", "L2C_FP32", "L2C_BF16X2"):
+                 "L2C_STATUS_WORKERS", "L2C_STATUS_STREAM", "L2C_FP64", "L2C_FP32", "L2C_BF16X2", "L2C_FP16X2"):
         m = re.search(r"\b%s\s*=\s*(\d+)" % name, text)
         assert m, name
         assert int(m.group(1)) == getattr(lib, name), name

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2411_00033_amd import inputs
-from tolerances import TOL32, TOLBF
+from tolerances import TOL32, TOLBF, TOLF16
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,61 @@ def test_bf16x2_ragged_batch(l2c):
         assert err <= TOLBF, (n, d, err)
 
 
+# ----------------------------------------------------------------- FP16 hi+lo form
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("n", [129, 1024, 3000, 20000])
+def test_fp16x2_parity_sizes(l2c, n, direction):
+    """A batch of 21 (a full tile and a ragged one) against the oracle."""
+    import torch
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 150 + n % 97, batch=21)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 16, precision=l2c.L2C_FP16X2, max_batch=21) as p:
+        info = p.info
+        Z = p.execute(x).cpu().numpy()
+    assert info["precision"] == l2c.L2C_FP16X2 and info["path"] == l2c.L2C_PATH_BATCHED
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(21))
+    print("FP16X2 n=%d dir=%d E_inf=%.2e" % (n, direction, worst), flush=True)
+    assert worst <= TOLF16
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_fp16x2_transforms_of_any_scale_share_a_tile(l2c, direction):
+    """FP16 spans only 2^-24 .. 2^16: transforms scaled by 10^-30 .. 10^30 in one tile of 16
+    each keep the form's relative accuracy (every runtime operand is scaled per transform),
+    and the scaled results are the unscaled ones times the scale."""
+    import torch
+    n, B = 5000, 16
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 160, batch=B)
+    scale = 10.0 ** np.linspace(-30, 30, B)
+    Fs = F * scale[:, None]
+    with l2c.Plan(n, direction, 64, 16, precision=l2c.L2C_FP16X2, max_batch=B) as p:
+        Z = p.execute(torch.from_numpy(F).cuda()).cpu().numpy()
+        Zs = p.execute(torch.from_numpy(Fs).cuda()).cpu().numpy()
+    worst = 0.0
+    for b in range(B):
+        ref = oracle.transform(Fs[b], direction)
+        worst = max(worst, oracle.einf(Zs[b], ref))
+        assert oracle.einf(Zs[b] / scale[b], Z[b]) <= 1e-6, b
+    print("FP16X2 scaled tile dir=%d E_inf=%.2e" % (direction, worst), flush=True)
+    assert worst <= TOLF16
+
+
+def test_fp16x2_ragged_batch(l2c):
+    import torch
+    sizes = [70, 300, 1024, 3000, 3001, 20000] * 2
+    dirs = [0] * 6 + [1] * 6
+    xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 170 + i)).cuda() for i, n in enumerate(sizes)]
+    with l2c.BatchPlan(sizes, dirs, rank=16, precision=l2c.L2C_FP16X2) as bp:
+        zs = bp.execute(xs)
+        torch.cuda.synchronize()
+    worst = 0.0
+    for i, (n, d) in enumerate(zip(sizes, dirs)):
+        err = oracle.einf(zs[i].cpu().numpy(), oracle.transform(xs[i].cpu().numpy(), d))
+        worst = max(worst, err)
+        assert err <= TOLF16, (n, d, err)
+    print("FP16X2 ragged E_inf=%.2e" % worst, flush=True)
+
+
 # ----------------------------------------------------------------- 3-D line batch
 def test_lines_3d_round_trip(l2c):
     """A 256 x 256 x 1024 tensor, f_k = z/(k+1) along the last axis (65536 lines of
@@ -171,12 +226,13 @@ def test_config3_fp64_path(l2c, cfg3):
     assert worst <= 1e-13
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x2"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x2", "fp16x2"])
 def test_config3_batch_256x65536(l2c, cfg3, form):
     """The batched form on all 256 transforms: whole transforms 0, 255 and 6 seeded others
     against the oracle, and all 256 against the FP64 path."""
     import torch
-    prec, tol = (l2c.L2C_FP32, TOL32) if form == "fp32" else (l2c.L2C_BF16X2, TOLBF)
+    prec, tol = {"fp32": (l2c.L2C_FP32, TOL32), "bf16x2": (l2c.L2C_BF16X2, TOLBF),
+                 "fp16x2": (l2c.L2C_FP16X2, TOLF16)}[form]
     with l2c.Plan(65536, 0, 64, 16, precision=prec, max_batch=256) as p:
         assert p.info["path"] == l2c.L2C_PATH_BATCHED
         z = p.execute(cfg3["x"]).cpu().numpy()
