@@ -239,7 +239,7 @@ def lines_form(l2c, inputs, torch, K, W, flush, flush_sink):
     return rec
 
 
-def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink):
+def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink, small=True):
     """The n = 1024 single transform (latency, cold) and the 2048-transform ragged batch
     (n log-uniform in [128, 262144], directions 50/50) through BatchPlan.execute_ptrs."""
     stream = torch.cuda.current_stream()
@@ -260,17 +260,18 @@ def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink):
         return float(np.mean([st[i].elapsed_time(en[i]) for i in range(k)]))
 
     rec = {}
-    x1 = torch.from_numpy(inputs.decaying(1024, 1.0, inputs.SEED_BASE + 1)).cuda()
-    y1 = torch.empty_like(x1)
-    with l2c.Plan(1024, l2c.LEG2CHEB, 64, 18) as p1:
-        one = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
-               "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
-               "path": p1.info["path"]}
-        p1.set_direct(False)   # the same transform by Alg. 4
-        one["multipole"] = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
-                            "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
-                            "path": p1.info["path"]}
-        rec["n1024_single"] = one
+    if small:
+        x1 = torch.from_numpy(inputs.decaying(1024, 1.0, inputs.SEED_BASE + 1)).cuda()
+        y1 = torch.empty_like(x1)
+        with l2c.Plan(1024, l2c.LEG2CHEB, 64, 18) as p1:
+            one = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
+                   "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
+                   "path": p1.info["path"]}
+            p1.set_direct(False)   # the same transform by Alg. 4
+            one["multipole"] = {"us_per_execute_cold": timed(lambda: p1.execute(x1, y1), K) * 1e3,
+                                "us_per_execute_warm": timed(lambda: p1.execute(x1, y1), K, cold=False) * 1e3,
+                                "path": p1.info["path"]}
+            rec["n1024_single"] = one
     sizes, dirs = inputs.ragged_sizes(2048, inputs.SEED_BASE + 4)
     offs = np.concatenate([[0], np.cumsum(sizes)])
     x = torch.randn(int(offs[-1]), dtype=torch.float64, device="cuda")
@@ -298,7 +299,7 @@ def main():
                     help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-form and line-batch measurements (profiling the N=10^6 kernel alone)")
-    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d"],
+    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d", "ragged"],
                     help="fp32_batch: only the batched FP32 form (256 x 65536); lines_3d: only the "
                          "65536 lines of n = 1024 (FP64 dense path and FP32 form); e.g. under a profiler")
     args = ap.parse_args()
@@ -332,6 +333,10 @@ def main():
     if args.workload == "fp32_batch":
         rec = batched_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink, with_fp64=False)
         print(json.dumps({"workload": "fp32_batch", "steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
+        return
+    if args.workload == "ragged":
+        rec = small_and_ragged(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink, small=False)
+        print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
         return
     if args.workload == "lines_3d":
         rec = lines_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)

@@ -190,6 +190,7 @@ struct l2c_batch_s {
     const double **d_in = nullptr;          // [count] input pointers, in position order
     double **d_out = nullptr;               // [count] output pointers, in position order
     void *h_stage = nullptr;                // pinned [2][count] pointers for the copies
+    void *h_cap = nullptr;                  // pinned [2][count] pointers of the latest captured call
     hipEvent_t staged = nullptr;            // the last pointer copy
     hipEvent_t done = nullptr;              // the end of the last execute on its stream
     bool any = false;                       // done has been recorded
@@ -201,6 +202,11 @@ struct l2c_batch_s {
     std::vector<int> lane;
     // batched forms: one launch per kernel shape for all groups with L >= 1
     l2c::BatGrouped *grouped = nullptr;
+    // the kernels of an execute (everything after the pointer copies) captured once into a
+    // graph on a private stream and replayed by every later execute
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_failed = false;              // capture or instantiation failed: launch directly
 };
 
 namespace {
@@ -212,6 +218,9 @@ void free_batch(l2c_batch_s *b)
     l2c::dev_free((void *)b->d_in);
     l2c::dev_free(b->d_out);
     l2c::host_free(b->h_stage);
+    l2c::host_free(b->h_cap);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->done) (void)hipEventDestroy(b->done);
     l2c::batched_grouped_free(b->grouped);
@@ -221,6 +230,80 @@ void free_batch(l2c_batch_s *b)
         if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
     }
     delete b;
+}
+
+// Pointer lists of a ragged execute in group (position) order: dst[0:count] inputs,
+// dst[count:2 count] outputs.
+void stage_pointers(const l2c_batch_s *b, void **dst, const double *const *in, double *const *out)
+{
+    for (int64_t k = 0; k < b->count; ++k) {
+        dst[k] = (void *)in[b->order[k]];
+        dst[b->count + k] = (void *)out[b->order[k]];
+    }
+}
+
+int ensure_workspace(l2c_plan_s *p, int64_t batch);
+int ensure_bworkspace(l2c_plan_s *p, int64_t items);
+
+// The kernels of a ragged execute on stream st (the pointer lists are on the device).
+// Batched forms: direct groups (L = 0), then every other group in grouped launches.  FP64:
+// the groups run concurrently on the side streams, forked from and joined back into st;
+// FP64 groups take the three-launch path (single-launch kernels need all their workgroups
+// resident and are never run side by side).  Nothing here allocates (the workspaces are
+// sized at batch-plan time) or synchronizes, so the sequence can be captured.
+int enqueue_batch(l2c_batch_s *b, hipStream_t st)
+{
+    if (b->grouped) {
+        for (size_t g = 0; g < b->plans.size(); ++g) {
+            l2c_plan_s *p = b->plans[g];
+            if (p->L != 0) continue;
+            const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
+            const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
+            if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
+        }
+        return l2c::batched_grouped_launch(b->grouped, st) == hipSuccess ? L2C_OK : L2C_EHIP;
+    }
+    if (hipEventRecord(b->fork, st) != hipSuccess) return L2C_EHIP;
+    for (int k = 0; k < l2c_batch_s::kSide; ++k)
+        if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) return L2C_EHIP;
+    for (size_t g = 0; g < b->plans.size(); ++g) {
+        l2c_plan_s *p = b->plans[g];
+        hipStream_t gs = b->side[b->lane[g]];
+        const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
+        const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
+        if (use_batched(p)) {
+            if (items > p->bw_tiles * 16) return L2C_EINVAL;
+            if (l2c::launch_batched(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
+        } else if (p->d_dense) {
+            if (l2c::launch_dense(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
+        } else {
+            if (p->L > 0 && items > p->ws_batch) return L2C_EINVAL;
+            if (l2c::launch_execute(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
+        }
+    }
+    for (int k = 0; k < l2c_batch_s::kSide; ++k)
+        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess || hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess)
+            return L2C_EHIP;
+    return L2C_OK;
+}
+
+// Capture the kernels of an execute once, on the batch's private stream, and instantiate
+// the graph; on any failure the batch launches directly from then on.
+void build_batch_graph(l2c_batch_s *b)
+{
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const int rc = enqueue_batch(b, b->cap);
+        ok = hipStreamEndCapture(b->cap, &g) == hipSuccess && rc == L2C_OK && g;
+    }
+    if (ok) ok = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        b->exec = nullptr;
+        b->graph_failed = true;
+        (void)hipGetLastError();
+    }
 }
 
 int ensure_workspace(l2c_plan_s *p, int64_t batch)
@@ -452,13 +535,14 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
     if (rc == L2C_OK &&
         (l2c::dev_alloc(&b->d_n, (size_t)count * sizeof(int64_t)) != hipSuccess ||
          l2c::dev_alloc(&b->d_in, cb) != hipSuccess || l2c::dev_alloc(&b->d_out, cb) != hipSuccess ||
-         l2c::host_alloc(&b->h_stage, 2 * cb) != hipSuccess ||
+         l2c::host_alloc(&b->h_stage, 2 * cb) != hipSuccess || l2c::host_alloc(&b->h_cap, 2 * cb) != hipSuccess ||
          hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess))
         rc = L2C_ENOMEM;
     if (rc == L2C_OK && hipMemcpy(b->d_n, nord.data(), (size_t)count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
         rc = L2C_EHIP;
     if (rc == L2C_OK && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-                         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess))
+                         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess ||
+                         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess))
         rc = L2C_EHIP;
     for (int k = 0; k < l2c_batch_s::kSide && rc == L2C_OK; ++k)
         if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
@@ -524,60 +608,36 @@ int leg2cheb_batch_execute(l2c_batch_t b, const double *const *in, double *const
         if (it != outs.begin() && std::prev(it)->second > lo) return L2C_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return L2C_EHIP;
+    const size_t cb = (size_t)b->count * sizeof(void *);
+    if (cs == hipStreamCaptureStatusActive) {
+        // the caller captures this call into a graph of its own: the pointer copies read the
+        // batch's capture staging (the pointers of the latest captured call) when the graph
+        // runs; nothing here waits or synchronizes
+        stage_pointers(b, (void **)b->h_cap, in, out);
+        if (hipMemcpyAsync(b->d_in, b->h_cap, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(b->d_out, (void **)b->h_cap + b->count, cb, hipMemcpyHostToDevice, st) != hipSuccess)
+            return L2C_EHIP;
+        return enqueue_batch(b, st);
+    }
+    if (cs != hipStreamCaptureStatusNone) return L2C_EINVAL;   // a capture that was invalidated
     if (hipEventSynchronize(b->staged) != hipSuccess) return L2C_EHIP;   // previous pointer copy done
     // the previous execute (possibly on another stream) still reads the device pointer
     // lists and the group workspaces until it ends: this one starts after it
     if (b->any && hipStreamWaitEvent(st, b->done, 0) != hipSuccess) return L2C_EHIP;
-    const double **si = (const double **)b->h_stage;
-    double **so = (double **)b->h_stage + b->count;
-    for (int64_t k = 0; k < b->count; ++k) {
-        si[k] = in[b->order[k]];
-        so[k] = out[b->order[k]];
-    }
-    const size_t cb = (size_t)b->count * sizeof(void *);
-    if (hipMemcpyAsync(b->d_in, si, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(b->d_out, so, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipEventRecord(b->staged, st) != hipSuccess || hipEventRecord(b->fork, st) != hipSuccess)
+    stage_pointers(b, (void **)b->h_stage, in, out);
+    if (hipMemcpyAsync(b->d_in, b->h_stage, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_out, (void **)b->h_stage + b->count, cb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(b->staged, st) != hipSuccess)
         return L2C_EHIP;
-    if (b->grouped) {
-        // batched forms: direct groups (L = 0), then every other group in grouped launches
-        for (size_t g = 0; g < b->plans.size(); ++g) {
-            l2c_plan_s *p = b->plans[g];
-            if (p->L != 0) continue;
-            const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
-            const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
-            if (l2c::launch_execute(*p, nullptr, nullptr, items, st, &ia) != hipSuccess) return L2C_EHIP;
-        }
-        if (l2c::batched_grouped_launch(b->grouped, st) != hipSuccess || hipEventRecord(b->done, st) != hipSuccess)
-            return L2C_EHIP;
-        b->any = true;
-        return L2C_OK;
+    if (!b->exec && !b->graph_failed) build_batch_graph(b);
+    if (b->exec) {
+        if (hipGraphLaunch(b->exec, st) != hipSuccess) return L2C_EHIP;
+    } else {
+        const int rc = enqueue_batch(b, st);
+        if (rc != L2C_OK) return rc;
     }
-    for (int k = 0; k < l2c_batch_s::kSide; ++k)
-        if (hipStreamWaitEvent(b->side[k], b->fork, 0) != hipSuccess) return L2C_EHIP;
-    // Groups are independent and run concurrently on the side streams.  FP64 groups take the
-    // three-launch path: single-launch kernels need all their workgroups resident and are
-    // never run side by side.
-    for (size_t g = 0; g < b->plans.size(); ++g) {
-        l2c_plan_s *p = b->plans[g];
-        hipStream_t gs = b->side[b->lane[g]];
-        const int64_t k0 = b->gstart[g], items = b->gstart[g + 1] - k0;
-        const l2c::ItemArrays ia = {b->d_n + k0, b->d_in + k0, b->d_out + k0};
-        if (use_batched(p)) {
-            const int rc = ensure_bworkspace(p, items);
-            if (rc != L2C_OK) return rc;
-            if (l2c::launch_batched(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
-        } else if (p->d_dense) {
-            if (l2c::launch_dense(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
-        } else {
-            const int rc = ensure_workspace(p, items);
-            if (rc != L2C_OK) return rc;
-            if (l2c::launch_execute(*p, nullptr, nullptr, items, gs, &ia) != hipSuccess) return L2C_EHIP;
-        }
-    }
-    for (int k = 0; k < l2c_batch_s::kSide; ++k)
-        if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess || hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess)
-            return L2C_EHIP;
     if (hipEventRecord(b->done, st) != hipSuccess) return L2C_EHIP;
     b->any = true;
     return L2C_OK;
@@ -669,6 +729,11 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     if (p->L >= L2C_MAX_LEVELS - 1) {
         delete p;
         return L2C_EINVAL;
+    }
+    if (!batched_form(precision) && l2c::prepare_launches(*p) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return L2C_EHIP;
     }
     hipStream_t st = (hipStream_t)stream;
     if (p->L > 0) {

@@ -540,6 +540,8 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double *in, double *o
     }
 }
 
+static hipError_t direct_attrs();
+
 hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
                          const ItemArrays *ia)
 {
@@ -547,11 +549,7 @@ hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int
     const int64_t HPm = (p.n + 1) / 2;
     const size_t lds = sizeof(double) * (size_t)(3 * HPm + kDirRows);
     if (lds > 64 * 1024) {
-        static std::once_flag attr_once;
-        static hipError_t attr_err = hipSuccess;
-        std::call_once(attr_once, [] {
-            attr_err = hipFuncSetAttribute((const void *)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        });
+        const hipError_t attr_err = direct_attrs();
         if (attr_err != hipSuccess) return attr_err;
     }
     const unsigned blocks = (unsigned)(2 * ((HPm + kDirRows - 1) / kDirRows));
@@ -590,6 +588,46 @@ static size_t main_lds_bytes(const Geometry &G)
     return sizeof(double) * (size_t)main_lds_doubles(G.L, G.M, G.s, G.kd);
 }
 
+// Allow the full 160 KiB LDS of a gfx950 CU for k_up<M> and k_main<M> (once per process and
+// rank; the result is kept).  Plans call it when they are made, so that an execute captured
+// into a graph makes no such call.
+template <int M>
+static hipError_t main_attrs()
+{
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] {
+        attr_err = hipFuncSetAttribute((const void *)k_up<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (attr_err == hipSuccess)
+            attr_err =
+                hipFuncSetAttribute((const void *)k_main<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    return attr_err;
+}
+
+static hipError_t direct_attrs()
+{
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [] {
+        attr_err = hipFuncSetAttribute((const void *)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    return attr_err;
+}
+
+hipError_t prepare_launches(const l2c_plan_s &p)
+{
+    hipError_t e = direct_attrs();
+    if (e != hipSuccess || p.L == 0) return e;
+    switch (p.M) {
+#define L2C_CASE(MM) \
+    case MM: return main_attrs<MM>();
+        L2C_FOR_EACH_RANK(L2C_CASE)
+#undef L2C_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int M>
 static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t st,
                       const ItemArrays *ia, double *w)
@@ -609,15 +647,7 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
     a.ahat_bot = p.d_bot;
     const int64_t P = int64_t(1) << (G.L + 1);
     const size_t up_lds = up_lds_bytes(G), main_lds = main_lds_bytes(G);
-    // allow the full 160 KiB LDS of a gfx950 CU (once per process and rank; the result is kept)
-    static std::once_flag attr_once;
-    static hipError_t attr_err = hipSuccess;
-    std::call_once(attr_once, [] {
-        attr_err = hipFuncSetAttribute((const void *)k_up<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (attr_err == hipSuccess)
-            attr_err =
-                hipFuncSetAttribute((const void *)k_main<M>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    });
+    const hipError_t attr_err = main_attrs<M>();
     if (attr_err != hipSuccess) return attr_err;
     for (int64_t b0 = 0; b0 < batch; b0 += kMaxItemsPerLaunch) {
         ExecArgs c = a;

@@ -174,6 +174,8 @@ hipError_t launch_direct(const l2c_plan_s &p, const double *in, double *out, int
                          const ItemArrays *ia = nullptr);
 hipError_t launch_execute(const l2c_plan_s &p, const double *in, double *out, int64_t batch,
                           hipStream_t stream, const ItemArrays *ia = nullptr);
+// kernel attributes of the plan's FP64 launches, set once per process (plan time)
+hipError_t prepare_launches(const l2c_plan_s &p);
 // leg2cheb_execute_noalloc: the three-launch path with w in a fixed device array of
 // kNoallocScratchBytes (resolved per device by noalloc_scratch)
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;

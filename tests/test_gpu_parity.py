@@ -567,3 +567,49 @@ def test_direct_option_errors(l2c):
     with l2c.Plan(1024, 0, 64, 16, precision=l2c.L2C_FP32) as p:
         with pytest.raises(l2c.L2CError):
             p.set_direct(True)
+
+
+# ----------------------------------------------------------------- ragged batches in graphs
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ragged_batch_graph_capture_and_replay(l2c, precision):
+    """A ragged batch captured by the caller into a graph (torch.cuda.graph) and replayed
+    three times, with eager executes of the same batch (other outputs) and synchronizations
+    between the replays: every replay equals the eager execute bit for bit (the same
+    kernels), and the eager executes (replays of the batch's own internal graph) stay
+    right as well."""
+    import torch
+    sizes, dirs = inputs.ragged_sizes(96, inputs.SEED_BASE + 44)
+    sizes = np.concatenate([sizes, [1, 5, 100, 129, 1000, 4096]])
+    dirs = np.concatenate([dirs, [0, 1, 0, 1, 0, 1]])
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(inputs.SEED_BASE + 45)
+    flat = rng.standard_normal(int(offs[-1]))
+    for i, n in enumerate(sizes):
+        flat[offs[i]:offs[i + 1]] /= np.arange(1, n + 1, dtype=np.float64)
+    prec, rank = (l2c.L2C_FP64, 18) if precision == "fp64" else (l2c.L2C_FP32, 16)
+    x = torch.from_numpy(flat).cuda()
+    y_eager, y_graph, y_other = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    ptrs = lambda t: [t.data_ptr() + 8 * int(o) for o in offs[:-1]]
+    with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), rank=rank, precision=prec) as bp:
+        bp.execute_ptrs(ptrs(x), ptrs(y_eager))
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            bp.execute_ptrs(ptrs(x), ptrs(y_graph))
+        for rep in range(3):
+            y_graph.fill_(float("nan"))
+            y_other.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            bp.execute_ptrs(ptrs(x), ptrs(y_other))        # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(y_graph, y_eager), rep
+            assert torch.equal(y_other, y_eager), rep
+        del g
+    yh = y_eager.cpu().numpy()
+    tol = TOL[(0, 18)] if precision == "fp64" else TOL32
+    for i in range(0, len(sizes), 7):
+        d = int(dirs[i])
+        err = oracle.einf(yh[offs[i]:offs[i + 1]], oracle.transform(flat[offs[i]:offs[i + 1]], d))
+        assert err <= (TOL[(d, 18)] if precision == "fp64" else tol), (i, err)
