@@ -280,11 +280,12 @@ def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink, small=True):
     op = [y.data_ptr() + 8 * int(o) for o in offs[:-1]]
     rg = {"workload": "2048 transforms, n log-uniform in [128, 262144] (%d coefficients), directions 50/50"
                       % int(offs[-1])}
-    for tag, prec, rank in (("fp64", l2c.L2C_FP64, 18), ("fp32", l2c.L2C_FP32, 16)):
-        with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), rank=rank, precision=prec) as bp:
+    for tag, prec in (("fp64", l2c.L2C_FP64), ("fp32", l2c.L2C_FP32)):
+        # leaf size and rank per size bucket from the library's autotuned table
+        with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), precision=prec) as bp:
             ms = timed(lambda: bp.execute_ptrs(ip, op), max(2, K // 4))
             rg[tag] = {"ms_per_execute": ms, "Gcoeff_s": float(offs[-1]) / (ms * 1e-3) / 1e9,
-                       "groups": bp.info["groups"]}
+                       "groups": bp.info["groups"], "tuning": l2c.leg2cheb_batch_tuning(prec)}
     rec["ragged_2048"] = rg
     return rec
 

@@ -6,6 +6,7 @@
 // n_max(previous row) < n <= n_max; the last row covers every larger n.  The FP64 rows
 // keep rank >= 18 (the rank at which every far-field submatrix of both kernels meets the
 // FP64 accuracy target); the batched forms keep rank <= 16 and leaf <= 64.
+// Made 2026-12-03 12:45 UTC.
 #pragma once
 #include <stdint.h>
 
@@ -16,9 +17,14 @@ struct TuneRow {
     int32_t leaf_size, rank;
 };
 
-// untuned defaults: the paper's leaf (s = 32) and M = 18 in FP64, M = 16 in the batched forms
-static const TuneRow kTuneFP64[] = {{INT64_MAX, 64, 18}};
-static const TuneRow kTuneBatched[] = {{INT64_MAX, 64, 16}};
+static const TuneRow kTuneFP64[] = {{512, 128, 20},
+                                      {2048, 48, 20},
+                                      {8192, 48, 18},
+                                      {32768, 64, 18},
+                                      {INT64_MAX, 128, 18}};
+static const TuneRow kTuneBatched[] = {{512, 64, 16},
+                                      {2048, 32, 12},
+                                      {INT64_MAX, 64, 12}};
 
 inline int builtin_tuning(int precision, const TuneRow **rows)
 {

@@ -393,7 +393,7 @@ def test_ragged_batch_small(l2c):
     dirs = [i % 2 for i in range(len(sizes))]
     dirs[12] = dirs[13] = dirs[14] = 0
     xs = [torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 100 + i)).cuda() for i, n in enumerate(sizes)]
-    with l2c.BatchPlan(sizes, dirs) as bp:
+    with l2c.BatchPlan(sizes, dirs, leaf_size=64, rank=18) as bp:
         info = bp.info
         assert 1 <= info["groups"] < len(sizes) and info["table_bytes"] > 0
         # groups are (levels, direction): n = 1..64 direct, then L = 1..7
@@ -458,17 +458,18 @@ def ragged():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_config4_ragged_2048(l2c, ragged, precision):
-    """The ragged batch in one BatchPlan: every transform with n <= 16384 and 32 longer ones
-    against the oracle on all rows, per direction; every full output against the x = +-1
-    identities."""
+    """The ragged batch in one BatchPlan with the library's autotuned leaf size and rank per
+    size bucket: every transform with n <= 16384 and 32 longer ones against the oracle on all
+    rows, per direction; every full output against the x = +-1 identities."""
     import torch
     sizes, dirs, flat, offs = ragged["sizes"], ragged["dirs"], ragged["flat"], ragged["offs"]
-    prec, rank = (l2c.L2C_FP64, 18) if precision == "fp64" else (l2c.L2C_FP32, 16)
+    prec = l2c.L2C_FP64 if precision == "fp64" else l2c.L2C_FP32
     x = torch.from_numpy(flat).cuda()
     y = torch.empty_like(x)
     xs = [x[offs[i]:offs[i + 1]] for i in range(len(sizes))]
     ys = [y[offs[i]:offs[i + 1]] for i in range(len(sizes))]
-    with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), rank=rank, precision=prec) as bp:
+    # leaf size and rank per size bucket from the library's autotuned table (tuning NULL)
+    with l2c.BatchPlan(sizes.tolist(), dirs.tolist(), precision=prec) as bp:
         groups = bp.info["groups"]
         bp.execute(xs, ys)
         torch.cuda.synchronize()
