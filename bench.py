@@ -203,6 +203,27 @@ def batched_form(l2c, inputs, torch, K, W, flush, flush_sink, with_fp64=True):
         rec.update({"fp64_path_ms_per_execute": ms64, "fp64_path_Gcoeff_s": coeffs / (ms64 * 1e-3) / 1e9,
                     "einf_fp32_vs_fp64_path": d, "einf_bf16x2_vs_fp64_path": db, "einf_fp16x2_vs_fp64_path": dh})
         p64.close()
+        # the FP64 tile form (rank 16, 16 transforms per FP64 matrix-core tile)
+        yt = torch.empty_like(x)
+        pt = l2c.Plan(BATCH_N, l2c.LEG2CHEB, 64, 16, max_batch=BATCH_B)
+        mst = timed(pt, yt)
+        ev = HipEvents(2 * K)
+        for i in range(K):
+            torch.sum(flush, dim=0, out=flush_sink)
+            l2c.leg2cheb_set_timing_events(pt.handle, ev.ev[2 * i], ev.ev[2 * i + 1])
+            pt.execute(x, yt)
+        torch.cuda.synchronize()
+        l2c.leg2cheb_set_timing_events(pt.handle, 0, 0)
+        kmt = float(np.mean([ev.elapsed_ms(2 * i, 2 * i + 1) for i in range(K)]))
+        ev.close()
+        flops64 = (4.5 * s + 4 * 16 + 8.0 * 16 * 16 / s) * info["n_pad"] * BATCH_B
+        dt = (yt - y64).abs().max().item() / y64.abs().max().item()
+        rec["fp64_tile_form"] = {"ms_per_execute": mst, "Gcoeff_s": coeffs / (mst * 1e-3) / 1e9, "rank": 16,
+                                 "path": pt.info["path"], "kb_main_ms": kmt,
+                                 "TFLOPs_achieved": flops64 / (mst * 1e-3) / 1e12,
+                                 "mfma_fp64_frac": flops64 / (mst * 1e-3) / 1e12 / 78.6,
+                                 "einf_vs_fp64_path_rank18": dt}
+        pt.close()
     p32.close()
     return rec
 

@@ -174,7 +174,7 @@ bool batched_form(int precision)
 {
     return precision == L2C_FP32 || precision == L2C_BF16X2 || precision == L2C_FP16X2;
 }
-bool use_batched(const l2c_plan_s *p) { return p->L > 0 && batched_form(p->precision); }
+bool use_batched(const l2c_plan_s *p) { return p->L > 0 && (batched_form(p->precision) || p->tile64); }
 size_t elem_bytes(const l2c_plan_s *p) { return batched_form(p->precision) ? sizeof(float) : sizeof(double); }
 
 }  // namespace
@@ -383,10 +383,15 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
         (void)hipGetLastError();
         return L2C_ENOMEM;
     }
-    ok = l2c::launch_to_f32(p->d_T, (float *)p->d_bT, nT, st) == hipSuccess &&
-         l2c::launch_to_f32(p->d_B, (float *)p->d_bB, nB, st) == hipSuccess &&
-         l2c::launch_to_f32(p->d_P + l2c::kPLead, (float *)p->d_bP, nP, st) == hipSuccess &&
-         l2c::batched_build_tables(*p, p->d_bA, p->d_bQ, qlen, st) == hipSuccess &&
+    if (p->tile64)   // the FP64 tile form keeps the FP64 values
+        ok = hipMemcpyAsync(p->d_bT, p->d_T, nT * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_bB, p->d_B, nB * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_bP, p->d_P + l2c::kPLead, nP * 8, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    else
+        ok = l2c::launch_to_f32(p->d_T, (float *)p->d_bT, nT, st) == hipSuccess &&
+             l2c::launch_to_f32(p->d_B, (float *)p->d_bB, nB, st) == hipSuccess &&
+             l2c::launch_to_f32(p->d_P + l2c::kPLead, (float *)p->d_bP, nP, st) == hipSuccess;
+    ok = ok && l2c::batched_build_tables(*p, p->d_bA, p->d_bQ, qlen, st) == hipSuccess &&
          hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -528,7 +533,7 @@ int leg2cheb_batch_plan(l2c_batch_t *batch, int64_t count, const int64_t *n, con
             b->plans.push_back(pl);
             // groups run side by side: FP64 groups use the three-launch path
             pl->fused_on = false;
-            if (!batched_form(precision) && !pl->d_dense) rc = ensure_workspace(pl, items);
+            if (!use_batched(pl) && !pl->d_dense) rc = ensure_workspace(pl, items);
         }
     }
     const size_t cb = (size_t)count * sizeof(void *);
@@ -773,7 +778,12 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             free_plan(p);
             return L2C_EHIP;
         }
-        if (batched_form(precision)) {
+        // batches of FP64 transforms at rank <= 16: the FP64 tile form (16 transforms per
+        // FP64 matrix-core tile), unless the dense or direct products serve them better
+        p->tile64 = !batched_form(precision) && M <= 16 && leaf_size <= 64 && n <= (int64_t(1) << 28) &&
+                    max_batch >= l2c::kTile64MinBatch && !(n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) &&
+                    !(n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n));
+        if (batched_form(precision) || p->tile64) {
             int rc = build_batched_tables(p, st);
             if (rc == L2C_OK) rc = ensure_bworkspace(p, max_batch);
             if (rc != L2C_OK) {
@@ -891,7 +901,7 @@ int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int
 {
     if (!plan || batch < 0) return L2C_EINVAL;
     if (batch == 0) return L2C_OK;
-    if (plan->precision != L2C_FP64) return L2C_EUNSUPPORTED;
+    if (plan->precision != L2C_FP64 || plan->tile64) return L2C_EUNSUPPORTED;
     const int rc = check_execute(plan, in, out, batch);
     if (rc != L2C_OK) return rc;
     hipStream_t st = (hipStream_t)stream;

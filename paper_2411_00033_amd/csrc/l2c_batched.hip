@@ -28,6 +28,8 @@
 // The tables (Ahat in the A-operand order, T, B(0), P, Q) and the workspace hold the
 // form's precision; inputs and outputs stay FP64 (converted on load, scaled by step (7)
 // in FP64 on store).
+#include <type_traits>
+
 #include "l2c_device.h"
 #include "../../include/leg2cheb.h"
 
@@ -44,6 +46,18 @@ struct Mx<float> {
     }
     // accumulator register r of lane group q holds row 4q + r
     static __host__ __device__ constexpr int row(int q, int r) { return 4 * q + r; }
+};
+// The FP64 tile form: the same 16 x 16 x 4 shape on the FP64 matrix cores, whose
+// accumulator register r of lane group q holds row 4r + q.  Every operand of the forms is
+// built through row(q, r), so the step k of a product pairs the same rows on both sides.
+template <>
+struct Mx<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __host__ __device__ constexpr int row(int q, int r) { return 4 * r + q; }
 };
 
 template <typename T>
@@ -186,10 +200,18 @@ __device__ __forceinline__ void node_stage(T *slot, const double (&x)[16], int64
 // largest magnitude in that column (a reduction over the column's four lanes), so that
 // transforms of any scale share a tile.  A product is then (A' B') / (s_A s_B), scaled back
 // in FP32 before it joins the accumulator.
+// FM = 3 (the FP64 tile form): FP64 products and accumulation, four 16 x 16 x 4 FP64
+// instructions per tile product; tables and workspace in FP64.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 template <int FM>
+using form_t = typename std::conditional<FM == 3, double, float>::type;
+template <int FM>
 struct Aop;
+template <>
+struct Aop<3> {
+    double v[4];
+};
 template <>
 struct Aop<0> {
     float v[4];
@@ -224,10 +246,10 @@ __device__ __forceinline__ void split_bf16(const float (&x)[4], bf16x4 &hi, bf16
 }
 
 template <int FM>
-__device__ __forceinline__ Aop<FM> aop(const float (&x)[4])
+__device__ __forceinline__ Aop<FM> aop(const form_t<FM> (&x)[4])
 {
     Aop<FM> r;
-    if constexpr (FM == 0) {
+    if constexpr (FM == 0 || FM == 3) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) r.v[j] = x[j];
     } else if constexpr (FM == 1) {
@@ -242,10 +264,10 @@ __device__ __forceinline__ Aop<FM> aop(const float (&x)[4])
 // The 16 bytes of a packed table entry: four FP32 values, or four hi then four lo BF16 values.
 // (FP16X2: four hi then four lo FP16 values of the scaled submatrix; inv undoes the scaling.)
 template <int FM>
-__device__ __forceinline__ Aop<FM> aop_raw(const v4_t<float> &raw, float inv = 1.0f)
+__device__ __forceinline__ Aop<FM> aop_raw(const v4_t<form_t<FM>> &raw, float inv = 1.0f)
 {
     Aop<FM> r;
-    if constexpr (FM == 0) {
+    if constexpr (FM == 0 || FM == 3) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) r.v[j] = raw[j];
     } else {
@@ -269,7 +291,7 @@ template <int FM>
 __device__ __forceinline__ Aop<FM> pick(const Aop<FM> &a0, const Aop<FM> &a1, bool c)
 {
     Aop<FM> r;
-    if constexpr (FM == 0) {
+    if constexpr (FM == 0 || FM == 3) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) r.v[j] = c ? a1.v[j] : a0.v[j];
     } else {
@@ -282,11 +304,11 @@ __device__ __forceinline__ Aop<FM> pick(const Aop<FM> &a0, const Aop<FM> &a1, bo
 
 // acc += A B for one tile, B given as the lane's four values (rows row(q, j) of its column).
 template <int FM>
-__device__ __forceinline__ v4_t<float> mac(v4_t<float> acc, const Aop<FM> &a, const float (&b)[4])
+__device__ __forceinline__ v4_t<form_t<FM>> mac(v4_t<form_t<FM>> acc, const Aop<FM> &a, const form_t<FM> (&b)[4])
 {
-    if constexpr (FM == 0) {
+    if constexpr (FM == 0 || FM == 3) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc = Mx<float>::mma(a.v[j], b[j], acc);
+        for (int j = 0; j < 4; ++j) acc = Mx<form_t<FM>>::mma(a.v[j], b[j], acc);
     } else if constexpr (FM == 1) {
         bf16x4 bh, bl;
         split_bf16(b, bh, bl);
@@ -315,9 +337,10 @@ __device__ __forceinline__ v4_t<float> mac(v4_t<float> acc, const Aop<FM> &a, co
     return acc;
 }
 template <int FM>
-__device__ __forceinline__ v4_t<float> mac_tile(v4_t<float> acc, const Aop<FM> &a, const v4_t<float> &x)
+__device__ __forceinline__ v4_t<form_t<FM>> mac_tile(v4_t<form_t<FM>> acc, const Aop<FM> &a,
+                                                     const v4_t<form_t<FM>> &x)
 {
-    const float b[4] = {x[0], x[1], x[2], x[3]};
+    const form_t<FM> b[4] = {x[0], x[1], x[2], x[3]};
     return mac<FM>(acc, a, b);
 }
 
@@ -333,7 +356,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
     // A operands of the parent transfer: B(0) and B(1) = B(0) with odd diagonals negated
     Aop<FM> b0a, b1a;
     {
-        float v0[4], v1[4];
+        T v0[4], v1[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = Mx<T>::row(q, kk);
@@ -348,7 +371,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
     Aop<FM> ta[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        float v[4];
+        T v[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int m = 16 * c + 4 * q + kk;
@@ -386,7 +409,7 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (c < nch) {
-                    float b[4];
+                    T b[4];
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) b[kk] = 16 * c + 4 * q + kk < s ? y[c][kk] : T(0);
                     cur = mac<FM>(cur, ta[c], b);
@@ -574,7 +597,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         }
     }
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
-    float btv[2][4], tev[2][4];
+    T btv[2][4], tev[2][4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const int k = Mx<T>::row(q, kk);
@@ -746,7 +769,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (c < nc && c >= rt) {
-                        float av[4];
+                        T av[4];
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) av[kk] = pm[rt][c][kk] * (qv[c + rt][kk] * rs) * bsc;
                         Aop<FM> ab = aop<FM>(av);
@@ -900,9 +923,11 @@ __global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, v
     const int kk = (int)(e & 3), lane = (int)((e >> 2) & 63);
     const int64_t br = e >> 8;
     const int r = (int)(br % 3);
-    const int k = lane & 15, l = Mx<float>::row(lane >> 4, kk);
+    const int k = lane & 15, l = FM == 3 ? Mx<double>::row(lane >> 4, kk) : Mx<float>::row(lane >> 4, kk);
     const double v = ahat_entry<M>(top, bot, G, br / 3, r, k, l);
-    if (FM == 0) {
+    if (FM == 3) {
+        ((double *)dst)[e] = v;
+    } else if (FM == 0) {
         ((float *)dst)[e] = (float)v;
     } else if (FM == 1) {
         // 16 bytes per lane entry: four hi then four lo BF16 values
@@ -935,7 +960,10 @@ static hipError_t pack(const l2c_plan_s &p, void *dst, hipStream_t st)
     const int64_t blocks = level_block_offset(p.L);
     const int64_t total = blocks * 3 * 256;
     const dim3 grid((unsigned)((total + 255) / 256));
-    if (p.precision == L2C_FP16X2) {
+    if (p.precision == L2C_FP64) {
+        hipLaunchKernelGGL((kb_pack_ahat<M, 3>), grid, dim3(256), 0, st, p.d_top, p.d_bot, p.geo, dst, blocks,
+                           (const float *)nullptr);
+    } else if (p.precision == L2C_FP16X2) {
         if (!p.d_bS) return hipErrorInvalidValue;
         hipLaunchKernelGGL((kb_ahat_scale<M>), dim3((unsigned)((blocks * 3 + 255) / 256)), dim3(256), 0, st, p.d_top,
                            p.d_bot, p.geo, p.d_bS, blocks * 3);
@@ -960,8 +988,12 @@ hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kb_q_table<float>, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st, (float *)q_dst,
-                       q_len, p.direction);
+    if (p.precision == L2C_FP64)
+        hipLaunchKernelGGL(kb_q_table<double>, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st,
+                           (double *)q_dst, q_len, p.direction);
+    else
+        hipLaunchKernelGGL(kb_q_table<float>, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st,
+                           (float *)q_dst, q_len, p.direction);
     return hipGetLastError();
 }
 
@@ -972,7 +1004,8 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
 {
     const int L = p.L;
     const int ku = L - 1 < kBatUpDepth ? L - 1 : kBatUpDepth;
-    const int kd = L - 1 < kBatMainDepth ? L - 1 : kBatMainDepth;
+    const int kdmax = bat_main_depth(FM);
+    const int kd = L - 1 < kdmax ? L - 1 : kdmax;
     const int64_t Pn = int64_t(1) << (L + 1);
     for (int64_t b0 = 0; b0 < batch; b0 += kBatMaxTiles * 16) {
         const int64_t nb = batch - b0 < kBatMaxTiles * 16 ? batch - b0 : kBatMaxTiles * 16;
@@ -1032,10 +1065,21 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
 #define L2C_MAIN(KK, NN) \
     case KK * 8 + NN: hipLaunchKernelGGL((kb_main<T, KK, NN, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
 #define L2C_MAIN4(KK) L2C_MAIN(KK, 1) L2C_MAIN(KK, 2) L2C_MAIN(KK, 3) L2C_MAIN(KK, 4)
-                L2C_MAIN4(0) L2C_MAIN4(1) L2C_MAIN4(2) L2C_MAIN4(3)
+                L2C_MAIN4(0) L2C_MAIN4(1) L2C_MAIN4(2)
 #undef L2C_MAIN4
 #undef L2C_MAIN
-            default: return hipErrorInvalidValue;
+            default:
+                if constexpr (FM != 3) {   // the FP64 form stops at depth 2 (its LDS)
+                    switch (kd * 8 + nc) {
+                    case 3 * 8 + 1: hipLaunchKernelGGL((kb_main<T, 3, 1, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+                    case 3 * 8 + 2: hipLaunchKernelGGL((kb_main<T, 3, 2, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+                    case 3 * 8 + 3: hipLaunchKernelGGL((kb_main<T, 3, 3, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+                    case 3 * 8 + 4: hipLaunchKernelGGL((kb_main<T, 3, 4, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
+                    default: return hipErrorInvalidValue;
+                    }
+                } else {
+                    return hipErrorInvalidValue;
+                }
             }
             if (timed) (void)hipEventRecord(p.ev_after, st);
         }
@@ -1049,6 +1093,7 @@ hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, in
                           const ItemArrays *ia)
 {
     if (p.L < 1 || p.s > 32 || p.M > 16) return hipErrorInvalidValue;
+    if (p.precision == L2C_FP64) return run_batched<double, 3>(p, in, out, batch, st, ia);
     if (p.precision == L2C_FP16X2) return run_batched<float, 2>(p, in, out, batch, st, ia);
     if (p.precision == L2C_BF16X2) return run_batched<float, 1>(p, in, out, batch, st, ia);
     return run_batched<float, 0>(p, in, out, batch, st, ia);

@@ -43,6 +43,9 @@ constexpr int64_t kMaxItemsPerLaunch = 32768;  // grid.y limit with margin
 constexpr int kBatUpDepth = 3;
 constexpr int kBatTopDepth = 3;
 constexpr int kBatMainDepth = 3;
+// kb_main subtree depth per form: 3, and 2 for the FP64 tile form (FM = 3), whose FP64 LDS
+// tiles at depth 3 would leave room for one workgroup per CU
+__host__ __device__ constexpr int bat_main_depth(int fm) { return fm == 3 ? 2 : kBatMainDepth; }
 constexpr int64_t kBatMaxTiles = 32768;        // tiles (of 16 items) per launch
 
 __host__ __device__ inline int64_t node_offset(int g) { return (int64_t(1) << (g + 2)) - 4; }
@@ -146,6 +149,7 @@ struct l2c_plan_s {
     void *d_bP = nullptr;       // [2s]
     void *d_bQ = nullptr;       // [n_pad + 2s]
     void *d_bw = nullptr;
+    bool tile64 = false;        // an FP64 plan that executes in the FP64 tile form (l2c_batched.hip)
     float *d_bS = nullptr;      // FP16X2: [blocks][3] factors undoing each submatrix's scaling
     int64_t bw_tiles = 0;
     // FP64 batches of short transforms (l2c_dense.hip): per parity the dense coefficient
@@ -191,6 +195,9 @@ hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t ba
 hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst, int64_t q_len, hipStream_t stream);
 hipError_t launch_batched(const l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                           const ItemArrays *ia = nullptr);
+// The FP64 tile form: FP64 plans with rank <= 16, leaf <= 64 and max_batch >= kTile64MinBatch
+// (one 16-transform tile or more) that the dense path does not take
+constexpr int64_t kTile64MinBatch = 16;
 // l2c_dense.hip: FP64 plans with L >= 1, n <= kDenseMaxN and max_batch >= kDenseMinBatch
 constexpr int64_t kDenseMaxN = 4096, kDenseMinBatch = 64;
 int64_t dense_hp(int64_t n);

@@ -242,3 +242,40 @@ def test_config3_batch_256x65536(l2c, cfg3, form):
     print("cfg3 %s: E_inf vs oracle (8 whole transforms) %.2e, vs FP64 path (all 256) %.2e" % (form, e_or, e64),
           flush=True)
     assert e_or <= tol and e64 <= tol
+
+
+# ----------------------------------------------------------------- FP64 tile form
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("n", [5000, 20000, 70001])
+def test_fp64_tile_form_parity(l2c, n, direction):
+    """FP64 plans at rank 16 for batches of 16 or more take the FP64 tile form (16
+    transforms per FP64 matrix-core tile): every item of a batch of 21 (a full tile and a
+    ragged one) against the oracle at the FP64 bound."""
+    import torch
+    from tolerances import TOL64
+    B = 21
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 180 + n % 97, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 16, max_batch=B) as p:
+        info = p.info
+        Z = p.execute(x).cpu().numpy()
+        z1 = p.execute(x[B - 1]).cpu().numpy()
+    assert info["precision"] == l2c.L2C_FP64 and info["path"] == l2c.L2C_PATH_BATCHED
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(B))
+    print("FP64 tile form n=%d dir=%d E_inf=%.2e" % (n, direction, worst), flush=True)
+    assert worst <= TOL64[(direction, 18)]
+    assert np.array_equal(z1, Z[B - 1])
+
+
+def test_config3_fp64_tile_form(l2c, cfg3):
+    """The 256 x 65536 batch in the FP64 tile form (rank 16): whole transforms against the
+    oracle at the FP64 bound, all 256 against the FP64 path at rank 18."""
+    import torch
+    with l2c.Plan(65536, 0, 64, 16, max_batch=256) as p:
+        assert p.info["path"] == l2c.L2C_PATH_BATCHED
+        z = p.execute(cfg3["x"]).cpu().numpy()
+        torch.cuda.synchronize()
+    e_or = max(oracle.einf(z[b], ref) for b, ref in cfg3["refs"].items())
+    e64 = max(oracle.einf(z[b], cfg3["z64"][b]) for b in range(256))
+    print("cfg3 FP64 tile form: E_inf vs oracle %.2e, vs FP64 path rank 18 %.2e" % (e_or, e64), flush=True)
+    assert e_or <= 1e-13 and e64 <= 1e-13
