@@ -60,12 +60,17 @@ __device__ __forceinline__ double load_coherent(const double *p)
 // LDS executes a wave's operations in order; this keeps the compiler from reordering.
 __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
-// Wait until this wave's LDS operations are complete (s_waitcnt lgkmcnt(0)).
+// Wait until this wave's LDS operations are complete (s_waitcnt lgkmcnt(0)).  The fence
+// orders LDS only: a workgroup-wide fence would also wait for the wave's outstanding global
+// stores (exchange nodes on their way to other workgroups), which nothing here depends on.
 __device__ __forceinline__ void wave_lds_done()
 {
     __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
 }
+
+// The reader's side: LDS written by other waves before their release is visible.
+__device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
 
 // Barrier of the worker waves only (LDS counter; target is this wave's running count).
 __device__ __forceinline__ void worker_sync(unsigned *cnt, unsigned &target, const ExecArgs &a)
@@ -83,7 +88,7 @@ __device__ __forceinline__ void worker_sync(unsigned *cnt, unsigned &target, con
             }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    lds_acquire();
 }
 
 __device__ __forceinline__ void lds_flag_set(unsigned *f, unsigned v)
@@ -129,7 +134,7 @@ __device__ __forceinline__ void stream_group(const ExecArgs &ea, int grp, int nx
             }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    lds_acquire();
     const double *wa = wl + (fused_wofs(d) + 2 * i + 2) * NS;   // w(2i+2); w(2i+3) follows
     // one parity at a time (M column values in registers next to the 3-row ring)
     double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
@@ -676,21 +681,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             nbr[0] = 0;
             qdone[0] = 0;
         }
-        // this unit's exchange nodes in the next launch's half of the buffer: empty again, for
-        // items item, item + batch, ... (the next launch may hold more items than this one)
-        {
-            const int kx = X == 0 ? G0 : min(G0, __ffs(X) - 1);
-            const int nxq = 2 * (kd - 1), nq = 1 + nxq + (kx < 3 ? kx : 3);
-            for (int64_t it = item; it < a.pub_items; it += a.batch) {
-                for (int e = wt; e < nq * M2; e += NWT) {
-                    const int q = e / M2, r = e - q * M2;
-                    const int64_t id = q == 0     ? node_offset(G0) + X
-                                       : q <= nxq ? nbase + (q - 1)
-                                                  : node_offset(G0 - (q - nxq)) + (X >> (q - nxq));
-                    store_coherent(pubn + (it * G.NX + id) * M2 + r, pub_empty());
-                }
-            }
-        }
         __syncthreads();                              // with the streamers' barrier below
         L2C_TS(3, 1);
         // ---- step (3), own blocks.  Slot (j, k) of a group = row k of the three submatrices of
@@ -814,7 +804,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            lds_acquire();
         }
         // ---- step (6): near field.  Item (node nd, parity sig, rows m0 .. m0+R-1): row m sums
         //      over m' in [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig], with P, Q
@@ -834,6 +824,22 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             }
         }
         L2C_TS(3, 4);
+        // this unit's exchange nodes in the next launch's half of the buffer: empty again, for
+        // items item, item + batch, ... (the next launch may hold more items than this one); by
+        // the near waves, off the path to the published root
+        if (near) {
+            const int kx = X == 0 ? G0 : min(G0, __ffs(X) - 1);
+            const int nxq = 2 * (kd - 1), nq = 1 + nxq + (kx < 3 ? kx : 3);
+            for (int64_t it = item; it < a.pub_items; it += a.batch) {
+                for (int e = ntid; e < nq * M2; e += 64 * kNearWaves) {
+                    const int q = e / M2, r = e - q * M2;
+                    const int64_t id = q == 0     ? node_offset(G0) + X
+                                       : q <= nxq ? nbase + (q - 1)
+                                                  : node_offset(G0 - (q - nxq)) + (X >> (q - nxq));
+                    store_coherent(pubn + (it * G.NX + id) * M2 + r, pub_empty());
+                }
+            }
+        }
         // ---- steps (2)-(4) above the unit (TopSlots, top_gather, top_combine)
         const TopSlots ts(X, G0);
         double ag0[M], ag1[M];
