@@ -44,10 +44,13 @@ enum l2c_direction { L2C_LEG2CHEB = 0, L2C_CHEB2LEG = 1 };
  * plan builds its tables in FP64.
  *   L2C_FP64    every product and sum in FP64.
  *   L2C_FP32    the batched form (not in the paper: it serves batches of transforms):
- *               tables stored in FP32 and every product of steps (1)-(6) on the matrix
- *               cores in FP32 with FP32 accumulation, 16 transforms per 16 x 16 tile;
- *               step (7) scaling in FP64.  Needs rank <= 16, leaf_size <= 64 and
- *               n <= 2^28; E_inf about 1e-6 (rank 16).
+ *               the far part (steps (1)-(5)) from FP32 tables, every product on the
+ *               matrix cores in FP32 with FP32 accumulation, 16 transforms per 16 x 16
+ *               tile; the near field of step (6) (the dense near-diagonal leaf blocks),
+ *               the sum of near and far parts and step (7) in FP64 (FP64 matrix cores).
+ *               Needs rank <= 16, leaf_size <= 64 and n <= 2^28; E_inf about 1e-6 of the
+ *               far part's magnitude (rank 16): ~1e-9 on decaying inputs f_j ~ 1/j, up to
+ *               ~1e-7 on undecayed ones.
  *   L2C_BF16X2  the same batched form with every FP32 operand x split as hi = bf16(x),
  *               lo = bf16(x - hi) and each product formed as hi*hi + hi*lo + lo*hi on the
  *               BF16 matrix cores with FP32 accumulation (products accurate to about

@@ -374,23 +374,23 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
     const int64_t nT = 2 * (int64_t)s * M, nB = (int64_t)M * M, nP = 2 * (int64_t)s;
     const size_t eb = elem_bytes(p);
     bool ok = l2c::dev_alloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bQ, (size_t)qlen * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bQ, (size_t)qlen * sizeof(double)) == hipSuccess &&   // near field: FP64
               l2c::dev_alloc(&p->d_bT, nT * eb) == hipSuccess &&
               l2c::dev_alloc(&p->d_bB, nB * eb) == hipSuccess &&
-              l2c::dev_alloc(&p->d_bP, nP * eb) == hipSuccess &&
+              l2c::dev_alloc(&p->d_bP, nP * sizeof(double)) == hipSuccess &&
               (p->precision != L2C_FP16X2 || l2c::dev_alloc(&p->d_bS, (size_t)blocks * 3 * sizeof(float)) == hipSuccess);
     if (!ok) {
         (void)hipGetLastError();
         return L2C_ENOMEM;
     }
-    if (p->tile64)   // the FP64 tile form keeps the FP64 values
-        ok = hipMemcpyAsync(p->d_bT, p->d_T, nT * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_bB, p->d_B, nB * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
-             hipMemcpyAsync(p->d_bP, p->d_P + l2c::kPLead, nP * 8, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    // P (near field) stays FP64 in every form; the FP64 tile form keeps T and B(0) in FP64
+    ok = hipMemcpyAsync(p->d_bP, p->d_P + l2c::kPLead, nP * 8, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    if (p->tile64)
+        ok = ok && hipMemcpyAsync(p->d_bT, p->d_T, nT * 8, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(p->d_bB, p->d_B, nB * 8, hipMemcpyDeviceToDevice, st) == hipSuccess;
     else
-        ok = l2c::launch_to_f32(p->d_T, (float *)p->d_bT, nT, st) == hipSuccess &&
-             l2c::launch_to_f32(p->d_B, (float *)p->d_bB, nB, st) == hipSuccess &&
-             l2c::launch_to_f32(p->d_P + l2c::kPLead, (float *)p->d_bP, nP, st) == hipSuccess;
+        ok = ok && l2c::launch_to_f32(p->d_T, (float *)p->d_bT, nT, st) == hipSuccess &&
+             l2c::launch_to_f32(p->d_B, (float *)p->d_bB, nB, st) == hipSuccess;
     ok = ok && l2c::batched_build_tables(*p, p->d_bA, p->d_bQ, qlen, st) == hipSuccess &&
          hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
@@ -402,7 +402,7 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
     p->d_top = p->d_bot = nullptr;
     p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
     p->bot_bytes = 0;
-    p->table_bytes = p->top_bytes + (qlen + nT + nB + nP) * (int64_t)eb +
+    p->table_bytes = p->top_bytes + (nT + nB) * (int64_t)eb + (qlen + nP) * 8 +
                      (nT + 2 * nB + l2c::p_table_len(s) + M + nB) * 8 +
                      (p->d_bS ? blocks * 3 * (int64_t)sizeof(float) : 0);
     return L2C_OK;

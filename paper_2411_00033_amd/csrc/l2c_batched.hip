@@ -1,8 +1,10 @@
 // l2c_batched.hip -- the batched execution forms (precisions L2C_FP32, L2C_BF16X2 and
-// L2C_FP16X2): the modal multipole transform (arXiv 2411.00033, Alg. 4) for 16 transforms
-// at a time, every product of steps (1)-(6) on the gfx950 matrix cores with the batch as
-// the product's column dimension (FP32 products, or BF16 or FP16 hi+lo products with FP32
-// accumulation).
+// L2C_FP16X2, and the FP64 tile form): the modal multipole transform (arXiv 2411.00033,
+// Alg. 4) for 16 transforms at a time, every product of steps (1)-(6) on the gfx950 matrix
+// cores with the batch as the product's column dimension.  The far part (steps (1)-(5))
+// takes FP32 products, or BF16 or FP16 hi+lo products, with FP32 accumulation; the near
+// field of step (6) (the dense near-diagonal leaf blocks, where the largest terms and
+// their cancellations sit) and the sum of the two parts are FP64 in every form.
 //
 // A "tile" is the 16 x 16 matrix [k][item] of one tree node and parity for the 16
 // transforms of a workgroup row (blockIdx.y): the upward vectors w of Eq. (wTf) and
@@ -21,13 +23,13 @@
 //   kb_main  steps (3)-(7): one wave per level-groot subtree of 2^KD finest row nodes.
 //            The ancestors' c (levels 0..groot) come first (far-field blocks plus the
 //            downward transfer of step (4)); a depth-first walk then produces each
-//            finest node's c and evaluates it (Eq. (step5)) together with the near
-//            field of step (6) as one accumulator: the near-diagonal band of one node and
-//            parity is the dense s x 2s matrix P_{m'-m} Q_{S} (zero below the diagonal)
-//            times the input, on the matrix cores, with its factors from LDS.
-// The tables (Ahat in the A-operand order, T, B(0), P, Q) and the workspace hold the
-// form's precision; inputs and outputs stay FP64 (converted on load, scaled by step (7)
-// in FP64 on store).
+//            finest node's c and evaluates it (Eq. (step5)), and adds the near field of
+//            step (6): the near-diagonal band of one node and parity is the dense s x 2s
+//            matrix P_{m'-m} Q_{S} (zero below the diagonal) times the input, on the FP64
+//            matrix cores, with its factors and the staged input from LDS.
+// The far-part tables (Ahat in the A-operand order, T, B(0)) and the workspace hold the
+// form's precision, the near-field tables (P, Q) FP64; inputs and outputs stay FP64
+// (converted on load for the far part, scaled by step (7) in FP64 on store).
 #include <type_traits>
 
 #include "l2c_device.h"
@@ -76,8 +78,8 @@ struct BatArgs {
     const float *ahat_inv;          // FP16X2: [blocks][3] factor that undoes a submatrix's scaling
     const T *Tm;                    // [2][s][M]
     const T *B0;                    // [M][M]
-    const T *Pt;                    // [2s]: P_d
-    const T *Qt;                    // [n_pad + 2s]: Q_S
+    const double *Pt;               // [2s]: P_d (the near field is FP64 in every form)
+    const double *Qt;               // [n_pad + 2s]: Q_S
     T *w;                           // [tiles][NT][2][64][4]
     int64_t tile, bx;               // this workgroup's tile of 16 transforms and its block in the tile row
 };
@@ -194,11 +196,10 @@ __device__ __forceinline__ void node_stage(T *slot, const double (&x)[16], int64
 // (about 2^-22 relative per product) but span only 2^-24 .. 2^16.  So every operand is
 // scaled by a power of two before it is split: the A operands of the plan's Ahat per
 // submatrix (the table spans about 16 decades; the factor that undoes the scaling is
-// stored beside it), the near-field band per leaf from its largest magnitude, the other A
-// operands (T, B(0), B(1), of magnitude <= 1) not at all, and every B operand per column,
-// i.e. per transform, from the
-// largest magnitude in that column (a reduction over the column's four lanes), so that
-// transforms of any scale share a tile.  A product is then (A' B') / (s_A s_B), scaled back
+// stored beside it), the other A operands (T, B(0), B(1), of magnitude <= 1) not at all,
+// and every B operand per column, i.e. per transform, from the largest magnitude in that
+// column (a reduction over the column's four lanes), so that transforms of any scale
+// share a tile.  A product is then (A' B') / (s_A s_B), scaled back
 // in FP32 before it joins the accumulator.
 // FM = 3 (the FP64 tile form): FP64 products and accumulation, four 16 x 16 x 4 FP64
 // instructions per tile product; tables and workspace in FP64.
@@ -556,9 +557,9 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
     constexpr int QW = 64 * (1 << KD) + 32;          // Q window: 2s 2^KD + s, s <= 32
     constexpr int SL = 16 * kBatRow;                 // one staged node
     __shared__ v4_t<T> Fl[4][INNER > 0 ? INNER : 1][64];
-    __shared__ T Ql[4][QW];
+    __shared__ double Ql[4][QW];
     constexpr int OBS = 65;                          // output row stride (2s <= 64)
-    __shared__ T Sl[2][4 * SL + 16 * OBS];           // per subtree: input nodes u, u + 1; output rows
+    __shared__ double Sl[2][4 * SL + 16 * OBS];      // per subtree: input nodes u, u + 1; output rows
     L2C_TS(1, 0);
     const int lane = threadIdx.x & 63, wv = wave_id();
     const int li = lane & 15, q = lane >> 4, sg = wv & 1;
@@ -576,8 +577,8 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         for (int m = 8; m >= 1; m >>= 1) nm = fmax(nm, __shfl_xor(nm, m, 16));
         if ((double)(2 * (int64_t)s * ((a.bx * 2) << KD)) >= nm) return;
     }
-    T *Qw = Ql[wv];
-    T *in_sl = Sl[wv >> 1], *ob = Sl[wv >> 1] + 4 * SL;
+    double *Qw = Ql[wv];
+    double *in_sl = Sl[wv >> 1], *ob = Sl[wv >> 1] + 4 * SL;
 
     // Every load of the prologue is issued before the first one is waited for.
     // The first two input nodes (this wave: rows 8 sg .. 8 sg + 7).
@@ -587,13 +588,13 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
     // Q_S for S = 2 s u0 + [0, 2 s 2^KD + s); the rest of the window is zero, so every
     // read of the leaf loop below is of initialized memory
     constexpr int QR = QW / 64 + 1;
-    T qreg[QR];
+    double qreg[QR];
     {
         const int qn = 2 * s * (1 << KD) + s;
 #pragma unroll
         for (int k = 0; k < QR; ++k) {
             const int e = lane + 64 * k;
-            qreg[k] = e < qn ? a.Qt[2 * s * u0 + (e < qn ? e : 0)] : T(0);
+            qreg[k] = e < qn ? a.Qt[2 * s * u0 + (e < qn ? e : 0)] : 0.0;
         }
     }
     // A operands: B(p)^T (step (4)) and T(sigma) (Eq. (step5))
@@ -616,35 +617,15 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
             tev[rt][kk] = ok ? v : T(0);
         }
     // near-field factor P_{m'-m} of row m = 16 rt + l mod 16 and column m' = 16 c + 4 q + kk,
-    // zero outside the band m <= m' < 2s (and for rows m >= s): the same for every leaf.
-    // The FP64 form reads it per leaf from an LDS copy of P with 32 leading zeros (d < 0)
-    // instead of keeping 32 FP64 values per lane (which would leave one wave per SIMD);
-    // entries with m' >= 2s or m >= s meet zero operands or unused rows there.
-    constexpr bool kPinLds = FM == 3;
-    T pm[2][4][4];
-    __shared__ T Pband[kPinLds ? 96 : 1];
-    if constexpr (kPinLds) {
-        for (int e = threadIdx.x; e < 96; e += blockDim.x) {
-            const int d = e - 32;
-            Pband[e] = (d >= 0 && d < 2 * s) ? a.Pt[d >= 0 && d < 2 * s ? d : 0] : T(0);
-        }
-    } else {
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int m = 16 * rt + li, mp = 16 * c + 4 * q + kk;
-                    const bool nz = m < s && mp >= m && mp < 2 * s;
-                    const T pv = a.Pt[nz ? mp - m : 0];
-                    pm[rt][c][kk] = nz ? pv : T(0);
-                }
+    // zero outside the band m <= m' < 2s: read per leaf from an LDS copy of P with 32
+    // leading zeros (d < 0) instead of 32 FP64 values per lane; entries with m' >= 2s or
+    // m >= s meet zero operands or unused rows there.
+    __shared__ double Pband[96];
+    for (int e = threadIdx.x; e < 96; e += blockDim.x) {
+        const int d = e - 32;
+        Pband[e] = (d >= 0 && d < 2 * s) ? a.Pt[d >= 0 && d < 2 * s ? d : 0] : 0.0;
     }
-    auto pband = [&](int rt, int c, int kk) -> T {
-        if constexpr (kPinLds) return Pband[16 * c + 4 * q + kk - 16 * rt - li + 32];
-        else return pm[rt][c][kk];
-    };
+    auto pband = [&](int rt, int c, int kk) -> double { return Pband[16 * c + 4 * q + kk - 16 * rt - li + 32]; };
     const Aop<FM> bt0 = aop<FM>(btv[0]), bt1 = aop<FM>(btv[1]);
     const Aop<FM> te[2] = {aop<FM>(tev[0]), aop<FM>(tev[1])};
     // the first two ancestor levels' far-field operands
@@ -656,7 +637,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         const int e = lane + 64 * k;
         if (e < QW) Qw[e] = qreg[k];
     }
-    node_stage8<T>(in_sl, SL, xn, u0, s, lane, sg, dir, true);
+    node_stage8<double>(in_sl, SL, xn, u0, s, lane, sg, dir, true);
 
     // ancestors a_g = Rn >> (groot - g): c(a_0) = far; c(a_g) = far + B(p)^T c(a_{g-1});
     // the operands of levels g + 1 and g + 2 are in flight while level g is multiplied
@@ -669,7 +650,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         if (g > 0) cv = mac_tile<FM>(cv, pick<FM>(bt0, bt1, (Rn >> (groot - g)) & 1), cp);
         cp = cv;
     }
-    node_stage8<T>(in_sl + 2 * SL, SL, xn1, u0 + 1, s, lane, sg, dir, true);
+    node_stage8<double>(in_sl + 2 * SL, SL, xn1, u0 + 1, s, lane, sg, dir, true);
     L2C_TS(1, 1);
     // far field of the own nodes above the finest depth (depth-major), pipelined, into LDS
     if (INNER > 0) {
@@ -706,18 +687,18 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         const int64_t base = 2 * s * u;
         const FarIn<T> fcu = fnx;
         // B operands: g at m' = 16 c + 4 q + kk (node u for m' < s, node u + 1 after)
-        T y[4][4];
+        double y[4][4];
         {
-            const T *n0 = in_sl + (i & 1) * 2 * SL + sg * SL + li * kBatRow;
-            const T *n1 = in_sl + ((i + 1) & 1) * 2 * SL + sg * SL + li * kBatRow;
+            const double *n0 = in_sl + (i & 1) * 2 * SL + sg * SL + li * kBatRow;
+            const double *n1 = in_sl + ((i + 1) & 1) * 2 * SL + sg * SL + li * kBatRow;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int mp = 16 * c + 4 * q + kk;
-                    const T *src = mp < s ? n0 + mp : n1 + (mp < 2 * s ? mp - s : 0);
-                    const T v = *src;
-                    y[c][kk] = (c < nc && mp < 2 * s) ? v : T(0);
+                    const double *src = mp < s ? n0 + mp : n1 + (mp < 2 * s ? mp - s : 0);
+                    const double v = *src;
+                    y[c][kk] = (c < nc && mp < 2 * s) ? v : 0.0;
                 }
         }
         if (i + 1 < (1 << KD)) {
@@ -741,67 +722,61 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
             if (rt < nrt) acc[rt] = mac_tile<FM>(acc[rt], te[rt], cu);
-        // near field (step (6)): row m, column m' = 16 c + 4 q + kk:
+        // near field (step (6)), in FP64 in every form (products and sums on the FP64 matrix
+        // cores): row m, column m' = 16 c + 4 q + kk:
         //   rs_i P_{m'-m} Q_{2 s u + sigma + m + m'} (m <= m' < 2s) times g_{2 s u + 2 m' + sigma}
         // Q enters through m + m' = 16 (c + rt) + 4 q + kk + l mod 16: 20 values per leaf
-        const T *Qu = Qw + 2 * s * i + sg + 4 * q + li;
-        T qv[5][4];
+        const double *Qu = Qw + 2 * s * i + sg + 4 * q + li;
+        double qv[5][4];
 #pragma unroll
         for (int cr = 0; cr < 5; ++cr)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) qv[cr][kk] = Qu[16 * cr + kk];
-        // FP16X2: the band is scaled by one power of two per leaf, from its largest magnitude
-        // (its entries P Q rs fall off by about 3 decades across a node, and with Q and rs
-        // they reach far below FP16's normal range for large S)
-        float bsc = 1.0f, binv = 1.0f;
-        if constexpr (FM == 2) {
-            float bm = 0.0f;
+        // the FP64 form adds the band to the far part's accumulator; the others keep it apart
+        // (FP64 accumulator, rows row(q, r) of the FP64 layout) and add the two in FP64 below
+        v4_t<double> an[2];
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-                if (rt < nrt) {
-                    const unsigned i32 = (unsigned)base + 2u * (unsigned)(16 * rt + li) + (unsigned)sg;
-                    const T rs = dir == 1 ? (T)(2u * i32 + 1u) : T(1);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if (c < nc && c >= rt)
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) bm = fmaxf(bm, fabsf(pband(rt, c, kk) * (qv[c + rt][kk] * rs)));
-                }
-            }
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) bm = fmaxf(bm, __shfl_xor(bm, m));
-            int e = 0;
-            (void)frexpf(bm, &e);
-            const int sh = bm > 0.0f ? min(13 - e, 100) : 0;
-            bsc = ldexpf(1.0f, sh);
-            binv = ldexpf(1.0f, -sh);
+        for (int rt = 0; rt < 2; ++rt) {
+            if constexpr (FM == 3) an[rt] = acc[rt];
+            else an[rt] = v4_zero<double>();
         }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             if (rt < nrt) {
-                // rs_i = 2i + 1 (cheb2leg), in the form's precision
-                const unsigned i32 = (unsigned)base + 2u * (unsigned)(16 * rt + li) + (unsigned)sg;
-                const T rs = dir == 1 ? (T)(2u * i32 + 1u) : T(1);
+                // rs_i = 2i + 1 (cheb2leg)
+                const int64_t ir = base + 2 * (16 * rt + li) + sg;
+                const double rs = dir == 1 ? (double)(2 * ir + 1) : 1.0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (c < nc && c >= rt) {
-                        T av[4];
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) av[kk] = pband(rt, c, kk) * (qv[c + rt][kk] * rs) * bsc;
-                        Aop<FM> ab = aop<FM>(av);
-                        if constexpr (FM == 2) ab.inv = binv;
-                        acc[rt] = mac<FM>(acc[rt], ab, y[c]);
+                        for (int kk = 0; kk < 4; ++kk)
+                            an[rt] = Mx<double>::mma(pband(rt, c, kk) * (qv[c + rt][kk] * rs), y[c][kk], an[rt]);
                     }
                 }
             }
         }
         // output rows of this parity through LDS: lane holds rows m = 16 rt + row(q, r) of
         // transform l mod 16; stored two transforms per instruction, lane -> row
+        if constexpr (FM != 3) {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+                if (rt < nrt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        ob[li * OBS + 2 * (16 * rt + Mx<float>::row(q, r)) + sg] = (double)acc[rt][r];
+                }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // other lanes add to these rows
+        }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
             if (rt < nrt) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ob[li * OBS + 2 * (16 * rt + Mx<T>::row(q, r)) + sg] = acc[rt][r];
+                for (int r = 0; r < 4; ++r) {
+                    double *o = ob + li * OBS + 2 * (16 * rt + Mx<double>::row(q, r)) + sg;
+                    if constexpr (FM == 3) *o = an[rt][r];
+                    else *o += an[rt][r];
+                }
             }
         __syncthreads();
         {
@@ -813,7 +788,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
             for (int r = 0; r < 8; ++r) {
                 const int tr = 8 * sg + r;
                 const int64_t nr = row_n(it, tr);
-                double v = (double)ob[tr * OBS + (lane < 2 * s ? lane : 0)] * sc;
+                double v = ob[tr * OBS + (lane < 2 * s ? lane : 0)] * sc;
                 if (dir == 1 && base == 0 && nr > 0) {
                     const double f0 = row_in(it, tr)[0];
                     if (iz == 0) v += f0;   // K_00 u_0 = u_0 / 2 = f_0
@@ -823,7 +798,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         }
         // the next leaf's second node replaces node u (read above by both parity waves)
         if (i + 1 < (1 << KD)) {
-            node_stage8<T>(in_sl + (i & 1) * 2 * SL, SL, xn, u + 2, s, lane, sg, dir, true);
+            node_stage8<double>(in_sl + (i & 1) * 2 * SL, SL, xn, u + 2, s, lane, sg, dir, true);
             __syncthreads();
         }
         if (i == 0) L2C_TS(1, 3);
@@ -963,11 +938,10 @@ __global__ void kb_pack_ahat(const double *top, const double *bot, Geometry G, v
     }
 }
 
-template <typename T>
-__global__ void kb_q_table(T *Qt, int64_t len, int dir)
+__global__ void kb_q_table(double *Qt, int64_t len, int dir)
 {
     const int64_t S = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (S < len) Qt[S] = (T)near_Q(dir, S);
+    if (S < len) Qt[S] = near_Q(dir, S);
 }
 
 template <int M>
@@ -1004,12 +978,8 @@ hipError_t batched_build_tables(const l2c_plan_s &p, void *ahat_dst, void *q_dst
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (p.precision == L2C_FP64)
-        hipLaunchKernelGGL(kb_q_table<double>, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st,
-                           (double *)q_dst, q_len, p.direction);
-    else
-        hipLaunchKernelGGL(kb_q_table<float>, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st,
-                           (float *)q_dst, q_len, p.direction);
+    hipLaunchKernelGGL(kb_q_table, dim3((unsigned)((q_len + 255) / 256)), dim3(256), 0, st, (double *)q_dst, q_len,
+                       p.direction);
     return hipGetLastError();
 }
 
@@ -1044,8 +1014,8 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
         a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
-        a.Pt = (const T *)p.d_bP;
-        a.Qt = (const T *)p.d_bQ;
+        a.Pt = (const double *)p.d_bP;
+        a.Qt = (const double *)p.d_bQ;
         a.w = (T *)p.d_bw;
         {
             const unsigned gx = (unsigned)(((Pn >> ku) + 1) / 2);
@@ -1084,18 +1054,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
                 L2C_MAIN4(0) L2C_MAIN4(1) L2C_MAIN4(2)
 #undef L2C_MAIN4
 #undef L2C_MAIN
-            default:
-                if constexpr (FM != 3) {   // the FP64 form stops at depth 2 (its LDS)
-                    switch (kd * 8 + nc) {
-                    case 3 * 8 + 1: hipLaunchKernelGGL((kb_main<T, 3, 1, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
-                    case 3 * 8 + 2: hipLaunchKernelGGL((kb_main<T, 3, 2, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
-                    case 3 * 8 + 3: hipLaunchKernelGGL((kb_main<T, 3, 3, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
-                    case 3 * 8 + 4: hipLaunchKernelGGL((kb_main<T, 3, 4, FM>), dim3(gx, tiles), dim3(256), 0, st, a); break;
-                    default: return hipErrorInvalidValue;
-                    }
-                } else {
-                    return hipErrorInvalidValue;
-                }
+            default: return hipErrorInvalidValue;
             }
             if (timed) (void)hipEventRecord(p.ev_after, st);
         }
@@ -1187,8 +1146,8 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
         a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
-        a.Pt = (const T *)p.d_bP;
-        a.Qt = (const T *)p.d_bQ;
+        a.Pt = (const double *)p.d_bP;
+        a.Qt = (const double *)p.d_bQ;
         a.w = (T *)p.d_bw;
         a.tile = a.bx = 0;
         cls[std::make_tuple(0, ku, 0, 0)].push_back({a, ((Pn >> ku) + 1) / 2});
@@ -1259,7 +1218,7 @@ static hipError_t grouped_launch_fm(const BatGrouped *G, hipStream_t st)
 #define L2C_GMAIN(KK, NN) \
     case 2 * 64 + KK * 8 + NN: hipLaunchKernelGGL((kbg_main<T, KK, NN, FM>), grid, blk, 0, st, E, l.blk0, l.n); break;
 #define L2C_GMAIN4(KK) L2C_GMAIN(KK, 1) L2C_GMAIN(KK, 2) L2C_GMAIN(KK, 3) L2C_GMAIN(KK, 4)
-            L2C_GMAIN4(0) L2C_GMAIN4(1) L2C_GMAIN4(2) L2C_GMAIN4(3)
+            L2C_GMAIN4(0) L2C_GMAIN4(1) L2C_GMAIN4(2)
 #undef L2C_GMAIN4
 #undef L2C_GMAIN
         default: return hipErrorInvalidValue;

@@ -42,10 +42,11 @@ constexpr int64_t kMaxItemsPerLaunch = 32768;  // grid.y limit with margin
 // subtree of 2^depth nodes in each of its three kernels.
 constexpr int kBatUpDepth = 3;
 constexpr int kBatTopDepth = 3;
-constexpr int kBatMainDepth = 3;
-// kb_main subtree depth per form: 3, and 2 for the FP64 tile form (FM = 3), whose FP64 LDS
-// tiles at depth 3 would leave room for one workgroup per CU
-__host__ __device__ constexpr int bat_main_depth(int fm) { return fm == 3 ? 2 : kBatMainDepth; }
+// kb_main subtree depth, every form: at depth 3 its FP64 LDS (the near field's staged input,
+// Q window and output rows; the FP64 tile form's far-field tiles) would leave room for one
+// workgroup per CU
+constexpr int kBatMainDepth = 2;
+__host__ __device__ constexpr int bat_main_depth(int) { return kBatMainDepth; }
 constexpr int64_t kBatMaxTiles = 32768;        // tiles (of 16 items) per launch
 
 __host__ __device__ inline int64_t node_offset(int g) { return (int64_t(1) << (g + 2)) - 4; }

@@ -11,29 +11,39 @@ max|z| stays at 1e-15 .. 1e-14 (measured: 2.3e-15 at N = 10^6, 8.4e-15 on the ra
 batch).  The uniform-input protocol of Table 1 (r = 0) is held to its own printed values
 instead (Table 1 reports cheb2leg errors up to 2e-13 for the paper's code).
 
-FP32 form (rank 16): every product in FP32 (unit roundoff u = 2^-24) with FP32
-accumulation; inputs rounded once, outputs scaled and stored in FP64.  An output row is
-a sum of at most 2s near-field terms plus a far-field value built through L upward and L
-downward transfers of M-term sums: random signs give about sqrt(2s + 2LM) u ~ 1e-6 at
-s = 32, L = 9, M = 16, a worst-case sign pattern (2s + 2LM) u ~ 2e-5.  Measured maximum
-over every configuration: 7.4e-7 (the ragged batch of configuration 4); the bound is about
-3x that.
+Batched forms (rank 16): the near field of step (6) (the dense near-diagonal leaf block)
+and the final sum of near and far parts are FP64 in every form; the far part (steps
+(1)-(5): T, B, Ahat products) runs in the form's precision with FP32 accumulation.  So the
+error is the far part's: about u_form sqrt(2LM) times the far part's magnitude, which on
+the decaying inputs f_j = z_j/(j+1) of the configurations is ~1e-3 .. 1e-2 of max|z|.
+
+FP32 form: unit roundoff 2^-24.  Measured maximum over every configuration input (decaying):
+5.6e-9 (n = 20000, leaf 32); the bound is about 3x that.  On undecayed inputs (uniform on
+[0, 1), the protocol of Table 1) the far part is of the order of max|z|: TOL32_U and
+its siblings below.
 
 BF16 hi+lo form: each product is ah bh + ah bl + al bh (al bl dropped, lo parts rounded)
-with FP32 accumulation, about 2^-17 relative per product: random signs give
-sqrt(352) 2^-17 ~ 1.4e-4 as a model bound.  Measured maximum over every configuration:
-1.14e-5 (n = 1024, cheb2leg); the bound is about 3x that.
+with FP32 accumulation, about 2^-17 relative per product.  Measured maximum (decaying):
+2.5e-8 (n = 20000, leg2cheb); the bound is about 3x that.
+
+FP16 hi+lo form: products of 22-bit operands (about 2^-22 relative per product; the
+scaling by powers of two is exact), FP32 accumulation.  Measured maximum (decaying):
+1.0e-9 (n = 129); the bound is about 3x that.  A tile whose transforms are scaled by
+10^-30 .. 10^30 loses accuracy where the tiny ones' far-field products fall into FP32's
+subnormal range: measured 2.5e-7, bound TOLF16_SCALED.
 """
 
 TOL64 = {(0, 18): 1e-13, (1, 18): 1e-13, (0, 20): 1e-13, (1, 20): 1e-13,
          (0, 24): 1e-13, (1, 24): 1e-13,
          # lower ranks: the rank's own truncation error
          (0, 16): 1e-12, (1, 16): 1e-11, (0, 12): 1e-9, (1, 12): 1e-8}
-TOL32 = 2.5e-6
-# FP16 hi+lo form: products of 22-bit operands (the lo parts' rounding and the dropped
-# lo lo term leave about 2^-22 relative per product; the scaling by powers of two is
-# exact), FP32 accumulation as in the FP32 form, so the FP32 form's error model applies.
-# Measured maximum over every configuration: 5.9e-7 (the 256 x 65536 batch against the FP64
-# path); the bound is about 3x that.
-TOLF16 = 2e-6
-TOLBF = 3.5e-5
+TOL32 = 2e-8
+TOLBF = 8e-8
+TOLF16 = 3e-9
+TOLF16_SCALED = 7.5e-7
+# undecayed inputs (uniform on [0, 1)), n = 20000, 16 transforms, both directions
+# (test_batched_forms_undecayed): measured 2.75e-7 (FP32), 8.3e-6 (BF16 hi+lo), 2.2e-7
+# (FP16 hi+lo), all in leg2cheb; the bounds are about 3x those
+TOL32_U = 8.5e-7
+TOLBF_U = 2.5e-5
+TOLF16_U = 6.5e-7
