@@ -311,6 +311,48 @@ def small_and_ragged(l2c, inputs, torch, K, W, flush, flush_sink, small=True):
     return rec
 
 
+def grid_form(l2c, inputs, torch, K, W, flush, flush_sink):
+    """The grid pipeline at N = 10^6 (Legendre series on the Chebyshev-Gauss grid and back,
+    Sec. 1) and the DCTs alone (Sec. 5.2 times the FMM against a DCT of type 2), cold; the
+    FMM's time is that of leg2cheb on the same input, so fmm_over_dct2 is the paper's ratio."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        for i in range(K):
+            torch.sum(flush, dim=0, out=flush_sink)
+            st[i].record(stream)
+            fn()
+            en[i].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([st[i].elapsed_time(en[i]) for i in range(K)]))
+
+    n = N
+    x = torch.from_numpy(inputs.decaying(n, 0.5, inputs.SEED_BASE + 2)).cuda()
+    u = torch.empty_like(x)
+    back = torch.empty_like(x)
+    rec = {"workload": "N=1000000, f_j = z_j/sqrt(j+1); leg2grid = leg2cheb + DCT-3, grid2leg = DCT-2 + cheb2leg "
+                       "(leaf 64, rank 18, FP64); DCTs on the library's FFT (1000 x 1000 four-step); cold HBM"}
+    with l2c.GridPlan(n, l2c.LEG2GRID) as fw, l2c.GridPlan(n, l2c.GRID2LEG) as bw, \
+            l2c.Dct(n, 2) as d2, l2c.Dct(n, 3) as d3, l2c.Plan(n, l2c.LEG2CHEB, LEAF, RANK) as p:
+        rec["leg2grid_ms"] = timed(lambda: fw.execute(x, u))
+        rec["grid2leg_ms"] = timed(lambda: bw.execute(u, back))
+        rec["dct2_ms"] = timed(lambda: d2.execute(x, back))
+        rec["dct3_ms"] = timed(lambda: d3.execute(x, back))
+        rec["fmm_leg2cheb_ms"] = timed(lambda: p.execute(x, back))
+        bw.execute(fw.execute(x, u), back)
+        torch.cuda.synchronize()
+        rec["round_trip_einf"] = ((back - x).abs().max() / x.abs().max()).item()
+    rec["fmm_over_dct2"] = rec["fmm_leg2cheb_ms"] / rec["dct2_ms"]
+    rec["dct2_GBs_io"] = 16.0 * n / (rec["dct2_ms"] * 1e-3) / 1e9
+    rec["leg2grid_Gcoeff_s"] = n / (rec["leg2grid_ms"] * 1e-3) / 1e9
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,9 +363,9 @@ def main():
                     help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-form and line-batch measurements (profiling the N=10^6 kernel alone)")
-    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d", "ragged"],
+    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d", "ragged", "grid"],
                     help="fp32_batch: only the batched FP32 form (256 x 65536); lines_3d: only the "
-                         "65536 lines of n = 1024 (FP64 dense path and FP32 form); e.g. under a profiler")
+                         "65536 lines of n = 1024 (FP64 dense path and FP32 form); grid: the grid pipeline and the DCTs at N = 10^6; e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the transform is a single-GPU kernel path "
@@ -362,6 +404,10 @@ def main():
         return
     if args.workload == "lines_3d":
         rec = lines_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)
+        print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
+        return
+    if args.workload == "grid":
+        rec = grid_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)
         print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
         return
 
@@ -480,6 +526,7 @@ def main():
         rec["batched_fp32_form"] = batched_form(l2c, inputs, torch, min(K, 20), min(W, 5), flush, flush_sink)
         rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
         rec.update(small_and_ragged(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink))
+        rec["grid_1e6"] = grid_form(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink)
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(f, z, 0)
         rec["cpu_baseline"] = base

@@ -326,6 +326,66 @@ int leg2cheb_batch_info(l2c_batch_t batch, int64_t *groups, int64_t *table_bytes
 /* Release the batch (synchronizes the device first).  NULL is a no-op. */
 int leg2cheb_batch_destroy(l2c_batch_t batch);
 
+/*
+ * Discrete cosine transforms (Sec. 1: the fast cosine transforms on the Chebyshev side of
+ * the transform; Sec. 5.2 compares the FMM's time with a DCT of type 2), in FP64:
+ *   kind 2:  y_k = sum_{j<n} x_j cos(pi k (j + 1/2) / n),   k < n;
+ *   kind 3:  y_j = sum_{k<n} x_k cos(pi k (j + 1/2) / n),   j < n
+ * (no normalization; kind 3 evaluates the Chebyshev series sum_k x_k T_k at the
+ * Chebyshev-Gauss points cos((j + 1/2) pi / n)).  Computed through an n-point complex FFT
+ * (hand-written, radices 2, 3, 4, 5, 7, 8): n must have no prime factor above 7 and
+ * n <= 2^27, else L2C_EUNSUPPORTED.
+ *   dct        [out] receives the plan (NULL on error).
+ *   kind       2 or 3.
+ *   max_batch  workspace (n > 4096: 16 n bytes per transform) is sized for this many
+ *              transforms; execute grows it on demand (a synchronizing allocation).
+ *   stream     hipStream_t on which the root tables are built (the call waits for them).
+ * Errors: L2C_EINVAL, L2C_EUNSUPPORTED, L2C_ENOMEM, L2C_EHIP.
+ */
+typedef struct l2c_dct_s *l2c_dct_t;
+int leg2cheb_dct_plan(l2c_dct_t *dct, int64_t n, int kind, int64_t max_batch, void *stream);
+
+/*
+ * out[b, :] = DCT(in[b, :]) for b < batch: caller-owned device arrays of batch x n FP64
+ * values, row-major, not overlapping (L2C_EINVAL).  Asynchronous on stream; batch = 0 is a
+ * no-op.  On L2C_EHIP the output is undefined.  Calls on one plan must not overlap in time
+ * on different streams (they share the plan's workspace).
+ */
+int leg2cheb_dct_execute(l2c_dct_t dct, const double *in, double *out, int64_t batch, void *stream);
+
+/* Release the plan (synchronizes the device first).  NULL is a no-op. */
+int leg2cheb_dct_destroy(l2c_dct_t dct);
+
+/*
+ * Legendre series on the Chebyshev-Gauss grid and back (the use of the transform that
+ * Sec. 1 describes): with x_j = cos((j + 1/2) pi / n),
+ *   L2C_LEG2GRID:  out_j = sum_{k<n} in_k P_k(x_j)  (leg2cheb, then the DCT of kind 3);
+ *   L2C_GRID2LEG:  out = the Legendre coefficients of the degree < n polynomial that
+ *                  takes the values in_j at x_j (the DCT of kind 2 scaled by
+ *                  (2 - delta_k0) / n, i.e. Chebyshev-Gauss quadrature, then cheb2leg).
+ * The two are inverse to each other up to the FMM's error.  leaf_size and rank as in
+ * leg2cheb_plan (FP64); n as for the DCT (prime factors 2, 3, 5, 7; n <= 2^27).
+ * Owns an FMM plan, a DCT plan and an intermediate array of max_batch x n FP64 values
+ * (grown on demand by execute, synchronizing).
+ * Errors: L2C_EINVAL, L2C_EUNSUPPORTED, L2C_ENOMEM, L2C_EHIP.
+ */
+enum l2c_grid_direction { L2C_LEG2GRID = 0, L2C_GRID2LEG = 1 };
+typedef struct l2c_grid_s *l2c_grid_t;
+int leg2cheb_grid_plan(l2c_grid_t *grid, int64_t n, int direction, int leaf_size, int rank, int64_t max_batch,
+                       void *stream);
+
+/* out[b, :] = the grid transform of in[b, :]; arguments and errors as leg2cheb_dct_execute,
+ * plus those of leg2cheb_execute on the owned FMM plan. */
+int leg2cheb_grid_execute(l2c_grid_t grid, const double *in, double *out, int64_t batch, void *stream);
+
+/* The FMM plan and the DCT plan a grid plan owns (for leg2cheb_plan_info and for timing
+ * the two stages apart); owned by the grid plan, never destroyed by the caller. */
+l2c_plan_t leg2cheb_grid_fmm(l2c_grid_t grid);
+l2c_dct_t leg2cheb_grid_dct(l2c_grid_t grid);
+
+/* Release the grid plan and what it owns (synchronizes the device first).  NULL is a no-op. */
+int leg2cheb_grid_destroy(l2c_grid_t grid);
+
 /* Non-zero if the library has kernels for rank M. */
 int leg2cheb_rank_supported(int rank);
 

@@ -10,6 +10,9 @@ Contents
   z = C^{-1} A f (leg2cheb) and z = A^{-1} C f (cheb2leg) from the closed forms
   of Sec. 1, Eqs. (aij)/(hik)/(Lambda), and of the reverse kernel, Eq. (Lxymod);
   plus a back-substitution route for cheb2leg.  See the header of oracle.c.
+* ``oracle.c`` also holds the grid pipeline of Sec. 1: the DCTs of kinds 2 and 3 as plain
+  cosine sums, and the Legendre series evaluated on the Chebyshev-Gauss points through the
+  three-term recurrence (``dct``, ``legval_cg``, ``grid2leg``).
 * ``fmm_ref``: the plan tables and the seven steps of Alg. 4 written out in
   numpy in the paper's order and notation (an approximation of the direct
   product; pinned against it in the tests).
@@ -35,10 +38,10 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so next to it (gcc, OpenMP, no fast-math)."""
+    """Compile oracle.c into liboracle.so next to it (gcc, OpenMP, libquadmath, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,6 +57,8 @@ def _load():
         for name in ("oracle_leg2cheb", "oracle_cheb2leg"):
             getattr(lib, name).argtypes = [i64, dp, i64, i64p, dp]
         lib.oracle_cheb2leg_backsub.argtypes = [i64, dp, dp]
+        lib.oracle_dct.argtypes = [i64, dp, ctypes.c_int, i64, i64p, dp]
+        lib.oracle_legval_cg.argtypes = [i64, dp, i64, i64p, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -124,3 +129,44 @@ def einf(z, zref) -> float:
     zref = np.asarray(zref, dtype=np.float64)
     den = np.max(np.abs(zref))
     return float(np.max(np.abs(z - zref)) / den) if den > 0 else float(np.max(np.abs(z)))
+
+
+def _rows_fn(fn, f, rows, *extra):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim != 1 or f.size < 1:
+        raise ValueError("input must be a non-empty 1-D array")
+    if rows is None:
+        z = np.empty(f.size, dtype=np.float64)
+        rc = fn(f.size, _dptr(f), *extra, 0, None, _dptr(z))
+    else:
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        z = np.empty(r.size, dtype=np.float64)
+        rc = fn(f.size, _dptr(f), *extra, r.size, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(z))
+    if rc != 0:
+        raise ValueError("oracle call failed (%d)" % rc)
+    return z
+
+
+def dct(x, kind: int, rows=None) -> np.ndarray:
+    """kind 2: y_k = sum_j x_j cos(pi k (2j+1)/(2n)); kind 3: y_j = sum_k x_k cos(pi k (2j+1)/(2n))."""
+    return _rows_fn(_load().oracle_dct, x, rows, int(kind))
+
+
+def legval_cg(f, rows=None) -> np.ndarray:
+    """u_j = sum_k f_k P_k(x_j) on the Chebyshev-Gauss points x_j = cos(pi (2j+1)/(2n))."""
+    return _rows_fn(_load().oracle_legval_cg, f, rows)
+
+
+def grid2leg(u) -> np.ndarray:
+    """Legendre coefficients of the degree < n interpolant of the values u_j at the
+    Chebyshev-Gauss points: Chebyshev coefficients c_k = (2 - delta_k0)/n sum_j u_j
+    cos(pi k (2j+1)/(2n)) (Gauss-Chebyshev quadrature), then cheb2leg (Sec. 1)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    c = dct(u, 2) * (2.0 / u.size)
+    c[0] *= 0.5
+    return cheb2leg(c)
+
+
+def leg2grid(f, rows=None) -> np.ndarray:
+    """Alias of legval_cg: the forward grid transform."""
+    return legval_cg(f, rows)

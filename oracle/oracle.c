@@ -39,6 +39,7 @@
  * Threads: OpenMP over output rows, dynamic schedule (row i costs ~ (n-i)/2).
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -190,5 +191,72 @@ int oracle_cheb2leg_backsub(int64_t n, const double *f, double *z)
     for (int64_t i = 0; i < n; ++i) z[i] = (double)zl[i];
     free(lam);
     free(zl);
+    return 0;
+}
+
+/*
+ * ---- The grid pipeline of Sec. 1 (Chebyshev-Gauss points x_j = cos(pi (2j+1) / (2n))).
+ *
+ *   oracle_dct, kind 2:  y_k = sum_{j<n} x_j cos(pi k (2j+1) / (2n))
+ *               kind 3:  y_j = sum_{k<n} x_k cos(pi k (2j+1) / (2n))
+ *   oracle_legval_cg:    u_j = sum_{k<n} f_k P_k(x_j), the Legendre polynomials from the
+ *                        three-term recurrence (k+1) P_{k+1}(x) = (2k+1) x P_k(x) - k P_{k-1}(x),
+ *                        P_0 = 1, P_1 = x, in binary128 (see there).
+ * The DCTs' cosine argument pi k (2j+1) / (2n) = 2 pi m / (4n) is reduced exactly in
+ * integers, m = k (2j+1) mod 4n, before cosl, with Neumaier-compensated long-double sums,
+ * rounded once to double.  Rows as in oracle_leg2cheb (rows == NULL: all n).
+ */
+#define PI_L 3.141592653589793238462643383279502884L
+
+static inline long double cos_frac(int64_t m, int64_t den)   /* cos(2 pi m / den) */
+{
+    return cosl(2.0L * PI_L * (long double)m / (long double)den);
+}
+
+int oracle_dct(int64_t n, const double *x, int kind, int64_t nrows, const int64_t *rows, double *y)
+{
+    if (n < 1 || !x || !y || (kind != 2 && kind != 3)) return -1;
+    int64_t m = rows ? nrows : n;
+    if (m < 0) return -1;
+    for (int64_t r = 0; rows && r < m; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t out = rows ? rows[r] : r;
+        nsum_t acc = {0.0L, 0.0L};
+        for (int64_t t = 0; t < n; ++t) {
+            /* kind 2: out = k, t = j;  kind 3: out = j, t = k */
+            const int64_t k = kind == 2 ? out : t, j = kind == 2 ? t : out;
+            const int64_t q = (k * (2 * j + 1)) % (4 * n);
+            nsum_add(&acc, (long double)x[t] * cos_frac(q, 4 * n));
+        }
+        y[r] = (double)nsum_get(&acc);
+    }
+    return 0;
+}
+
+int oracle_legval_cg(int64_t n, const double *f, int64_t nrows, const int64_t *rows, double *u)
+{
+    if (n < 1 || !f || !u) return -1;
+    int64_t m = rows ? nrows : n;
+    if (m < 0) return -1;
+    for (int64_t r = 0; rows && r < m; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return -1;
+    /* binary128: for large n the outer points lie within ~1/n^2 of +-1, where P_k moves
+     * like k^2 / 2 per unit of x, so the point itself must carry ~30 digits (in long
+     * double its rounding alone would shift P_k by up to ~k^2 5e-20, 3e-8 at k = 10^6). */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t j = rows ? rows[r] : r;
+        const __float128 x = cosq(M_PIq * (__float128)(2 * j + 1) / (__float128)(2 * n));
+        __float128 pm = 1, p = x, acc = (__float128)f[0];
+        for (int64_t k = 1; k < n; ++k) {
+            acc += (__float128)f[k] * p;
+            const __float128 pn = ((__float128)(2 * k + 1) * x * p - (__float128)k * pm) / (__float128)(k + 1);
+            pm = p;
+            p = pn;
+        }
+        u[r] = (double)acc;
+    }
     return 0;
 }

@@ -22,9 +22,12 @@ from ._lib import (  # noqa: F401  (re-exported ABI names)
     leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
     leg2cheb_rank_supported, leg2cheb_debug_alloc_hook, leg2cheb_set_timing_events, leg2cheb_batch_plan, leg2cheb_batch_execute,
     leg2cheb_batch_info, leg2cheb_batch_destroy, leg2cheb_batch_tuning,
+    L2C_LEG2GRID, L2C_GRID2LEG, leg2cheb_dct_plan, leg2cheb_dct_execute, leg2cheb_dct_destroy, leg2cheb_grid_plan,
+    leg2cheb_grid_execute, leg2cheb_grid_destroy, leg2cheb_grid_fmm, leg2cheb_grid_dct,
 )
 
 LEG2CHEB, CHEB2LEG = L2C_LEG2CHEB, L2C_CHEB2LEG
+LEG2GRID, GRID2LEG = L2C_LEG2GRID, L2C_GRID2LEG
 
 
 def _torch():
@@ -113,6 +116,93 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _rows(x, n: int, device: int, out):
+    """Check x (and out) as (n,) or (batch, n) contiguous float64 CUDA tensors; return out, batch."""
+    torch = _torch()
+    if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 CUDA tensor")
+    if x.shape[-1] != n or x.dim() not in (1, 2):
+        raise ValueError("x must have shape (n,) or (batch, n) with n = %d" % n)
+    if x.device.index != device:
+        raise ValueError("x is on cuda:%d but the plan was made on cuda:%d" % (x.device.index, device))
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != torch.float64 or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype, device and be contiguous")
+    return out, 1 if x.dim() == 1 else x.shape[0]
+
+
+class _Handle:
+    _destroy = None
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            type(self)._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Dct(_Handle):
+    """DCT of kind 2 (y_k = sum_j x_j cos(pi k (j + 1/2) / n)) or kind 3 (y_j = sum_k x_k
+    cos(pi k (j + 1/2) / n)) on the library's FFT; n with prime factors 2, 3, 5, 7 only."""
+    _destroy = staticmethod(leg2cheb_dct_destroy)
+
+    def __init__(self, n: int, kind: int = 2, max_batch: int = 1, stream=None):
+        torch = _torch()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.cuda.current_device()
+        self.handle = leg2cheb_dct_plan(n, kind, max_batch, st.cuda_stream)
+        self.n, self.kind = int(n), int(kind)
+
+    def execute(self, x, out=None, stream=None):
+        torch = _torch()
+        out, batch = _rows(x, self.n, self.device, out)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        leg2cheb_dct_execute(self.handle, x.data_ptr(), out.data_ptr(), batch, st.cuda_stream)
+        return out
+
+    __call__ = execute
+
+
+class GridPlan(_Handle):
+    """Legendre series on the n Chebyshev-Gauss points x_j = cos((j + 1/2) pi / n)
+    (LEG2GRID: values sum_k f_k P_k(x_j)) and back (GRID2LEG: Legendre coefficients of
+    the interpolant): the FMM plus the DCT of kind 3, or the DCT of kind 2 plus the FMM."""
+    _destroy = staticmethod(leg2cheb_grid_destroy)
+
+    def __init__(self, n: int, direction: int = L2C_LEG2GRID, leaf_size: int = 64, rank: int = 18,
+                 max_batch: int = 1, stream=None):
+        torch = _torch()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.device = torch.cuda.current_device()
+        self.handle = leg2cheb_grid_plan(n, direction, leaf_size, rank, max_batch, st.cuda_stream)
+        self.n, self.direction = int(n), int(direction)
+
+    @property
+    def fmm_info(self) -> dict:
+        return leg2cheb_plan_info(leg2cheb_grid_fmm(self.handle))
+
+    def execute(self, x, out=None, stream=None):
+        torch = _torch()
+        out, batch = _rows(x, self.n, self.device, out)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        leg2cheb_grid_execute(self.handle, x.data_ptr(), out.data_ptr(), batch, st.cuda_stream)
+        return out
+
+    __call__ = execute
 
 
 class BatchPlan:

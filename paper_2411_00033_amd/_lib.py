@@ -19,6 +19,7 @@ TABLE_AHAT, TABLE_T, TABLE_B, TABLE_W = 0, 1, 2, 3
 L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE = 0, 1, 2, 3, 4
 L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US = 1, 2, 3
 L2C_STATUS_EXCHANGE, L2C_STATUS_WORKERS, L2C_STATUS_STREAM = 1, 2, 4
+L2C_LEG2GRID, L2C_GRID2LEG = 0, 1
 
 EXPORTED = (
     "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
@@ -27,6 +28,8 @@ EXPORTED = (
     "leg2cheb_rank_supported", "leg2cheb_strerror",
     "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
     "leg2cheb_batch_tuning", "leg2cheb_debug_alloc_hook",
+    "leg2cheb_dct_plan", "leg2cheb_dct_execute", "leg2cheb_dct_destroy",
+    "leg2cheb_grid_plan", "leg2cheb_grid_execute", "leg2cheb_grid_destroy", "leg2cheb_grid_fmm", "leg2cheb_grid_dct",
 )
 
 
@@ -91,9 +94,19 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.leg2cheb_batch_destroy.argtypes = [vp]
     lib.leg2cheb_debug_alloc_hook.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.leg2cheb_dct_plan.argtypes = [ctypes.POINTER(vp), i64, ci, i64, vp]
+    lib.leg2cheb_dct_execute.argtypes = [vp, vp, vp, i64, vp]
+    lib.leg2cheb_dct_destroy.argtypes = [vp]
+    lib.leg2cheb_grid_plan.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, i64, vp]
+    lib.leg2cheb_grid_execute.argtypes = [vp, vp, vp, i64, vp]
+    lib.leg2cheb_grid_destroy.argtypes = [vp]
+    lib.leg2cheb_grid_fmm.argtypes = [vp]
+    lib.leg2cheb_grid_dct.argtypes = [vp]
     for name in EXPORTED:
-        if name != "leg2cheb_strerror":
+        if name not in ("leg2cheb_strerror", "leg2cheb_grid_fmm", "leg2cheb_grid_dct"):
             getattr(lib, name).restype = ci
+    lib.leg2cheb_grid_fmm.restype = vp
+    lib.leg2cheb_grid_dct.restype = vp
     _lib = lib
     return lib
 
@@ -230,3 +243,46 @@ def leg2cheb_batch_info(batch: int) -> dict:
 
 def leg2cheb_batch_destroy(batch: int) -> None:
     _check(load().leg2cheb_batch_destroy(ctypes.c_void_p(batch)), "leg2cheb_batch_destroy")
+
+
+def leg2cheb_dct_plan(n: int, kind: int, max_batch: int = 1, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_dct_plan(ctypes.byref(h), int(n), int(kind), int(max_batch), ctypes.c_void_p(stream or None)),
+           "leg2cheb_dct_plan")
+    return h.value
+
+
+def leg2cheb_dct_execute(dct: int, in_ptr: int, out_ptr: int, batch: int, stream: int = 0) -> None:
+    _check(load().leg2cheb_dct_execute(ctypes.c_void_p(dct), ctypes.c_void_p(in_ptr or None),
+                                       ctypes.c_void_p(out_ptr or None), int(batch), ctypes.c_void_p(stream or None)),
+           "leg2cheb_dct_execute")
+
+
+def leg2cheb_dct_destroy(dct: int) -> None:
+    _check(load().leg2cheb_dct_destroy(ctypes.c_void_p(dct)), "leg2cheb_dct_destroy")
+
+
+def leg2cheb_grid_plan(n: int, direction: int, leaf_size: int = 64, rank: int = 18, max_batch: int = 1,
+                       stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_grid_plan(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
+                                     int(max_batch), ctypes.c_void_p(stream or None)), "leg2cheb_grid_plan")
+    return h.value
+
+
+def leg2cheb_grid_execute(grid: int, in_ptr: int, out_ptr: int, batch: int, stream: int = 0) -> None:
+    _check(load().leg2cheb_grid_execute(ctypes.c_void_p(grid), ctypes.c_void_p(in_ptr or None),
+                                        ctypes.c_void_p(out_ptr or None), int(batch), ctypes.c_void_p(stream or None)),
+           "leg2cheb_grid_execute")
+
+
+def leg2cheb_grid_destroy(grid: int) -> None:
+    _check(load().leg2cheb_grid_destroy(ctypes.c_void_p(grid)), "leg2cheb_grid_destroy")
+
+
+def leg2cheb_grid_fmm(grid: int) -> int:
+    return load().leg2cheb_grid_fmm(ctypes.c_void_p(grid)) or 0
+
+
+def leg2cheb_grid_dct(grid: int) -> int:
+    return load().leg2cheb_grid_dct(ctypes.c_void_p(grid)) or 0

@@ -1,0 +1,647 @@
+// l2c_dct.hip -- discrete cosine transforms of types 2 and 3 on a hand-written complex FFT,
+// and the pipeline that evaluates a Legendre series on the Chebyshev-Gauss grid and back.
+//
+// Sec. 1 motivates the transform between Legendre and Chebyshev coefficients by the fast
+// cosine transforms that the Chebyshev side allows: a Legendre series sum_k f_k P_k(x) is
+// evaluated on the n Chebyshev-Gauss points x_j = cos((j + 1/2) pi / n) as leg2cheb
+// (c = C^-1 A f, Eq. (directmv)) followed by u_j = sum_k c_k T_k(x_j) = sum_k c_k cos(pi k
+// (j + 1/2) / n), a DCT of type 3; the inverse takes the DCT of type 2 of the values,
+// c_k = (2 - delta_k0) / n sum_j u_j cos(pi k (j + 1/2) / n) (Chebyshev-Gauss quadrature,
+// exact for the degree < n interpolant), then cheb2leg.  Sec. 5.2 times the FMM against a
+// DCT of type 2.
+//
+// DCT through an n-point complex DFT (Makhoul's reordering): with v_m = x_{p(m)},
+// p(m) = 2m for m < ceil(n/2) and 2(n-1-m)+1 otherwise,
+//   DCT-2:  y_k = Re(e^{-i pi k / (2n)} V_k),  V = DFT(v);
+//   DCT-3:  V_k = e^{i pi k / (2n)} (X_k - i X_{n-k}), X_0 = c_0, X_k = c_k / 2 (k >= 1),
+//           X_n = 0;  v = unnormalized inverse DFT of V;  y_{p(m)} = Re v_m.
+// The reordering and the quarter-wave factors are applied while the FFT loads its input
+// and stores its output, so a DCT is one pass over the data (n <= 4096) or two (larger n).
+//
+// The FFT: Stockham autosort passes of radix 8, 4, 2, 3, 5 and 7 on lines held in LDS
+// (a workgroup takes C lines of length n, C n <= 4096 complex values, 64 KiB); every
+// pass reads all its butterflies' inputs into registers, then writes the outputs in
+// place, so one LDS buffer serves.  For n > 4096 the four-step split n = na nb, applied
+// once (two passes: na, nb <= 512) or twice (three passes, n = na nb nc, each <= 4096 and
+// as equal as the factors allow): with n = na (nb nc) and index t = ta (nb nc) + t',
+// pass 1 takes the DFTs of length na along stride nb nc (one per t'; adjacent lines are
+// adjacent in memory) and multiplies output ka by the twist exp(-+2 pi i ka t' / n); the
+// rest is, for each ka, a DFT of length nb nc of contiguous data, split the same way, and
+// output K of that DFT is output ka + na K of the whole.  The last pass stores adjacent
+// lines (adjacent ka) at adjacent addresses.  Small factors keep many lines per workgroup
+// (4096 / length), so every strided access moves hundreds of contiguous bytes.  The roots of unity come
+// from tables built on the device with sincospi: per length, exp(-2 pi i t / len); for the
+// twist and quarter-wave factors of length n, the product of two tables of about sqrt(n)
+// entries (exact index split t = th b + tl), which keeps them in cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <new>
+#include <vector>
+
+#include "l2c_alloc.h"
+#include "../../include/leg2cheb.h"
+
+namespace l2c {
+
+constexpr int kFftThreads = 512;
+constexpr int kFftLds = 4096;                    // complex values per workgroup
+constexpr int kFftMaxPass = 16;
+constexpr int64_t kFftMaxN = int64_t(1) << 27;
+
+enum { kLoadComplex = 0, kLoadDct2 = 1, kLoadDct3 = 2 };
+enum { kStoreComplex = 0, kStoreDct2 = 1, kStoreDct3 = 2 };
+
+struct FftArgs {
+    int n;                     // DFT length of this launch
+    int npass;
+    int radix[kFftMaxPass];
+    int C;                     // lines per workgroup
+    int64_t lpt;               // lines per transform
+    int64_t lines;             // lines of the launch (transforms x lpt)
+    int64_t L1;                // line li of a transform = l1 + L1 l2
+    int64_t es_in, ls1_in, ls2_in, es_out, ls1_out, ls2_out;   // index in a transform: e es + l1 ls1 + l2 ls2
+    int64_t N;                 // transform length
+    int sign;                  // -1: forward DFT; +1: unnormalized inverse
+    const double2 *tw;         // [n]: exp(-2 pi i t / n)
+    int twist;                 // store: times exp(sign 2 pi i ((tw_full ? li : l1) e tmul mod N) / N)
+    int tw_full;
+    int64_t tmul;
+    const double2 *wh, *wl;    // exp(-2 pi i m / N) = wh[m / wb] wl[m % wb]
+    int64_t wb;
+    const double2 *qh, *ql;    // exp(i pi k / (2N)) = qh[k / qb] ql[k % qb]
+    int64_t qb;
+    int load, store;
+    double scale0, scale;      // DCT-2 store: y_0 scale0, y_k scale (k >= 1)
+    const double *rin;         // real input [transform][N]
+    double *rout;              // real output [transform][N]
+    const double2 *cin;        // complex input [transform][N]
+    double2 *cout;             // complex output [transform][N]
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// sign * i * a
+__device__ __forceinline__ double2 cmuli(double2 a, int sign)
+{
+    return sign < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+__device__ __forceinline__ double2 conj_if(double2 a, bool c) { return c ? make_double2(a.x, -a.y) : a; }
+
+__device__ __forceinline__ int64_t dct_perm(int64_t m, int64_t N)
+{
+    return m < (N + 1) / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
+}
+
+__device__ __forceinline__ double2 split_root(const double2 *hi, const double2 *lo, int64_t b, int64_t t)
+{
+    const int64_t th = t / b;
+    return cmul(hi[th], lo[t - th * b]);
+}
+
+// y_q = sum_r v_r w^(r q), w = exp(sign 2 pi i / R); roots[m] = exp(-2 pi i m / R)
+template <int R>
+__device__ __forceinline__ void small_dft(double2 (&v)[R], int sign, const double2 (&roots)[R])
+{
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const double2 s13 = cadd(v[1], v[3]), d13 = cmuli(csub(v[1], v[3]), sign);
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        double2 r4[4];
+        small_dft<4>(e, sign, r4);
+        small_dft<4>(o, sign, r4);
+        constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+        const double sg = (double)sign;
+        const double2 w1 = make_double2(h, sg * h), w3 = make_double2(-h, sg * h);
+        const double2 t[4] = {o[0], cmul(o[1], w1), cmuli(o[2], sign), cmul(o[3], w3)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = cadd(e[q], t[q]);
+            v[q + 4] = csub(e[q], t[q]);
+        }
+    } else {
+        double2 y[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            double2 acc = v[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], conj_if(roots[(r * q) % R], sign > 0)));
+            y[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = y[q];
+    }
+}
+
+// One Stockham pass of radix R over C lines of length n in LDS (Ns = product of the
+// radices of the earlier passes): butterfly j of a line reads elements j + r n/R, applies
+// exp(sign 2 pi i r k / (Ns R)), k = j mod Ns, and writes (j / Ns) Ns R + k + q Ns.
+template <int R>
+__device__ void fft_pass(double2 *buf, int n, int C, int Ns, int sign, const double2 *tw)
+{
+    constexpr int MB = (kFftLds / R + kFftThreads - 1) / kFftThreads;
+    const int nb = n / R, tot = C * nb;
+    double2 roots[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) roots[m] = tw[(int64_t)m * (n / R)];
+    double2 v[MB][R];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int b = (int)threadIdx.x + i * kFftThreads;
+        if (b < tot) {
+            const int c = b / nb, j = b - c * nb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[c * n + j + r * nb];
+        }
+    }
+    __syncthreads();
+    const int step = n / (Ns * R);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int b = (int)threadIdx.x + i * kFftThreads;
+        if (b < tot) {
+            const int c = b / nb, j = b - c * nb, k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], conj_if(tw[r * k * step], sign > 0));
+            small_dft<R>(v[i], sign, roots);
+            const int o = c * n + (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[o + q * Ns] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_fft(FftArgs a)
+{
+    __shared__ double2 buf[kFftLds];
+    const int n = a.n, C = a.C;
+    const int64_t line0 = (int64_t)blockIdx.x * C;
+    const int cnt = C * n;
+    // load: adjacent threads take adjacent elements of a line, or (strided lines) the same
+    // element of adjacent lines, whichever is adjacent in memory
+    const bool lcol = a.es_in != 1;
+    for (int idx = threadIdx.x; idx < cnt; idx += kFftThreads) {
+        const int c = lcol ? idx % C : idx / n, e = lcol ? idx / C : idx % n;
+        const int64_t line = line0 + c;
+        double2 v = make_double2(0.0, 0.0);
+        if (line < a.lines) {
+            const int64_t tr = line / a.lpt, li = line - tr * a.lpt;
+            const int64_t l2 = li / a.L1, l1 = li - l2 * a.L1;
+            const int64_t g = l1 * a.ls1_in + l2 * a.ls2_in + (int64_t)e * a.es_in;
+            const int64_t N = a.N;
+            if (a.load == kLoadComplex) {
+                v = a.cin[tr * N + g];
+            } else if (a.load == kLoadDct2) {
+                v = make_double2(a.rin[tr * N + dct_perm(g, N)], 0.0);
+            } else {
+                const double *x = a.rin + tr * N;
+                const double xg = g == 0 ? x[0] : 0.5 * x[g];
+                const double xn = g == 0 ? 0.0 : 0.5 * x[N - g];
+                v = cmul(split_root(a.qh, a.ql, a.qb, g), make_double2(xg, -xn));
+            }
+        }
+        buf[c * n + e] = v;
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int p = 0; p < a.npass; ++p) {
+        const int R = a.radix[p];
+        switch (R) {
+        case 8: fft_pass<8>(buf, n, C, Ns, a.sign, a.tw); break;
+        case 4: fft_pass<4>(buf, n, C, Ns, a.sign, a.tw); break;
+        case 2: fft_pass<2>(buf, n, C, Ns, a.sign, a.tw); break;
+        case 3: fft_pass<3>(buf, n, C, Ns, a.sign, a.tw); break;
+        case 5: fft_pass<5>(buf, n, C, Ns, a.sign, a.tw); break;
+        default: fft_pass<7>(buf, n, C, Ns, a.sign, a.tw); break;
+        }
+        Ns *= R;
+    }
+    const bool scol = a.es_out != 1;
+    for (int idx = threadIdx.x; idx < cnt; idx += kFftThreads) {
+        const int c = scol ? idx % C : idx / n, e = scol ? idx / C : idx % n;
+        const int64_t line = line0 + c;
+        if (line >= a.lines) continue;
+        const int64_t tr = line / a.lpt, li = line - tr * a.lpt;
+        const int64_t l2 = li / a.L1, l1 = li - l2 * a.L1;
+        const int64_t g = l1 * a.ls1_out + l2 * a.ls2_out + (int64_t)e * a.es_out;
+        const int64_t N = a.N;
+        double2 v = buf[c * n + e];
+        if (a.store == kStoreComplex) {
+            if (a.twist) {
+                const int64_t m = (((a.tw_full ? li : l1) * (int64_t)e) % N) * a.tmul % N;
+                v = cmul(v, conj_if(split_root(a.wh, a.wl, a.wb, m), a.sign > 0));
+            }
+            a.cout[tr * N + g] = v;
+        } else if (a.store == kStoreDct2) {
+            const double2 q = split_root(a.qh, a.ql, a.qb, g);   // Re(conj(q) V)
+            a.rout[tr * N + g] = (q.x * v.x + q.y * v.y) * (g == 0 ? a.scale0 : a.scale);
+        } else {
+            a.rout[tr * N + dct_perm(g, N)] = v.x;
+        }
+    }
+}
+
+// dst[t] = exp(i pi num(t) / den), num(t) = sgn * 2^e2 * t * mult, t < count
+__global__ void k_roots(double2 *dst, int64_t count, int64_t mult, double den, double fac)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    double s, c;
+    sincospi(fac * (double)(t * mult) / den, &s, &c);
+    dst[t] = make_double2(c, s);
+}
+
+}  // namespace l2c
+
+// ------------------------------------------------------------------------------------
+// Plans and the C ABI.
+
+struct l2c_dct_s {
+    int64_t n = 0;
+    int kind = 2;
+    int device = 0;
+    std::vector<int64_t> dim;                // pass lengths (1 to 3), product n
+    std::vector<std::vector<int>> rad;       // radices per pass
+    std::vector<double2 *> tw;               // per pass: exp(-2 pi i t / dim)
+    double2 *wh = nullptr, *wl = nullptr, *qh = nullptr, *ql = nullptr;
+    int64_t wb = 1, qb = 1;
+    double2 *work = nullptr;                 // four-step intermediate [items][n]
+    int64_t work_items = 0;
+    double scale0 = 1.0, scale = 1.0;
+};
+
+struct l2c_grid_s {
+    int64_t n = 0;
+    int direction = 0;
+    l2c_plan_t fmm = nullptr;
+    l2c_dct_t dct = nullptr;
+    double *tmp = nullptr;                   // [items][n]
+    int64_t tmp_items = 0;
+    int device = 0;
+};
+
+namespace {
+
+bool radices(int64_t n, std::vector<int> &out)
+{
+    out.clear();
+    while (n % 8 == 0) { out.push_back(8); n /= 8; }
+    while (n % 4 == 0) { out.push_back(4); n /= 4; }
+    while (n % 2 == 0) { out.push_back(2); n /= 2; }
+    for (int r : {3, 5, 7})
+        while (n % r == 0) { out.push_back(r); n /= r; }
+    return n == 1 && (int)out.size() <= l2c::kFftMaxPass;
+}
+
+int64_t isqrt_up(int64_t n)
+{
+    int64_t b = (int64_t)std::sqrt((double)n);
+    while (b * b < n) ++b;
+    return std::max<int64_t>(b, 1);
+}
+
+hipError_t roots(double2 **dst, int64_t count, int64_t mult, double den, double fac, hipStream_t st)
+{
+    hipError_t e = l2c::dev_alloc(dst, (size_t)count * sizeof(double2));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(l2c::k_roots, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, *dst, count, mult, den, fac);
+    return hipGetLastError();
+}
+
+void free_dct(l2c_dct_t d)
+{
+    if (!d) return;
+    for (const void *p : {(const void *)d->wh, (const void *)d->wl, (const void *)d->qh, (const void *)d->ql,
+                          (const void *)d->work})
+        l2c::dev_free(p);
+    for (double2 *t : d->tw) l2c::dev_free(t);
+    delete d;
+}
+
+int ensure_work(l2c_dct_t d, int64_t items)
+{
+    if (d->dim.size() == 1 || items <= d->work_items) return L2C_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
+    l2c::dev_free(d->work);
+    d->work = nullptr;
+    d->work_items = 0;
+    if (l2c::dev_alloc(&d->work, (size_t)items * d->n * sizeof(double2)) != hipSuccess) {
+        (void)hipGetLastError();
+        return L2C_ENOMEM;
+    }
+    d->work_items = items;
+    return L2C_OK;
+}
+
+l2c::FftArgs base_args(const l2c_dct_t d)
+{
+    l2c::FftArgs a{};
+    a.N = d->n;
+    a.sign = d->kind == 2 ? -1 : 1;
+    a.wh = d->wh;
+    a.wl = d->wl;
+    a.wb = d->wb;
+    a.qh = d->qh;
+    a.ql = d->ql;
+    a.qb = d->qb;
+    a.scale0 = d->scale0;
+    a.scale = d->scale;
+    return a;
+}
+
+void set_pass(l2c::FftArgs &a, int n, const std::vector<int> &r, const double2 *tw)
+{
+    a.n = n;
+    a.npass = (int)r.size();
+    for (int i = 0; i < a.npass; ++i) a.radix[i] = r[i];
+    a.tw = tw;
+    a.C = std::max(1, l2c::kFftLds / n);
+}
+
+hipError_t launch(const l2c::FftArgs &a, hipStream_t st)
+{
+    const int64_t blocks = (a.lines + a.C - 1) / a.C;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(l2c::k_fft, dim3((unsigned)blocks), dim3(l2c::kFftThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream_t st)
+{
+    const int load = d->kind == 2 ? l2c::kLoadDct2 : l2c::kLoadDct3;
+    const int store = d->kind == 2 ? l2c::kStoreDct2 : l2c::kStoreDct3;
+    const int P = (int)d->dim.size();
+    const int64_t n = d->n;
+    // at most 2^30 lines per launch (grid.x), in whole transforms
+    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 30) / (P == 1 ? 1 : n));
+    for (int64_t b0 = 0; b0 < batch; b0 += per) {
+        const int64_t nb = std::min(per, batch - b0);
+        for (int p = 0; p < P; ++p) {
+            l2c::FftArgs a = base_args(d);
+            set_pass(a, (int)d->dim[p], d->rad[p], d->tw[p]);
+            a.load = p == 0 ? load : l2c::kLoadComplex;
+            a.store = p == P - 1 ? store : l2c::kStoreComplex;
+            a.rin = in + b0 * n;
+            a.rout = out + b0 * n;
+            a.cin = d->work;
+            a.cout = d->work;
+            const int64_t lpt = n / d->dim[p];
+            a.lpt = lpt;
+            a.lines = nb * lpt;
+            a.L1 = lpt;
+            a.tmul = 1;
+            if (P == 1) {                       // one line per transform
+                a.es_in = a.es_out = 1;
+            } else if (p == 0) {                // along stride n / na, twist by the whole line index
+                a.es_in = a.es_out = lpt;
+                a.ls1_in = a.ls1_out = 1;
+                a.twist = 1;
+                a.tw_full = 1;
+            } else if (p == P - 1) {            // contiguous rows; out at l1 + L1 (l2 + ...) order
+                const int64_t nl = d->dim[P - 1];
+                if (P == 2) {                   // lines ka
+                    a.ls1_in = nl;
+                    a.es_in = 1;
+                    a.ls1_out = 1;
+                    a.es_out = d->dim[0];
+                } else {                        // lines (ka, kb), ka fastest
+                    a.L1 = d->dim[0];
+                    a.ls1_in = n / d->dim[0];
+                    a.ls2_in = nl;
+                    a.es_in = 1;
+                    a.ls1_out = 1;
+                    a.ls2_out = d->dim[0];
+                    a.es_out = d->dim[0] * d->dim[1];
+                }
+            } else {                            // P = 3, pass 2: lines (nc, ka) along stride nc
+                const int64_t nc = d->dim[2], inner = d->dim[1] * nc;
+                a.L1 = nc;
+                a.es_in = a.es_out = nc;
+                a.ls1_in = a.ls1_out = 1;
+                a.ls2_in = a.ls2_out = inner;
+                a.twist = 1;
+                a.tw_full = 0;
+                a.tmul = d->dim[0];             // exp(-2 pi i kb nc / (nb nc)) = exp(-2 pi i kb nc na / n)
+            }
+            if (launch(a, st) != hipSuccess) return L2C_EHIP;
+        }
+    }
+    return L2C_OK;
+}
+
+// Pass lengths: n itself (n <= 4096); two balanced factors when both are <= 512; else
+// three factors <= 4096, the largest as small as possible.  Empty: not supported.
+std::vector<int64_t> pass_lengths(int64_t n)
+{
+    if (n <= l2c::kFftLds) return {n};
+    int64_t best = 0;
+    for (int64_t f = 2; f * f <= n; ++f)
+        if (n % f == 0) best = f;                       // the largest divisor <= sqrt(n)
+    if (best && n / best <= 512) return {n / best, best};
+    std::vector<int64_t> b3;
+    for (int64_t a = 2; a <= l2c::kFftLds; ++a) {
+        if (n % a) continue;
+        const int64_t m = n / a;
+        for (int64_t f = 1; f * f <= m; ++f) {
+            if (m % f || m / f > l2c::kFftLds) continue;
+            const int64_t c = m / f, mx = std::max(a, std::max(f, c));
+            if (b3.empty() || mx < std::max(b3[0], std::max(b3[1], b3[2]))) b3 = {a, c, f};
+        }
+    }
+    return b3;
+}
+
+int dct_length_ok(int64_t n)
+{
+    if (n > l2c::kFftMaxN) return L2C_EUNSUPPORTED;
+    int64_t m = n;
+    for (int64_t r : {2, 3, 5, 7})
+        while (m % r == 0) m /= r;
+    if (m != 1) return L2C_EUNSUPPORTED;            // prime factors 2, 3, 5, 7 only
+    return pass_lengths(n).empty() ? L2C_EUNSUPPORTED : L2C_OK;
+}
+
+int dct_plan_impl(l2c_dct_t *dct, int64_t n, int kind, int64_t max_batch, void *stream)
+{
+    if (!dct) return L2C_EINVAL;
+    *dct = nullptr;
+    if (n < 1 || (kind != 2 && kind != 3) || max_batch < 1) return L2C_EINVAL;
+    const int lrc = dct_length_ok(n);
+    if (lrc != L2C_OK) return lrc;
+    l2c_dct_t d = new (std::nothrow) l2c_dct_s();
+    if (!d) return L2C_ENOMEM;
+    d->n = n;
+    d->kind = kind;
+    if (hipGetDevice(&d->device) != hipSuccess) {
+        delete d;
+        return L2C_EHIP;
+    }
+    d->dim = pass_lengths(n);
+    d->rad.resize(d->dim.size());
+    d->tw.assign(d->dim.size(), nullptr);
+    for (size_t i = 0; i < d->dim.size(); ++i) radices(d->dim[i], d->rad[i]);
+    hipStream_t st = (hipStream_t)stream;
+    d->wb = isqrt_up(n);
+    d->qb = d->wb;
+    const int64_t wh_n = (n + d->wb - 1) / d->wb + 1;
+    bool ok = true;
+    for (size_t i = 0; i < d->dim.size() && ok; ++i)
+        ok = roots(&d->tw[i], d->dim[i], 1, (double)d->dim[i], -2.0, st) == hipSuccess;
+    ok = ok && roots(&d->wl, d->wb, 1, (double)n, -2.0, st) == hipSuccess &&
+              roots(&d->wh, wh_n, d->wb, (double)n, -2.0, st) == hipSuccess &&
+              roots(&d->ql, d->qb, 1, 2.0 * (double)n, 1.0, st) == hipSuccess &&
+              roots(&d->qh, wh_n, d->qb, 2.0 * (double)n, 1.0, st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_dct(d);
+        return L2C_ENOMEM;
+    }
+    const int rc = ensure_work(d, max_batch);
+    if (rc != L2C_OK || hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        free_dct(d);
+        return rc != L2C_OK ? rc : L2C_EHIP;
+    }
+    *dct = d;
+    return L2C_OK;
+}
+
+int check_io(int64_t n, const double *in, double *out, int64_t batch, int device)
+{
+    if (!in || !out || batch < 0) return L2C_EINVAL;
+    if (batch > (int64_t(1) << 40) / n) return L2C_EINVAL;
+    const int64_t len = batch * n;
+    const char *ib = (const char *)in, *ie = (const char *)(in + len);
+    const char *ob = (const char *)out, *oe = (const char *)(out + len);
+    if (ib < oe && ob < ie) return L2C_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
+    if (dev != device) return L2C_EINVAL;
+    return L2C_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int leg2cheb_dct_plan(l2c_dct_t *dct, int64_t n, int kind, int64_t max_batch, void *stream)
+{
+    return dct_plan_impl(dct, n, kind, max_batch, stream);
+}
+
+int leg2cheb_dct_execute(l2c_dct_t dct, const double *in, double *out, int64_t batch, void *stream)
+{
+    if (!dct || batch < 0) return L2C_EINVAL;
+    if (batch == 0) return L2C_OK;
+    int rc = check_io(dct->n, in, out, batch, dct->device);
+    if (rc != L2C_OK) return rc;
+    rc = ensure_work(dct, batch);
+    if (rc != L2C_OK) return rc;
+    return dct_run(dct, in, out, batch, (hipStream_t)stream);
+}
+
+int leg2cheb_dct_destroy(l2c_dct_t dct)
+{
+    if (!dct) return L2C_OK;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    free_dct(dct);
+    return ok ? L2C_OK : L2C_EHIP;
+}
+
+int leg2cheb_grid_plan(l2c_grid_t *grid, int64_t n, int direction, int leaf_size, int rank, int64_t max_batch,
+                       void *stream)
+{
+    if (!grid) return L2C_EINVAL;
+    *grid = nullptr;
+    if (n < 1 || (direction != L2C_LEG2GRID && direction != L2C_GRID2LEG) || max_batch < 1) return L2C_EINVAL;
+    if (leaf_size < 4 || leaf_size > 128 || (leaf_size & 1) || rank < 1 || rank > 32) return L2C_EINVAL;
+    const int lrc = dct_length_ok(n);
+    if (lrc != L2C_OK) return lrc;
+    l2c_grid_t g = new (std::nothrow) l2c_grid_s();
+    if (!g) return L2C_ENOMEM;
+    g->n = n;
+    g->direction = direction;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return L2C_EHIP;
+    }
+    int rc = leg2cheb_dct_plan(&g->dct, n, direction == L2C_LEG2GRID ? 3 : 2, max_batch, stream);
+    if (rc == L2C_OK) {
+        if (direction == L2C_GRID2LEG) {   // Chebyshev coefficients of the interpolant
+            g->dct->scale0 = 1.0 / (double)n;
+            g->dct->scale = 2.0 / (double)n;
+        }
+        rc = leg2cheb_plan_ex(&g->fmm, n, direction == L2C_LEG2GRID ? L2C_LEG2CHEB : L2C_CHEB2LEG, leaf_size, rank,
+                              L2C_FP64, max_batch, stream);
+    }
+    if (rc == L2C_OK && l2c::dev_alloc(&g->tmp, (size_t)max_batch * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = L2C_ENOMEM;
+    }
+    if (rc != L2C_OK) {
+        leg2cheb_grid_destroy(g);
+        return rc;
+    }
+    g->tmp_items = max_batch;
+    *grid = g;
+    return L2C_OK;
+}
+
+int leg2cheb_grid_execute(l2c_grid_t grid, const double *in, double *out, int64_t batch, void *stream)
+{
+    if (!grid || batch < 0) return L2C_EINVAL;
+    if (batch == 0) return L2C_OK;
+    int rc = check_io(grid->n, in, out, batch, grid->device);
+    if (rc != L2C_OK) return rc;
+    if (batch > grid->tmp_items) {
+        if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
+        l2c::dev_free(grid->tmp);
+        grid->tmp = nullptr;
+        grid->tmp_items = 0;
+        if (l2c::dev_alloc(&grid->tmp, (size_t)batch * grid->n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return L2C_ENOMEM;
+        }
+        grid->tmp_items = batch;
+    }
+    if (grid->direction == L2C_LEG2GRID) {
+        rc = leg2cheb_execute(grid->fmm, in, grid->tmp, batch, stream);
+        return rc != L2C_OK ? rc : leg2cheb_dct_execute(grid->dct, grid->tmp, out, batch, stream);
+    }
+    rc = leg2cheb_dct_execute(grid->dct, in, grid->tmp, batch, stream);
+    return rc != L2C_OK ? rc : leg2cheb_execute(grid->fmm, grid->tmp, out, batch, stream);
+}
+
+l2c_plan_t leg2cheb_grid_fmm(l2c_grid_t grid) { return grid ? grid->fmm : nullptr; }
+
+l2c_dct_t leg2cheb_grid_dct(l2c_grid_t grid) { return grid ? grid->dct : nullptr; }
+
+int leg2cheb_grid_destroy(l2c_grid_t grid)
+{
+    if (!grid) return L2C_OK;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    int rc = leg2cheb_destroy(grid->fmm);
+    const int rc2 = leg2cheb_dct_destroy(grid->dct);
+    l2c::dev_free(grid->tmp);
+    delete grid;
+    if (rc == L2C_OK) rc = rc2;
+    return !ok ? L2C_EHIP : rc;
+}
+
+}  // extern "C"

@@ -183,3 +183,24 @@ def test_status_and_option_constants_match_header(lib):
         m = re.search(r"\b%s\s*=\s*(\d+)" % name, text)
         assert m, name
         assert int(m.group(1)) == getattr(lib, name), name
+
+
+def test_dct_and_grid_argument_errors(lib):
+    """Argument checks of the DCT and grid plans run before any device call."""
+    L = lib.load()
+    h = ctypes.c_void_p(1)
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 0, 2, 1, None) == -1 and h.value is None
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 64, 4, 1, None) == -1          # kind 2 or 3
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 64, 2, 0, None) == -1          # max_batch >= 1
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 11, 2, 1, None) == -4          # prime factor 11
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 4099, 3, 1, None) == -4        # prime
+    assert L.leg2cheb_dct_plan(ctypes.byref(h), 1 << 28, 2, 1, None) == -4     # above 2^27
+    assert L.leg2cheb_dct_plan(None, 64, 2, 1, None) == -1
+    assert L.leg2cheb_grid_plan(ctypes.byref(h), 64, 2, 64, 18, 1, None) == -1  # direction
+    assert L.leg2cheb_grid_plan(ctypes.byref(h), 64, 0, 3, 18, 1, None) == -1   # leaf
+    assert L.leg2cheb_grid_plan(ctypes.byref(h), 64, 0, 64, 0, 1, None) == -1   # rank
+    assert L.leg2cheb_grid_plan(ctypes.byref(h), 13, 1, 64, 18, 1, None) == -4  # DCT length
+    assert L.leg2cheb_dct_execute(None, None, None, 1, None) == -1
+    assert L.leg2cheb_grid_execute(None, None, None, 1, None) == -1
+    assert L.leg2cheb_dct_destroy(None) == 0 and L.leg2cheb_grid_destroy(None) == 0
+    assert not L.leg2cheb_grid_fmm(None) and not L.leg2cheb_grid_dct(None)

@@ -47,3 +47,19 @@ TOLF16_SCALED = 7.5e-7
 TOL32_U = 8.5e-7
 TOLBF_U = 2.5e-5
 TOLF16_U = 6.5e-7
+
+# DCTs of kinds 2 and 3 (the library's FFT, FP64), E_inf relative to max|y|: an FFT's
+# rounding error grows like sqrt(log2 n) u in norm.  Measured maximum over n = 1 .. 2^20
+# (one-, two- and three-pass lengths, radices 2 .. 8): 1.63e-15 (n = 3^11, kind 2); the
+# bound is about 3x that.
+TOL_DCT = 5e-15
+
+
+# The grid pipeline (Sec. 1: leg2cheb then the DCT of kind 3, or the DCT of kind 2 then
+# cheb2leg).  The FMM's error is about u times max|c| in every coefficient, also in the
+# small ones, and the DCT of kind 3 sums n such errors with varying signs: the grid values
+# carry about sqrt(n) u max|c| (the round trip the same again).  Measured E_inf / (sqrt(n) u),
+# u = 2^-53: 0.4 (leg2grid, n = 6000), 2.0 (leg2grid, n = 65536), 1.6 (round trip,
+# n = 10^6); the bound is 6 sqrt(n) u.
+def TOL_GRID(n):
+    return 6.0 * max(n, 1) ** 0.5 * 2.0 ** -53
