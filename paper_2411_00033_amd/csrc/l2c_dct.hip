@@ -38,6 +38,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -46,8 +47,8 @@
 
 namespace l2c {
 
-constexpr int kFftThreads = 512;
-constexpr int kFftLds = 4096;                    // complex values per workgroup
+constexpr int kFftLds = 4096;                    // complex values per workgroup, at most
+constexpr int kFftSmall = 2048;                  // ... for lengths up to this
 constexpr int kFftMaxPass = 16;
 constexpr int64_t kFftMaxN = int64_t(1) << 27;
 
@@ -94,20 +95,41 @@ __device__ __forceinline__ double2 cmuli(double2 a, int sign)
 }
 __device__ __forceinline__ double2 conj_if(double2 a, bool c) { return c ? make_double2(a.x, -a.y) : a; }
 
-__device__ __forceinline__ int64_t dct_perm(int64_t m, int64_t N)
-{
-    return m < (N + 1) / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
-}
+// floor(x / d) for 0 <= x < 2^31 and 1 <= d < 2^18 in three FP64 operations: (x + 1/2) / d
+// lies at least 1/(2d) from every integer, far above the product's rounding error.
+struct FastDiv {
+    int d;
+    double inv;
+    __device__ explicit FastDiv(int d_) : d(d_), inv(1.0 / (double)d_) {}
+    __device__ __forceinline__ int quot(int x) const { return (int)(((double)x + 0.5) * inv); }
+};
 
-__device__ __forceinline__ double2 split_root(const double2 *hi, const double2 *lo, int64_t b, int64_t t)
-{
-    const int64_t th = t / b;
-    return cmul(hi[th], lo[t - th * b]);
-}
 
-// y_q = sum_r v_r w^(r q), w = exp(sign 2 pi i / R); roots[m] = exp(-2 pi i m / R)
+// cos and sin of 2 pi m / R, m = 1 .. (R-1)/2, for the odd radices
 template <int R>
-__device__ __forceinline__ void small_dft(double2 (&v)[R], int sign, const double2 (&roots)[R])
+struct OddRoots;
+template <>
+struct OddRoots<3> {
+    static constexpr double c[1] = {-0.5};
+    static constexpr double s[1] = {0.8660254037844386467637};
+};
+template <>
+struct OddRoots<5> {
+    static constexpr double c[2] = {0.3090169943749474241023, -0.8090169943749474241023};
+    static constexpr double s[2] = {0.9510565162951535721164, 0.5877852522924731291687};
+};
+template <>
+struct OddRoots<7> {
+    static constexpr double c[3] = {0.6234898018587335305251, -0.2225209339563144042889, -0.9009688679024191262361};
+    static constexpr double s[3] = {0.7818314824680298087084, 0.9749279121818236070181, 0.4338837391175581204758};
+};
+
+// y_q = sum_r v_r w^(r q), w = exp(sign 2 pi i / R).  Odd R: with s_r = v_r + v_{R-r},
+// d_r = v_r - v_{R-r} (r = 1 .. H, H = (R-1)/2), y_q = A_q + sign i B_q and
+// y_{R-q} = A_q - sign i B_q, A_q = v_0 + sum_r s_r cos(2 pi r q / R),
+// B_q = sum_r d_r sin(2 pi r q / R).
+template <int R>
+__device__ __forceinline__ void small_dft(double2 (&v)[R], int sign)
 {
     if constexpr (R == 2) {
         const double2 a = v[0], b = v[1];
@@ -122,9 +144,8 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], int sign, const doubl
         v[3] = csub(d02, d13);
     } else if constexpr (R == 8) {
         double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
-        double2 r4[4];
-        small_dft<4>(e, sign, r4);
-        small_dft<4>(o, sign, r4);
+        small_dft<4>(e, sign);
+        small_dft<4>(o, sign);
         constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
         const double sg = (double)sign;
         const double2 w1 = make_double2(h, sg * h), w3 = make_double2(-h, sg * h);
@@ -135,36 +156,49 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R], int sign, const doubl
             v[q + 4] = csub(e[q], t[q]);
         }
     } else {
-        double2 y[R];
+        constexpr int H = (R - 1) / 2;
+        double2 sm[H], df[H];
+        double2 y0 = v[0];
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            double2 acc = v[0];
-#pragma unroll
-            for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], conj_if(roots[(r * q) % R], sign > 0)));
-            y[q] = acc;
+        for (int r = 1; r <= H; ++r) {
+            sm[r - 1] = cadd(v[r], v[R - r]);
+            df[r - 1] = csub(v[r], v[R - r]);
+            y0 = cadd(y0, sm[r - 1]);
         }
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = y[q];
+        for (int q = 1; q <= H; ++q) {
+            double2 A = v[0], B = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                const int m = (r * q) % R, mm = m <= H ? m : R - m;   // cos is even, sin odd in m
+                const double cs = OddRoots<R>::c[mm - 1], sn = m <= H ? OddRoots<R>::s[mm - 1] : -OddRoots<R>::s[mm - 1];
+                A = make_double2(fma(sm[r - 1].x, cs, A.x), fma(sm[r - 1].y, cs, A.y));
+                B = make_double2(fma(df[r - 1].x, sn, B.x), fma(df[r - 1].y, sn, B.y));
+            }
+            const double2 iB = cmuli(B, sign);
+            v[q] = cadd(A, iB);
+            v[R - q] = csub(A, iB);
+        }
+        v[0] = y0;
     }
 }
 
 // One Stockham pass of radix R over C lines of length n in LDS (Ns = product of the
 // radices of the earlier passes): butterfly j of a line reads elements j + r n/R, applies
 // exp(sign 2 pi i r k / (Ns R)), k = j mod Ns, and writes (j / Ns) Ns R + k + q Ns.
-template <int R>
+// CAP values of the workgroup's NT threads; tw = exp(-2 pi i t / n) in LDS.
+template <int R, int CAP, int NT>
 __device__ void fft_pass(double2 *buf, int n, int C, int Ns, int sign, const double2 *tw)
 {
-    constexpr int MB = (kFftLds / R + kFftThreads - 1) / kFftThreads;
+    constexpr int MB = (CAP / R + NT - 1) / NT;
     const int nb = n / R, tot = C * nb;
-    double2 roots[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) roots[m] = tw[(int64_t)m * (n / R)];
+    const FastDiv dnb(nb), dns(Ns);
     double2 v[MB][R];
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-        const int b = (int)threadIdx.x + i * kFftThreads;
+        const int b = (int)threadIdx.x + i * NT;
         if (b < tot) {
-            const int c = b / nb, j = b - c * nb;
+            const int c = dnb.quot(b), j = b - c * nb;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = buf[c * n + j + r * nb];
         }
@@ -173,13 +207,13 @@ __device__ void fft_pass(double2 *buf, int n, int C, int Ns, int sign, const dou
     const int step = n / (Ns * R);
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-        const int b = (int)threadIdx.x + i * kFftThreads;
+        const int b = (int)threadIdx.x + i * NT;
         if (b < tot) {
-            const int c = b / nb, j = b - c * nb, k = j % Ns;
+            const int c = dnb.quot(b), j = b - c * nb, jq = dns.quot(j), k = j - jq * Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], conj_if(tw[r * k * step], sign > 0));
-            small_dft<R>(v[i], sign, roots);
-            const int o = c * n + (j / Ns) * Ns * R + k;
+            small_dft<R>(v[i], sign);
+            const int o = c * n + jq * Ns * R + k;
 #pragma unroll
             for (int q = 0; q < R; ++q) buf[o + q * Ns] = v[i][q];
         }
@@ -187,72 +221,162 @@ __device__ void fft_pass(double2 *buf, int n, int C, int Ns, int sign, const dou
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kFftThreads) void k_fft(FftArgs a)
+// m = x mod N for 0 <= x < 2^52, in FP64 (exact: every value is an integer below 2^53)
+__device__ __forceinline__ int mod_n(double x, double N, double invN)
 {
-    __shared__ double2 buf[kFftLds];
-    const int n = a.n, C = a.C;
+    double r = x - trunc(x * invN) * N;
+    if (r < 0.0) r += N;
+    if (r >= N) r -= N;
+    return (int)r;
+}
+
+// Per line of the workgroup, set up once: the transform's offset, the line's part of the
+// in-transform index on both sides, and the twist multiplier (line index times tmul, mod N).
+struct FftLine {
+    int64_t base;        // transform * N; -1: past the last line
+    int gin, gout;
+    int twa;
+};
+
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_fft(FftArgs a)
+{
+    extern __shared__ double2 smem[];
+    const int n = a.n, C = a.C, N = (int)a.N;
+    double2 *buf = smem, *tw = smem + C * n;
+    FftLine *ln = reinterpret_cast<FftLine *>(tw + n);
     const int64_t line0 = (int64_t)blockIdx.x * C;
-    const int cnt = C * n;
-    // load: adjacent threads take adjacent elements of a line, or (strided lines) the same
-    // element of adjacent lines, whichever is adjacent in memory
-    const bool lcol = a.es_in != 1;
-    for (int idx = threadIdx.x; idx < cnt; idx += kFftThreads) {
-        const int c = lcol ? idx % C : idx / n, e = lcol ? idx / C : idx % n;
+    for (int c = threadIdx.x; c < C; c += NT) {
         const int64_t line = line0 + c;
-        double2 v = make_double2(0.0, 0.0);
+        FftLine L{-1, 0, 0, 0};
         if (line < a.lines) {
             const int64_t tr = line / a.lpt, li = line - tr * a.lpt;
             const int64_t l2 = li / a.L1, l1 = li - l2 * a.L1;
-            const int64_t g = l1 * a.ls1_in + l2 * a.ls2_in + (int64_t)e * a.es_in;
-            const int64_t N = a.N;
-            if (a.load == kLoadComplex) {
-                v = a.cin[tr * N + g];
-            } else if (a.load == kLoadDct2) {
-                v = make_double2(a.rin[tr * N + dct_perm(g, N)], 0.0);
-            } else {
-                const double *x = a.rin + tr * N;
-                const double xg = g == 0 ? x[0] : 0.5 * x[g];
-                const double xn = g == 0 ? 0.0 : 0.5 * x[N - g];
-                v = cmul(split_root(a.qh, a.ql, a.qb, g), make_double2(xg, -xn));
+            L.base = tr * a.N;
+            L.gin = (int)(l1 * a.ls1_in + l2 * a.ls2_in);
+            L.gout = (int)(l1 * a.ls1_out + l2 * a.ls2_out);
+            L.twa = a.twist ? (int)(((a.tw_full ? li : l1) * a.tmul) % a.N) : 0;
+        }
+        ln[c] = L;
+    }
+    for (int t = threadIdx.x; t < n; t += NT) tw[t] = a.tw[t];
+    __syncthreads();
+    const int cnt = C * n;
+    const int es_in = (int)a.es_in, es_out = (int)a.es_out;
+    constexpr int EPT = CAP / NT;                 // elements per thread, at most
+    // load: adjacent threads take adjacent elements of a line, or (strided lines) the same
+    // element of adjacent lines, whichever is adjacent in memory.  Every global load of
+    // the thread is issued before the first is used.
+    {
+        const bool lcol = es_in != 1;
+        const FastDiv dv(lcol ? C : n), dqb((int)a.qb);
+        double2 raw[EPT], rh[EPT], rl[EPT];
+        int pos[EPT], gg[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int idx = (int)threadIdx.x + u * NT;
+            pos[u] = -1;
+            gg[u] = -1;
+            raw[u] = make_double2(0.0, 0.0);
+            if (idx < cnt) {
+                const int q = dv.quot(idx), rm = idx - q * dv.d;
+                const int c = lcol ? rm : q, e = lcol ? q : rm;
+                const FftLine L = ln[c];
+                pos[u] = c * n + e;
+                if (L.base >= 0) {
+                    const int g = L.gin + e * es_in;
+                    gg[u] = g;
+                    if (a.load == kLoadComplex) {
+                        raw[u] = a.cin[L.base + g];
+                    } else if (a.load == kLoadDct2) {
+                        raw[u].x = a.rin[L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1)];
+                    } else {
+                        const double *x = a.rin + L.base;
+                        raw[u] = make_double2(x[g], x[g == 0 ? 0 : N - g]);
+                        const int th = dqb.quot(g);
+                        rh[u] = a.qh[th];
+                        rl[u] = a.ql[g - th * dqb.d];
+                    }
+                }
             }
         }
-        buf[c * n + e] = v;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            if (pos[u] < 0) continue;
+            double2 v = raw[u];
+            if (a.load == kLoadDct3 && gg[u] >= 0) {
+                const bool z = gg[u] == 0;
+                v = cmul(cmul(rh[u], rl[u]), make_double2(z ? v.x : 0.5 * v.x, z ? 0.0 : -0.5 * v.y));
+            }
+            buf[pos[u]] = v;
+        }
     }
     __syncthreads();
     int Ns = 1;
     for (int p = 0; p < a.npass; ++p) {
         const int R = a.radix[p];
         switch (R) {
-        case 8: fft_pass<8>(buf, n, C, Ns, a.sign, a.tw); break;
-        case 4: fft_pass<4>(buf, n, C, Ns, a.sign, a.tw); break;
-        case 2: fft_pass<2>(buf, n, C, Ns, a.sign, a.tw); break;
-        case 3: fft_pass<3>(buf, n, C, Ns, a.sign, a.tw); break;
-        case 5: fft_pass<5>(buf, n, C, Ns, a.sign, a.tw); break;
-        default: fft_pass<7>(buf, n, C, Ns, a.sign, a.tw); break;
+        case 8: fft_pass<8, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
+        case 4: fft_pass<4, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
+        case 2: fft_pass<2, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
+        case 3: fft_pass<3, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
+        case 5: fft_pass<5, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
+        default: fft_pass<7, CAP, NT>(buf, n, C, Ns, a.sign, tw); break;
         }
         Ns *= R;
     }
-    const bool scol = a.es_out != 1;
-    for (int idx = threadIdx.x; idx < cnt; idx += kFftThreads) {
-        const int c = scol ? idx % C : idx / n, e = scol ? idx / C : idx % n;
-        const int64_t line = line0 + c;
-        if (line >= a.lines) continue;
-        const int64_t tr = line / a.lpt, li = line - tr * a.lpt;
-        const int64_t l2 = li / a.L1, l1 = li - l2 * a.L1;
-        const int64_t g = l1 * a.ls1_out + l2 * a.ls2_out + (int64_t)e * a.es_out;
-        const int64_t N = a.N;
-        double2 v = buf[c * n + e];
-        if (a.store == kStoreComplex) {
-            if (a.twist) {
-                const int64_t m = (((a.tw_full ? li : l1) * (int64_t)e) % N) * a.tmul % N;
-                v = cmul(v, conj_if(split_root(a.wh, a.wl, a.wb, m), a.sign > 0));
+    const bool scol = es_out != 1;
+    const double Nd = (double)N, invN = 1.0 / Nd;
+    const FastDiv dv(scol ? C : n), dtb((int)(a.store == kStoreDct2 ? a.qb : a.wb));
+    double2 val[EPT], rh[EPT], rl[EPT];
+    int64_t dst[EPT];
+    int gg[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int idx = (int)threadIdx.x + u * NT;
+        dst[u] = -1;
+        gg[u] = 0;
+        if (idx < cnt) {
+            const int q = dv.quot(idx), rm = idx - q * dv.d;
+            const int c = scol ? rm : q, e = scol ? q : rm;
+            const FftLine L = ln[c];
+            if (L.base >= 0) {
+                const int g = L.gout + e * es_out;
+                gg[u] = g;
+                val[u] = buf[c * n + e];
+                int t = -1;
+                const double2 *hi = a.wh, *lo = a.wl;
+                if (a.store == kStoreComplex) {
+                    dst[u] = L.base + g;
+                    if (a.twist) t = mod_n((double)L.twa * (double)e, Nd, invN);
+                } else if (a.store == kStoreDct2) {
+                    dst[u] = L.base + g;
+                    t = g;
+                    hi = a.qh;
+                    lo = a.ql;
+                } else {
+                    dst[u] = L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1);
+                }
+                if (t >= 0) {
+                    const int th = dtb.quot(t);
+                    rh[u] = hi[th];
+                    rl[u] = lo[t - th * dtb.d];
+                } else {
+                    rh[u] = rl[u] = make_double2(1.0, 0.0);
+                }
             }
-            a.cout[tr * N + g] = v;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        if (dst[u] < 0) continue;
+        const double2 q = cmul(rh[u], rl[u]);
+        if (a.store == kStoreComplex) {
+            a.cout[dst[u]] = cmul(val[u], conj_if(q, a.sign > 0));
         } else if (a.store == kStoreDct2) {
-            const double2 q = split_root(a.qh, a.ql, a.qb, g);   // Re(conj(q) V)
-            a.rout[tr * N + g] = (q.x * v.x + q.y * v.y) * (g == 0 ? a.scale0 : a.scale);
+            a.rout[dst[u]] = (q.x * val[u].x + q.y * val[u].y) * (gg[u] == 0 ? a.scale0 : a.scale);   // Re(conj(q) V)
         } else {
-            a.rout[tr * N + dct_perm(g, N)] = v.x;
+            a.rout[dst[u]] = val[u].x;
         }
     }
 }
@@ -371,14 +495,37 @@ void set_pass(l2c::FftArgs &a, int n, const std::vector<int> &r, const double2 *
     a.npass = (int)r.size();
     for (int i = 0; i < a.npass; ++i) a.radix[i] = r[i];
     a.tw = tw;
-    a.C = std::max(1, l2c::kFftLds / n);
+    a.C = std::max(1, (n <= l2c::kFftSmall ? l2c::kFftSmall : l2c::kFftLds) / n);
+}
+
+// Both kernel shapes may take more than 64 KiB of dynamic LDS (up to 128 KiB + the line
+// table at n = 4096): raise their limit once per process.
+hipError_t fft_attrs()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        const int lds = 160 * 1024;
+        err = hipFuncSetAttribute((const void *)l2c::k_fft<l2c::kFftSmall, 512>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute((const void *)l2c::k_fft<l2c::kFftLds, 512>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    });
+    return err;
 }
 
 hipError_t launch(const l2c::FftArgs &a, hipStream_t st)
 {
     const int64_t blocks = (a.lines + a.C - 1) / a.C;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(l2c::k_fft, dim3((unsigned)blocks), dim3(l2c::kFftThreads), 0, st, a);
+    const hipError_t e = fft_attrs();
+    if (e != hipSuccess) return e;
+    const size_t lds = ((size_t)a.C * a.n + a.n) * sizeof(double2) + (size_t)a.C * sizeof(l2c::FftLine);
+    if (a.n <= l2c::kFftSmall)
+        hipLaunchKernelGGL((l2c::k_fft<l2c::kFftSmall, 512>), dim3((unsigned)blocks), dim3(512), lds, st, a);
+    else
+        hipLaunchKernelGGL((l2c::k_fft<l2c::kFftLds, 512>), dim3((unsigned)blocks), dim3(512), lds, st, a);
     return hipGetLastError();
 }
 
