@@ -144,6 +144,7 @@ void free_plan(l2c_plan_s *p)
     l2c::dev_free(p->d_D);
     l2c::dev_free(p->d_w);
     l2c::dev_free(p->d_pub);
+    l2c::dev_free(p->d_topsch);
     l2c::host_free(p->h_status);
     l2c::dev_free(p->d_bA);
     l2c::dev_free(p->d_bT);
@@ -824,6 +825,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             // both halves of the exchange buffer start out "not written"
             const size_t pwords = (size_t)2 * items * p->geo.NX * 2 * p->M * 2;
             ok = l2c::dev_alloc(&p->d_pub, pwords * 4) == hipSuccess &&
+                 l2c::fused_top_table(*p, &p->d_topsch) == hipSuccess &&
                  l2c::host_alloc((void **)&p->h_status, l2c::kStatusWords * sizeof(int),
                                  hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
             if (!ok) {

@@ -12,7 +12,7 @@
 // passed the point (first item of the launch, units < 4096).  Each source file has its
 // own copy of the table.
 #ifdef L2C_PHASE_TIMING
-constexpr int kPhaseKernels = 4, kPhaseUnits = 4096, kPhaseSlots = 16;
+constexpr int kPhaseKernels = 4, kPhaseUnits = 4096, kPhaseSlots = 24;
 static __device__ unsigned long long l2c_phase_ts[kPhaseKernels * kPhaseUnits * kPhaseSlots];
 #define L2C_TS(kern, ph)                                                                               \
     do {                                                                                               \

@@ -39,7 +39,9 @@
 // single-launch kernels of different streams from overlapping, so every workgroup of a
 // launch becomes resident.
 #include <mutex>
+#include <vector>
 
+#include "l2c_alloc.h"
 #include "l2c_device.h"
 
 namespace l2c {
@@ -243,27 +245,68 @@ __device__ __forceinline__ void poll_values(double (&v)[NU], const double *p, co
 // Item i of the workgroup's list is one exchange node; a slot's items are consecutive.
 struct TopSlots {
     int X, G0, H, gl, nsl;
-    __device__ TopSlots(int X_, int G0_) : X(X_), G0(G0_)
+    __host__ __device__ TopSlots(int X_, int G0_) : X(X_), G0(G0_)
     {
         H = G0 < 3 ? G0 : 3;
         gl = G0 - H;
         nsl = 2 * (G0 + 1);
     }
-    __device__ int64_t anc(int g) const { return (int64_t)X >> (G0 - g); }
-    __device__ bool ok(int sl) const
+    __host__ __device__ int64_t anc(int g) const { return (int64_t)X >> (G0 - g); }
+    __host__ __device__ bool ok(int sl) const
     {
         const int64_t an = anc(sl >> 1);
         return an < (int64_t(1) << ((sl >> 1) + 2)) - 2 && ((sl & 1) == 0 || (an & 1) == 0);
     }
-    __device__ int64_t col(int sl) const { return anc(sl >> 1) + 2 + (sl & 1); }
-    __device__ int cnt(int sl) const { return (sl >> 1) >= gl ? 1 : 1 << (gl - (sl >> 1)); }
-    __device__ int base(int sl) const      // first item of slot sl
-    {
-        int b = 0;
-        for (int t = 0; t < sl; ++t) b += ok(t) ? cnt(t) : 0;
-        return b;
-    }
+    __host__ __device__ int64_t col(int sl) const { return anc(sl >> 1) + 2 + (sl & 1); }
+    __host__ __device__ int cnt(int sl) const { return (sl >> 1) >= gl ? 1 : 1 << (gl - (sl >> 1)); }
 };
+
+// The per-unit tree-top table (kTopSchedInts ints, built on the host at plan time; each
+// worker wave holds entries 0..63 as one int per lane and reads them by lane shuffles,
+// the top wave also entries 64.. (the item nodes, one per lane)):
+//   [0, 3)            pairs of reduction round r = 1, 2, 3
+//   [3, 45)           round r's pairs: the item of each pair's left child (14 per round)
+//   [45, 59)          each slot's first item (-1: no block)
+//   [59]              nitem, the tree-top items the unit loads
+//   [64, 64 + nitem)  item i's exchange node
+constexpr int kSchPairs = 3, kSchBase = kSchPairs + 3 * 14, kSchItems = kSchBase + 14, kSchNodes = 64;
+static_assert(kSchItems < kSchNodes && kSchNodes + 36 <= kTopSchedInts, "tree-top table layout");
+
+void top_table_unit(int X, int G0, int *rec)
+{
+    const TopSlots ts(X, G0);
+    for (int i = 0; i < kTopSchedInts; ++i) rec[i] = 0;
+    for (int r = 1; r <= 3; ++r) {
+        const int step = 1 << r;
+        int t = 0, base = 0;
+        for (int sl = 0; sl < ts.nsl; ++sl) {
+            if (!ts.ok(sl)) continue;
+            const int c = ts.cnt(sl);
+            if (r <= ts.gl)
+                for (int pp = 0; pp + step <= c; pp += step) rec[kSchPairs + 14 * (r - 1) + t++] = base + pp;
+            base += c;
+        }
+        rec[r - 1] = t;
+    }
+    int base = 0;
+    for (int sl = 0; sl < 14; ++sl) {
+        const bool ok = sl < ts.nsl && ts.ok(sl);
+        rec[kSchBase + sl] = ok ? base : -1;
+        base += ok ? ts.cnt(sl) : 0;
+    }
+    int nitem = 0;
+    for (int sl = 0; sl < ts.nsl; ++sl) {
+        if (!ts.ok(sl)) continue;
+        const int g = sl >> 1;
+        for (int i = 0; i < ts.cnt(sl); ++i)
+            rec[kSchNodes + nitem++] = g >= ts.gl ? (int)(node_offset(g) + ts.col(sl))
+                                                  : (int)(node_offset(ts.gl) + (ts.col(sl) << (ts.gl - g)) + i);
+    }
+    rec[kSchItems] = nitem;
+}
+
+// wave-uniform entry i < 64 of the table held as entry lane of every lane
+__device__ __forceinline__ int sched_at(int lo, int i) { return __shfl(lo, i); }
 
 // The top wave of unit X, while the near field runs, up to the point where the workgroup's
 // tree-top items sit in LDS (itm, nitem x NS, in the T area, which step (1) no longer needs):
@@ -273,16 +316,17 @@ struct TopSlots {
 //      levels G0-1 .. G0-k; it reduces the roots of units X .. X+2^k-1 in the scratch xs and
 //      writes those ancestors to the exchange buffer.  Both inputs come in one poll.
 //   2. The items: wait until every one of them is written, loading it in the same polls.
-constexpr int kSchPairs = 3, kSchBase = kSchPairs + 3 * 14;   // reduction schedule (ints)
 template <int M>
 __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts, int kd, int U, int64_t nbase,
                                            double *wl, double *xs, double *itm, const double *Bl, double *pubc,
-                                           unsigned *nbr, int *sch, int lane)
+                                           unsigned *nbr, int sch_lo, int lane)
 {
     constexpr int M2 = 2 * M, NS = lds_ns<M>();
     const int X = ts.X, G0 = ts.G0;
     const bool act = lane < M2;
     const int sg = lane >= M ? 1 : 0, nn = act ? lane - sg * M : 0;
+    // item i's exchange node, lane i (used after the first poll)
+    const int mine = a.top_sched[(int64_t)X * kTopSchedInts + kSchNodes + lane];
     const int kx = X == 0 ? G0 : min(G0, __ffs(X) - 1);
     const int k = kx < ts.H ? kx : ts.H;
     const int nin = 1 << k;                           // roots X .. X + nin - 1 (k = 0: none)
@@ -304,6 +348,7 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
                 return u < UN ? idx < cntn : (k >= 1 && idx >= M2 && idx < nin * M2);
             },
             [&](int u) { return u < UN ? nb1 + u * 64 + lane : rb + (u - UN) * 64 + lane; }, a);
+        L2C_TS(3, 11);
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
             const int e = u * 64 + lane;
@@ -337,22 +382,9 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
             if (act) store_coherent(pubc + (node_offset(G0 - j) + (X >> j)) * M2 + lane, xs[lane]);
         }
     }
-    // 2. items: lane i < nitem finds the exchange node of item i
-    int nitem = 0;
-    for (int sl = 0; sl < ts.nsl; ++sl) nitem += ts.ok(sl) ? ts.cnt(sl) : 0;
-    int mine = 0;
-    if (lane < nitem) {
-        int i = lane, sl = 0;
-        for (; sl < ts.nsl; ++sl) {
-            if (!ts.ok(sl)) continue;
-            const int c = ts.cnt(sl);
-            if (i < c) break;
-            i -= c;
-        }
-        const int g = sl >> 1;
-        mine = g >= ts.gl ? (int)(node_offset(g) + ts.col(sl))
-                          : (int)(node_offset(ts.gl) + (ts.col(sl) << (ts.gl - g)) + i);
-    }
+    L2C_TS(3, 13);
+    // 2. items: lane i < nitem holds the exchange node of item i (the unit's table)
+    const int nitem = sched_at(sch_lo, kSchItems);
     constexpr int UC = (36 * M2 + 63) / 64;           // at most 36 items (groot <= 6)
     double vc[UC];
     int nid[UC];
@@ -365,33 +397,12 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
     poll_values(
         vc, pubc, [&](int u) { return (u * 64 + lane) / M2 < nitem; },
         [&](int u) { return nid[u] * M2 + (u * 64 + lane) % M2; }, a);
+    L2C_TS(3, 14);
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
         const int idx = u * 64 + lane;
         const int i = idx / M2, e = idx - i * M2;
         if (i < nitem) itm[i * NS + e] = vc[u];
-    }
-    // 3. the schedule of the reduction (scalar bookkeeping, done once here): per round r the
-    //    item of each pair's left child, and each slot's first item (-1: no block)
-    if (lane == 0) {
-        for (int r = 1; r <= 3; ++r) {
-            const int step = 1 << r;
-            int t = 0, base = 0;
-            for (int sl = 0; sl < ts.nsl; ++sl) {
-                if (!ts.ok(sl)) continue;
-                const int c = ts.cnt(sl);
-                if (r <= ts.gl)
-                    for (int pp = 0; pp + step <= c; pp += step) sch[kSchPairs + 14 * (r - 1) + t++] = base + pp;
-                base += c;
-            }
-            sch[r - 1] = t;
-        }
-        int base = 0;
-        for (int sl = 0; sl < 14; ++sl) {
-            const bool ok = sl < ts.nsl && ts.ok(sl);
-            sch[kSchBase + sl] = ok ? base : -1;
-            base += ok ? ts.cnt(sl) : 0;
-        }
     }
 }
 
@@ -404,7 +415,7 @@ __device__ __forceinline__ void top_gather(const ExecArgs &a, const TopSlots &ts
 //   5. the top wave: the chain of step (4) from level 0 down to the unit root,
 //      c(a_g) = canc_g + B(p)^T c(a_{g-1}), p = a_g & 1, into cR.
 template <int M>
-__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm, const int *sch,
+__device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &ts, double *itm, int sch_lo,
                                             const double (&ag0)[M], const double (&ag1)[M], double *canc,
                                             double *zb, double *cR, const double *Bl, unsigned *wcnt,
                                             unsigned &wtarget, int ww, bool top, int lane)
@@ -417,9 +428,9 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
 #pragma unroll
         for (int kk = 0; kk < M; ++kk) brow[kk] = Bl[nn * M + kk];
         for (int r = 1; r <= ts.gl; ++r) {
-            const int np = sch[r - 1], half = (1 << (r - 1)) * NS;
+            const int np = sched_at(sch_lo, r - 1), half = (1 << (r - 1)) * NS;
             for (int t = ww; t < np; t += kWorkWaves) {
-                const int xi = sch[kSchPairs + 14 * (r - 1) + t];
+                const int xi = sched_at(sch_lo, kSchPairs + 14 * (r - 1) + t);
                 const double *x = itm + xi * NS + sg * M;
                 const double v = up_pair<M>(brow, x, x + half, nn);
                 if (act) itm[xi * NS + lane] = v;
@@ -430,7 +441,7 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
     if (ww <= ts.G0) {
         const int g = ww;
         double c0 = 0.0, c1 = 0.0;
-        const int b0 = sch[kSchBase + 2 * g], b1 = sch[kSchBase + 2 * g + 1];
+        const int b0 = sched_at(sch_lo, kSchBase + 2 * g), b1 = sched_at(sch_lo, kSchBase + 2 * g + 1);
         const bool ok0 = b0 >= 0, ok1 = b1 >= 0;
         const double *x0 = itm + (ok0 ? b0 : 0) * NS + sg * M;
         const double *x1 = itm + (ok1 ? b1 : 0) * NS + sg * M;
@@ -625,10 +636,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 #pragma unroll
             for (int c = 0; c < NC3; ++c) t2[c] = sub[(wv * NCH + 2 * NC3 + c) * 64];
         }
+        L2C_TS(3, 17);
         int grp = wv;
 #pragma unroll 1
-        for (; grp + NSW < G.sub_groups; grp += NSW)
+        for (; grp + NSW < G.sub_groups; grp += NSW) {
             stream_group<M, true>(a, grp, grp + NSW, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
+            if (grp == wv) L2C_TS(3, 15);
+        }
         if (grp < G.sub_groups) stream_group<M, false>(a, grp, 0, sub, wl, cown, dummy, kd, nslots, lane, rdy, nbr, t0, t1, t2);
         L2C_TS(3, 8);
     } else {
@@ -726,6 +740,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
+        L2C_TS(3, 16);
         worker_sync(wcnt, wtarget, a);
         if (wt == 0) lds_flag_set(rdy, (unsigned)kd);
         L2C_TS(3, 2);
@@ -805,6 +820,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
             lds_acquire();
+            L2C_TS(3, 18);
         }
         // ---- step (6): near field.  Item (node nd, parity sig, rows m0 .. m0+R-1): row m sums
         //      over m' in [m, 2s): P[m'-m] Q[2s u + sig + m + m'] g[2s u + 2m' + sig], with P, Q
@@ -842,6 +858,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         }
         // ---- steps (2)-(4) above the unit (TopSlots, top_gather, top_combine)
         const TopSlots ts(X, G0);
+        // the unit's tree-top table, entry lane in every lane (read by lane shuffles)
+        const int sch_lo = a.top_sched[(int64_t)X * kTopSchedInts + lane];
         double ag0[M], ag1[M];
         load_anc_rows<M>(a, ts, ww, lane, ag0, ag1);
         // T again, for step (5): the near waves load it now and write it once the column
@@ -854,7 +872,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             vtr[u] = (near && e < 2 * s * M) ? a.T[e] : 0.0;
         }
         if (top) {
-            top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, reinterpret_cast<int *>(w7), lane);
+            top_gather<M>(a, ts, kd, U, nbase, wl, w7, Tl, Bl, pubc, nbr, sch_lo, lane);
             L2C_TS(3, 9);
         }
         worker_sync(wcnt, wtarget, a);         // items and schedule in LDS; near field done
@@ -876,7 +894,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 }
             }
         }
-        top_combine<M>(a, ts, Tl, reinterpret_cast<const int *>(w7), ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget,
+        top_combine<M>(a, ts, Tl, sch_lo, ag0, ag1, w7 + 2 * M2, w7, cR, Bl, wcnt, wtarget,
                        ww, top, lane);
         if (top) L2C_TS(3, 10);
         if (near) {
@@ -1015,6 +1033,17 @@ static const void *fused_kernel(int M)
     }
 }
 
+hipError_t fused_top_table(const l2c_plan_s &p, int **dst)
+{
+    *dst = nullptr;
+    const int G0 = p.geo.groot, U = 1 << (G0 + 2);
+    std::vector<int> tab((size_t)U * kTopSchedInts);
+    for (int X = 0; X < U; ++X) top_table_unit(X, G0, tab.data() + (size_t)X * kTopSchedInts);
+    hipError_t e = dev_alloc(dst, tab.size() * sizeof(int));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice);
+}
+
 // Items per launch such that every workgroup is resident at once (0: path unavailable).
 hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items)
 {
@@ -1077,6 +1106,7 @@ static hipError_t run_fused(l2c_plan_s &p, const double *in, double *out, int64_
     a.ahat_bot = p.d_bot;
     a.w = p.d_w;
     a.pub = p.d_pub;
+    a.top_sched = p.d_topsch;
     a.pub_items = p.fused_items;
     a.status = p.d_status;
     const uint64_t khz = (uint64_t)(p.clock_khz > 0 ? p.clock_khz : 100000);

@@ -96,7 +96,11 @@ struct ExecArgs {
     int *status;         // k_fused: status words (host-mapped); word k set to 1 when a wait of kind k gave up
     uint64_t wait_ticks; // k_fused: bound of the waits inside a workgroup, in wall-clock ticks
     uint64_t poll_ticks; // k_fused: bound of the waits for other workgroups, in wall-clock ticks
+    const int *top_sched; // k_fused: [units][kTopSchedInts] tree-top table per unit (built at plan time)
 };
+
+// Ints per unit of k_fused's tree-top table (reduction schedule and item nodes).
+constexpr int kTopSchedInts = 128;
 
 // Status words of the single-launch path (ExecArgs::status), one per kind of wait; the
 // plan reports word k as bit k (leg2cheb_plan_status).
@@ -137,6 +141,7 @@ struct l2c_plan_s {
     bool fused_on = true;       // caller preference (leg2cheb_plan_set_option)
     int64_t fused_items = 0;    // items per k_fused launch (all workgroups co-resident)
     double *d_pub = nullptr;    // ExecArgs::pub, fused_items items per half
+    int *d_topsch = nullptr;    // ExecArgs::top_sched
     int *h_status = nullptr;    // kStatusWords words of pinned, device-mapped host memory
     int *d_status = nullptr;    // the device address of h_status
     unsigned epoch = 0;
@@ -190,6 +195,8 @@ hipError_t launch_execute_scratch(const l2c_plan_s &p, const double *in, double 
 // l2c_fused.hip
 bool fused_supported(int M);
 hipError_t fused_max_items(const l2c_plan_s &p, int64_t *items);
+// k_fused's tree-top table of every unit, into a new device array (synchronous).
+hipError_t fused_top_table(const l2c_plan_s &p, int **dst);
 hipError_t launch_fused(l2c_plan_s &p, const double *in, double *out, int64_t batch, hipStream_t stream,
                         const ItemArrays *ia = nullptr);
 // l2c_batched.hip

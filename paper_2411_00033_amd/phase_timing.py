@@ -23,11 +23,18 @@ from . import build as hipbuild
 PHASES = [
     (0, "start"),
     (1, "input, T, B, P staged (workers' first barrier)"),
+    (17, "streamer: first group's loads issued"),
+    (16, "workers: step (1) products done (before their barrier)"),
     (2, "step (1) done (finest w)"),
     (12, "step (2) inside the unit done"),
     (3, "unit root and boundary nodes published"),
+    (18, "near waves: Q table done"),
     (4, "near field (step (6)) done"),
+    (11, "top wave: next unit's nodes and the roots below its ancestors polled"),
+    (13, "top wave: its ancestors (step (2) above the units) published"),
+    (14, "top wave: tree-top items polled"),
     (9, "top wave: tree-top items in LDS"),
+    (15, "streamer: first group multiplied"),
     (8, "streamer: own far-field blocks done (step (3))"),
     (10, "top wave: tree-top reduction, ancestor blocks, chain to the unit root"),
     (5, "all waves joined"),
@@ -36,7 +43,7 @@ PHASES = [
 ]
 __doc__ += "\n".join("  %2d  %s" % p for p in PHASES) + "\n"
 
-KERNELS, UNITS, SLOTS = 4, 4096, 16
+KERNELS, UNITS, SLOTS = 4, 4096, 24
 
 
 def build_variant() -> str:
