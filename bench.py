@@ -224,6 +224,16 @@ def batched_form(l2c, inputs, torch, K, W, flush, flush_sink, with_fp64=True):
                                  "mfma_fp64_frac": flops64 / (mst * 1e-3) / 1e12 / 78.6,
                                  "einf_vs_fp64_path_rank18": dt}
         pt.close()
+        # the nodal basis (Eq. (AijLag)) on the same kernels: FP32 form and FP64 tile form
+        nod = {}
+        for tag, prec in (("fp32", l2c.L2C_FP32), ("fp64_tile", l2c.L2C_FP64)):
+            yn = torch.empty_like(x)
+            pn = l2c.Plan(BATCH_N, l2c.LEG2CHEB, 64, 16, precision=prec, max_batch=BATCH_B, basis=l2c.L2C_NODAL)
+            msn = timed(pn, yn)
+            pn.close()
+            nod[tag] = {"ms_per_execute": msn, "Gcoeff_s": coeffs / (msn * 1e-3) / 1e9,
+                        "einf_vs_fp64_path_rank18": (yn - y64).abs().max().item() / y64.abs().max().item()}
+        rec["nodal_basis"] = nod
     p32.close()
     return rec
 

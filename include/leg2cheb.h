@@ -112,6 +112,8 @@ struct l2c_plan_info {
     int64_t table_bytes;   /* device bytes of the plan tables (Ahat, T, B, ...) */
     int64_t workspace_bytes; /* device bytes of the execution workspace for the current batch capacity */
     int64_t ahat_bytes;    /* bytes of the Ahat table alone (read once per execute) */
+    int32_t basis;         /* l2c_basis */
+    int32_t reserved;      /* zero */
 };
 
 /*
@@ -140,6 +142,28 @@ int leg2cheb_plan(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int
  */
 int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank,
                      int precision, int64_t max_batch, void *stream);
+
+/* Basis of the far-field expansions (leg2cheb_plan_basis).
+ *   L2C_MODAL  Chebyshev coefficients (the paper's method, Secs. 3.2 and 4.1): Ahat from a
+ *              2-D DCT of the kernel samples, T(sigma) Chebyshev polynomials, the exact
+ *              dyadic B(0), B(1) (App. A3).
+ *   L2C_NODAL  values at the Chebyshev-Gauss nodes with the Lagrange basis (Alpert and
+ *              Rokhlin's nodal method, Sec. 3.2, Eq. (AijLag)): the far-field blocks are
+ *              the kernel samples themselves, the leaf matrices hold l_k(X_m^sigma), and
+ *              the transfers are the dense interpolation matrices l_k((X_j + 2l - 1)/2).
+ *              Mathematically the same approximation (the interpolant of degree M-1 at the
+ *              nodes); the upward and downward transfers cost dense M x M products
+ *              instead of the modal triangular ones (Sec. 4.2). */
+enum l2c_basis { L2C_MODAL = 0, L2C_NODAL = 1 };
+
+/*
+ * As leg2cheb_plan_ex, with the expansion basis.  L2C_NODAL is served by the batched
+ * kernels only: precision L2C_FP32, L2C_BF16X2 or L2C_FP16X2, or L2C_FP64 with rank <= 16,
+ * leaf_size <= 64 and a batch large enough for the FP64 tile form (max_batch >= 16, and
+ * n above the short-transform paths' bounds); otherwise L2C_EUNSUPPORTED.
+ */
+int leg2cheb_plan_basis(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
+                        int64_t max_batch, int basis, void *stream);
 
 /*
  * out[b, 0:n] = T(in[b, 0:n]) for b < batch, T = C^{-1}A (leg2cheb) or A^{-1}C

@@ -20,9 +20,10 @@ L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DEN
 L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US = 1, 2, 3
 L2C_STATUS_EXCHANGE, L2C_STATUS_WORKERS, L2C_STATUS_STREAM = 1, 2, 4
 L2C_LEG2GRID, L2C_GRID2LEG = 0, 1
+L2C_MODAL, L2C_NODAL = 0, 1
 
 EXPORTED = (
-    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
+    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_plan_basis", "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
     "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
@@ -40,6 +41,7 @@ class PlanInfo(ctypes.Structure):
         ("direction", ctypes.c_int32), ("precision", ctypes.c_int32), ("path", ctypes.c_int32),
         ("n_blocks", ctypes.c_int64), ("n_submatrices", ctypes.c_int64),
         ("table_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("ahat_bytes", ctypes.c_int64),
+        ("basis", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -75,6 +77,7 @@ def load() -> ctypes.CDLL:
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.leg2cheb_plan.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci]
     lib.leg2cheb_plan_ex.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, vp]
+    lib.leg2cheb_plan_basis.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, ci, vp]
     lib.leg2cheb_execute.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_execute_noalloc.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_destroy.argtypes = [vp]
@@ -133,6 +136,15 @@ def leg2cheb_plan_ex(n: int, direction: int, leaf_size: int, rank: int, precisio
     _check(load().leg2cheb_plan_ex(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
                                    int(precision), int(max_batch), ctypes.c_void_p(stream or None)),
            "leg2cheb_plan_ex")
+    return h.value
+
+
+def leg2cheb_plan_basis(n: int, direction: int, leaf_size: int, rank: int, precision: int = L2C_FP64,
+                        max_batch: int = 1, basis: int = L2C_MODAL, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_plan_basis(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
+                                      int(precision), int(max_batch), int(basis), ctypes.c_void_p(stream or None)),
+           "leg2cheb_plan_basis")
     return h.value
 
 

@@ -121,6 +121,52 @@ void b_matrices(int M, std::vector<double> &B)
     }
 }
 
+// The nodal basis (Eq. (AijLag)): Lagrange polynomials l_k on the Chebyshev-Gauss nodes
+// x_k = cos((k + 1/2) pi / M), evaluated through the discrete orthogonality of T_j at those
+// nodes, l_k(x) = (1/M) (1 + 2 sum_{j=1}^{M-1} T_j(x_k) T_j(x)), in long double.
+long double lagrange(int M, int k, long double x)
+{
+    const long double xk = cosl(((long double)k + 0.5L) * 3.141592653589793238462643383279502884L / (long double)M);
+    long double tk0 = 1.0L, tk1 = xk, t0 = 1.0L, t1 = x, sum = 1.0L;
+    if (M > 1) sum += 2.0L * tk1 * t1;
+    for (int j = 2; j < M; ++j) {
+        const long double tk = 2.0L * xk * tk1 - tk0, t = 2.0L * x * t1 - t0;
+        sum += 2.0L * tk * t;
+        tk0 = tk1;
+        tk1 = tk;
+        t0 = t1;
+        t1 = t;
+    }
+    return sum / (long double)M;
+}
+
+// Nodal transfers: B(l)[k][j] = l_k((x_j + 2l - 1)/2), the parent's basis function k at
+// child l's node j (left child l = 0), so that w(parent) = B(0) w(2b) + B(1) w(2b+1) and
+// c(child l) += B(l)^T c(parent), as in the modal case.
+void nodal_b_matrices(int M, std::vector<double> &B)
+{
+    B.assign(2 * M * M, 0.0);
+    for (int l = 0; l < 2; ++l)
+        for (int j = 0; j < M; ++j) {
+            const long double xj =
+                cosl(((long double)j + 0.5L) * 3.141592653589793238462643383279502884L / (long double)M);
+            const long double u = (xj + 2.0L * l - 1.0L) / 2.0L;
+            for (int k = 0; k < M; ++k) B[(size_t)l * M * M + k * M + j] = (double)lagrange(M, k, u);
+        }
+}
+
+// Nodal leaf matrices: L[sigma][m][k] = l_k(X), X = -1 + (2m + sigma)/s (the points of
+// Eq. (Xs)).
+void nodal_leaf_matrices(int M, int s, std::vector<double> &Lm)
+{
+    Lm.assign((size_t)2 * s * M, 0.0);
+    for (int sg = 0; sg < 2; ++sg)
+        for (int m = 0; m < s; ++m) {
+            const long double x = -1.0L + (long double)(2 * m + sg) / (long double)s;
+            for (int k = 0; k < M; ++k) Lm[((size_t)sg * s + m) * M + k] = (double)lagrange(M, k, x);
+        }
+}
+
 bool rank_supported(int M)
 {
     switch (M) {
@@ -327,7 +373,7 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
 }
 
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf);
+              void *stream, bool full_leaf, int basis = L2C_MODAL);
 
 // Workspace of the batched form: tiles of 16 items, NT nodes x 2 parities x 256 values.
 int ensure_bworkspace(l2c_plan_s *p, int64_t items)
@@ -372,7 +418,8 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
     const int M = p->M, s = p->s;
     const int64_t blocks = l2c::level_block_offset(p->L);
     const int64_t qlen = p->n_pad + 2 * (int64_t)s;
-    const int64_t nT = 2 * (int64_t)s * M, nB = (int64_t)M * M, nP = 2 * (int64_t)s;
+    const int64_t nT = 2 * (int64_t)s * M, nP = 2 * (int64_t)s;
+    const int64_t nB = (int64_t)M * M * (p->basis == L2C_NODAL ? 2 : 1);   // nodal: B(1) is a table too
     const size_t eb = elem_bytes(p);
     bool ok = l2c::dev_alloc(&p->d_bA, (size_t)blocks * 3 * 256 * eb) == hipSuccess &&
               l2c::dev_alloc(&p->d_bQ, (size_t)qlen * sizeof(double)) == hipSuccess &&   // near field: FP64
@@ -404,7 +451,7 @@ int build_batched_tables(l2c_plan_s *p, hipStream_t st)
     p->top_bytes = (int64_t)blocks * 3 * 256 * (int64_t)eb;   // Ahat as stored
     p->bot_bytes = 0;
     p->table_bytes = p->top_bytes + (nT + nB) * (int64_t)eb + (qlen + nP) * 8 +
-                     (nT + 2 * nB + l2c::p_table_len(s) + M + nB) * 8 +
+                     (nT + 3 * (int64_t)M * M + l2c::p_table_len(s) + M) * 8 +   // FP64 T, B(0), B(1), D, P, points
                      (p->d_bS ? blocks * 3 * (int64_t)sizeof(float) : 0);
     return L2C_OK;
 }
@@ -686,7 +733,7 @@ namespace {
 // full_leaf: s = leaf_size / 2 instead of the smallest s of Eq. (numlevels) that covers n
 // (same L; more padding), so that transforms of one L share every table.
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf);
+              void *stream, bool full_leaf, int basis);
 }  // namespace
 
 extern "C" {
@@ -697,11 +744,17 @@ int leg2cheb_plan_ex(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, 
     return plan_impl(plan, n, direction, leaf_size, rank, precision, max_batch, stream, false);
 }
 
+int leg2cheb_plan_basis(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
+                        int64_t max_batch, int basis, void *stream)
+{
+    return plan_impl(plan, n, direction, leaf_size, rank, precision, max_batch, stream, false, basis);
+}
+
 }  // extern "C"
 
 namespace {
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf)
+              void *stream, bool full_leaf, int basis)
 {
     if (!plan) return L2C_EINVAL;
     *plan = nullptr;
@@ -715,6 +768,14 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     // the batched forms: one 16 x 16 tile per node (M <= 16), s <= 32, rows of at most
     // 2^28 values (32-bit buffer ranges)
     if (batched_form(precision) && (rank > 16 || leaf_size > 64 || n > (int64_t(1) << 28))) return L2C_EUNSUPPORTED;
+    if (basis != L2C_MODAL && basis != L2C_NODAL) return L2C_EINVAL;
+    // the FP64 tile form: batches of FP64 transforms at rank <= 16, unless the dense or
+    // direct products serve them better
+    const bool tile64 = !batched_form(precision) && rank <= 16 && leaf_size <= 64 && n <= (int64_t(1) << 28) &&
+                        max_batch >= l2c::kTile64MinBatch && !(n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) &&
+                        !(n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n));
+    // the nodal basis runs on the batched kernels only (dense tile products)
+    if (basis == L2C_NODAL && !batched_form(precision) && !tile64) return L2C_EUNSUPPORTED;
 
     l2c_plan_s *p = new (std::nothrow) l2c_plan_s();
     if (!p) return L2C_ENOMEM;
@@ -723,6 +784,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     p->precision = precision;
     p->leaf = leaf_size;
     p->M = rank;
+    p->basis = basis;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return L2C_EHIP;
@@ -753,8 +815,13 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
 
         // B(0), B(1) on the host (exact dyadic rationals); T, P, the Chebyshev-Gauss points,
         // the DCT matrix and Ahat on the device
-        std::vector<double> B;
-        b_matrices(M, B);
+        std::vector<double> B, Lnod;
+        if (basis == L2C_NODAL) {
+            nodal_b_matrices(M, B);
+            nodal_leaf_matrices(M, s, Lnod);
+        } else {
+            b_matrices(M, B);
+        }
         const int64_t nT = 2 * (int64_t)s * M, nP = l2c::p_table_len(s);
 
         bool ok = l2c::dev_alloc(&p->d_top, p->top_bytes) == hipSuccess &&
@@ -772,6 +839,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         p->table_bytes = p->top_bytes + p->bot_bytes + (nT + (int64_t)B.size() + nP + M + (int64_t)M * M) * 8;
         ok = hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              l2c::launch_build_small(*p, st) == hipSuccess &&
+             (Lnod.empty() || hipMemcpyAsync(p->d_T, Lnod.data(), Lnod.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess) &&
              (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
              l2c::launch_build_ahat(*p, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
         if (!ok) {
@@ -779,11 +847,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             free_plan(p);
             return L2C_EHIP;
         }
-        // batches of FP64 transforms at rank <= 16: the FP64 tile form (16 transforms per
-        // FP64 matrix-core tile), unless the dense or direct products serve them better
-        p->tile64 = !batched_form(precision) && M <= 16 && leaf_size <= 64 && n <= (int64_t(1) << 28) &&
-                    max_batch >= l2c::kTile64MinBatch && !(n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) &&
-                    !(n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n));
+        p->tile64 = tile64;
         if (batched_form(precision) || p->tile64) {
             int rc = build_batched_tables(p, st);
             if (rc == L2C_OK) rc = ensure_bworkspace(p, max_batch);
@@ -978,6 +1042,7 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
     info->workspace_bytes = plan->ws_batch * plan->geo.NT * 2 * plan->M * (int64_t)sizeof(double) +
                             plan->bw_tiles * plan->geo.NT * 2 * 256 * (int64_t)elem_bytes(plan);
     info->ahat_bytes = plan->top_bytes + plan->bot_bytes;
+    info->basis = plan->basis;
     info->path = plan->L == 0                           ? L2C_PATH_DIRECT
                  : plan->d_dense                        ? L2C_PATH_DENSE
                  : use_batched(plan)                    ? L2C_PATH_BATCHED

@@ -78,6 +78,7 @@ struct BatArgs {
     const float *ahat_inv;          // FP16X2: [blocks][3] factor that undoes a submatrix's scaling
     const T *Tm;                    // [2][s][M]
     const T *B0;                    // [M][M]
+    const T *B1;                    // [M][M], nodal basis; null: B(1) = B(0) with odd diagonals negated
     const double *Pt;               // [2s]: P_d (the near field is FP64 in every form)
     const double *Qt;               // [n_pad + 2s]: Q_S
     T *w;                           // [tiles][NT][2][64][4]
@@ -354,16 +355,18 @@ __device__ __forceinline__ void up_walk(const BatArgs<T> &a, int64_t t0, int gle
 {
     const int li = lane & 15, q = lane >> 4;
     const int M = a.M, s = a.s;
-    // A operands of the parent transfer: B(0) and B(1) = B(0) with odd diagonals negated
+    // A operands of the parent transfer: B(0) and B(1) (modal: B(0) with odd diagonals
+    // negated; nodal: its own table)
     Aop<FM> b0a, b1a;
     {
         T v0[4], v1[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = Mx<T>::row(q, kk);
-            const T v = (li < M && k < M) ? a.B0[li * M + k] : T(0);
+            const bool ok = li < M && k < M;
+            const T v = ok ? a.B0[li * M + k] : T(0);
             v0[kk] = v;
-            v1[kk] = ((li - k) & 1) ? -v : v;
+            v1[kk] = a.B1 ? (ok ? a.B1[li * M + k] : T(0)) : (((li - k) & 1) ? -v : v);
         }
         b0a = aop<FM>(v0);
         b1a = aop<FM>(v1);
@@ -605,7 +608,7 @@ __device__ __forceinline__ void main_body(const BatArgs<T> &a)
         const bool ok = li < M && k < M;
         const T v = a.B0[ok ? k * M + li : 0];
         btv[0][kk] = ok ? v : T(0);
-        btv[1][kk] = ((k - li) & 1) ? -btv[0][kk] : btv[0][kk];
+        btv[1][kk] = a.B1 ? (ok ? a.B1[k * M + li] : T(0)) : (((k - li) & 1) ? -btv[0][kk] : btv[0][kk]);
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -1014,6 +1017,7 @@ static hipError_t run_batched(const l2c_plan_s &p, const double *in, double *out
         a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
+        a.B1 = p.basis == L2C_NODAL ? (const T *)p.d_bB + p.M * p.M : nullptr;
         a.Pt = (const double *)p.d_bP;
         a.Qt = (const double *)p.d_bQ;
         a.w = (T *)p.d_bw;
@@ -1146,6 +1150,7 @@ hipError_t batched_grouped_make(const l2c_plan_s *const *plans, const ItemArrays
         a.ahat_inv = p.d_bS;
         a.Tm = (const T *)p.d_bT;
         a.B0 = (const T *)p.d_bB;
+        a.B1 = p.basis == L2C_NODAL ? (const T *)p.d_bB + p.M * p.M : nullptr;
         a.Pt = (const double *)p.d_bP;
         a.Qt = (const double *)p.d_bQ;
         a.w = (T *)p.d_bw;

@@ -151,8 +151,9 @@ struct l2c_plan_s {
     // [tiles][NT][2][16 x 16] tiles; the FP64 Ahat tables are released after packing
     void *d_bA = nullptr;       // Ahat, [blocks][3][64][4] A operands
     void *d_bT = nullptr;       // [2][s][M]
-    void *d_bB = nullptr;       // [M][M]
+    void *d_bB = nullptr;       // [M][M] (nodal basis: [2][M][M], B(0) then B(1))
     void *d_bP = nullptr;       // [2s]
+    int basis = 0;              // l2c_basis
     void *d_bQ = nullptr;       // [n_pad + 2s]
     void *d_bw = nullptr;
     bool tile64 = false;        // an FP64 plan that executes in the FP64 tile form (l2c_batched.hip)

@@ -8,7 +8,8 @@
 // cheb2leg kernel of Eq. (Lxymod), and applies the 2-D DCT-II
 //     ahat_kl = 4/(c_k c_l M^2) sum_m sum_n K(x_m, y_n) D_km D_ln,  D_km = cos(k (m+1/2) pi / M),
 // as two M x M x M products in LDS.  All in FP64.  Results go straight into the
-// far-field tables that k_main reads (layouts in l2c_internal.h).
+// far-field tables that k_main reads (layouts in l2c_internal.h).  For the nodal basis
+// (Eq. (AijLag)) the samples K(x_k, y_l) themselves are the far-field blocks.
 //
 // k_build_small makes the Vandermonde matrices T(sigma) of Eq. (Xs), the near-field factor
 // P_d, the Chebyshev-Gauss points and the DCT matrix, also in FP64 on the device.
@@ -47,7 +48,7 @@ __device__ __forceinline__ double *ahat_addr(double *top, double *bot, const Geo
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bot, Geometry G, int dir,
-                                                          const double *XG, const double *Dm)
+                                                          const double *XG, const double *Dm, int nodal)
 {
     constexpr int MM = M * M;
     __shared__ double S[3 * MM];
@@ -76,7 +77,9 @@ __global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bo
         const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
         const double j0 = 2.0 * h * (double)(2 * b + q + 2);
         S[e] = kernel_value(dir, i0 + h * (Xl[m] + 1.0), j0 + h * (Xl[n] + 1.0));
+        if (nodal) *ahat_addr<M>(top, bot, G, g, b, r, m, n) = S[e];
     }
+    if (nodal) return;
     __syncthreads();
     // U[r][m][l] = sum_n S[r][m][n] D[l][n]
     for (int e = tid; e < 3 * MM; e += kThreads) {
@@ -184,7 +187,7 @@ template <int M>
 static hipError_t build(const l2c_plan_s &p, hipStream_t st)
 {
     hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)p.nb), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
-                       p.direction, p.d_XG, p.d_D);
+                       p.direction, p.d_XG, p.d_D, p.basis);
     return hipGetLastError();
 }
 

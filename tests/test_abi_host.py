@@ -204,3 +204,14 @@ def test_dct_and_grid_argument_errors(lib):
     assert L.leg2cheb_grid_execute(None, None, None, 1, None) == -1
     assert L.leg2cheb_dct_destroy(None) == 0 and L.leg2cheb_grid_destroy(None) == 0
     assert not L.leg2cheb_grid_fmm(None) and not L.leg2cheb_grid_dct(None)
+
+
+def test_plan_basis_argument_errors(lib):
+    """The nodal basis is served by the batched kernels only; checked before any device call."""
+    L = lib.load()
+    h = ctypes.c_void_p(1)
+    assert L.leg2cheb_plan_basis(ctypes.byref(h), 1000, 0, 64, 16, 1, 1, 2, None) == -1 and h.value is None
+    assert L.leg2cheb_plan_basis(ctypes.byref(h), 100000, 0, 64, 18, 0, 64, 1, None) == -4   # FP64 rank 18
+    assert L.leg2cheb_plan_basis(ctypes.byref(h), 100000, 0, 64, 16, 0, 1, 1, None) == -4    # FP64, batch of 1
+    assert L.leg2cheb_plan_basis(ctypes.byref(h), 1000, 0, 64, 16, 0, 64, 1, None) == -4     # dense path's range
+    assert L.leg2cheb_plan_basis(None, 1000, 0, 64, 16, 1, 1, 1, None) == -1

@@ -313,3 +313,29 @@ def test_config3_fp64_tile_form(l2c, cfg3):
     e64 = max(oracle.einf(z[b], cfg3["z64"][b]) for b in range(256))
     print("cfg3 FP64 tile form: E_inf vs oracle %.2e, vs FP64 path rank 18 %.2e" % (e_or, e64), flush=True)
     assert e_or <= 1e-13 and e64 <= 1e-13
+
+
+# ----------------------------------------------------------------- nodal basis
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("form", ["fp32", "bf16x2", "fp16x2", "fp64"])
+def test_nodal_basis_against_oracle(l2c, form, direction):
+    """The nodal (Lagrange) basis of Eq. (AijLag) on the batched kernels: the same
+    approximation as the modal one, so the same bound; compared with the oracle on every
+    transform of a batch of 21 (a full tile and a ragged one)."""
+    import torch
+    from tolerances import TOL64
+    n, B = 20000, 21
+    prec, tol = {"fp32": (l2c.L2C_FP32, TOL32), "bf16x2": (l2c.L2C_BF16X2, TOLBF),
+                 "fp16x2": (l2c.L2C_FP16X2, TOLF16), "fp64": (l2c.L2C_FP64, TOL64[(direction, 16)])}[form]
+    F = inputs.decaying(n, 1.0, inputs.SEED_BASE + 600 + direction, batch=B)
+    x = torch.from_numpy(F).cuda()
+    with l2c.Plan(n, direction, 64, 16, precision=prec, max_batch=B, basis=l2c.L2C_NODAL) as p:
+        info = p.info
+        Z = p.execute(x).cpu().numpy()
+    with l2c.Plan(n, direction, 64, 16, precision=prec, max_batch=B) as pm:
+        Zm = pm.execute(x).cpu().numpy()
+    assert info["basis"] == l2c.L2C_NODAL and info["path"] == l2c.L2C_PATH_BATCHED
+    worst = max(oracle.einf(Z[b], oracle.transform(F[b], direction)) for b in range(B))
+    dm = max(oracle.einf(Z[b], Zm[b]) for b in range(B))
+    print("nodal %s dir=%d E_inf=%.2e (modal differs by %.2e)" % (form, direction, worst, dm), flush=True)
+    assert worst <= tol
