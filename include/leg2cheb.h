@@ -166,6 +166,20 @@ int leg2cheb_plan_basis(l2c_plan_t *plan, int64_t n, int direction, int leaf_siz
                         int64_t max_batch, int basis, void *stream);
 
 /*
+ * The plan cache (planning costs about 3 times an execute, Sec. 5.2): returns the shared
+ * plan made with exactly these arguments on the current device, building it on the first
+ * call, and takes one reference to it; leg2cheb_destroy releases one reference and frees
+ * the plan with the last.  A shared plan is one plan: executes through it on different
+ * streams must be ordered by the caller, as for any plan.  Thread-safe.
+ * Errors: those of leg2cheb_plan_basis.
+ */
+int leg2cheb_plan_cached(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
+                         int64_t max_batch, int basis, void *stream);
+
+/* Plans in the cache and the references they hold (either pointer may be NULL). */
+int leg2cheb_plan_cache_size(int64_t *plans, int64_t *references);
+
+/*
  * out[b, 0:n] = T(in[b, 0:n]) for b < batch, T = C^{-1}A (leg2cheb) or A^{-1}C
  * (cheb2leg) as fixed at plan time (Alg. 4, steps (1)-(7)).
  *   in, out  device pointers, FP64 [batch][n], non-overlapping.
@@ -196,7 +210,8 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
  */
 int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
 
-/* Release the plan and its device memory (synchronizes the device first). NULL is a no-op. */
+/* Release the plan and its device memory (synchronizes the device first); for a plan of
+ * the plan cache, release one reference (the memory goes with the last).  NULL is a no-op. */
 int leg2cheb_destroy(l2c_plan_t plan);
 
 /* Sizes and memory of a plan. */

@@ -22,7 +22,8 @@ from ._lib import (  # noqa: F401  (re-exported ABI names)
     leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
     leg2cheb_rank_supported, leg2cheb_debug_alloc_hook, leg2cheb_set_timing_events, leg2cheb_batch_plan, leg2cheb_batch_execute,
     leg2cheb_batch_info, leg2cheb_batch_destroy, leg2cheb_batch_tuning,
-    L2C_LEG2GRID, L2C_GRID2LEG, L2C_MODAL, L2C_NODAL, leg2cheb_plan_basis, leg2cheb_dct_plan, leg2cheb_dct_execute, leg2cheb_dct_destroy, leg2cheb_grid_plan,
+    L2C_LEG2GRID, L2C_GRID2LEG, L2C_MODAL, L2C_NODAL, leg2cheb_plan_basis, leg2cheb_plan_cached,
+    leg2cheb_plan_cache_size, leg2cheb_dct_plan, leg2cheb_dct_execute, leg2cheb_dct_destroy, leg2cheb_grid_plan,
     leg2cheb_grid_execute, leg2cheb_grid_destroy, leg2cheb_grid_fmm, leg2cheb_grid_dct,
 )
 
@@ -39,11 +40,15 @@ class Plan:
     """Owns one library plan (device tables + workspace) for transforms of length n."""
 
     def __init__(self, n: int, direction: int = LEG2CHEB, leaf_size: int = 64, rank: int = 18,
-                 precision: int = L2C_FP64, max_batch: int = 1, stream=None, basis: int = L2C_MODAL):
+                 precision: int = L2C_FP64, max_batch: int = 1, stream=None, basis: int = L2C_MODAL,
+                 cached: bool = False):
         torch = _torch()
         st = stream if stream is not None else torch.cuda.current_stream()
         self.device = torch.cuda.current_device()
-        if basis == L2C_MODAL:
+        if cached:   # a reference to the shared plan of the plan cache (close releases it)
+            self.handle = leg2cheb_plan_cached(n, direction, leaf_size, rank, precision, max_batch, basis,
+                                               st.cuda_stream)
+        elif basis == L2C_MODAL:
             self.handle = leg2cheb_plan_ex(n, direction, leaf_size, rank, precision, max_batch, st.cuda_stream)
         else:
             self.handle = leg2cheb_plan_basis(n, direction, leaf_size, rank, precision, max_batch, basis,

@@ -23,7 +23,8 @@ L2C_LEG2GRID, L2C_GRID2LEG = 0, 1
 L2C_MODAL, L2C_NODAL = 0, 1
 
 EXPORTED = (
-    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_plan_basis", "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
+    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_plan_basis", "leg2cheb_plan_cached", "leg2cheb_plan_cache_size",
+    "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
     "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
@@ -78,6 +79,8 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_plan.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci]
     lib.leg2cheb_plan_ex.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, vp]
     lib.leg2cheb_plan_basis.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, ci, vp]
+    lib.leg2cheb_plan_cached.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, ci, vp]
+    lib.leg2cheb_plan_cache_size.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.leg2cheb_execute.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_execute_noalloc.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_destroy.argtypes = [vp]
@@ -146,6 +149,21 @@ def leg2cheb_plan_basis(n: int, direction: int, leaf_size: int, rank: int, preci
                                       int(precision), int(max_batch), int(basis), ctypes.c_void_p(stream or None)),
            "leg2cheb_plan_basis")
     return h.value
+
+
+def leg2cheb_plan_cached(n: int, direction: int, leaf_size: int, rank: int, precision: int = L2C_FP64,
+                         max_batch: int = 1, basis: int = L2C_MODAL, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_plan_cached(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
+                                       int(precision), int(max_batch), int(basis), ctypes.c_void_p(stream or None)),
+           "leg2cheb_plan_cached")
+    return h.value
+
+
+def leg2cheb_plan_cache_size():
+    plans, refs = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().leg2cheb_plan_cache_size(ctypes.byref(plans), ctypes.byref(refs)), "leg2cheb_plan_cache_size")
+    return plans.value, refs.value
 
 
 def leg2cheb_execute(plan: int, in_ptr: int, out_ptr: int, batch: int, stream: int = 0) -> None:

@@ -3,6 +3,7 @@
 // device), device memory ownership, and dispatch to the kernels.
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -785,6 +786,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     p->leaf = leaf_size;
     p->M = rank;
     p->basis = basis;
+    p->max_batch = max_batch;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return L2C_EHIP;
@@ -1017,9 +1019,62 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
     return L2C_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The plan cache: shared plans keyed by every plan argument and the device, each with a
+// reference count; leg2cheb_destroy releases one reference.
+std::mutex g_cache_mu;
+std::vector<l2c_plan_s *> g_cache;
+}  // namespace
+
+extern "C" {
+
+int leg2cheb_plan_cached(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
+                         int64_t max_batch, int basis, void *stream)
+{
+    if (!plan) return L2C_EINVAL;
+    *plan = nullptr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return L2C_EHIP;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (l2c_plan_s *p : g_cache) {
+        if (p->device == dev && p->n == n && p->direction == direction && p->leaf == leaf_size && p->M == rank &&
+            p->precision == precision && p->max_batch == max_batch && p->basis == basis) {
+            ++p->cache_refs;
+            *plan = p;
+            return L2C_OK;
+        }
+    }
+    l2c_plan_t p = nullptr;
+    const int rc = plan_impl(&p, n, direction, leaf_size, rank, precision, max_batch, stream, false, basis);
+    if (rc != L2C_OK) return rc;
+    p->cache_refs = 1;
+    g_cache.push_back(p);
+    *plan = p;
+    return L2C_OK;
+}
+
+int leg2cheb_plan_cache_size(int64_t *plans, int64_t *references)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    int64_t r = 0;
+    for (l2c_plan_s *p : g_cache) r += p->cache_refs;
+    if (plans) *plans = (int64_t)g_cache.size();
+    if (references) *references = r;
+    return L2C_OK;
+}
+
 int leg2cheb_destroy(l2c_plan_t plan)
 {
     if (!plan) return L2C_OK;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (plan->cache_refs > 0) {
+            if (--plan->cache_refs > 0) return L2C_OK;
+            g_cache.erase(std::find(g_cache.begin(), g_cache.end(), plan));
+        }
+    }
     const bool ok = hipDeviceSynchronize() == hipSuccess;
     free_plan(plan);
     return ok ? L2C_OK : L2C_EHIP;

@@ -154,6 +154,8 @@ struct l2c_plan_s {
     void *d_bB = nullptr;       // [M][M] (nodal basis: [2][M][M], B(0) then B(1))
     void *d_bP = nullptr;       // [2s]
     int basis = 0;              // l2c_basis
+    int64_t max_batch = 0;      // as requested at plan time
+    int cache_refs = 0;         // > 0: a shared plan of the plan cache (leg2cheb_plan_cached)
     void *d_bQ = nullptr;       // [n_pad + 2s]
     void *d_bw = nullptr;
     bool tile64 = false;        // an FP64 plan that executes in the FP64 tile form (l2c_batched.hip)

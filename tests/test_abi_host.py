@@ -215,3 +215,12 @@ def test_plan_basis_argument_errors(lib):
     assert L.leg2cheb_plan_basis(ctypes.byref(h), 100000, 0, 64, 16, 0, 1, 1, None) == -4    # FP64, batch of 1
     assert L.leg2cheb_plan_basis(ctypes.byref(h), 1000, 0, 64, 16, 0, 64, 1, None) == -4     # dense path's range
     assert L.leg2cheb_plan_basis(None, 1000, 0, 64, 16, 1, 1, 1, None) == -1
+
+
+def test_plan_cache_host_logic(lib):
+    L = lib.load()
+    plans, refs = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    assert L.leg2cheb_plan_cache_size(ctypes.byref(plans), ctypes.byref(refs)) == 0
+    assert plans.value == 0 and refs.value == 0
+    assert L.leg2cheb_plan_cache_size(None, None) == 0
+    assert L.leg2cheb_plan_cached(None, 1000, 0, 64, 18, 0, 1, 0, None) == -1

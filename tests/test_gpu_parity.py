@@ -614,3 +614,25 @@ def test_ragged_batch_graph_capture_and_replay(l2c, precision):
         d = int(dirs[i])
         err = oracle.einf(yh[offs[i]:offs[i + 1]], oracle.transform(flat[offs[i]:offs[i + 1]], d))
         assert err <= (TOL[(d, 18)] if precision == "fp64" else tol), (i, err)
+
+
+def test_plan_cache_shares_and_releases(l2c):
+    """Two cached requests with the same arguments share one plan; other arguments make
+    another; each close releases one reference and the last frees the plan; results equal
+    an uncached plan's."""
+    import torch
+    n = 5000
+    x = torch.from_numpy(inputs.decaying(n, 1.0, inputs.SEED_BASE + 700)).cuda()
+    p0 = l2c.leg2cheb_plan_cache_size()
+    a = l2c.Plan(n, 0, cached=True)
+    b = l2c.Plan(n, 0, cached=True)
+    c = l2c.Plan(n, 1, cached=True)
+    assert a.handle == b.handle and c.handle != a.handle
+    assert l2c.leg2cheb_plan_cache_size() == (p0[0] + 2, p0[1] + 3)
+    with l2c.Plan(n, 0) as u:
+        assert torch.equal(a.execute(x), u.execute(x))
+    a.close()
+    assert torch.equal(b.execute(x), b.execute(x))     # b still holds the shared plan
+    b.close()
+    c.close()
+    assert l2c.leg2cheb_plan_cache_size() == p0
