@@ -438,6 +438,7 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
             worker_sync(wcnt, wtarget, a);
         }
     }
+    L2C_TS(3, 21);
     if (ww <= ts.G0) {
         const int g = ww;
         double c0 = 0.0, c1 = 0.0;
@@ -463,6 +464,7 @@ __device__ __forceinline__ void top_combine(const ExecArgs &a, const TopSlots &t
         if (act) canc[g * M2 + lane] = c0 + c1;
     }
     worker_sync(wcnt, wtarget, a);
+    L2C_TS(3, 22);
     if (top) {
         double bcol[M];
 #pragma unroll
@@ -517,6 +519,30 @@ __device__ __forceinline__ void load_anc_rows(const ExecArgs &a, const TopSlots 
 // of R).  Each step's operands are loaded before its products.  GPAD, QPAD: the pads of
 // the node strides of g (between nodes) and Q (one, at 2s), known at compile time so that
 // the index arithmetic vanishes where they are zero.
+template <int R, int GPAD, int QPAD, bool TAIL>
+__device__ __forceinline__ void near_step(double (&acc)[R], double (&pb)[R], double (&qb)[R], const double *gs,
+                                          const double *qs, const double *ps, int s, int sig, int m0, int st)
+{
+    const int mb = m0 + st * R, cb = sig + m0 + mb + R - 1;
+    double pn[R], qn[R], gn[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int mp = mb + t, c = cb + t;
+        pn[t] = ps[mp];
+        qn[t] = qs[c + (QPAD && c >= 2 * s ? 1 : 0)];
+        gn[t] = gs[mp + (GPAD ? (mp >= s ? 1 : 0) + (mp >= 2 * s ? 1 : 0) : 0)];
+    }
+    ops_first<3 * R>();
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        pb[t] = pn[t];
+        qb[(t + R - 1) % R] = qn[t];
+        const double gv = (TAIL && mb + t >= 2 * s) ? 0.0 : gn[t];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[r]);
+    }
+}
+
 template <int R, int GPAD, int QPAD>
 __device__ __forceinline__ void near_item(double (&acc)[R], const double *gs, const double *qs, const double *ps,
                                           int s, int sig, int m0)
@@ -529,28 +555,11 @@ __device__ __forceinline__ void near_item(double (&acc)[R], const double *gs, co
         const int c = sig + 2 * m0 + r;
         qb[r] = qs[c + (QPAD && c >= 2 * s ? 1 : 0)];
     }
+    // only the last step reaches past m' = 2s (the rows end there): the others take no
+    // per-element bound
     const int steps = ((2 * s - m0) + R - 1) / R;
-    for (int st = 0; st < steps; ++st) {
-        const int mb = m0 + st * R, cb = sig + m0 + mb + R - 1;
-        double pn[R], qn[R], gn[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const int mp = mb + t, c = cb + t;
-            pn[t] = ps[mp];
-            qn[t] = qs[c + (QPAD && c >= 2 * s ? 1 : 0)];
-            gn[t] = gs[mp + (GPAD ? (mp >= s ? 1 : 0) + (mp >= 2 * s ? 1 : 0) : 0)];
-        }
-        ops_first<3 * R>();
-        const bool tail = mb + R > 2 * s;
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            pb[t] = pn[t];
-            qb[(t + R - 1) % R] = qn[t];
-            const double gv = (tail && mb + t >= 2 * s) ? 0.0 : gn[t];
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = fma(pb[(t - r + R) % R] * qb[(t + r) % R], gv, acc[r]);
-        }
-    }
+    for (int st = 0; st < steps - 1; ++st) near_step<R, GPAD, QPAD, false>(acc, pb, qb, gs, qs, ps, s, sig, m0, st);
+    near_step<R, GPAD, QPAD, true>(acc, pb, qb, gs, qs, ps, s, sig, m0, steps - 1);
 }
 
 template <int M>
@@ -707,13 +716,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
         //      FP64 matrix cores in 16 x 16 tiles, m in steps of 4 (zero padded); lane l
         //      supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4q + l / 16][l % 16].
         {
-            constexpr int KTL = (M + 15) / 16;                  // mode tiles
+            // modes 17..20 (M = 17..20) are a small remainder: the matrix cores take modes
+            // 0..15 (one 16-mode tile instead of two mostly empty ones) and the vector units the
+            // rest, on the waves that hold one tile fewer
+            constexpr int KV = (M > 16 && M <= 20) ? M - 16 : 0;       // modes on the vector units
+            constexpr int KTL = (M - KV + 15) / 16;                      // mode tiles
             const int nall = nodes + 2, ntl = (nall + 15) / 16, tiles = 2 * ntl * KTL;
             const int li = lane & 15, lk = lane >> 4;
             for (int t = ww; t < tiles; t += kWorkWaves) {
                 const int kt = t % KTL, rest = t / KTL, ntile = rest % ntl, sig = rest / ntl;
                 const int na = ntile * 16 + li, kb = kt * 16 + li;
-                const bool arow = na < nall, bcol = kb < M;
+                const bool arow = na < nall, bcol = kb < M - KV;
                 const double *fa = gp + sig * GX + (arow ? na : 0) * GS;
                 const double *tb = Tl + sig * s * M + (bcol ? kb : 0);
                 double av[8], bv[8];                              // s <= 32: at most 8 steps
@@ -737,6 +750,34 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
                 for (int q = 0; q < 4; ++q) {
                     const int node = ntile * 16 + 4 * q + lk;     // nodes >= 2^kd: neighbour slots
                     if (node < nall && bcol) wl[(fused_wofs(kd) + node) * NS + sig * M + kb] = d[q];
+                }
+            }
+            if (KV > 0) {
+                // output (node, sig, mode 16 + kv), node fastest (the T values are broadcast);
+                // the index rotates so that the waves after the last one with an extra tile
+                // start first
+                const int w0 = tiles % kWorkWaves;
+                const int cnt = nall * 2 * KV;
+                for (int e = (wt + NWT - 64 * w0) % NWT; e < cnt; e += NWT) {
+                    const int node = e % nall, rest = e / nall, kv = rest % KV, sig = rest / KV;
+                    const double *fa = gp + sig * GX + node * GS;
+                    const double *tb = Tl + sig * s * M + 16 + kv;
+                    double acc0 = 0.0, acc1 = 0.0;
+                    for (int m0 = 0; m0 < s; m0 += 8) {
+                        double fv[8], tv[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int m = m0 + i, mc = m < s ? m : s - 1;
+                            fv[i] = fa[mc];
+                            tv[i] = tb[mc * M];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 8; i += 2) {
+                            if (m0 + i < s) acc0 = fma(fv[i], tv[i], acc0);
+                            if (m0 + i + 1 < s) acc1 = fma(fv[i + 1], tv[i + 1], acc1);
+                        }
+                    }
+                    wl[(fused_wofs(kd) + node) * NS + sig * M + 16 + kv] = acc0 + acc1;
                 }
             }
         }
@@ -876,6 +917,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
             L2C_TS(3, 9);
         }
         worker_sync(wcnt, wtarget, a);         // items and schedule in LDS; near field done
+        L2C_TS(3, 20);
         // the near part of the unit's output rows (step (7)'s row scale rs for cheb2leg, and
         // its K_00 term) into the near-field area, now free: node stride 2s+1
         if (near && ntid < nwork) {

@@ -36,6 +36,9 @@ PHASES = [
     (9, "top wave: tree-top items in LDS"),
     (15, "streamer: first group multiplied"),
     (8, "streamer: own far-field blocks done (step (3))"),
+    (20, "workers: near field and tree-top items both done (worker barrier)"),
+    (21, "workers: tree-top reduction rounds done"),
+    (22, "workers: ancestor far-field blocks done (worker barrier)"),
     (10, "top wave: tree-top reduction, ancestor blocks, chain to the unit root"),
     (5, "all waves joined"),
     (6, "step (4) inside the unit done"),
