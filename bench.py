@@ -363,6 +363,49 @@ def grid_form(l2c, inputs, torch, K, W, flush, flush_sink):
     return rec
 
 
+def regen_form(l2c, inputs, torch, K, W, flush, flush_sink):
+    """N = 10^6 on plans that recompute the far-field blocks in every execute
+    (L2C_TABLES_REGEN) against the stored-table plans: plan time, table bytes, cold execute
+    time per direction, and the largest difference of the outputs relative to max|z|."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        for i in range(K):
+            torch.sum(flush, dim=0, out=flush_sink)
+            st[i].record(stream)
+            fn()
+            en[i].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([st[i].elapsed_time(en[i]) for i in range(K)]))
+
+    n = N
+    x = torch.from_numpy(inputs.decaying(n, 0.5, inputs.SEED_BASE + 2)).cuda()
+    zr, zs = torch.empty_like(x), torch.empty_like(x)
+    rec = {"workload": "N=1000000, f_j = z_j/sqrt(j+1), leaf 64, rank 18, FP64; far-field blocks below the "
+                       "subtree roots recomputed from the kernel samples in every execute; cold HBM"}
+    for direction, name in ((l2c.LEG2CHEB, "leg2cheb"), (l2c.CHEB2LEG, "cheb2leg")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = l2c.Plan(n, direction, LEAF, RANK, tables=l2c.L2C_TABLES_REGEN)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        with pr, l2c.Plan(n, direction, LEAF, RANK) as ps:
+            ms = timed(lambda: pr.execute(x, zr))
+            ms_stored = timed(lambda: ps.execute(x, zs))
+            torch.cuda.synchronize()
+            diff = ((zr - zs).abs().max() / zs.abs().max()).item()
+            rec[name] = {"ms_per_execute": ms, "Gcoeff_s": n / (ms * 1e-3) / 1e9, "path": pr.info["path"],
+                         "plan_ms": plan_ms, "table_bytes": pr.info["table_bytes"],
+                         "stored_table_bytes": ps.info["table_bytes"], "stored_ms_per_execute": ms_stored,
+                         "einf_vs_stored_tables": diff}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,9 +416,12 @@ def main():
                     help="also run a plain 256 MiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-form and line-batch measurements (profiling the N=10^6 kernel alone)")
-    ap.add_argument("--workload", default="leg2cheb_1e6", choices=["leg2cheb_1e6", "fp32_batch", "lines_3d", "ragged", "grid"],
+    ap.add_argument("--workload", default="leg2cheb_1e6",
+                    choices=["leg2cheb_1e6", "fp32_batch", "lines_3d", "ragged", "grid", "regen"],
                     help="fp32_batch: only the batched FP32 form (256 x 65536); lines_3d: only the "
-                         "65536 lines of n = 1024 (FP64 dense path and FP32 form); grid: the grid pipeline and the DCTs at N = 10^6; e.g. under a profiler")
+                         "65536 lines of n = 1024 (FP64 dense path and FP32 form); grid: the grid pipeline and the "
+                         "DCTs at N = 10^6; regen: N = 10^6 with the far-field blocks recomputed per execute; "
+                         "e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the transform is a single-GPU kernel path "
@@ -414,6 +460,10 @@ def main():
         return
     if args.workload == "lines_3d":
         rec = lines_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)
+        print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
+        return
+    if args.workload == "regen":
+        rec = regen_form(l2c, inputs, torch, args.steps, args.warmup, flush, flush_sink)
         print(json.dumps({"steps": args.steps, "warmup": args.warmup, **rec}), flush=True)
         return
     if args.workload == "grid":
@@ -537,6 +587,7 @@ def main():
         rec["lines_3d"] = lines_form(l2c, inputs, torch, min(K, 10), min(W, 3), flush, flush_sink)
         rec.update(small_and_ragged(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink))
         rec["grid_1e6"] = grid_form(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink)
+        rec["regen_tables_1e6"] = regen_form(l2c, inputs, torch, min(K, 20), min(W, 3), flush, flush_sink)
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(f, z, 0)
         rec["cpu_baseline"] = base

@@ -70,8 +70,11 @@ enum l2c_path {
     L2C_PATH_THREE = 1,  /* three launches: upward pass, top levels, far field + rest */
     L2C_PATH_SINGLE = 2, /* one launch, workgroups exchange tree nodes through ready flags */
     L2C_PATH_BATCHED = 3, /* L2C_FP32 / L2C_BF16X2 / L2C_FP16X2 plans: 16 transforms per matrix-core tile */
-    L2C_PATH_DENSE = 4    /* FP64 plans with n <= 4096 and max_batch >= 64: Alg. 1 as dense
+    L2C_PATH_DENSE = 4,   /* FP64 plans with n <= 4096 and max_batch >= 64: Alg. 1 as dense
                              per-parity products on the FP64 matrix cores */
+    L2C_PATH_REGEN = 5    /* three launches plus one, for plans made with L2C_TABLES_REGEN: the
+                             far-field blocks below the subtree roots are recomputed from the
+                             kernel samples in every execute instead of read from a table */
 };
 
 /* Plan options (leg2cheb_plan_set_option). */
@@ -165,6 +168,37 @@ enum l2c_basis { L2C_MODAL = 0, L2C_NODAL = 1 };
 int leg2cheb_plan_basis(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision,
                         int64_t max_batch, int basis, void *stream);
 
+/* What a plan keeps of the far-field submatrices (leg2cheb_plan_tables).
+ *   L2C_TABLES_STORED  every Ahat submatrix (Eq. (aklmore)), built once at plan time and read
+ *                      by every execute: 8 M^2 bytes per submatrix, the dominant traffic of an
+ *                      execute (127 MB at n = 10^6, rank 18).
+ *   L2C_TABLES_REGEN   only the submatrices of the tree's top levels; every execute recomputes
+ *                      the others (all but a few hundred) from the kernel samples and applies
+ *                      each in the factored form D (S (D^T w)) of its 2-D DCT, so it is never
+ *                      formed.  The samples use Sec. 4.3's split of the kernel: the factor
+ *                      Lambda((y-x)/2) depends only on the level and the offset from the
+ *                      diagonal and is tabulated at plan time (2 M^2 doubles per level); the
+ *                      factor in (x+y)/2 is evaluated per sample (Eq. (tau)).  The stored
+ *                      submatrices are those of levels 0..L-1-kd, where kd (<= 7) is the
+ *                      depth of the subtrees the execute kernels take, so the plan holds about
+ *                      2^kd times fewer (at n = 10^6: 127 MB -> 2 MB) and builds faster; each
+ *                      execute trades the table's bytes for the samples' arithmetic.  The same
+ *                      approximation as L2C_TABLES_STORED, up to rounding. */
+enum l2c_tables { L2C_TABLES_STORED = 0, L2C_TABLES_REGEN = 1 };
+
+/*
+ * An FP64 plan in the modal basis, with the far-field submatrices kept as `tables` says
+ * (l2c_tables); the other arguments as in leg2cheb_plan_ex.  L2C_TABLES_STORED is
+ * leg2cheb_plan_ex with precision L2C_FP64.  A plan with L2C_TABLES_REGEN and L >= 1 always
+ * executes on L2C_PATH_REGEN (the direct, dense, tile and single-launch paths need the
+ * stored blocks); leg2cheb_execute_noalloc refuses it (L2C_EUNSUPPORTED), and
+ * leg2cheb_plan_export has no table 0 for it (L2C_EUNSUPPORTED).
+ * Errors: L2C_EINVAL (tables not one of l2c_tables, and those of leg2cheb_plan_ex),
+ * L2C_EUNSUPPORTED (rank), L2C_ENOMEM, L2C_EHIP.
+ */
+int leg2cheb_plan_tables(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int64_t max_batch,
+                         int tables, void *stream);
+
 /*
  * The plan cache (planning costs about 3 times an execute, Sec. 5.2): returns the shared
  * plan made with exactly these arguments on the current device, building it on the first
@@ -206,7 +240,7 @@ int leg2cheb_execute(l2c_plan_t plan, const double *in, double *out, int64_t bat
  *   in, out, batch, stream  as in leg2cheb_execute.
  * Errors: L2C_EINVAL as leg2cheb_execute, and when batch x (2^(L+2) - 4) x 2 x rank x 8
  * bytes exceeds 64 MiB (at n = 10^6, rank 18: batch > 7); L2C_EUNSUPPORTED (a plan of a
- * batched precision form); L2C_EHIP as leg2cheb_execute.
+ * batched precision form, or one made with L2C_TABLES_REGEN); L2C_EHIP as leg2cheb_execute.
  */
 int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int64_t batch, void *stream);
 

@@ -17,12 +17,13 @@ from . import _lib
 from ._lib import (  # noqa: F401  (re-exported ABI names)
     L2C_BF16X2, L2C_FP16X2, L2C_CHEB2LEG, L2C_EHIP, L2C_EINVAL, L2C_ENOMEM, L2C_EUNSUPPORTED, L2C_FP32, L2C_FP64,
     L2C_LEG2CHEB, L2C_OK, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US, L2C_OPT_SINGLE_LAUNCH,
-    L2C_STATUS_EXCHANGE, L2C_STATUS_STREAM, L2C_STATUS_WORKERS, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_THREE, L2CError,
+    L2C_STATUS_EXCHANGE, L2C_STATUS_STREAM, L2C_STATUS_WORKERS, L2C_PATH_DIRECT, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_THREE,
+    L2C_PATH_REGEN, L2C_TABLES_STORED, L2C_TABLES_REGEN, L2CError,
     TABLE_AHAT, TABLE_B, TABLE_T, TABLE_W, leg2cheb_destroy, leg2cheb_execute, leg2cheb_execute_noalloc, leg2cheb_plan, leg2cheb_plan_ex,
     leg2cheb_plan_export, leg2cheb_plan_info, leg2cheb_plan_set_option, leg2cheb_plan_status,
     leg2cheb_rank_supported, leg2cheb_debug_alloc_hook, leg2cheb_set_timing_events, leg2cheb_batch_plan, leg2cheb_batch_execute,
     leg2cheb_batch_info, leg2cheb_batch_destroy, leg2cheb_batch_tuning,
-    L2C_LEG2GRID, L2C_GRID2LEG, L2C_MODAL, L2C_NODAL, leg2cheb_plan_basis, leg2cheb_plan_cached,
+    L2C_LEG2GRID, L2C_GRID2LEG, L2C_MODAL, L2C_NODAL, leg2cheb_plan_basis, leg2cheb_plan_tables, leg2cheb_plan_cached,
     leg2cheb_plan_cache_size, leg2cheb_dct_plan, leg2cheb_dct_execute, leg2cheb_dct_destroy, leg2cheb_grid_plan,
     leg2cheb_grid_execute, leg2cheb_grid_destroy, leg2cheb_grid_fmm, leg2cheb_grid_dct,
 )
@@ -41,11 +42,15 @@ class Plan:
 
     def __init__(self, n: int, direction: int = LEG2CHEB, leaf_size: int = 64, rank: int = 18,
                  precision: int = L2C_FP64, max_batch: int = 1, stream=None, basis: int = L2C_MODAL,
-                 cached: bool = False):
+                 cached: bool = False, tables: int = L2C_TABLES_STORED):
         torch = _torch()
         st = stream if stream is not None else torch.cuda.current_stream()
         self.device = torch.cuda.current_device()
-        if cached:   # a reference to the shared plan of the plan cache (close releases it)
+        if tables != L2C_TABLES_STORED:   # FP64, modal: far-field blocks regenerated per execute
+            if precision != L2C_FP64 or basis != L2C_MODAL or cached:
+                raise ValueError("tables=L2C_TABLES_REGEN takes an FP64 plan in the modal basis, not cached")
+            self.handle = leg2cheb_plan_tables(n, direction, leaf_size, rank, max_batch, tables, st.cuda_stream)
+        elif cached:   # a reference to the shared plan of the plan cache (close releases it)
             self.handle = leg2cheb_plan_cached(n, direction, leaf_size, rank, precision, max_batch, basis,
                                                st.cuda_stream)
         elif basis == L2C_MODAL:

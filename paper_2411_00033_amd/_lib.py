@@ -16,14 +16,16 @@ L2C_LEG2CHEB, L2C_CHEB2LEG = 0, 1
 L2C_FP64, L2C_FP32, L2C_BF16X2, L2C_FP16X2 = 0, 1, 2, 3
 L2C_OK, L2C_EINVAL, L2C_ENOMEM, L2C_EHIP, L2C_EUNSUPPORTED = 0, -1, -2, -3, -4
 TABLE_AHAT, TABLE_T, TABLE_B, TABLE_W = 0, 1, 2, 3
-L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE = 0, 1, 2, 3, 4
+L2C_PATH_DIRECT, L2C_PATH_THREE, L2C_PATH_SINGLE, L2C_PATH_BATCHED, L2C_PATH_DENSE, L2C_PATH_REGEN = 0, 1, 2, 3, 4, 5
 L2C_OPT_SINGLE_LAUNCH, L2C_OPT_DIRECT, L2C_OPT_EXCHANGE_TIMEOUT_US = 1, 2, 3
 L2C_STATUS_EXCHANGE, L2C_STATUS_WORKERS, L2C_STATUS_STREAM = 1, 2, 4
 L2C_LEG2GRID, L2C_GRID2LEG = 0, 1
 L2C_MODAL, L2C_NODAL = 0, 1
+L2C_TABLES_STORED, L2C_TABLES_REGEN = 0, 1
 
 EXPORTED = (
-    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_plan_basis", "leg2cheb_plan_cached", "leg2cheb_plan_cache_size",
+    "leg2cheb_plan", "leg2cheb_plan_ex", "leg2cheb_plan_basis", "leg2cheb_plan_tables", "leg2cheb_plan_cached",
+    "leg2cheb_plan_cache_size",
     "leg2cheb_execute", "leg2cheb_execute_noalloc", "leg2cheb_destroy",
     "leg2cheb_plan_info",
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
@@ -80,6 +82,7 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_plan_ex.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, vp]
     lib.leg2cheb_plan_basis.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, ci, vp]
     lib.leg2cheb_plan_cached.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, ci, i64, ci, vp]
+    lib.leg2cheb_plan_tables.argtypes = [ctypes.POINTER(vp), i64, ci, ci, ci, i64, ci, vp]
     lib.leg2cheb_plan_cache_size.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.leg2cheb_execute.argtypes = [vp, vp, vp, i64, vp]
     lib.leg2cheb_execute_noalloc.argtypes = [vp, vp, vp, i64, vp]
@@ -148,6 +151,15 @@ def leg2cheb_plan_basis(n: int, direction: int, leaf_size: int, rank: int, preci
     _check(load().leg2cheb_plan_basis(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
                                       int(precision), int(max_batch), int(basis), ctypes.c_void_p(stream or None)),
            "leg2cheb_plan_basis")
+    return h.value
+
+
+def leg2cheb_plan_tables(n: int, direction: int, leaf_size: int, rank: int, max_batch: int = 1,
+                         tables: int = L2C_TABLES_STORED, stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().leg2cheb_plan_tables(ctypes.byref(h), int(n), int(direction), int(leaf_size), int(rank),
+                                       int(max_batch), int(tables), ctypes.c_void_p(stream or None)),
+           "leg2cheb_plan_tables")
     return h.value
 
 

@@ -202,6 +202,8 @@ void free_plan(l2c_plan_s *p)
     l2c::dev_free(p->d_bS);
     l2c::dev_free(p->d_dense);
     l2c::dev_free(p->d_dir);
+    l2c::dev_free(p->d_lm);
+    l2c::dev_free(p->d_cf);
     delete p;
 }
 
@@ -361,11 +363,17 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
         if (hipDeviceSynchronize() != hipSuccess) return L2C_EHIP;
     }
     l2c::dev_free(p->d_w);
+    l2c::dev_free(p->d_cf);
     p->d_w = nullptr;
+    p->d_cf = nullptr;
     p->ws_batch = 0;
     const size_t bytes = (size_t)batch * p->geo.NT * 2 * p->M * sizeof(double);
-    if (l2c::dev_alloc(&p->d_w, bytes) != hipSuccess) {
+    if (l2c::dev_alloc(&p->d_w, bytes) != hipSuccess ||
+        (p->regen &&
+         l2c::dev_alloc(&p->d_cf, std::max<size_t>(256, (size_t)batch * l2c::regen_cf_per_item(p->geo) * sizeof(double))) !=
+             hipSuccess)) {
         (void)hipGetLastError();
+        l2c::dev_free(p->d_w);
         p->d_w = nullptr;
         return L2C_ENOMEM;
     }
@@ -374,7 +382,7 @@ int ensure_workspace(l2c_plan_s *p, int64_t batch)
 }
 
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf, int basis = L2C_MODAL);
+              void *stream, bool full_leaf, int basis = L2C_MODAL, bool regen = false);
 
 // Workspace of the batched form: tiles of 16 items, NT nodes x 2 parities x 256 values.
 int ensure_bworkspace(l2c_plan_s *p, int64_t items)
@@ -734,7 +742,7 @@ namespace {
 // full_leaf: s = leaf_size / 2 instead of the smallest s of Eq. (numlevels) that covers n
 // (same L; more padding), so that transforms of one L share every table.
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf, int basis);
+              void *stream, bool full_leaf, int basis, bool regen);
 }  // namespace
 
 extern "C" {
@@ -751,11 +759,22 @@ int leg2cheb_plan_basis(l2c_plan_t *plan, int64_t n, int direction, int leaf_siz
     return plan_impl(plan, n, direction, leaf_size, rank, precision, max_batch, stream, false, basis);
 }
 
+int leg2cheb_plan_tables(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int64_t max_batch,
+                         int tables, void *stream)
+{
+    if (tables != L2C_TABLES_STORED && tables != L2C_TABLES_REGEN) {
+        if (plan) *plan = nullptr;
+        return L2C_EINVAL;
+    }
+    return plan_impl(plan, n, direction, leaf_size, rank, L2C_FP64, max_batch, stream, false, L2C_MODAL,
+                     tables == L2C_TABLES_REGEN);
+}
+
 }  // extern "C"
 
 namespace {
 int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int rank, int precision, int64_t max_batch,
-              void *stream, bool full_leaf, int basis)
+              void *stream, bool full_leaf, int basis, bool regen)
 {
     if (!plan) return L2C_EINVAL;
     *plan = nullptr;
@@ -770,9 +789,11 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     // 2^28 values (32-bit buffer ranges)
     if (batched_form(precision) && (rank > 16 || leaf_size > 64 || n > (int64_t(1) << 28))) return L2C_EUNSUPPORTED;
     if (basis != L2C_MODAL && basis != L2C_NODAL) return L2C_EINVAL;
+    // regenerated far-field blocks: FP64, modal basis, the three-launch path
+    if (regen && (precision != L2C_FP64 || basis != L2C_MODAL)) return L2C_EUNSUPPORTED;
     // the FP64 tile form: batches of FP64 transforms at rank <= 16, unless the dense or
     // direct products serve them better
-    const bool tile64 = !batched_form(precision) && rank <= 16 && leaf_size <= 64 && n <= (int64_t(1) << 28) &&
+    const bool tile64 = !regen && !batched_form(precision) && rank <= 16 && leaf_size <= 64 && n <= (int64_t(1) << 28) &&
                         max_batch >= l2c::kTile64MinBatch && !(n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) &&
                         !(n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n));
     // the nodal basis runs on the batched kernels only (dense tile products)
@@ -787,6 +808,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
     p->M = rank;
     p->basis = basis;
     p->max_batch = max_batch;
+    p->regen = regen;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return L2C_EHIP;
@@ -813,7 +835,9 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         p->geo = l2c::make_geometry(L, M, s);
         const int64_t top_blocks = l2c::level_block_offset(p->geo.groot + 1);
         p->top_bytes = top_blocks * 3 * M * M * (int64_t)sizeof(double);
-        p->bot_bytes = (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
+        p->bot_bytes = regen ? 0 : (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
+        // regenerated blocks: Lambda((y-x)/2) per level below the subtree roots and offset
+        const int64_t nlm = regen ? (int64_t)(L - 1 - p->geo.groot) * 2 * M * M : 0;
 
         // B(0), B(1) on the host (exact dyadic rationals); T, P, the Chebyshev-Gauss points,
         // the DCT matrix and Ahat on the device
@@ -832,18 +856,20 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
                   l2c::dev_alloc(&p->d_B, B.size() * sizeof(double)) == hipSuccess &&
                   l2c::dev_alloc(&p->d_P, nP * sizeof(double)) == hipSuccess &&
                   l2c::dev_alloc(&p->d_XG, M * sizeof(double)) == hipSuccess &&
-                  l2c::dev_alloc(&p->d_D, (size_t)M * M * sizeof(double)) == hipSuccess;
+                  l2c::dev_alloc(&p->d_D, (size_t)M * M * sizeof(double)) == hipSuccess &&
+                  (nlm == 0 || l2c::dev_alloc(&p->d_lm, nlm * sizeof(double)) == hipSuccess);
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);
             return L2C_ENOMEM;
         }
-        p->table_bytes = p->top_bytes + p->bot_bytes + (nT + (int64_t)B.size() + nP + M + (int64_t)M * M) * 8;
+        p->table_bytes = p->top_bytes + p->bot_bytes + (nT + (int64_t)B.size() + nP + M + (int64_t)M * M + nlm) * 8;
         ok = hipMemcpyAsync(p->d_B, B.data(), B.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess &&
              l2c::launch_build_small(*p, st) == hipSuccess &&
              (Lnod.empty() || hipMemcpyAsync(p->d_T, Lnod.data(), Lnod.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess) &&
              (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
-             l2c::launch_build_ahat(*p, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+             l2c::launch_build_ahat(*p, st) == hipSuccess &&
+             (nlm == 0 || l2c::launch_build_lminus(*p, st) == hipSuccess) && hipStreamSynchronize(st) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);
@@ -861,7 +887,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             return L2C_OK;
         }
         // short transforms: Alg. 1 row by row (the multipole tables stay available)
-        p->direct_ok = n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n);
+        p->direct_ok = !regen && n <= l2c::kDirectMaxN && max_batch <= l2c::direct_max_work(n) / (n * n);
         if (p->direct_ok) {
             const int rc = build_direct_tables(p, st);
             if (rc != L2C_OK) {
@@ -870,7 +896,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
             }
         }
         // batches of short transforms: the direct product on the matrix cores
-        if (n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
+        if (!regen && n <= l2c::kDenseMaxN && max_batch >= l2c::kDenseMinBatch) {
             const int64_t HP = l2c::dense_hp(n);
             ok = l2c::dev_alloc(&p->d_dense, (size_t)2 * HP * HP * sizeof(double)) == hipSuccess &&
                  l2c::dense_build(*p, p->d_dense, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
@@ -883,7 +909,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         }
         // single-launch path: items per launch with every workgroup resident
         int64_t items = 0;
-        if (l2c::fused_max_items(*p, &items) != hipSuccess) {
+        if (!regen && l2c::fused_max_items(*p, &items) != hipSuccess) {
             (void)hipGetLastError();
             items = 0;
         }
@@ -969,7 +995,7 @@ int leg2cheb_execute_noalloc(l2c_plan_t plan, const double *in, double *out, int
 {
     if (!plan || batch < 0) return L2C_EINVAL;
     if (batch == 0) return L2C_OK;
-    if (plan->precision != L2C_FP64 || plan->tile64) return L2C_EUNSUPPORTED;
+    if (plan->precision != L2C_FP64 || plan->tile64 || (plan->regen && plan->L > 0)) return L2C_EUNSUPPORTED;
     const int rc = check_execute(plan, in, out, batch);
     if (rc != L2C_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -1103,6 +1129,7 @@ int leg2cheb_plan_info(l2c_plan_t plan, struct l2c_plan_info *info)
                  : use_batched(plan)                    ? L2C_PATH_BATCHED
                  : plan->direct_ok && plan->direct_on   ? L2C_PATH_DIRECT
                  : use_fused(plan)                      ? L2C_PATH_SINGLE
+                 : plan->regen                          ? L2C_PATH_REGEN
                                                         : L2C_PATH_THREE;
     return L2C_OK;
 }
@@ -1128,7 +1155,8 @@ int leg2cheb_plan_export(l2c_plan_t plan, int table, void *dst, int64_t bytes, i
     }
     if (table == 1) return hipMemcpy(dst, plan->d_T, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
     if (table == 2) return hipMemcpy(dst, plan->d_B, need, hipMemcpyDeviceToHost) == hipSuccess ? L2C_OK : L2C_EHIP;
-    if (!plan->d_top) return L2C_EUNSUPPORTED;   // FP32 plans keep Ahat only in the batched layout
+    if (!plan->d_top || plan->regen) return L2C_EUNSUPPORTED;   // FP32 plans keep Ahat only in the batched layout;
+                                                                 // regenerating plans keep its top levels only
     double *tmp = nullptr;
     if (l2c::dev_alloc(&tmp, need) != hipSuccess) {
         (void)hipGetLastError();

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
     const int nslots = (nodes - 1) * M;
     const double2 *sub = reinterpret_cast<const double2 *>(a.ahat_bot) + Rn * G.sub_groups * NCH * 64 + lane;
     double2 ar[NCH];
-    if (wv < G.sub_groups) {
+    if (!a.cfar && wv < G.sub_groups) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) ar[ch] = sub[(wv * NCH + ch) * 64];
     }
@@ -349,7 +349,13 @@ __global__ __launch_bounds__(kMainThreads) void k_main(ExecArgs a)
     //      c(2i)[k] = Ahat(.,0)[k,:] w(2i+2) + Ahat(.,1)[k,:] w(2i+3),  c(2i+1)[k] = Ahat(.,2)[k,:] w(2i+3)
     //      for both parities (i = block index within its depth).  The wave's first group
     //      was put in flight at the start; later groups are loaded when reached.
-    for (int grp = wv; grp < G.sub_groups; grp += kMainThreads / 64) {
+    if (a.cfar) {
+        // the far-field part of the own blocks, computed by k_regen (the blocks regenerated
+        // from the kernel samples instead of read from a stored table)
+        const double *cf = a.cfar + (item * (P >> kd) + Rn) * own * M2;
+        for (int e = tid; e < own * M2; e += kMainThreads) cown[(e / M2) * NS + e % M2] = cf[e];
+    }
+    for (int grp = wv; !a.cfar && grp < G.sub_groups; grp += kMainThreads / 64) {
         if (grp != wv) {
 #pragma unroll
             for (int c2 = 0; c2 < NCH; ++c2) ar[c2] = sub[(grp * NCH + c2) * 64];
@@ -667,6 +673,13 @@ static hipError_t run(const l2c_plan_s &p, const double *in, double *out, int64_
             const unsigned wgs = (unsigned)((int64_t(1) << (gin + 2)) >> kt);
             hipLaunchKernelGGL(k_top<M>, dim3(wgs, items), dim3(kThreads), top_lds_bytes(G, kt), st, c, gin, kt);
             gin -= kt;
+        }
+        if (p.regen) {
+            // the own blocks' far-field products, their submatrices recomputed from the samples
+            double *cf = p.d_cf + b0 * regen_cf_per_item(G);
+            const hipError_t e = launch_regen(p, c, cf, st);
+            if (e != hipSuccess) return e;
+            c.cfar = cf;
         }
         const bool timed = p.ev_before && p.ev_after && b0 == 0;
         if (timed) (void)hipEventRecord(p.ev_before, st);

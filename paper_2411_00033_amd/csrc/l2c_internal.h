@@ -97,6 +97,9 @@ struct ExecArgs {
     uint64_t wait_ticks; // k_fused: bound of the waits inside a workgroup, in wall-clock ticks
     uint64_t poll_ticks; // k_fused: bound of the waits for other workgroups, in wall-clock ticks
     const int *top_sched; // k_fused: [units][kTopSchedInts] tree-top table per unit (built at plan time)
+    // k_main: the far-field part of step (3) for the own blocks, computed by k_regen
+    // ([batch][subtrees][own nodes][2][M]); null: k_main streams the stored bottom table
+    const double *cfar = nullptr;
 };
 
 // Ints per unit of k_fused's tree-top table (reduction schedule and item nodes).
@@ -172,6 +175,12 @@ struct l2c_plan_s {
     // k_direct's factor tables: P_d for d < ceil(n/2), then Q_S for S < n + 17 (plans with
     // L = 0, and plans with direct_ok)
     double *d_dir = nullptr;
+    // far-field blocks below the subtree roots recomputed in every execute (L2C_TABLES_REGEN,
+    // l2c_regen.hip): no bottom table; Lambda((y-x)/2) per level and offset, [L-1-groot][2][M][M];
+    // the far-field part of step (3) per own node, [ws_batch][subtrees][own nodes][2][M]
+    bool regen = false;
+    double *d_lm = nullptr;
+    double *d_cf = nullptr;
 };
 
 namespace l2c {
@@ -220,6 +229,16 @@ hipError_t launch_build_small(const l2c_plan_s &p, hipStream_t stream);   // T, 
 hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t stream);
 hipError_t launch_build_ahat(const l2c_plan_s &p, hipStream_t stream);
 hipError_t launch_export_ahat(const l2c_plan_s &p, double *dst_dev, hipStream_t stream);
+// l2c_regen.hip: plans with L2C_TABLES_REGEN
+hipError_t launch_build_lminus(const l2c_plan_s &p, hipStream_t stream);   // d_lm
+// k_regen: the far-field part of step (3) of the own blocks of items 0..c.batch-1 of c
+// into cf, from the upward vectors in c.w
+hipError_t launch_regen(const l2c_plan_s &p, const ExecArgs &c, double *cf, hipStream_t stream);
+// doubles of cf per item
+inline int64_t regen_cf_per_item(const Geometry &G)
+{
+    return (int64_t(1) << (G.groot + 2)) * (2 * (int64_t(1) << G.kd) - 2) * 2 * G.M;
+}
 
 // Near-field LDS padding of k_main: the per-parity input g has node stride s + gpad and
 // the Q table node stride 2s + qpad, odd when padded (distinct banks across 64 nodes).

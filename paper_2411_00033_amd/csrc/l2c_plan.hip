@@ -186,7 +186,11 @@ hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s
 template <int M>
 static hipError_t build(const l2c_plan_s &p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)p.nb), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
+    // plans that regenerate the blocks below the subtree roots store levels 0..groot only
+    // (the first blocks of the level-major enumeration)
+    const int64_t blocks = p.regen ? level_block_offset(p.geo.groot + 1) : p.nb;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)blocks), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
                        p.direction, p.d_XG, p.d_D, p.basis);
     return hipGetLastError();
 }

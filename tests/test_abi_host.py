@@ -217,6 +217,26 @@ def test_plan_basis_argument_errors(lib):
     assert L.leg2cheb_plan_basis(None, 1000, 0, 64, 16, 1, 1, 1, None) == -1
 
 
+def test_plan_tables_argument_errors(lib):
+    """leg2cheb_plan_tables: the table mode and the plan arguments are checked before any
+    device call; the constants match the header."""
+    L = lib.load()
+    h = ctypes.c_void_p(1)
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 0, 64, 18, 1, 2, None) == -1 and h.value is None
+    h = ctypes.c_void_p(1)
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 0, 64, 18, 1, -1, None) == -1 and h.value is None
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 0, 0, 64, 18, 1, 1, None) == -1          # n < 1
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 2, 64, 18, 1, 1, None) == -1       # direction
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 0, 63, 18, 1, 1, None) == -1       # odd leaf
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 0, 64, 18, 0, 1, None) == -1       # max_batch
+    assert L.leg2cheb_plan_tables(ctypes.byref(h), 1000, 0, 64, 17, 1, 1, None) == -4       # rank
+    assert L.leg2cheb_plan_tables(None, 1000, 0, 64, 18, 1, 1, None) == -1
+    text = open(HEADER).read()
+    for name in ("L2C_TABLES_STORED", "L2C_TABLES_REGEN", "L2C_PATH_REGEN"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(lib, name), name
+
+
 def test_plan_cache_host_logic(lib):
     L = lib.load()
     plans, refs = ctypes.c_int64(-1), ctypes.c_int64(-1)
