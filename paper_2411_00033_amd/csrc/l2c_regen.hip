@@ -65,6 +65,22 @@ __device__ __forceinline__ double inv_tau_poly(double t)
     return fma(p, t, 1.0);
 }
 
+// 1/x and 1/sqrt(x) (x > 0, normal) from the hardware estimates and two Newton steps each
+// (quadratic convergence; a few ulp), cheaper than the correctly rounded library sequences.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 // Pair index pr of (m, n), m <= n, in row-major order of the upper triangle -> m.
 template <int M>
 __device__ __forceinline__ int pair_row(int pr)
@@ -128,10 +144,10 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
             const double *lmr = lmg + (q + 2 - p - 2) * MM;             // offset (q + 2 - p) h
             const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
             double *Sr = S + r * MM;
-            // Lambda(zp) = tau(x) / sqrt(x), x = zp + 1/4 (Eq. (tau), zp >= 20): with rx = 1/x,
-            // tau(rx^2) sqrt(rx); its reciprocal from the reciprocal series, x sqrt(rx) / tau
+            // Lambda(zp) = tau(x) / sqrt(x), x = zp + 1/4 (Eq. (tau), zp >= 20): with rx = 1/x and
+            // sr = 1/sqrt(x), tau(rx^2) sr; its reciprocal from the reciprocal series, x sr / tau
             const bool big = zp >= 20.0;
-            const double x = zp + 0.25, rx = 1.0 / x, sr = sqrt(rx), t = rx * rx;
+            const double x = zp + 0.25, rx = recip(x), sr = rsqrt_nr(x), t = rx * rx;
             if (dir == 0) {
                 const double lp = big ? tau_poly(t) * sr : lambda_real(zp);
                 Sr[m * M + n] = lmr[m * M + n] * lp;
@@ -145,7 +161,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
                 const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
                 const double sp = xm + yn;                                // = xn + ym
                 const double d1 = xm - yn + 1.0, d2 = xn - ym + 1.0;
-                const double c2 = ilp / (sp * (sp + 1.0) * d1 * d2);
+                const double c2 = ilp * recip(sp * (sp + 1.0) * d1 * d2);
                 Sr[m * M + n] = 2.0 * (xm + 0.5) * yn * d2 * c2 * lmr[m * M + n];
                 Sr[n * M + m] = 2.0 * (xn + 0.5) * ym * d1 * c2 * lmr[n * M + m];
             }
