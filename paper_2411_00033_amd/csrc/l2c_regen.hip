@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
     constexpr int MM = M * M, M2 = 2 * M, NPAIR = M * (M + 1) / 2;
     __shared__ double Dl[MM];
     __shared__ double Xl[M];
+    __shared__ unsigned char Pm[NPAIR], Pn[NPAIR];   // pair index -> (m, n), m <= n
     __shared__ double S[3 * MM];      // the three submatrices' samples, [r][m][n]
     __shared__ double W[2 * M2];      // w(2b+2), w(2b+3): [q][sigma][l]
     __shared__ double Uv[2 * M2];     // u = D^T w
@@ -111,7 +112,14 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
     const int64_t U = int64_t(1) << (groot + 2);     // subtrees of an item
     const int64_t item = blockIdx.y;
     const int lane = threadIdx.x;
-    for (int e = lane; e < MM; e += kRegenThreads) Dl[e] = Dm[e];
+    // the scaled DCT matrix of Eq. (aklmore): Dl[k][m] = sc_k cos(k (m + 1/2) pi / M), sc_0 = 1/M,
+    // sc_k = 2/M (D^T w reads it by columns, D v by rows)
+    for (int e = lane; e < MM; e += kRegenThreads) Dl[e] = Dm[e] * ((e < M ? 1.0 : 2.0) / M);
+    for (int pr = lane; pr < NPAIR; pr += kRegenThreads) {
+        const int m = pair_row<M>(pr);
+        Pm[pr] = (unsigned char)m;
+        Pn[pr] = (unsigned char)(pr - (m * (2 * M - m + 1)) / 2 + m);
+    }
     for (int e = lane; e < M; e += kRegenThreads) Xl[e] = XG[e];
     const double *wit = a.w + item * G.NT * M2;
     for (int bb = 0; bb < kRegenBlocks; ++bb) {
@@ -139,7 +147,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
 #pragma unroll 2
         for (int e = lane; e < 3 * NPAIR; e += kRegenThreads) {
             const int r = e / NPAIR, pr = e - r * NPAIR;
-            const int m = pair_row<M>(pr), n = pr - (m * (2 * M - m + 1)) / 2 + m;
+            const int m = Pm[pr], n = Pn[pr];
             const int p = r == 2 ? 1 : 0, q = r == 0 ? 0 : 1;          // r = p + q (q + 1) / 2
             const double *lmr = lmg + (q + 2 - p - 2) * MM;             // offset (q + 2 - p) h
             const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
@@ -167,13 +175,13 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
             }
         }
         __syncthreads();
-        // u = D^T w: u[q][sigma][n] = sum_l sc_l cos(l (n + 1/2) pi / M) w[q][sigma][l]
+        // u = D^T w: u[q][sigma][n] = sum_l Dl[l][n] w[q][sigma][l]
         for (int e = lane; e < 2 * M2; e += kRegenThreads) {
             const int qs = e / M, n = e - qs * M;
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(Dl[l * M + n] * (l == 0 ? 1.0 : 2.0), W[qs * M + l], acc);
-            Uv[e] = acc * (1.0 / M);
+            for (int l = 0; l < M; ++l) acc = fma(Dl[l * M + n], W[qs * M + l], acc);
+            Uv[e] = acc;
         }
         __syncthreads();
         // v = S u: row node 2b takes S(0) u(2b+2) + S(1) u(2b+3), row node 2b+1 takes S(2) u(2b+3)
@@ -193,13 +201,13 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
             V[e] = acc;
         }
         __syncthreads();
-        // c = D v: c[k] = sc_k sum_m cos(k (m + 1/2) pi / M) v[m]
+        // c = D v: c[k] = sum_m sc_k cos(k (m + 1/2) pi / M) v[m]
         for (int e = lane; e < 2 * M2; e += kRegenThreads) {
             const int tsg = e / M, k = e - tsg * M;
             double acc = 0.0;
 #pragma unroll
             for (int m = 0; m < M; ++m) acc = fma(Dl[k * M + m], V[tsg * M + m], acc);
-            co[e] = acc * ((k == 0 ? 1.0 : 2.0) / M);
+            co[e] = acc;
         }
     }
 }
