@@ -475,6 +475,22 @@ int leg2cheb_rank_supported(int rank);
  */
 int leg2cheb_debug_alloc_hook(int64_t fail_at, int64_t *pending, int64_t *live);
 
+/*
+ * Test hook for the index arithmetic (no paper passage): for the plan geometry that
+ * leg2cheb_plan would make from (n, leaf_size, rank) -- L, s of Eq. (numlevels) and the
+ * kernels' subtree depths -- evaluates on the host every index map of the execute kernels
+ * (local block <-> depth and index, table groups, workspace nodes of every block's column
+ * nodes, the LDS layouts, each single-launch unit's tree-top table, the regenerated
+ * blocks' output and factor rows) and compares each index with the size of the buffer it
+ * addresses.  Makes no device call and allocates no device memory.
+ * Returns L2C_OK when every index is in bounds (and for direct-only geometries, L = 0), a
+ * positive number naming the first check that fails (1 block map, 2 table groups,
+ * 3 workspace, 4 three-launch LDS, 5 single-launch LDS, 6 tree-top items, 7 tree-top
+ * schedule, 8 regenerated blocks, 9 subtree count), or L2C_EINVAL for arguments
+ * leg2cheb_plan refuses.
+ */
+int leg2cheb_debug_check_geometry(int64_t n, int leaf_size, int rank);
+
 /* Static description of a status code. */
 const char *leg2cheb_strerror(int code);
 

@@ -31,7 +31,7 @@ EXPORTED = (
     "leg2cheb_plan_export", "leg2cheb_plan_set_option", "leg2cheb_plan_status", "leg2cheb_set_timing_events",
     "leg2cheb_rank_supported", "leg2cheb_strerror",
     "leg2cheb_batch_plan", "leg2cheb_batch_execute", "leg2cheb_batch_info", "leg2cheb_batch_destroy",
-    "leg2cheb_batch_tuning", "leg2cheb_debug_alloc_hook",
+    "leg2cheb_batch_tuning", "leg2cheb_debug_alloc_hook", "leg2cheb_debug_check_geometry",
     "leg2cheb_dct_plan", "leg2cheb_dct_execute", "leg2cheb_dct_destroy",
     "leg2cheb_grid_plan", "leg2cheb_grid_execute", "leg2cheb_grid_destroy", "leg2cheb_grid_fmm", "leg2cheb_grid_dct",
 )
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
     lib.leg2cheb_plan_status.argtypes = [vp, ctypes.POINTER(ci)]
     lib.leg2cheb_set_timing_events.argtypes = [vp, vp, vp]
     lib.leg2cheb_rank_supported.argtypes = [ci]
+    lib.leg2cheb_debug_check_geometry.argtypes = [i64, ci, ci]
     lib.leg2cheb_strerror.argtypes = [ci]
     lib.leg2cheb_strerror.restype = ctypes.c_char_p
     lib.leg2cheb_batch_plan.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(i64), ctypes.POINTER(ci), ci,

@@ -19,6 +19,8 @@
 
 namespace l2c {
 
+int check_geometry_indices(int L, int M, int s);   // l2c_check.hip
+
 // Allocation-failure hook: the k-th allocation from the arming call fails (0: disarmed).
 static std::atomic<int64_t> g_fail_at{0};
 static std::atomic<int64_t> g_live{0};   // allocations made here and not yet released
@@ -734,6 +736,19 @@ int leg2cheb_debug_alloc_hook(int64_t fail_at, int64_t *pending, int64_t *live)
     if (pending) *pending = before;
     if (live) *live = l2c::g_live.load();
     return L2C_OK;
+}
+
+int leg2cheb_debug_check_geometry(int64_t n, int leaf_size, int rank)
+{
+    if (n < 1 || n > (int64_t(1) << 31) || leaf_size < 4 || leaf_size > 128 || (leaf_size & 1) ||
+        !rank_supported(rank))
+        return L2C_EINVAL;
+    int L = 0, s = 0;
+    int64_t n_pad = 0;
+    plan_sizes(n, leaf_size, &L, &s, &n_pad);
+    if (L == 0) return L2C_OK;   // the direct product: no multipole index maps
+    if (L >= L2C_MAX_LEVELS - 1) return L2C_EINVAL;
+    return l2c::check_geometry_indices(L, rank, s);
 }
 
 }  // extern "C"

@@ -974,8 +974,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(ExecArgs a)
 
     // ---- steps (5) and (7): z = rs * near + sum_k T_k(X_m^sig) c(u)[sig][k] (row nodes
     //      u < P - 2); leg2cheb divides by c_i pi/2.  The unit's rows are assembled in LDS
-    //      (the near-field area, free by now; node stride 2s+1 against bank conflicts, and
-    //      2 GX > nodes (2s+1) always), then written out in contiguous wave-wide stores.
+    //      (the near-field area, free by now; node stride 2s+1 against bank conflicts; with
+    //      small s and many nodes the rows reach past the input part into the Q table, dead
+    //      by then), then written out in contiguous wave-wide stores.
     double *out = a.item_out ? a.item_out[item] : a.out + item * a.n;
     double *ob = gp;
     const int OS = 2 * s + 1;

@@ -244,3 +244,29 @@ def test_plan_cache_host_logic(lib):
     assert plans.value == 0 and refs.value == 0
     assert L.leg2cheb_plan_cache_size(None, None) == 0
     assert L.leg2cheb_plan_cached(None, 1000, 0, 64, 18, 0, 1, 0, None) == -1
+
+
+def test_index_maps_in_bounds_for_every_geometry(lib):
+    """leg2cheb_debug_check_geometry: every index map of the execute kernels (block map,
+    table groups, workspace nodes, LDS layouts, the single launch's tree-top tables, the
+    regenerated blocks' rows) stays inside its buffer, for every leaf size and rank the
+    library accepts and lengths from 1 to 2^31 (a fixed list plus seeded random ones);
+    argument errors as leg2cheb_plan."""
+    import numpy as np
+    L = lib.load()
+    rng = np.random.default_rng(2411000 + 77)
+    ns = sorted(set([1, 2, 3, 64, 127, 128, 129, 255, 256, 257, 1000, 1024, 1025, 4096, 5000, 65536, 10 ** 5,
+                     300000, 10 ** 6, 2 ** 20, 2 ** 20 + 1, 3 * 10 ** 6, 10 ** 7, 2 ** 24, 2 ** 26 + 5, 10 ** 8, 2 ** 31]
+                    + [int(v) for v in rng.integers(1, 2 ** 31, 300)]))
+    bad = []
+    for n in ns:
+        for leaf in (4, 6, 8, 16, 32, 40, 64, 96, 128):
+            for rank in (12, 16, 18, 20, 24):
+                rc = L.leg2cheb_debug_check_geometry(n, leaf, rank)
+                if rc != 0:
+                    bad.append((n, leaf, rank, rc))
+    assert not bad, bad[:10]
+    assert L.leg2cheb_debug_check_geometry(0, 64, 18) == -1
+    assert L.leg2cheb_debug_check_geometry(2 ** 31 + 1, 64, 18) == -1
+    assert L.leg2cheb_debug_check_geometry(1000, 63, 18) == -1
+    assert L.leg2cheb_debug_check_geometry(1000, 64, 17) == -1
