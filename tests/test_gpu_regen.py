@@ -147,3 +147,41 @@ def test_regen_plan_limits(l2c):
                                           ctypes.c_void_p(y.data_ptr()), 1, None) == l2c.L2C_EUNSUPPORTED
     with pytest.raises(ValueError):
         l2c.Plan(5000, 0, 64, 16, precision=l2c.L2C_FP32, tables=l2c.L2C_TABLES_REGEN)
+
+
+def test_regen_allocation_failures_and_workspace_growth(l2c):
+    """Every allocation of a regenerating plan failed in turn: L2C_ENOMEM, a NULL handle and
+    nothing leaked; the plan made afterwards gives the same output as one made without the
+    hook.  An execute with a batch above max_batch regrows the workspace (upward vectors and
+    regenerated far-field parts) and matches the single executes bit for bit."""
+    import ctypes
+    import torch
+    from test_gpu_errors import fail_each
+    L = l2c._lib.load()
+    n = 40000
+
+    def make():
+        h = ctypes.c_void_p(1)
+        rc = L.leg2cheb_plan_tables(ctypes.byref(h), n, 1, 64, 18, 1, l2c.L2C_TABLES_REGEN, None)
+        return rc, h
+    try:
+        h, count = fail_each(l2c, make)
+    finally:
+        l2c.leg2cheb_debug_alloc_hook(0)
+    assert count >= 5
+    F = inputs.decaying(n, 0.5, inputs.SEED_BASE + 760, batch=3)
+    x = torch.from_numpy(F).cuda()
+    y = torch.empty_like(x)
+    assert L.leg2cheb_execute(ctypes.c_void_p(h.value), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                              3, None) == 0          # batch 3 > max_batch 1: the workspace grows
+    torch.cuda.synchronize()
+    info = l2c.leg2cheb_plan_info(h.value)
+    l2c.leg2cheb_destroy(h.value)
+    assert info["path"] == l2c.L2C_PATH_REGEN
+    Y = y.cpu().numpy()
+    for b in range(3):
+        z, _ = run(l2c, F[b], 1)
+        assert np.array_equal(z, Y[b])
+    err = max(oracle.einf(Y[b], oracle.transform(F[b], 1)) for b in range(3))
+    print("regen plan after %d failed allocations, batch 3 over max_batch 1: E_inf %.3e" % (count, err))
+    assert err <= TOL[(1, 18)]
