@@ -851,8 +851,8 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
         const int64_t top_blocks = l2c::level_block_offset(p->geo.groot + 1);
         p->top_bytes = top_blocks * 3 * M * M * (int64_t)sizeof(double);
         p->bot_bytes = regen ? 0 : (int64_t(1) << (p->geo.groot + 2)) * p->geo.sub_groups * 64 * 3 * M * (int64_t)sizeof(double);
-        // regenerated blocks: Lambda((y-x)/2) per level below the subtree roots and offset
-        const int64_t nlm = regen ? (int64_t)(L - 1 - p->geo.groot) * 2 * M * M : 0;
+        // Lambda((y-x)/2) per level and offset (the plan's samples; regenerating executes)
+        const int64_t nlm = (int64_t)L * 2 * M * M;
 
         // B(0), B(1) on the host (exact dyadic rationals); T, P, the Chebyshev-Gauss points,
         // the DCT matrix and Ahat on the device
@@ -872,7 +872,7 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
                   l2c::dev_alloc(&p->d_P, nP * sizeof(double)) == hipSuccess &&
                   l2c::dev_alloc(&p->d_XG, M * sizeof(double)) == hipSuccess &&
                   l2c::dev_alloc(&p->d_D, (size_t)M * M * sizeof(double)) == hipSuccess &&
-                  (nlm == 0 || l2c::dev_alloc(&p->d_lm, nlm * sizeof(double)) == hipSuccess);
+                  l2c::dev_alloc(&p->d_lm, nlm * sizeof(double)) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);
@@ -883,8 +883,8 @@ int plan_impl(l2c_plan_t *plan, int64_t n, int direction, int leaf_size, int ran
              l2c::launch_build_small(*p, st) == hipSuccess &&
              (Lnod.empty() || hipMemcpyAsync(p->d_T, Lnod.data(), Lnod.size() * 8, hipMemcpyHostToDevice, st) == hipSuccess) &&
              (p->bot_bytes == 0 || hipMemsetAsync(p->d_bot, 0, p->bot_bytes, st) == hipSuccess) &&
-             l2c::launch_build_ahat(*p, st) == hipSuccess &&
-             (nlm == 0 || l2c::launch_build_lminus(*p, st) == hipSuccess) && hipStreamSynchronize(st) == hipSuccess;
+             l2c::launch_build_lminus(*p, st) == hipSuccess && l2c::launch_build_ahat(*p, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             free_plan(p);

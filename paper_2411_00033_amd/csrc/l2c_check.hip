@@ -100,13 +100,13 @@ int check_geometry_indices(int L, int M, int s)
     // factor-table rows inside the plan's table
     if (kd >= 1) {
         const int own = 2 * nodes - 2;
-        const int64_t per_item = regen_cf_per_item(G), nlm = (int64_t)(L - 1 - G0) * 2 * M * M;
+        const int64_t per_item = regen_cf_per_item(G), nlm = (int64_t)L * 2 * M * M;
         for (int j = 0; j < nown; ++j) {
             int d, i;
             slot_depth(j, kd, d, i);
             const int64_t last = ((U - 1) * own + (1 << d) - 2 + 2 * i) * 2 * M + 2 * 2 * M;
             if (last > per_item) return kGeoRegen;
-            if ((int64_t)(d - 1) * 2 * M * M + 2 * M * M > nlm) return kGeoRegen;
+            if ((int64_t)(G0 + d) * 2 * M * M + 2 * M * M > nlm) return kGeoRegen;
         }
     }
     return kGeoOk;

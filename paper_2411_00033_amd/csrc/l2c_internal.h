@@ -175,11 +175,12 @@ struct l2c_plan_s {
     // k_direct's factor tables: P_d for d < ceil(n/2), then Q_S for S < n + 17 (plans with
     // L = 0, and plans with direct_ok)
     double *d_dir = nullptr;
-    // far-field blocks below the subtree roots recomputed in every execute (L2C_TABLES_REGEN,
-    // l2c_regen.hip): no bottom table; Lambda((y-x)/2) per level and offset, [L-1-groot][2][M][M];
-    // the far-field part of step (3) per own node, [ws_batch][subtrees][own nodes][2][M]
-    bool regen = false;
+    // Lambda((y-x)/2) per level and offset, [L][2][M][M] (the plan's samples, l2c_regen.hip)
     double *d_lm = nullptr;
+    // far-field blocks below the subtree roots recomputed in every execute (L2C_TABLES_REGEN,
+    // l2c_regen.hip): no bottom table; the far-field part of step (3) per own node,
+    // [ws_batch][subtrees][own nodes][2][M]
+    bool regen = false;
     double *d_cf = nullptr;
 };
 

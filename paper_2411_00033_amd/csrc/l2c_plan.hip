@@ -14,20 +14,16 @@
 // k_build_small makes the Vandermonde matrices T(sigma) of Eq. (Xs), the near-field factor
 // P_d, the Chebyshev-Gauss points and the DCT matrix, also in FP64 on the device.
 //
-// The paper's planning shortcuts (persymmetry of Lambda^-, reuse across a level,
-// term dropping in Eq. (tau), the radix-2/3 DCT of size 18) reduce CPU flops; here
-// every sample is evaluated directly, which keeps one independent thread per sample.
+// Two of the paper's planning shortcuts (Sec. 4.3) cut the Lambda evaluations per block
+// from 6 M^2 to 3 M (M+1)/2: the factor Lambda((y-x)/2) depends only on the level and the
+// submatrix's offset from the diagonal, and comes from a table built once per plan
+// (k_build_lminus, l2c_regen.hip); the factor in (x+y)/2 is symmetric in the sample
+// indices and is evaluated once per pair m <= n.  (Its other shortcuts, term dropping in
+// Eq. (tau) and a radix-2/3 DCT of size 18, save CPU flops that do not bound this kernel.)
 #include "l2c_internal.h"
 #include "l2c_math.h"
 
 namespace l2c {
-
-__device__ inline double kernel_value(int dir, double x, double y)
-{
-    if (dir == 0) return lambda_real(0.5 * (y - x)) * lambda_real(0.5 * (y + x));
-    const double g = 2.0 * (x + 0.5) * y / ((x + y) * (x + y + 1.0) * (x - y + 1.0));
-    return g * lambda_real(0.5 * (y - x)) / lambda_real(0.5 * (x + y));
-}
 
 // Address (in doubles) of element (r, k, l) of block b of level g in the plan tables.
 template <int M>
@@ -48,9 +44,10 @@ __device__ __forceinline__ double *ahat_addr(double *top, double *bot, const Geo
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bot, Geometry G, int dir,
-                                                          const double *XG, const double *Dm, int nodal)
+                                                          const double *XG, const double *Dm, int nodal,
+                                                          const double *lm)
 {
-    constexpr int MM = M * M;
+    constexpr int MM = M * M, NPAIR = M * (M + 1) / 2;
     __shared__ double S[3 * MM];
     __shared__ double U[3 * MM];
     __shared__ double Dl[MM];
@@ -70,14 +67,40 @@ __global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bo
     for (int e = tid; e < M; e += kThreads) Xl[e] = XG[e];
     __syncthreads();
 
-    for (int e = tid; e < 3 * MM; e += kThreads) {
-        const int r = e / MM, mn = e - r * MM;
-        const int m = mn / M, n = mn - m * M;
+    // samples (m, n) and (n, m) of submatrix r from one Lambda((x+y)/2)
+    for (int e = tid; e < 3 * NPAIR; e += kThreads) {
+        const int r = e / NPAIR;
+        int pr = e - r * NPAIR, m = 0;
+        while (pr >= M - m) {                                    // pair index -> (m, n), m <= n
+            pr -= M - m;
+            ++m;
+        }
+        const int n = m + pr;
         const int p = (r == 2) ? 1 : 0, q = (r == 0) ? 0 : 1;   // r = p + q(q+1)/2
         const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
         const double j0 = 2.0 * h * (double)(2 * b + q + 2);
-        S[e] = kernel_value(dir, i0 + h * (Xl[m] + 1.0), j0 + h * (Xl[n] + 1.0));
-        if (nodal) *ahat_addr<M>(top, bot, G, g, b, r, m, n) = S[e];
+        const double *lmr = lm + ((int64_t)g * 2 + (q - p)) * MM;   // offset (q + 2 - p) h
+        const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
+        double vmn, vnm;
+        if (dir == 0) {
+            const double lp = lambda_real(zp);
+            vmn = lmr[m * M + n] * lp;
+            vnm = lmr[n * M + m] * lp;
+        } else {
+            // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2)
+            const double ilp = 1.0 / lambda_real(zp);
+            const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
+            const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
+            const double sp = xm + yn;
+            vmn = 2.0 * (xm + 0.5) * yn / (sp * (sp + 1.0) * (xm - yn + 1.0)) * ilp * lmr[m * M + n];
+            vnm = 2.0 * (xn + 0.5) * ym / (sp * (sp + 1.0) * (xn - ym + 1.0)) * ilp * lmr[n * M + m];
+        }
+        S[r * MM + m * M + n] = vmn;
+        S[r * MM + n * M + m] = vnm;
+        if (nodal) {
+            *ahat_addr<M>(top, bot, G, g, b, r, m, n) = vmn;
+            *ahat_addr<M>(top, bot, G, g, b, r, n, m) = vnm;
+        }
     }
     if (nodal) return;
     __syncthreads();
@@ -191,7 +214,7 @@ static hipError_t build(const l2c_plan_s &p, hipStream_t st)
     const int64_t blocks = p.regen ? level_block_offset(p.geo.groot + 1) : p.nb;
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)blocks), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
-                       p.direction, p.d_XG, p.d_D, p.basis);
+                       p.direction, p.d_XG, p.d_D, p.basis, (const double *)p.d_lm);
     return hipGetLastError();
 }
 

@@ -9,9 +9,9 @@
 // Sec. 4.3: S[m][n] = Lambda((y-x)/2) Lambda((x+y)/2) for leg2cheb (Eq. (Aij)), and for
 // cheb2leg the reverse kernel of Eq. (Lxymod), a rational factor times
 // Lambda((y-x)/2) / Lambda((x+y)/2).  The first factor depends only on the level and on
-// the submatrix's offset from the diagonal (2 h or 3 h, Eq. (globalij)): the plan keeps it
-// as a table of 2 (L-1-groot) M x M blocks (k_build_lminus).  The second is evaluated per
-// sample in the execute.
+// the submatrix's offset from the diagonal (2 h or 3 h, Eq. (globalij)): every plan keeps it
+// as a table of 2 L M x M blocks (k_build_lminus; the plan's own k_build_ahat samples from
+// it too).  The second is evaluated per sample in the execute.
 //
 // k_regen computes, for every block below the subtree roots of level groot (the blocks
 // whose table the single-launch and three-launch paths stream), the far-field part of
@@ -28,18 +28,16 @@ namespace l2c {
 constexpr int kRegenThreads = 64;    // one wave per workgroup
 constexpr int kRegenBlocks = 4;      // far-field blocks per workgroup (in sequence)
 
-// Lambda((y - x)/2) for the submatrices of level g = groot + 1 + gi at offset dl h from
-// the diagonal (dl = 2 + di), sample (m, n): table [gi][di][m][n].
+// Lambda((y - x)/2) for the submatrices of level g at offset dl h from the diagonal
+// (dl = 2 + di), sample (m, n): table [g][di][m][n], g = 0..L-1.
 template <int M>
 __global__ void k_build_lminus(double *lm, Geometry G, const double *XG)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nlev = G.L - 1 - G.groot;
-    if (e >= (int64_t)nlev * 2 * M * M) return;
+    if (e >= (int64_t)G.L * 2 * M * M) return;
     const int mn = (int)(e % (M * M)), t = (int)(e / (M * M));
-    const int di = t & 1, gi = t >> 1;
+    const int di = t & 1, g = t >> 1;
     const int m = mn / M, n = mn % M;
-    const int g = G.groot + 1 + gi;
     const double h = (double)((int64_t)G.s << (G.L - g - 1));
     lm[e] = lambda_real((2.0 + di) * h + 0.5 * h * (XG[n] - XG[m]));
 }
@@ -143,7 +141,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
         // The factor in (x+y)/2 depends on X_m + X_n only: one evaluation per pair m <= n
         // serves samples (m, n) and (n, m) (M (M+1)/2 pairs per submatrix).
         const double h = (double)((int64_t)s << (L - g - 1));
-        const double *lmg = lm + (int64_t)(d - 1) * 2 * MM;
+        const double *lmg = lm + (int64_t)g * 2 * MM;
 #pragma unroll 2
         for (int e = lane; e < 3 * NPAIR; e += kRegenThreads) {
             const int r = e / NPAIR, pr = e - r * NPAIR;
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
 template <int M>
 static hipError_t build_lm(const l2c_plan_s &p, hipStream_t st)
 {
-    const int64_t total = (int64_t)(p.L - 1 - p.geo.groot) * 2 * M * M;
+    const int64_t total = (int64_t)p.L * 2 * M * M;
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_build_lminus<M>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, p.d_lm, p.geo,
                        (const double *)p.d_XG);
