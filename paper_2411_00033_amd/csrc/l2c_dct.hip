@@ -49,6 +49,8 @@ namespace l2c {
 
 constexpr int kFftLds = 4096;                    // complex values per workgroup, at most
 constexpr int kFftSmall = 2048;                  // ... for lengths up to this
+constexpr int kFftPre = 512;                     // lines up to this long load the store factors first
+static_assert(kFftPre <= kFftSmall, "the up-front store factors live in the small kernel shape");
 constexpr int kFftMaxPass = 16;
 constexpr int64_t kFftMaxN = int64_t(1) << 27;
 
@@ -75,6 +77,7 @@ struct FftArgs {
     const double2 *qh, *ql;    // exp(i pi k / (2N)) = qh[k / qb] ql[k % qb]
     int64_t qb;
     int load, store;
+    int pre;                   // store factors loaded up front (n <= kFftPre, CAP = kFftSmall)
     double scale0, scale;      // DCT-2 store: y_0 scale0, y_k scale (k >= 1)
     const double *rin;         // real input [transform][N]
     double *rout;              // real output [transform][N]
@@ -238,13 +241,24 @@ struct FftLine {
     int twa;
 };
 
-template <int CAP, int NT>
-__global__ __launch_bounds__(NT) void k_fft(FftArgs a)
+// One launch of the FFT: C lines per workgroup, loaded (with the DCT reordering or the
+// quarter-wave factors of the first pass), transformed in LDS, stored (with the twist of
+// the four-step split or the DCT's last factors).  LOAD and STORE are the kLoad / kStore
+// modes.  Every global load of a workgroup is issued before the first of them is used:
+// the input, the pass's root table, and (CAP / NT <= 4 values per thread) the twist or
+// quarter-wave factors of the store, so a launch waits for memory once before its radix
+// passes instead of three times.
+template <int CAP, int NT, int LOAD, int STORE>
+__global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
 {
     extern __shared__ double2 smem[];
     const int n = a.n, C = a.C, N = (int)a.N;
-    double2 *buf = smem, *tw = smem + C * n;
-    FftLine *ln = reinterpret_cast<FftLine *>(tw + n);
+    // store factors loaded up front (lines of at most kFftPre points): one per value, in a
+    // slot of LDS private to the thread, so that no register holds them across the passes
+    constexpr bool kPreOk = CAP == kFftSmall && STORE != kStoreDct3 && LOAD != kLoadDct3;   // fft_pre_ok
+    const bool pre = kPreOk && a.pre;
+    double2 *buf = smem, *tw = smem + C * n, *fqs = tw + n;
+    FftLine *ln = reinterpret_cast<FftLine *>(fqs + (pre ? CAP : 0));
     const int64_t line0 = (int64_t)blockIdx.x * C;
     for (int c = threadIdx.x; c < C; c += NT) {
         const int64_t line = line0 + c;
@@ -259,19 +273,19 @@ __global__ __launch_bounds__(NT) void k_fft(FftArgs a)
         }
         ln[c] = L;
     }
-    for (int t = threadIdx.x; t < n; t += NT) tw[t] = a.tw[t];
     __syncthreads();
     const int cnt = C * n;
     const int es_in = (int)a.es_in, es_out = (int)a.es_out;
     constexpr int EPT = CAP / NT;                 // elements per thread, at most
-    // load: adjacent threads take adjacent elements of a line, or (strided lines) the same
-    // element of adjacent lines, whichever is adjacent in memory.  Every global load of
-    // the thread is issued before the first is used.
+    constexpr int TPT = (CAP + NT - 1) / NT;      // root-table entries per thread, at most
+    const double Nd = (double)N, invN = 1.0 / Nd;
+    // input: adjacent threads take adjacent elements of a line, or (strided lines) the same
+    // element of adjacent lines, whichever is adjacent in memory
+    double2 raw[EPT], rh[EPT], rl[EPT];
+    int pos[EPT], gg[EPT];
     {
         const bool lcol = es_in != 1;
         const FastDiv dv(lcol ? C : n), dqb((int)a.qb);
-        double2 raw[EPT], rh[EPT], rl[EPT];
-        int pos[EPT], gg[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int idx = (int)threadIdx.x + u * NT;
@@ -286,9 +300,9 @@ __global__ __launch_bounds__(NT) void k_fft(FftArgs a)
                 if (L.base >= 0) {
                     const int g = L.gin + e * es_in;
                     gg[u] = g;
-                    if (a.load == kLoadComplex) {
+                    if constexpr (LOAD == kLoadComplex) {
                         raw[u] = a.cin[L.base + g];
-                    } else if (a.load == kLoadDct2) {
+                    } else if constexpr (LOAD == kLoadDct2) {
                         raw[u].x = a.rin[L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1)];
                     } else {
                         const double *x = a.rin + L.base;
@@ -300,15 +314,95 @@ __global__ __launch_bounds__(NT) void k_fft(FftArgs a)
                 }
             }
         }
+    }
+    // the pass's roots
+    double twx[TPT], twy[TPT];                  // (components: a conditional struct copy stays in memory)
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            if (pos[u] < 0) continue;
-            double2 v = raw[u];
-            if (a.load == kLoadDct3 && gg[u] >= 0) {
+    for (int u = 0; u < TPT; ++u) {
+        const int t = (int)threadIdx.x + u * NT;
+        twx[u] = twy[u] = 0.0;
+        if (t < n) {
+            const double2 w = a.tw[t];
+            twx[u] = w.x;
+            twy[u] = w.y;
+        }
+    }
+    // store side: where each value goes and the factor it takes
+    const bool scol = es_out != 1;
+    const FastDiv dvs(scol ? C : n), dtb((int)(STORE == kStoreDct2 ? a.qb : a.wb));
+    double2 sh[EPT], sl[EPT];
+    int64_t dst[EPT];
+    int sp[EPT], sg[EPT], st[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int idx = (int)threadIdx.x + u * NT;
+        dst[u] = -1;
+        sg[u] = 0;
+        sp[u] = 0;
+        st[u] = -1;
+        if (idx < cnt) {
+            const int q = dvs.quot(idx), rm = idx - q * dvs.d;
+            const int c = scol ? rm : q, e = scol ? q : rm;
+            const FftLine L = ln[c];
+            if (L.base >= 0) {
+                const int g = L.gout + e * es_out;
+                sg[u] = g;
+                sp[u] = c * n + e;
+                if constexpr (STORE == kStoreComplex) {
+                    dst[u] = L.base + g;
+                    if (a.twist) st[u] = mod_n((double)L.twa * (double)e, Nd, invN);
+                } else if constexpr (STORE == kStoreDct2) {
+                    dst[u] = L.base + g;
+                    st[u] = g;
+                } else {
+                    dst[u] = L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1);
+                }
+                if constexpr (kPreOk) {
+                    if (pre && st[u] >= 0) {
+                        const double2 *hi = STORE == kStoreDct2 ? a.qh : a.wh, *lo = STORE == kStoreDct2 ? a.ql : a.wl;
+                        const int th = dtb.quot(st[u]);
+                        sh[u] = hi[th];
+                        sl[u] = lo[st[u] - th * dtb.d];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        const int t = (int)threadIdx.x + u * NT;
+        if (t < n) tw[t] = make_double2(twx[u], twy[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        if (pos[u] < 0) continue;
+        double2 v = raw[u];
+        if constexpr (LOAD == kLoadDct3) {
+            if (gg[u] >= 0) {
                 const bool z = gg[u] == 0;
                 v = cmul(cmul(rh[u], rl[u]), make_double2(z ? v.x : 0.5 * v.x, z ? 0.0 : -0.5 * v.y));
             }
-            buf[pos[u]] = v;
+        }
+        buf[pos[u]] = v;
+    }
+    // the store factor of each value as one complex number (twist: conjugated for the
+    // inverse; DCT-2: times the output scale)
+    if constexpr (kPreOk) {
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double2 f = make_double2(1.0, 0.0);
+                if (dst[u] >= 0 && st[u] >= 0) {
+                    const double2 q = cmul(sh[u], sl[u]);
+                    if constexpr (STORE == kStoreComplex) {
+                        f = conj_if(q, a.sign > 0);
+                    } else {
+                        const double sc = sg[u] == 0 ? a.scale0 : a.scale;
+                        f = make_double2(q.x * sc, q.y * sc);
+                    }
+                }
+                fqs[u * NT + threadIdx.x] = f;
+            }
         }
     }
     __syncthreads();
@@ -325,44 +419,22 @@ __global__ __launch_bounds__(NT) void k_fft(FftArgs a)
         }
         Ns *= R;
     }
-    const bool scol = es_out != 1;
-    const double Nd = (double)N, invN = 1.0 / Nd;
-    const FastDiv dv(scol ? C : n), dtb((int)(a.store == kStoreDct2 ? a.qb : a.wb));
-    double2 val[EPT], rh[EPT], rl[EPT];
-    int64_t dst[EPT];
-    int gg[EPT];
+    double2 fq[EPT];
+    if constexpr (STORE != kStoreDct3) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int idx = (int)threadIdx.x + u * NT;
-        dst[u] = -1;
-        gg[u] = 0;
-        if (idx < cnt) {
-            const int q = dv.quot(idx), rm = idx - q * dv.d;
-            const int c = scol ? rm : q, e = scol ? q : rm;
-            const FftLine L = ln[c];
-            if (L.base >= 0) {
-                const int g = L.gout + e * es_out;
-                gg[u] = g;
-                val[u] = buf[c * n + e];
-                int t = -1;
-                const double2 *hi = a.wh, *lo = a.wl;
-                if (a.store == kStoreComplex) {
-                    dst[u] = L.base + g;
-                    if (a.twist) t = mod_n((double)L.twa * (double)e, Nd, invN);
-                } else if (a.store == kStoreDct2) {
-                    dst[u] = L.base + g;
-                    t = g;
-                    hi = a.qh;
-                    lo = a.ql;
+        for (int u = 0; u < EPT; ++u) {
+            fq[u] = make_double2(1.0, 0.0);
+            if (kPreOk && pre) {
+                fq[u] = fqs[u * NT + threadIdx.x];
+            } else if (dst[u] >= 0 && st[u] >= 0) {
+                const double2 *hi = STORE == kStoreDct2 ? a.qh : a.wh, *lo = STORE == kStoreDct2 ? a.ql : a.wl;
+                const int th = dtb.quot(st[u]);
+                const double2 q = cmul(hi[th], lo[st[u] - th * dtb.d]);
+                if constexpr (STORE == kStoreComplex) {
+                    fq[u] = conj_if(q, a.sign > 0);
                 } else {
-                    dst[u] = L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1);
-                }
-                if (t >= 0) {
-                    const int th = dtb.quot(t);
-                    rh[u] = hi[th];
-                    rl[u] = lo[t - th * dtb.d];
-                } else {
-                    rh[u] = rl[u] = make_double2(1.0, 0.0);
+                    const double sc = sg[u] == 0 ? a.scale0 : a.scale;
+                    fq[u] = make_double2(q.x * sc, q.y * sc);
                 }
             }
         }
@@ -370,13 +442,13 @@ __global__ __launch_bounds__(NT) void k_fft(FftArgs a)
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         if (dst[u] < 0) continue;
-        const double2 q = cmul(rh[u], rl[u]);
-        if (a.store == kStoreComplex) {
-            a.cout[dst[u]] = cmul(val[u], conj_if(q, a.sign > 0));
-        } else if (a.store == kStoreDct2) {
-            a.rout[dst[u]] = (q.x * val[u].x + q.y * val[u].y) * (gg[u] == 0 ? a.scale0 : a.scale);   // Re(conj(q) V)
+        const double2 val = buf[sp[u]];
+        if constexpr (STORE == kStoreComplex) {
+            a.cout[dst[u]] = cmul(val, fq[u]);
+        } else if constexpr (STORE == kStoreDct2) {
+            a.rout[dst[u]] = fq[u].x * val.x + fq[u].y * val.y;   // Re(conj(q) V), scaled
         } else {
-            a.rout[dst[u]] = val[u].x;
+            a.rout[dst[u]] = val.x;
         }
     }
 }
@@ -498,7 +570,31 @@ void set_pass(l2c::FftArgs &a, int n, const std::vector<int> &r, const double2 *
     a.C = std::max(1, (n <= l2c::kFftSmall ? l2c::kFftSmall : l2c::kFftLds) / n);
 }
 
-// Both kernel shapes may take more than 64 KiB of dynamic LDS (up to 128 KiB + the line
+// The launches whose kernel loads the store factors up front (the kernel's kPreOk, plus the
+// line length): the LDS size depends on it.
+bool fft_pre_ok(const l2c::FftArgs &a)
+{
+    return a.n <= l2c::kFftPre && a.store != l2c::kStoreDct3 && a.load != l2c::kLoadDct3;
+}
+
+// The (load, store) pairs a DCT uses: one pass (DCT load and store), the first of several
+// (DCT load, complex store), a middle one (complex, complex) and the last (complex load,
+// DCT store).
+template <int CAP>
+const void *fft_kernel(int load, int store)
+{
+    using namespace l2c;
+    if (load == kLoadDct2 && store == kStoreDct2) return (const void *)k_fft<CAP, 512, kLoadDct2, kStoreDct2>;
+    if (load == kLoadDct3 && store == kStoreDct3) return (const void *)k_fft<CAP, 512, kLoadDct3, kStoreDct3>;
+    if (load == kLoadDct2 && store == kStoreComplex) return (const void *)k_fft<CAP, 512, kLoadDct2, kStoreComplex>;
+    if (load == kLoadDct3 && store == kStoreComplex) return (const void *)k_fft<CAP, 512, kLoadDct3, kStoreComplex>;
+    if (load == kLoadComplex && store == kStoreComplex) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreComplex>;
+    if (load == kLoadComplex && store == kStoreDct2) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreDct2>;
+    if (load == kLoadComplex && store == kStoreDct3) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreDct3>;
+    return nullptr;
+}
+
+// Every kernel shape may take more than 64 KiB of dynamic LDS (up to 128 KiB + the line
 // table at n = 4096): raise their limit once per process.
 hipError_t fft_attrs()
 {
@@ -506,11 +602,15 @@ hipError_t fft_attrs()
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
         const int lds = 160 * 1024;
-        err = hipFuncSetAttribute((const void *)l2c::k_fft<l2c::kFftSmall, 512>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (err == hipSuccess)
-            err = hipFuncSetAttribute((const void *)l2c::k_fft<l2c::kFftLds, 512>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const int pairs[7][2] = {{l2c::kLoadDct2, l2c::kStoreDct2},       {l2c::kLoadDct3, l2c::kStoreDct3},
+                                 {l2c::kLoadDct2, l2c::kStoreComplex},    {l2c::kLoadDct3, l2c::kStoreComplex},
+                                 {l2c::kLoadComplex, l2c::kStoreComplex}, {l2c::kLoadComplex, l2c::kStoreDct2},
+                                 {l2c::kLoadComplex, l2c::kStoreDct3}};
+        for (const auto &pr : pairs) {
+            for (const void *k : {fft_kernel<l2c::kFftSmall>(pr[0], pr[1]), fft_kernel<l2c::kFftLds>(pr[0], pr[1])}) {
+                if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            }
+        }
     });
     return err;
 }
@@ -521,12 +621,15 @@ hipError_t launch(const l2c::FftArgs &a, hipStream_t st)
     if (blocks <= 0) return hipSuccess;
     const hipError_t e = fft_attrs();
     if (e != hipSuccess) return e;
-    const size_t lds = ((size_t)a.C * a.n + a.n) * sizeof(double2) + (size_t)a.C * sizeof(l2c::FftLine);
-    if (a.n <= l2c::kFftSmall)
-        hipLaunchKernelGGL((l2c::k_fft<l2c::kFftSmall, 512>), dim3((unsigned)blocks), dim3(512), lds, st, a);
-    else
-        hipLaunchKernelGGL((l2c::k_fft<l2c::kFftLds, 512>), dim3((unsigned)blocks), dim3(512), lds, st, a);
-    return hipGetLastError();
+    l2c::FftArgs b = a;
+    b.pre = fft_pre_ok(a) ? 1 : 0;
+    const size_t lds = ((size_t)a.C * a.n + a.n + (b.pre ? l2c::kFftSmall : 0)) * sizeof(double2) +
+                       (size_t)a.C * sizeof(l2c::FftLine);
+    const void *k = a.n <= l2c::kFftSmall ? fft_kernel<l2c::kFftSmall>(a.load, a.store)
+                                          : fft_kernel<l2c::kFftLds>(a.load, a.store);
+    if (!k) return hipErrorInvalidValue;
+    void *args[] = {(void *)&b};
+    return hipLaunchKernel(k, dim3((unsigned)blocks), dim3(512), args, lds, st);
 }
 
 int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream_t st)
