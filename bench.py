@@ -346,7 +346,7 @@ def grid_form(l2c, inputs, torch, K, W, flush, flush_sink):
     u = torch.empty_like(x)
     back = torch.empty_like(x)
     rec = {"workload": "N=1000000, f_j = z_j/sqrt(j+1); leg2grid = leg2cheb + DCT-3, grid2leg = DCT-2 + cheb2leg "
-                       "(leaf 64, rank 18, FP64); DCTs on the library's FFT (1000 x 1000 four-step); cold HBM"}
+                       "(leaf 64, rank 18, FP64); DCTs on the library's FFT (100 x 100 x 100 four-step split); cold HBM"}
     with l2c.GridPlan(n, l2c.LEG2GRID) as fw, l2c.GridPlan(n, l2c.GRID2LEG) as bw, \
             l2c.Dct(n, 2) as d2, l2c.Dct(n, 3) as d3, l2c.Plan(n, l2c.LEG2CHEB, LEAF, RANK) as p:
         rec["leg2grid_ms"] = timed(lambda: fw.execute(x, u))
