@@ -1,13 +1,17 @@
 // l2c_plan.hip -- device part of the plan stage (arXiv 2411.00033, Secs. 3.2 and 4.3).
 //
-// k_build_ahat: one workgroup per block (g, b) of the decomposition; for each of its
+// k_build_ahat: one wave per block (g, b) of the decomposition, adjacent blocks of a level
+// in one workgroup (so that the rows they share in the far-field tables meet in one L2);
+// for each of its
 // three submatrices r = (p,q) it samples the kernel at the M x M Chebyshev-Gauss
 // points of its domain [i, i+2h] x [j, j+2h] (Eq. (aklmore)),
 //     x_m = i + h (X_m + 1),  y_n = j + h (X_n + 1),  X_m = cos((m+1/2) pi / M),
 // with the leg2cheb kernel A(x,y) = Lambda((y-x)/2) Lambda((y+x)/2) (Sec. 3.2) or the
 // cheb2leg kernel of Eq. (Lxymod), and applies the 2-D DCT-II
 //     ahat_kl = 4/(c_k c_l M^2) sum_m sum_n K(x_m, y_n) D_km D_ln,  D_km = cos(k (m+1/2) pi / M),
-// as two M x M x M products in LDS.  All in FP64.  Results go straight into the
+// as two M x M x M products: each lane holds one row of the samples (then one column of
+// the partial product) in registers, and the DCT matrix enters as operands that are the
+// same for every lane.  All in FP64.  Results go straight into the
 // far-field tables that k_main reads (layouts in l2c_internal.h).  For the nodal basis
 // (Eq. (AijLag)) the samples K(x_k, y_l) themselves are the far-field blocks.
 //
@@ -24,6 +28,8 @@
 #include "l2c_math.h"
 
 namespace l2c {
+
+constexpr int kAhatWaves = 4;                     // k_build_ahat: blocks (one per wave) per workgroup
 
 // Address (in doubles) of element (r, k, l) of block b of level g in the plan tables.
 template <int M>
@@ -43,84 +49,106 @@ __device__ __forceinline__ double *ahat_addr(double *top, double *bot, const Geo
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_build_ahat(double *top, double *bot, Geometry G, int dir,
-                                                          const double *XG, const double *Dm, int nodal,
-                                                          const double *lm)
+__global__ __launch_bounds__(64 * kAhatWaves) void k_build_ahat(double *top, double *bot, Geometry G, int dir,
+                                                                const double *XG, const double *__restrict__ Dm,
+                                                                int nodal, const double *lm, int64_t nblocks)
 {
     constexpr int MM = M * M, NPAIR = M * (M + 1) / 2;
-    __shared__ double S[3 * MM];
-    __shared__ double U[3 * MM];
-    __shared__ double Dl[MM];
+    __shared__ double Sw[kAhatWaves][3 * MM];        // per wave: the samples, then S D^T
     __shared__ double Xl[M];
-    const int L = G.L, s = G.s;
-    // block index -> (level g, block b): level g holds 2^(g+1) - 1 blocks
-    int64_t gb = blockIdx.x;
+    __shared__ unsigned char pm[NPAIR], pn[NPAIR];    // pair index -> (m, n), m <= n
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < M; e += 64 * kAhatWaves) Xl[e] = XG[e];
+    for (int e = tid; e < NPAIR; e += 64 * kAhatWaves) {
+        int pr = e, m = 0;
+        while (pr >= M - m) {
+            pr -= M - m;
+            ++m;
+        }
+        pm[e] = (unsigned char)m;
+        pn[e] = (unsigned char)(m + pr);
+    }
+    __syncthreads();
+    // one block (level g, block b) per wave; adjacent blocks of a level in one workgroup
+    const int64_t blk = (int64_t)blockIdx.x * kAhatWaves + wave;
+    const bool act = blk < nblocks;
+    int64_t gb = act ? blk : 0;
     int g = 0;
     while (gb >= (int64_t(1) << (g + 1)) - 1) {
         gb -= (int64_t(1) << (g + 1)) - 1;
         ++g;
     }
     const int64_t b = gb;
-    const double h = (double)((int64_t)s << (L - g - 1));
-    const int tid = threadIdx.x;
-    for (int e = tid; e < MM; e += kThreads) Dl[e] = Dm[e];
-    for (int e = tid; e < M; e += kThreads) Xl[e] = XG[e];
-    __syncthreads();
+    const double h = (double)((int64_t)G.s << (G.L - g - 1));
+    double *S = Sw[wave];
 
     // samples (m, n) and (n, m) of submatrix r from one Lambda((x+y)/2)
-    for (int e = tid; e < 3 * NPAIR; e += kThreads) {
-        const int r = e / NPAIR;
-        int pr = e - r * NPAIR, m = 0;
-        while (pr >= M - m) {                                    // pair index -> (m, n), m <= n
-            pr -= M - m;
-            ++m;
-        }
-        const int n = m + pr;
-        const int p = (r == 2) ? 1 : 0, q = (r == 0) ? 0 : 1;   // r = p + q(q+1)/2
-        const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
-        const double j0 = 2.0 * h * (double)(2 * b + q + 2);
-        const double *lmr = lm + ((int64_t)g * 2 + (q - p)) * MM;   // offset (q + 2 - p) h
-        const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
-        double vmn, vnm;
-        if (dir == 0) {
-            const double lp = lambda_real(zp);
-            vmn = lmr[m * M + n] * lp;
-            vnm = lmr[n * M + m] * lp;
-        } else {
-            // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2)
-            const double ilp = 1.0 / lambda_real(zp);
-            const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
-            const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
-            const double sp = xm + yn;
-            vmn = 2.0 * (xm + 0.5) * yn / (sp * (sp + 1.0) * (xm - yn + 1.0)) * ilp * lmr[m * M + n];
-            vnm = 2.0 * (xn + 0.5) * ym / (sp * (sp + 1.0) * (xn - ym + 1.0)) * ilp * lmr[n * M + m];
-        }
-        S[r * MM + m * M + n] = vmn;
-        S[r * MM + n * M + m] = vnm;
-        if (nodal) {
-            *ahat_addr<M>(top, bot, G, g, b, r, m, n) = vmn;
-            *ahat_addr<M>(top, bot, G, g, b, r, n, m) = vnm;
+    if (act) {
+        for (int e = lane; e < 3 * NPAIR; e += 64) {
+            const int r = e / NPAIR, pr = e - r * NPAIR;
+            const int m = pm[pr], n = pn[pr];
+            const int p = (r == 2) ? 1 : 0, q = (r == 0) ? 0 : 1;   // r = p + q(q+1)/2
+            const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
+            const double j0 = 2.0 * h * (double)(2 * b + q + 2);
+            const double *lmr = lm + ((int64_t)g * 2 + (q - p)) * MM;   // offset (q + 2 - p) h
+            const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
+            double vmn, vnm;
+            if (dir == 0) {
+                const double lp = lambda_real(zp);
+                vmn = lmr[m * M + n] * lp;
+                vnm = lmr[n * M + m] * lp;
+            } else {
+                // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2)
+                const double ilp = 1.0 / lambda_real(zp);
+                const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
+                const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
+                const double sp = xm + yn;
+                vmn = 2.0 * (xm + 0.5) * yn / (sp * (sp + 1.0) * (xm - yn + 1.0)) * ilp * lmr[m * M + n];
+                vnm = 2.0 * (xn + 0.5) * ym / (sp * (sp + 1.0) * (xn - ym + 1.0)) * ilp * lmr[n * M + m];
+            }
+            S[r * MM + m * M + n] = vmn;
+            S[r * MM + n * M + m] = vnm;
+            if (nodal) {
+                *ahat_addr<M>(top, bot, G, g, b, r, m, n) = vmn;
+                *ahat_addr<M>(top, bot, G, g, b, r, n, m) = vnm;
+            }
         }
     }
-    if (nodal) return;
+    if (nodal) return;                                // uniform: no barrier follows
     __syncthreads();
-    // U[r][m][l] = sum_n S[r][m][n] D[l][n]
-    for (int e = tid; e < 3 * MM; e += kThreads) {
-        const int r = e / MM, ml = e - r * MM;
-        const int m = ml / M, l = ml - m * M;
-        double acc = 0.0;
-        for (int n = 0; n < M; ++n) acc = fma(S[r * MM + m * M + n], Dl[l * M + n], acc);
-        U[e] = acc;
+    // U[r][m][l] = sum_n S[r][m][n] D[l][n]: one row (r, m) per lane, held in registers; D is
+    // the same for every lane (scalar operands).  Each lane rewrites only its own row.
+    if (act) {
+        for (int t = lane; t < 3 * M; t += 64) {
+            double srow[M];
+#pragma unroll
+            for (int n = 0; n < M; ++n) srow[n] = S[t * M + n];
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                double acc = 0.0;
+#pragma unroll
+                for (int n = 0; n < M; ++n) acc = fma(srow[n], Dm[l * M + n], acc);
+                S[t * M + l] = acc;
+            }
+        }
     }
     __syncthreads();
-    // ahat[r][k][l] = 4/(c_k c_l M^2) sum_m D[k][m] U[r][m][l]
-    for (int e = tid; e < 3 * MM; e += kThreads) {
-        const int r = e / MM, kl = e - r * MM;
-        const int k = kl / M, l = kl - k * M;
-        double acc = 0.0;
-        for (int m = 0; m < M; ++m) acc = fma(Dl[k * M + m], U[r * MM + m * M + l], acc);
-        const double sc = 4.0 / ((k == 0 ? 2.0 : 1.0) * (l == 0 ? 2.0 : 1.0) * M * M);
-        *ahat_addr<M>(top, bot, G, g, b, r, k, l) = acc * sc;
+    // ahat[r][k][l] = 4/(c_k c_l M^2) sum_m D[k][m] U[r][m][l]: one column (r, l) per lane
+    if (act) {
+        for (int t = lane; t < 3 * M; t += 64) {
+            const int r = t / M, l = t - r * M;
+            double ucol[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) ucol[m] = S[r * MM + m * M + l];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < M; ++m) acc = fma(Dm[k * M + m], ucol[m], acc);
+                const double sc = 4.0 / ((k == 0 ? 2.0 : 1.0) * (l == 0 ? 2.0 : 1.0) * M * M);
+                *ahat_addr<M>(top, bot, G, g, b, r, k, l) = acc * sc;
+            }
+        }
     }
 }
 
@@ -213,8 +241,9 @@ static hipError_t build(const l2c_plan_s &p, hipStream_t st)
     // (the first blocks of the level-major enumeration)
     const int64_t blocks = p.regen ? level_block_offset(p.geo.groot + 1) : p.nb;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)blocks), dim3(kThreads), 0, st, p.d_top, p.d_bot, p.geo,
-                       p.direction, p.d_XG, p.d_D, p.basis, (const double *)p.d_lm);
+    hipLaunchKernelGGL(k_build_ahat<M>, dim3((unsigned)((blocks + kAhatWaves - 1) / kAhatWaves)),
+                       dim3(64 * kAhatWaves), 0, st, p.d_top, p.d_bot, p.geo, p.direction, p.d_XG,
+                       (const double *)p.d_D, p.basis, (const double *)p.d_lm, blocks);
     return hipGetLastError();
 }
 
