@@ -173,39 +173,59 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
             }
         }
         __syncthreads();
+        // The three products below take both parities per lane (one read of D or S serves
+        // two multiply-adds): 2M lanes, one pass of the wave.
         // u = D^T w: u[q][sigma][n] = sum_l Dl[l][n] w[q][sigma][l]
-        for (int e = lane; e < 2 * M2; e += kRegenThreads) {
-            const int qs = e / M, n = e - qs * M;
-            double acc = 0.0;
+        for (int e = lane; e < M2; e += kRegenThreads) {
+            const int q = e / M, n = e - q * M;
+            double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(Dl[l * M + n], W[qs * M + l], acc);
-            Uv[e] = acc;
+            for (int l = 0; l < M; ++l) {
+                const double dv = Dl[l * M + n];
+                a0 = fma(dv, W[(2 * q) * M + l], a0);
+                a1 = fma(dv, W[(2 * q + 1) * M + l], a1);
+            }
+            Uv[(2 * q) * M + n] = a0;
+            Uv[(2 * q + 1) * M + n] = a1;
         }
         __syncthreads();
         // v = S u: row node 2b takes S(0) u(2b+2) + S(1) u(2b+3), row node 2b+1 takes S(2) u(2b+3)
-        for (int e = lane; e < 2 * M2; e += kRegenThreads) {
-            const int t = e / M2, sg = (e / M) & 1, m = e % M;
-            double acc = 0.0;
+        for (int e = lane; e < M2; e += kRegenThreads) {
+            const int t = e / M, m = e - t * M;
+            double a0 = 0.0, a1 = 0.0;
             if (t == 0) {
 #pragma unroll
                 for (int n = 0; n < M; ++n) {
-                    acc = fma(S[m * M + n], Uv[sg * M + n], acc);
-                    acc = fma(S[MM + m * M + n], Uv[M2 + sg * M + n], acc);
+                    const double s0 = S[m * M + n], s1 = S[MM + m * M + n];
+                    a0 = fma(s0, Uv[n], a0);
+                    a0 = fma(s1, Uv[M2 + n], a0);
+                    a1 = fma(s0, Uv[M + n], a1);
+                    a1 = fma(s1, Uv[M2 + M + n], a1);
                 }
             } else {
 #pragma unroll
-                for (int n = 0; n < M; ++n) acc = fma(S[2 * MM + m * M + n], Uv[M2 + sg * M + n], acc);
+                for (int n = 0; n < M; ++n) {
+                    const double s2 = S[2 * MM + m * M + n];
+                    a0 = fma(s2, Uv[M2 + n], a0);
+                    a1 = fma(s2, Uv[M2 + M + n], a1);
+                }
             }
-            V[e] = acc;
+            V[t * M2 + m] = a0;
+            V[t * M2 + M + m] = a1;
         }
         __syncthreads();
         // c = D v: c[k] = sum_m sc_k cos(k (m + 1/2) pi / M) v[m]
-        for (int e = lane; e < 2 * M2; e += kRegenThreads) {
-            const int tsg = e / M, k = e - tsg * M;
-            double acc = 0.0;
+        for (int e = lane; e < M2; e += kRegenThreads) {
+            const int t = e / M, k = e - t * M;
+            double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc = fma(Dl[k * M + m], V[tsg * M + m], acc);
-            co[e] = acc;
+            for (int m = 0; m < M; ++m) {
+                const double dv = Dl[k * M + m];
+                a0 = fma(dv, V[(2 * t) * M + m], a0);
+                a1 = fma(dv, V[(2 * t + 1) * M + m], a1);
+            }
+            co[(2 * t) * M + k] = a0;
+            co[(2 * t + 1) * M + k] = a1;
         }
     }
 }
