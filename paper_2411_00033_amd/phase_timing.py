@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--lib", default="", help="use this instrumented library instead of building one")
+    ap.add_argument("--dump", default="", help="also save every unit's times (us, reps x units x phases) to this .npy file")
     args = ap.parse_args()
     path = args.lib or build_variant()
     from . import _lib
@@ -104,6 +105,8 @@ def main():
     t = np.stack(rows)                       # reps x units x slots
     t0 = np.min(np.where(t[:, :, 0:1] > 0, t[:, :, 0:1], np.inf), axis=1, keepdims=True)
     rel = (t - t0) * tick_us
+    if args.dump:
+        np.save(args.dump, np.where(t > 0, rel, np.nan))
     print("k_fused phase timeline, n = %d, direction %d, %d units, %d cold executes (wall clock %d kHz)"
           % (args.n, args.direction, t.shape[1], args.reps, khz.value))
     print("| phase | what | median over units (us) | max over units (us) |")
