@@ -18,6 +18,14 @@
 // The reordering and the quarter-wave factors are applied while the FFT loads its input
 // and stores its output, so a DCT is one pass over the data (n <= 4096) or two (larger n).
 //
+// A DCT-3 of even length n >= 16 runs on a complex DFT of half the length, P = n / 2.
+// Since V is Hermitian, v is real, and z_m = v_2m + i v_2m+1 (m < P) is the unnormalized
+// inverse P-point DFT of
+//   Z_k = q (A + B) + i q^5 (A - B),  q = e^{i pi k / (2n)},  A = X_k - i X_{n-k},
+//   B = e^{i pi / 4} (X_{k+P} - i X_{P-k})        (V_k = q A, V_{k+P} = q B),
+// so each Z_k reads the input at k, n - k, k + P and P - k, and the last pass writes
+// Re z_m and Im z_m to rows p(2m) and p(2m+1): half the points, half the bytes per pass.
+//
 // The FFT: Stockham autosort passes of radix 8, 4, 2, 3, 5 and 7 on lines held in LDS
 // (a workgroup takes C lines of length n, C n <= 4096 complex values, 64 KiB); every
 // pass reads all its butterflies' inputs into registers, then writes the outputs in
@@ -54,8 +62,10 @@ static_assert(kFftPre <= kFftSmall, "the up-front store factors live in the smal
 constexpr int kFftMaxPass = 16;
 constexpr int64_t kFftMaxN = int64_t(1) << 27;
 
-enum { kLoadComplex = 0, kLoadDct2 = 1, kLoadDct3 = 2 };
-enum { kStoreComplex = 0, kStoreDct2 = 1, kStoreDct3 = 2 };
+// kLoadDct3H / kStoreDct3H: the DCT-3 of an even length NR on a complex FFT of length
+// N = NR / 2 (the split of the input before the first pass, of the output after the last)
+enum { kLoadComplex = 0, kLoadDct2 = 1, kLoadDct3 = 2, kLoadDct3H = 3 };
+enum { kStoreComplex = 0, kStoreDct2 = 1, kStoreDct3 = 2, kStoreDct3H = 3 };
 
 struct FftArgs {
     int n;                     // DFT length of this launch
@@ -66,7 +76,8 @@ struct FftArgs {
     int64_t lines;             // lines of the launch (transforms x lpt)
     int64_t L1;                // line li of a transform = l1 + L1 l2
     int64_t es_in, ls1_in, ls2_in, es_out, ls1_out, ls2_out;   // index in a transform: e es + l1 ls1 + l2 ls2
-    int64_t N;                 // transform length
+    int64_t N;                 // transform length (of the complex DFT)
+    int64_t NR;                // length of a real input or output row (N, or 2 N for the half-length DCT-3)
     int sign;                  // -1: forward DFT; +1: unnormalized inverse
     const double2 *tw;         // [n]: exp(-2 pi i t / n)
     int twist;                 // store: times exp(sign 2 pi i ((tw_full ? li : l1) e tmul mod N) / N)
@@ -237,6 +248,7 @@ __device__ __forceinline__ int mod_n(double x, double N, double invN)
 // in-transform index on both sides, and the twist multiplier (line index times tmul, mod N).
 struct FftLine {
     int64_t base;        // transform * N; -1: past the last line
+    int64_t rbase;       // transform * NR (the real rows)
     int gin, gout;
     int twa;
 };
@@ -255,7 +267,8 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
     const int n = a.n, C = a.C, N = (int)a.N;
     // store factors loaded up front (lines of at most kFftPre points): one per value, in a
     // slot of LDS private to the thread, so that no register holds them across the passes
-    constexpr bool kPreOk = CAP == kFftSmall && STORE != kStoreDct3 && LOAD != kLoadDct3;   // fft_pre_ok
+    constexpr bool kPreOk = CAP == kFftSmall && (STORE == kStoreComplex || STORE == kStoreDct2) &&
+                            (LOAD == kLoadComplex || LOAD == kLoadDct2);   // fft_pre_ok
     const bool pre = kPreOk && a.pre;
     double2 *buf = smem, *tw = smem + C * n, *fqs = tw + n;
     FftLine *ln = reinterpret_cast<FftLine *>(fqs + (pre ? CAP : 0));
@@ -267,6 +280,7 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
             const int64_t tr = line / a.lpt, li = line - tr * a.lpt;
             const int64_t l2 = li / a.L1, l1 = li - l2 * a.L1;
             L.base = tr * a.N;
+            L.rbase = tr * a.NR;
             L.gin = (int)(l1 * a.ls1_in + l2 * a.ls2_in);
             L.gout = (int)(l1 * a.ls1_out + l2 * a.ls2_out);
             L.twa = a.twist ? (int)(((a.tw_full ? li : l1) * a.tmul) % a.N) : 0;
@@ -281,8 +295,9 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
     const double Nd = (double)N, invN = 1.0 / Nd;
     // input: adjacent threads take adjacent elements of a line, or (strided lines) the same
     // element of adjacent lines, whichever is adjacent in memory
-    double2 raw[EPT], rh[EPT], rl[EPT];
+    double2 raw[EPT], raw2[EPT], rh[EPT], rl[EPT];
     int pos[EPT], gg[EPT];
+    const int NR = (int)a.NR;
     {
         const bool lcol = es_in != 1;
         const FastDiv dv(lcol ? C : n), dqb((int)a.qb);
@@ -303,10 +318,18 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
                     if constexpr (LOAD == kLoadComplex) {
                         raw[u] = a.cin[L.base + g];
                     } else if constexpr (LOAD == kLoadDct2) {
-                        raw[u].x = a.rin[L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1)];
-                    } else {
-                        const double *x = a.rin + L.base;
+                        raw[u].x = a.rin[L.rbase + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1)];
+                    } else if constexpr (LOAD == kLoadDct3) {
+                        const double *x = a.rin + L.rbase;
                         raw[u] = make_double2(x[g], x[g == 0 ? 0 : N - g]);
+                        const int th = dqb.quot(g);
+                        rh[u] = a.qh[th];
+                        rl[u] = a.ql[g - th * dqb.d];
+                    } else {
+                        // c at g, NR - g (none for g = 0), g + N and N - g (all inside the row)
+                        const double *x = a.rin + L.rbase;
+                        raw[u] = make_double2(x[g], g == 0 ? 0.0 : x[NR - g]);
+                        raw2[u] = make_double2(x[g + N], x[N - g]);
                         const int th = dqb.quot(g);
                         rh[u] = a.qh[th];
                         rl[u] = a.ql[g - th * dqb.d];
@@ -331,7 +354,7 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
     const bool scol = es_out != 1;
     const FastDiv dvs(scol ? C : n), dtb((int)(STORE == kStoreDct2 ? a.qb : a.wb));
     double2 sh[EPT], sl[EPT];
-    int64_t dst[EPT];
+    int64_t dst[EPT], dst2[EPT];
     int sp[EPT], sg[EPT], st[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
@@ -352,10 +375,15 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
                     dst[u] = L.base + g;
                     if (a.twist) st[u] = mod_n((double)L.twa * (double)e, Nd, invN);
                 } else if constexpr (STORE == kStoreDct2) {
-                    dst[u] = L.base + g;
+                    dst[u] = L.rbase + g;
                     st[u] = g;
+                } else if constexpr (STORE == kStoreDct3) {
+                    dst[u] = L.rbase + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1);
                 } else {
-                    dst[u] = L.base + (g < (N + 1) / 2 ? 2 * g : 2 * (N - 1 - g) + 1);
+                    // z_g = v_2g + i v_2g+1 goes to rows p(2g) and p(2g+1) of Makhoul's order
+                    const int j0 = 2 * g, j1 = 2 * g + 1;
+                    dst[u] = L.rbase + (j0 < NR / 2 ? 2 * j0 : 2 * (NR - 1 - j0) + 1);
+                    dst2[u] = L.rbase + (j1 < NR / 2 ? 2 * j1 : 2 * (NR - 1 - j1) + 1);
                 }
                 if constexpr (kPreOk) {
                     if (pre && st[u] >= 0) {
@@ -381,6 +409,22 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
             if (gg[u] >= 0) {
                 const bool z = gg[u] == 0;
                 v = cmul(cmul(rh[u], rl[u]), make_double2(z ? v.x : 0.5 * v.x, z ? 0.0 : -0.5 * v.y));
+            }
+        } else if constexpr (LOAD == kLoadDct3H) {
+            if (gg[u] >= 0) {
+                // Z_g = q (A + B) + i q^5 (A - B), q = exp(i pi g / (2 NR)), A = X_g - i X_(NR-g),
+                // B = exp(i pi / 4) (X_(g+N) - i X_(N-g)); X_0 = c_0, X_k = c_k / 2, X_NR = 0
+                const bool z = gg[u] == 0;
+                const double2 A = make_double2(z ? v.x : 0.5 * v.x, -0.5 * v.y);
+                const double2 b0 = make_double2(0.5 * raw2[u].x, -0.5 * raw2[u].y);
+                constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+                const double2 B = make_double2(h * (b0.x - b0.y), h * (b0.x + b0.y));
+                // q^4 = e^{2 pi i g / NR} = e^{i pi g / N} from sincospi (powers of q would
+                // compound the rounding of the tabulated q)
+                double s4, c4;
+                sincospi((double)gg[u] / (double)N, &s4, &c4);
+                const double2 q = cmul(rh[u], rl[u]), q5 = cmul(q, make_double2(c4, s4));
+                v = cadd(cmul(q, cadd(A, B)), cmuli(cmul(q5, csub(A, B)), 1));
             }
         }
         buf[pos[u]] = v;
@@ -420,7 +464,7 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
         Ns *= R;
     }
     double2 fq[EPT];
-    if constexpr (STORE != kStoreDct3) {
+    if constexpr (STORE == kStoreComplex || STORE == kStoreDct2) {
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             fq[u] = make_double2(1.0, 0.0);
@@ -447,8 +491,11 @@ __global__ __launch_bounds__(NT, CAP <= 2048 ? 4 : 2) void k_fft(FftArgs a)
             a.cout[dst[u]] = cmul(val, fq[u]);
         } else if constexpr (STORE == kStoreDct2) {
             a.rout[dst[u]] = fq[u].x * val.x + fq[u].y * val.y;   // Re(conj(q) V), scaled
+        } else if constexpr (STORE == kStoreDct3) {
+            a.rout[dst[u]] = val.x;
         } else {
             a.rout[dst[u]] = val.x;
+            a.rout[dst2[u]] = val.y;
         }
     }
 }
@@ -472,10 +519,12 @@ struct l2c_dct_s {
     int64_t n = 0;
     int kind = 2;
     int device = 0;
-    std::vector<int64_t> dim;                // pass lengths (1 to 3), product n
+    int64_t nf = 0;                          // length of the complex DFT: n, or n / 2 for the half-length DCT-3
+    std::vector<int64_t> dim;                // pass lengths (1 to 3), product nf
     std::vector<std::vector<int>> rad;       // radices per pass
     std::vector<double2 *> tw;               // per pass: exp(-2 pi i t / dim)
-    double2 *wh = nullptr, *wl = nullptr, *qh = nullptr, *ql = nullptr;
+    double2 *wh = nullptr, *wl = nullptr;    // twist: exp(-2 pi i m / nf) = wh[m / wb] wl[m % wb]
+    double2 *qh = nullptr, *ql = nullptr;    // quarter wave: exp(i pi k / (2 n)) = qh[k / qb] ql[k % qb]
     int64_t wb = 1, qb = 1;
     double2 *work = nullptr;                 // four-step intermediate [items][n]
     int64_t work_items = 0;
@@ -493,6 +542,8 @@ struct l2c_grid_s {
 };
 
 namespace {
+
+constexpr int64_t kDct3HalfMin = 16;     // shortest DCT-3 taken on a half-length DFT
 
 bool radices(int64_t n, std::vector<int> &out)
 {
@@ -548,7 +599,8 @@ int ensure_work(l2c_dct_t d, int64_t items)
 l2c::FftArgs base_args(const l2c_dct_t d)
 {
     l2c::FftArgs a{};
-    a.N = d->n;
+    a.N = d->nf;
+    a.NR = d->n;
     a.sign = d->kind == 2 ? -1 : 1;
     a.wh = d->wh;
     a.wl = d->wl;
@@ -574,7 +626,8 @@ void set_pass(l2c::FftArgs &a, int n, const std::vector<int> &r, const double2 *
 // line length): the LDS size depends on it.
 bool fft_pre_ok(const l2c::FftArgs &a)
 {
-    return a.n <= l2c::kFftPre && a.store != l2c::kStoreDct3 && a.load != l2c::kLoadDct3;
+    return a.n <= l2c::kFftPre && (a.store == l2c::kStoreComplex || a.store == l2c::kStoreDct2) &&
+           (a.load == l2c::kLoadComplex || a.load == l2c::kLoadDct2);
 }
 
 // The (load, store) pairs a DCT uses: one pass (DCT load and store), the first of several
@@ -591,6 +644,9 @@ const void *fft_kernel(int load, int store)
     if (load == kLoadComplex && store == kStoreComplex) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreComplex>;
     if (load == kLoadComplex && store == kStoreDct2) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreDct2>;
     if (load == kLoadComplex && store == kStoreDct3) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreDct3>;
+    if (load == kLoadDct3H && store == kStoreDct3H) return (const void *)k_fft<CAP, 512, kLoadDct3H, kStoreDct3H>;
+    if (load == kLoadDct3H && store == kStoreComplex) return (const void *)k_fft<CAP, 512, kLoadDct3H, kStoreComplex>;
+    if (load == kLoadComplex && store == kStoreDct3H) return (const void *)k_fft<CAP, 512, kLoadComplex, kStoreDct3H>;
     return nullptr;
 }
 
@@ -602,10 +658,11 @@ hipError_t fft_attrs()
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
         const int lds = 160 * 1024;
-        const int pairs[7][2] = {{l2c::kLoadDct2, l2c::kStoreDct2},       {l2c::kLoadDct3, l2c::kStoreDct3},
-                                 {l2c::kLoadDct2, l2c::kStoreComplex},    {l2c::kLoadDct3, l2c::kStoreComplex},
-                                 {l2c::kLoadComplex, l2c::kStoreComplex}, {l2c::kLoadComplex, l2c::kStoreDct2},
-                                 {l2c::kLoadComplex, l2c::kStoreDct3}};
+        const int pairs[10][2] = {{l2c::kLoadDct2, l2c::kStoreDct2},       {l2c::kLoadDct3, l2c::kStoreDct3},
+                                  {l2c::kLoadDct2, l2c::kStoreComplex},    {l2c::kLoadDct3, l2c::kStoreComplex},
+                                  {l2c::kLoadComplex, l2c::kStoreComplex}, {l2c::kLoadComplex, l2c::kStoreDct2},
+                                  {l2c::kLoadComplex, l2c::kStoreDct3},    {l2c::kLoadDct3H, l2c::kStoreDct3H},
+                                  {l2c::kLoadDct3H, l2c::kStoreComplex},   {l2c::kLoadComplex, l2c::kStoreDct3H}};
         for (const auto &pr : pairs) {
             for (const void *k : {fft_kernel<l2c::kFftSmall>(pr[0], pr[1]), fft_kernel<l2c::kFftLds>(pr[0], pr[1])}) {
                 if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -634,12 +691,13 @@ hipError_t launch(const l2c::FftArgs &a, hipStream_t st)
 
 int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream_t st)
 {
-    const int load = d->kind == 2 ? l2c::kLoadDct2 : l2c::kLoadDct3;
-    const int store = d->kind == 2 ? l2c::kStoreDct2 : l2c::kStoreDct3;
+    const bool half = d->nf != d->n;         // the DCT-3 on a DFT of half the length
+    const int load = d->kind == 2 ? l2c::kLoadDct2 : half ? l2c::kLoadDct3H : l2c::kLoadDct3;
+    const int store = d->kind == 2 ? l2c::kStoreDct2 : half ? l2c::kStoreDct3H : l2c::kStoreDct3;
     const int P = (int)d->dim.size();
-    const int64_t n = d->n;
+    const int64_t n = d->n, nf = d->nf;     // real rows of n; complex DFTs of nf
     // at most 2^30 lines per launch (grid.x), in whole transforms
-    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 30) / (P == 1 ? 1 : n));
+    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 30) / (P == 1 ? 1 : nf));
     for (int64_t b0 = 0; b0 < batch; b0 += per) {
         const int64_t nb = std::min(per, batch - b0);
         for (int p = 0; p < P; ++p) {
@@ -651,7 +709,7 @@ int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream
             a.rout = out + b0 * n;
             a.cin = d->work;
             a.cout = d->work;
-            const int64_t lpt = n / d->dim[p];
+            const int64_t lpt = nf / d->dim[p];
             a.lpt = lpt;
             a.lines = nb * lpt;
             a.L1 = lpt;
@@ -672,7 +730,7 @@ int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream
                     a.es_out = d->dim[0];
                 } else {                        // lines (ka, kb), ka fastest
                     a.L1 = d->dim[0];
-                    a.ls1_in = n / d->dim[0];
+                    a.ls1_in = nf / d->dim[0];
                     a.ls2_in = nl;
                     a.es_in = 1;
                     a.ls1_out = 1;
@@ -687,7 +745,7 @@ int dct_run(l2c_dct_t d, const double *in, double *out, int64_t batch, hipStream
                 a.ls2_in = a.ls2_out = inner;
                 a.twist = 1;
                 a.tw_full = 0;
-                a.tmul = d->dim[0];             // exp(-2 pi i kb nc / (nb nc)) = exp(-2 pi i kb nc na / n)
+                a.tmul = d->dim[0];             // exp(-2 pi i kb nc / (nb nc)) = exp(-2 pi i kb nc na / nf)
             }
             if (launch(a, st) != hipSuccess) return L2C_EHIP;
         }
@@ -742,21 +800,25 @@ int dct_plan_impl(l2c_dct_t *dct, int64_t n, int kind, int64_t max_batch, void *
         delete d;
         return L2C_EHIP;
     }
-    d->dim = pass_lengths(n);
+    // the DCT-3 of an even length takes a complex DFT of half the length (the input split
+    // into z_m = v_2m + i v_2m+1 of Makhoul's sequence v), when that length is supported
+    d->nf = (kind == 3 && n % 2 == 0 && n >= kDct3HalfMin && !pass_lengths(n / 2).empty()) ? n / 2 : n;
+    const int64_t nf = d->nf;
+    d->dim = pass_lengths(nf);
     d->rad.resize(d->dim.size());
     d->tw.assign(d->dim.size(), nullptr);
     for (size_t i = 0; i < d->dim.size(); ++i) radices(d->dim[i], d->rad[i]);
     hipStream_t st = (hipStream_t)stream;
-    d->wb = isqrt_up(n);
-    d->qb = d->wb;
-    const int64_t wh_n = (n + d->wb - 1) / d->wb + 1;
+    d->wb = isqrt_up(nf);
+    d->qb = isqrt_up(n);
+    const int64_t wh_n = (nf + d->wb - 1) / d->wb + 1, qh_n = (n + d->qb - 1) / d->qb + 1;
     bool ok = true;
     for (size_t i = 0; i < d->dim.size() && ok; ++i)
         ok = roots(&d->tw[i], d->dim[i], 1, (double)d->dim[i], -2.0, st) == hipSuccess;
-    ok = ok && roots(&d->wl, d->wb, 1, (double)n, -2.0, st) == hipSuccess &&
-              roots(&d->wh, wh_n, d->wb, (double)n, -2.0, st) == hipSuccess &&
+    ok = ok && roots(&d->wl, d->wb, 1, (double)nf, -2.0, st) == hipSuccess &&
+              roots(&d->wh, wh_n, d->wb, (double)nf, -2.0, st) == hipSuccess &&
               roots(&d->ql, d->qb, 1, 2.0 * (double)n, 1.0, st) == hipSuccess &&
-              roots(&d->qh, wh_n, d->qb, 2.0 * (double)n, 1.0, st) == hipSuccess;
+              roots(&d->qh, qh_n, d->qb, 2.0 * (double)n, 1.0, st) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_dct(d);

@@ -48,7 +48,8 @@ def test_dct_against_oracle(l2c, n, kind):
 
 @pytest.mark.parametrize("kind", [2, 3])
 def test_dct_n_1e6_sampled(l2c, kind):
-    """The configuration-2 length, 10^6 (three FFT passes of 100): 48 sampled outputs against the oracle."""
+    """The configuration-2 length, 10^6 (three FFT passes; DCT-3 on the half-length DFT): 48 sampled outputs
+    against the oracle."""
     import torch
     n = 10 ** 6
     f = inputs.decaying(n, 0.5, inputs.SEED_BASE + 2)
