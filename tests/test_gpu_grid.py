@@ -24,8 +24,10 @@ def rel(z, ref):
 
 
 # one-pass lengths (<= 4096, mixed radices, a ragged last workgroup of lines) and
-# four-step lengths (n1 n2 with n1, n2 <= 4096)
-SMALL = [1, 2, 3, 5, 7, 8, 12, 30, 49, 64, 100, 343, 1000, 1024, 2187, 3125, 4096]
+# four-step lengths (n1 n2 with n1, n2 <= 4096); a DCT-3 of even length >= 16 takes the
+# half-length DFT (16: the shortest, 18: an odd half length; 12 and the odd lengths: the
+# full-length DFT)
+SMALL = [1, 2, 3, 5, 7, 8, 12, 16, 18, 30, 49, 64, 100, 343, 1000, 1024, 2187, 3125, 4096]
 LARGE = [4200, 6000, 65536, 100000, 117649, 177147, 1 << 20]
 
 
