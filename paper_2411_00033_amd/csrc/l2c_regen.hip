@@ -99,6 +99,7 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
     __shared__ double Dl[MM];
     __shared__ double Xl[M];
     __shared__ unsigned char Pm[NPAIR], Pn[NPAIR];   // pair index -> (m, n), m <= n
+    __shared__ double Ph[NPAIR];                     // (X_m + X_n + 2) / 2 of the pair
     __shared__ double S[3 * MM];      // the three submatrices' samples, [r][m][n]
     __shared__ double W[2 * M2];      // w(2b+2), w(2b+3): [q][sigma][l]
     __shared__ double Uv[2 * M2];     // u = D^T w
@@ -119,6 +120,8 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
         Pn[pr] = (unsigned char)(pr - (m * (2 * M - m + 1)) / 2 + m);
     }
     for (int e = lane; e < M; e += kRegenThreads) Xl[e] = XG[e];
+    __syncthreads();
+    for (int pr = lane; pr < NPAIR; pr += kRegenThreads) Ph[pr] = 0.5 * (Xl[Pm[pr]] + Xl[Pn[pr]] + 2.0);
     const double *wit = a.w + item * G.NT * M2;
     for (int bb = 0; bb < kRegenBlocks; ++bb) {
         const int64_t gblk = (int64_t)blockIdx.x * kRegenBlocks + bb;
@@ -142,34 +145,37 @@ __global__ __launch_bounds__(kRegenThreads) void k_regen(ExecArgs a, const doubl
         // serves samples (m, n) and (n, m) (M (M+1)/2 pairs per submatrix).
         const double h = (double)((int64_t)s << (L - g - 1));
         const double *lmg = lm + (int64_t)g * 2 * MM;
-#pragma unroll 2
-        for (int e = lane; e < 3 * NPAIR; e += kRegenThreads) {
-            const int r = e / NPAIR, pr = e - r * NPAIR;
-            const int m = Pm[pr], n = Pn[pr];
+        for (int r = 0; r < 3; ++r) {                  // the submatrix: p, q and its row bases are uniform
             const int p = r == 2 ? 1 : 0, q = r == 0 ? 0 : 1;          // r = p + q (q + 1) / 2
             const double *lmr = lmg + (q + 2 - p - 2) * MM;             // offset (q + 2 - p) h
-            const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
+            const double zb = h * (double)(4 * b + p + q + 2);
+            const double i0 = 2.0 * h * (double)(2 * b + p), j0 = 2.0 * h * (double)(2 * b + q + 2);
             double *Sr = S + r * MM;
-            // Lambda(zp) = tau(x) / sqrt(x), x = zp + 1/4 (Eq. (tau), zp >= 20): with rx = 1/x and
-            // sr = 1/sqrt(x), tau(rx^2) sr; its reciprocal from the reciprocal series, x sr / tau
-            const bool big = zp >= 20.0;
-            const double x = zp + 0.25, rx = recip(x), sr = rsqrt_nr(x), t = rx * rx;
-            if (dir == 0) {
-                const double lp = big ? tau_poly(t) * sr : lambda_real(zp);
-                Sr[m * M + n] = lmr[m * M + n] * lp;
-                Sr[n * M + m] = lmr[n * M + m] * lp;
-            } else {
-                // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2),
-                // one division for both samples of the pair
-                const double ilp = big ? inv_tau_poly(t) * x * sr : 1.0 / lambda_real(zp);
-                const double i0 = 2.0 * h * (double)(2 * b + p), j0 = 2.0 * h * (double)(2 * b + q + 2);
-                const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
-                const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
-                const double sp = xm + yn;                                // = xn + ym
-                const double d1 = xm - yn + 1.0, d2 = xn - ym + 1.0;
-                const double c2 = ilp * recip(sp * (sp + 1.0) * d1 * d2);
-                Sr[m * M + n] = 2.0 * (xm + 0.5) * yn * d2 * c2 * lmr[m * M + n];
-                Sr[n * M + m] = 2.0 * (xn + 0.5) * ym * d1 * c2 * lmr[n * M + m];
+#pragma unroll 2
+            for (int pr = lane; pr < NPAIR; pr += kRegenThreads) {
+                const int m = Pm[pr], n = Pn[pr];
+                const double zp = zb + h * Ph[pr];
+                // Lambda(zp) = tau(x) / sqrt(x), x = zp + 1/4 (Eq. (tau), zp >= 20): with rx = 1/x
+                // and sr = 1/sqrt(x), tau(rx^2) sr; its reciprocal from the reciprocal series,
+                // x sr / tau
+                const bool big = zp >= 20.0;
+                const double x = zp + 0.25, rx = recip(x), sr = rsqrt_nr(x), tt = rx * rx;
+                if (dir == 0) {
+                    const double lp = big ? tau_poly(tt) * sr : lambda_real(zp);
+                    Sr[m * M + n] = lmr[m * M + n] * lp;
+                    Sr[n * M + m] = lmr[n * M + m] * lp;
+                } else {
+                    // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) /
+                    // Lambda((x+y)/2), one division for both samples of the pair
+                    const double ilp = big ? inv_tau_poly(tt) * x * sr : 1.0 / lambda_real(zp);
+                    const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
+                    const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
+                    const double sp = xm + yn;                                // = xn + ym
+                    const double d1 = xm - yn + 1.0, d2 = xn - ym + 1.0;
+                    const double c2 = ilp * recip(sp * (sp + 1.0) * d1 * d2);
+                    Sr[m * M + n] = 2.0 * (xm + 0.5) * yn * d2 * c2 * lmr[m * M + n];
+                    Sr[n * M + m] = 2.0 * (xn + 0.5) * ym * d1 * c2 * lmr[n * M + m];
+                }
             }
         }
         __syncthreads();
