@@ -82,35 +82,38 @@ __global__ __launch_bounds__(64 * kAhatWaves) void k_build_ahat(double *top, dou
     const double h = (double)((int64_t)G.s << (G.L - g - 1));
     double *S = Sw[wave];
 
-    // samples (m, n) and (n, m) of submatrix r from one Lambda((x+y)/2)
+    // samples (m, n) and (n, m) of submatrix r from one Lambda((x+y)/2); per submatrix, p, q,
+    // the factor table's rows and the corner are the same for the whole wave
     if (act) {
-        for (int e = lane; e < 3 * NPAIR; e += 64) {
-            const int r = e / NPAIR, pr = e - r * NPAIR;
-            const int m = pm[pr], n = pn[pr];
+        for (int r = 0; r < 3; ++r) {
             const int p = (r == 2) ? 1 : 0, q = (r == 0) ? 0 : 1;   // r = p + q(q+1)/2
             const double i0 = 2.0 * h * (double)(2 * b + p);        // Eq. (globalij)
             const double j0 = 2.0 * h * (double)(2 * b + q + 2);
             const double *lmr = lm + ((int64_t)g * 2 + (q - p)) * MM;   // offset (q + 2 - p) h
-            const double zp = h * (double)(4 * b + p + q + 2) + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
-            double vmn, vnm;
-            if (dir == 0) {
-                const double lp = lambda_real(zp);
-                vmn = lmr[m * M + n] * lp;
-                vnm = lmr[n * M + m] * lp;
-            } else {
-                // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2)
-                const double ilp = 1.0 / lambda_real(zp);
-                const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
-                const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
-                const double sp = xm + yn;
-                vmn = 2.0 * (xm + 0.5) * yn / (sp * (sp + 1.0) * (xm - yn + 1.0)) * ilp * lmr[m * M + n];
-                vnm = 2.0 * (xn + 0.5) * ym / (sp * (sp + 1.0) * (xn - ym + 1.0)) * ilp * lmr[n * M + m];
-            }
-            S[r * MM + m * M + n] = vmn;
-            S[r * MM + n * M + m] = vnm;
-            if (nodal) {
-                *ahat_addr<M>(top, bot, G, g, b, r, m, n) = vmn;
-                *ahat_addr<M>(top, bot, G, g, b, r, n, m) = vnm;
+            const double zb = h * (double)(4 * b + p + q + 2);
+            for (int pr = lane; pr < NPAIR; pr += 64) {
+                const int m = pm[pr], n = pn[pr];
+                const double zp = zb + 0.5 * h * (Xl[m] + Xl[n] + 2.0);
+                double vmn, vnm;
+                if (dir == 0) {
+                    const double lp = lambda_real(zp);
+                    vmn = lmr[m * M + n] * lp;
+                    vnm = lmr[n * M + m] * lp;
+                } else {
+                    // Eq. (Lxymod): 2 (x+1/2) y / ((x+y)(x+y+1)(x-y+1)) Lambda((y-x)/2) / Lambda((x+y)/2)
+                    const double ilp = 1.0 / lambda_real(zp);
+                    const double xm = i0 + h * (Xl[m] + 1.0), yn = j0 + h * (Xl[n] + 1.0);
+                    const double xn = i0 + h * (Xl[n] + 1.0), ym = j0 + h * (Xl[m] + 1.0);
+                    const double sp = xm + yn;
+                    vmn = 2.0 * (xm + 0.5) * yn / (sp * (sp + 1.0) * (xm - yn + 1.0)) * ilp * lmr[m * M + n];
+                    vnm = 2.0 * (xn + 0.5) * ym / (sp * (sp + 1.0) * (xn - ym + 1.0)) * ilp * lmr[n * M + m];
+                }
+                S[r * MM + m * M + n] = vmn;
+                S[r * MM + n * M + m] = vnm;
+                if (nodal) {
+                    *ahat_addr<M>(top, bot, G, g, b, r, m, n) = vmn;
+                    *ahat_addr<M>(top, bot, G, g, b, r, n, m) = vnm;
+                }
             }
         }
     }
